@@ -1,0 +1,141 @@
+/*
+ * SPS hot-path ORACLE -- test infrastructure only.
+ *
+ * A plain, slow FP64 CPU implementation of the forward model, photometry,
+ * likelihood and HMC sampler of "Bayesian Posteriors with Stellar Population
+ * Synthesis on GPUs" (Zacharegkas, Hearin & Benson), written from the paper's
+ * equations.  It exists to check the HIP library; only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header or table with the HIP library.
+ *
+ * All arrays are host FP64, row-major.  Parameters are AoS: theta[g][10] in the
+ * slot order documented in synth/__init__.py.  Gradients come from forward-mode
+ * dual numbers (an independent differentiation route from the library's
+ * hand-written adjoint).
+ *
+ * Return codes: 0 ok, 1 invalid argument, 2 z outside the table range.
+ */
+#ifndef SPS_ORACLE_H
+#define SPS_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NPARAM 10
+
+typedef struct {
+    int n_met, n_age, n_wave;
+    const double *log10_met;     /* [n_met]  log10 Z/Zsun, increasing          */
+    const double *log10_age_yr;  /* [n_age]  log10 age/yr, increasing          */
+    const double *wave_A;        /* [n_wave] rest-frame wavelength, increasing  */
+    const double *lum;           /* [n_met][n_age][n_wave] Lsun/A per Msun formed */
+} orc_ssp;
+
+typedef struct {
+    int n_band;
+    const double *center_A;      /* Gaussian transmission, peak 1, observed frame */
+    const double *sigma_A;
+} orc_filters;
+
+typedef struct { double H0, Om; } orc_cosmo;   /* flat LCDM, km/s/Mpc */
+
+typedef struct {
+    double sigma_logz;   /* width of the log-normal metallicity distribution [dex] */
+    double burst_dlogt;  /* log10 T_max - log10 T_peak [dex]                        */
+} orc_model;
+
+/* ---- cosmology (flat LCDM, matter + Lambda) ---- */
+double orc_age_universe_gyr(const orc_cosmo *c, double z);
+double orc_lum_distance_mpc(const orc_cosmo *c, double z);
+
+/* ---- per-galaxy SSP weights ---- */
+/* p_age[n_age], p_smooth[n_age], p_burst[n_age], p_met[n_met]; any may be NULL. */
+int orc_age_weights(const orc_ssp *s, const orc_cosmo *c, const orc_model *m, int sfh,
+                    const double *theta, double z,
+                    double *p_age, double *p_smooth, double *p_burst);
+int orc_met_weights(const orc_ssp *s, const orc_model *m, const double *theta, double *p_met);
+/* w[g][n_met][n_age], summing to 10^theta[0] (mass formed) */
+int orc_weights(const orc_ssp *s, const orc_cosmo *c, const orc_model *m, int sfh,
+                int n_gal, const double *theta, const double *z, double *w);
+/* smooth-SFH mass formed per age bin, unnormalised [n_age] (rate amplitude 1) */
+int orc_smooth_bin_mass(const orc_ssp *s, const orc_cosmo *c, int sfh,
+                        const double *theta, double z, double *mass);
+
+/* ---- dust ---- */
+double orc_dust_att(const double *theta, double lam_rest_A);
+
+/* ---- filters ---- */
+double orc_lambda_eff(const orc_filters *f, int band);
+
+/* ---- photometry: AB magnitudes mags[g][n_band] ---- */
+int orc_phot_exact(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                   int sfh, int n_gal, const double *theta, const double *z, double *mags);
+/* Q[n_z][n_band][n_met][n_age]: distance-free SSP band fluxes on z nodes */
+int orc_ztable(const orc_ssp *s, const orc_filters *f, int n_z, double z_lo, double z_hi, double *q);
+int orc_phot_approx(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                    int n_z, double z_lo, double z_hi, const double *q,
+                    int sfh, int n_gal, const double *theta, const double *z, double *mags);
+
+/* ---- Gaussian log-likelihood and its gradient w.r.t. the 10 physical params ----
+ * path 0 = approximate (needs q), 1 = exact.  obs, sigma [g][n_band]; mask[g] bit b = band used.
+ * grad [g][10] may be NULL. */
+int orc_loglike_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                     int path, int n_z, double z_lo, double z_hi, const double *q,
+                     int sfh, int n_gal, const double *theta, const double *z,
+                     const double *obs, const double *sigma, const uint8_t *mask,
+                     double *logl, double *grad);
+
+/* ---- bounding function and skew-normal prior ---- */
+/* bounds[p][4] = (y_lo, y_hi, k, x0); prior[p][3] = (xi, omega, s) on the unbounded value */
+double orc_bound(const double *bnd, double x_unbounded);
+double orc_unbound(const double *bnd, double theta);
+double orc_log_prior(const double *pri, double x_unbounded);
+/* log posterior on the unbounded parameters and its gradient [10] */
+int orc_logpost_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                     int n_z, double z_lo, double z_hi, const double *q, int sfh,
+                     const double *theta_u, double z, const double *obs, const double *sigma,
+                     uint8_t mask, const double *bounds, const double *prior,
+                     double *logp, double *grad);
+
+/* n_step leapfrog steps (half kick, drift, half kick) of the HMC dynamics from
+ * (x, p) in place; logp = log target at the final x.  gauss_prec as in orc_hmc_run. */
+int orc_leapfrog(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                 int n_z, double z_lo, double z_hi, const double *q, int sfh, double z, const double *obs,
+                 const double *sigma, uint8_t mask, const double *bounds, const double *prior,
+                 const double *gauss_prec, int n_step, double eps, double *x, double *p, double *logp);
+
+/* ---- counter-based RNG (Philox4x32-10) ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* ---- HMC ---- */
+typedef struct {
+    int n_chain, n_leapfrog, n_warmup, n_sample;
+    double target_accept, init_step;
+    uint64_t seed;
+} orc_hmc_cfg;
+
+/* theta0[c][g][10] unbounded start; outputs:
+ *   post_mean, post_sd, rhat [g][10] (physical parameters),
+ *   accept [g] (fraction accepted in the sampling phase, all chains),
+ *   step [c][g] (step size after warm-up),
+ *   samples [n_sample][c][g][10] physical (may be NULL),
+ *   trace_logp [n_warmup+n_sample][c][g] log posterior after each iteration (may be NULL).
+ * gauss_prec (may be NULL): if set, the target is the zero-mean Gaussian with this
+ * 10x10 precision matrix instead of the SPS posterior (sampler validation mode;
+ * then the physical map is the identity). */
+int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                int n_z, double z_lo, double z_hi, const double *q, int sfh,
+                const orc_hmc_cfg *cfg, int n_gal, const double *z, const double *obs,
+                const double *sigma, const uint8_t *mask, const double *bounds, const double *prior,
+                const double *theta0, const double *gauss_prec,
+                double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
+                double *samples, double *trace_logp);
+
+/* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
+double orc_rhat(int n_chain, int n, const double *x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
