@@ -1,0 +1,174 @@
+/*
+ * sps.h -- C ABI of the MI355X (gfx950) SPS photometry / likelihood / HMC library.
+ *
+ * Implements the per-galaxy forward model of "Bayesian Posteriors with Stellar
+ * Population Synthesis on GPUs" (Zacharegkas, Hearin & Benson):
+ *   SSP weights from the star-formation history and metallicity distribution
+ *     (App. A.1 Eqs. totalMstarFormed, SFRsmooth, smoothPsfh, composite age
+ *      weights, triweight; App. A.2),
+ *   dust attenuation (App. A.3, Eq. DustAtt and the unobscured floor),
+ *   exact photometry (Sec. 3, Eq. photo_integral_exact),
+ *   approximate photometry with a precomputed SSP x band table interpolated in
+ *     redshift (Sec. 3, Eqs. lambda_eff and photo_integral_approx),
+ *   the Gaussian photometric log-likelihood and its gradient (App. D.1), and
+ *   batched HMC chains on the unbounded parameters (Sec. 4; App. C bounding
+ *     function and skew-normal prior; App. D.2).
+ *
+ * Conventions
+ *  - Every array argument of a compute call is a DEVICE pointer on the
+ *    context's device, contiguous, owned by the caller.  The library never
+ *    frees or retains them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *    enqueue work and return without synchronising, except where stated.
+ *  - Parameters are structure-of-arrays: params[p * n_gal + g], p = 0..9 in
+ *    this slot order (physical units):
+ *      0 log10 M_formed [Msun]   1 tau [Gyr] (DPL) | t_peak [Gyr] (log-normal)
+ *      2 alpha (DPL) | width w (log-normal, natural-log units)
+ *      3 beta (DPL) | unused     4 F_burst     5 log10 T_peak [yr]
+ *      6 mu_logZ                 7 tau_V       8 delta       9 F_floor
+ *  - Magnitudes, observations and sigmas are [n_gal][n_band] row-major.
+ *  - Return value: SPS_OK or an error code; sps_last_error() gives a
+ *    thread-local message.  Invalid sizes, enums or NULL required pointers are
+ *    errors.  NaN parameters propagate to NaN outputs and are not errors.  A
+ *    redshift outside the context's z table gives NaN outputs for that galaxy
+ *    on the approximate path (no host synchronisation is made to report it).
+ *  - Calls on one context from several host threads must be serialised by the
+ *    caller; work enqueued on different streams must not overlap in time when
+ *    it uses the context's internal workspace (all compute calls do).
+ */
+#ifndef SPS_H
+#define SPS_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPS_NPARAM 10
+#define SPS_MAX_BAND 8
+
+enum {
+    SPS_OK = 0,
+    SPS_E_INVAL = 1,   /* bad argument: size, enum, NULL pointer, unsupported grid */
+    SPS_E_RANGE = 2,   /* value outside a supported range (e.g. z table bounds)   */
+    SPS_E_NOMEM = 3,   /* device allocation failed                                */
+    SPS_E_HIP = 4,     /* HIP runtime error                                       */
+    SPS_E_STATE = 5    /* call out of order (e.g. no z table built yet)           */
+};
+
+typedef enum { SPS_F64 = 0, SPS_F32 = 1, SPS_BF16X = 2 } sps_prec;   /* exact-path arithmetic */
+typedef enum { SPS_SFH_LOGNORMAL = 0, SPS_SFH_DPL = 1 } sps_sfh;
+typedef enum { SPS_PATH_APPROX = 0, SPS_PATH_EXACT = 1 } sps_path;
+
+/* Host FP64 descriptors, copied (and uploaded) at sps_create. */
+typedef struct {
+    int n_met, n_age, n_wave;
+    const double *log10_met;     /* [n_met] increasing, log10 Z/Zsun                    */
+    const double *log10_age_yr;  /* [n_age] increasing, log10 age / yr                 */
+    const double *wave_A;        /* [n_wave] increasing rest-frame wavelength, Angstrom */
+    const double *lum;           /* [n_met][n_age][n_wave] Lsun / A per Msun formed     */
+} sps_ssp_desc;
+
+typedef struct {
+    int n_band;                  /* 1 .. SPS_MAX_BAND                                   */
+    const double *center_A;      /* Gaussian transmission T(l) = exp(-(l-c)^2/(2 s^2)), */
+    const double *sigma_A;       /* observed frame, peak 1                              */
+} sps_filter_desc;
+
+typedef struct {
+    double H0;          /* km/s/Mpc, flat LCDM with matter + Lambda (e.g. 70)          */
+    double Om;          /* matter density (e.g. 0.3)                                   */
+    double sigma_logz;  /* width of the log-normal metallicity distribution, dex (0.2) */
+    double burst_dlogt; /* log10 T_max - log10 T_peak of the triweight burst, dex (0.3) */
+} sps_model_desc;
+
+typedef struct sps_ctx sps_ctx;
+
+/* Create a context on `device`: uploads the SSP grid (FP64 always; FP32 if
+ * prec_mask has bit 1<<SPS_F32; BF16 hi+lo pair if bit 1<<SPS_BF16X), the
+ * wavelength quadrature weights and the filter constants, and reserves
+ * workspace for up to max_gal galaxies.  Supported SSP grid: n_age = 94,
+ * n_met = 12 (compile-time register tiles); n_band <= 8.  On error *out is NULL. */
+int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_filter_desc *filters,
+               const sps_model_desc *model, unsigned prec_mask, int max_gal);
+
+/* Grow the per-galaxy workspace to max_gal galaxies (synchronises the device). */
+int sps_reserve(sps_ctx *ctx, int max_gal);
+
+/* Build the SSP x band flux table c_SSP(z) on n_z uniform nodes in [z_lo, z_hi]
+ * (Sec. 3: "calculated in advance ... on a lookup table").  Stored distance-free
+ * and divided by the band normalisation: Q[k][b][j][i] =
+ *   sum_l L[j][i][l] T_b((1+z_k) l) l q_l / sum_l T_b((1+z_k) l) q_l / l
+ * with trapezoid weights q_l on the SSP wavelength grid; FP64 arithmetic,
+ * FP32 storage.  Synchronises the device.  2 <= n_z <= 1024. */
+int sps_build_ztable(sps_ctx *ctx, int n_z, double z_lo, double z_hi);
+
+/* Copy the z table to host memory q[n_z][n_band][n_met][n_age] (FP32). */
+int sps_get_ztable(sps_ctx *ctx, float *q_host);
+
+void sps_destroy(sps_ctx *ctx);
+const char *sps_last_error(void);
+
+/* SSP weights W[g][j][i] = M_formed P_met(j) P_age(i) (Eq. galSED_decomposed;
+ * sums to 10^params[0]).  params [10][n_gal], z [n_gal], w_out [n_gal][n_met][n_age]. */
+int sps_weights(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float *params, const float *z,
+                float *w_out);
+
+/* Approximate AB magnitudes (Eq. photo_integral_approx; attenuation evaluated at
+ * the rest-frame effective wavelength, table interpolated linearly in z, in
+ * flux).  Needs a z table.  mag_out [n_gal][n_band] FP32. */
+int sps_phot_approx(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float *params,
+                    const float *z, float *mag_out);
+
+/* Exact AB magnitudes (Eq. photo_integral_exact): dense (galaxies x SSPs) x
+ * (SSPs x wavelengths) contraction on MFMA with the attenuation x redshifted
+ * filter x quadrature weight applied in the epilogue.  prec = SPS_F64:
+ * params/z/mag_out are double; SPS_F32 and SPS_BF16X (split hi+lo BF16 with
+ * FP32 accumulation): float.  The requested precision's table must have been
+ * uploaded at create. */
+int sps_phot_exact(sps_ctx *ctx, void *stream, int n_gal, int sfh, int prec, const void *params,
+                   const void *z, void *mag_out);
+
+/* Gaussian log-likelihood  log L = sum_b mask_b [-(m_b - d_b)^2 / (2 s_b^2) - ln(s_b sqrt(2 pi))]
+ * and its gradient w.r.t. the 10 physical parameters (hand-written adjoint).
+ * path SPS_PATH_APPROX (prec ignored) or SPS_PATH_EXACT (prec SPS_F32 or SPS_BF16X).
+ * obs, sigma [n_gal][n_band]; band_mask [n_gal] (bit b set = band used);
+ * logl_out [n_gal]; grad_out [10][n_gal] or NULL for value only. */
+int sps_loglike_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, int path, int prec,
+                     const float *params, const float *z, const float *obs, const float *sigma,
+                     const uint8_t *band_mask, float *logl_out, float *grad_out);
+
+/* Log posterior on the unbounded parameters x (App. C): theta_p = F_B(x_p) with
+ * bounds[p] = (y_lo, y_hi, k, x0), plus the skew-normal log prior with
+ * prior[p] = (xi, omega, s) on x_p; value logp_out [n_gal] and gradient
+ * grad_out [10][n_gal] w.r.t. x (approximate path).  bounds, prior: device [10][4], [10][3]. */
+int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float *x,
+                     const float *z, const float *obs, const float *sigma, const uint8_t *band_mask,
+                     const float *bounds, const float *prior, float *logp_out, float *grad_out);
+
+/* Batched HMC: n_chain chains per galaxy, identity mass matrix, n_leapfrog
+ * leapfrog steps per iteration, per-chain step size adapted by dual averaging
+ * over n_warmup iterations, then n_sample recorded iterations; momentum and
+ * accept draws from Philox4x32-10 keyed by seed with counter (draw block,
+ * iteration, chain id = c * n_gal + g, 0).  Hamiltonian and accept test in FP64.
+ * All device pointers:
+ *   theta0 [n_chain][10][n_gal] unbounded starting points (required),
+ *   samples [n_sample][n_chain][10][n_gal] physical draws or NULL,
+ *   post_mean, post_sd, rhat [10][n_gal] (physical parameters, pooled chains),
+ *   accept [n_gal] acceptance fraction in the sampling phase,
+ *   step [n_chain][n_gal] step size after warm-up. */
+typedef struct {
+    int n_chain, n_leapfrog, n_warmup, n_sample;
+    float target_accept, init_step;
+    unsigned long long seed;
+} sps_hmc_cfg;
+
+int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh,
+                const float *z, const float *obs, const float *sigma, const uint8_t *band_mask,
+                const float *bounds, const float *prior, const float *theta0, float *samples,
+                float *post_mean, float *post_sd, float *rhat, float *accept, float *step);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPS_H */

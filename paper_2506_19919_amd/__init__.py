@@ -1,0 +1,279 @@
+"""MI355X-native SPS photometry, likelihood and HMC (binding of libsps.so).
+
+Thin marshalling layer over the C ABI declared in include/sps.h: every step of
+the computation runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensors) and the current HIP stream.  The library must have been built
+(``python paper_2506_19919_amd/build.py``); importing this module on a machine
+without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsps.so")
+
+SPS_OK, SPS_E_INVAL, SPS_E_RANGE, SPS_E_NOMEM, SPS_E_HIP, SPS_E_STATE = range(6)
+SPS_F64, SPS_F32, SPS_BF16X = 0, 1, 2
+SPS_SFH_LOGNORMAL, SPS_SFH_DPL = 0, 1
+SPS_PATH_APPROX, SPS_PATH_EXACT = 0, 1
+NPARAM = 10
+MAX_BAND = 8
+
+ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_build_ztable", "sps_get_ztable", "sps_destroy",
+                 "sps_last_error", "sps_weights", "sps_phot_approx", "sps_phot_exact",
+                 "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run")
+
+
+class SpsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sps error {code}: {msg}")
+        self.code = code
+
+
+class _SspDesc(C.Structure):
+    _fields_ = [("n_met", C.c_int), ("n_age", C.c_int), ("n_wave", C.c_int),
+                ("log10_met", C.POINTER(C.c_double)), ("log10_age_yr", C.POINTER(C.c_double)),
+                ("wave_A", C.POINTER(C.c_double)), ("lum", C.POINTER(C.c_double))]
+
+
+class _FilterDesc(C.Structure):
+    _fields_ = [("n_band", C.c_int), ("center_A", C.POINTER(C.c_double)),
+                ("sigma_A", C.POINTER(C.c_double))]
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [("H0", C.c_double), ("Om", C.c_double), ("sigma_logz", C.c_double),
+                ("burst_dlogt", C.c_double)]
+
+
+class _HmcCfg(C.Structure):
+    _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
+                ("n_sample", C.c_int), ("target_accept", C.c_float), ("init_step", C.c_float),
+                ("seed", C.c_ulonglong)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_19919_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i = C.c_void_p, C.c_int
+    lib.sps_last_error.restype = C.c_char_p
+    lib.sps_last_error.argtypes = []
+    lib.sps_create.argtypes = [C.POINTER(vp), i, C.POINTER(_SspDesc), C.POINTER(_FilterDesc),
+                               C.POINTER(_ModelDesc), C.c_uint, i]
+    lib.sps_reserve.argtypes = [vp, i]
+    lib.sps_build_ztable.argtypes = [vp, i, C.c_double, C.c_double]
+    lib.sps_get_ztable.argtypes = [vp, vp]
+    lib.sps_destroy.argtypes = [vp]
+    lib.sps_destroy.restype = None
+    lib.sps_weights.argtypes = [vp, vp, i, i, vp, vp, vp]
+    lib.sps_phot_approx.argtypes = [vp, vp, i, i, vp, vp, vp]
+    lib.sps_phot_exact.argtypes = [vp, vp, i, i, i, vp, vp, vp]
+    lib.sps_loglike_grad.argtypes = [vp, vp, i, i, i, i, vp, vp, vp, vp, vp, vp, vp]
+    lib.sps_logpost_grad.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sps_hmc_run.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
+                                vp, vp, vp, vp, vp]
+    for name in ABI_FUNCTIONS:
+        if name not in ("sps_destroy", "sps_last_error"):
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != SPS_OK:
+        raise SpsError(rc, _lib.sps_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, shape, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """One library context: SSP grid, filters and model constants on one GPU."""
+
+    def __init__(self, ssp: dict, filters: dict, model: dict | None = None, device: int = 0,
+                 precisions=(SPS_F64, SPS_F32), max_gal: int = 1 << 20):
+        m = dict(H0=70.0, Om=0.3, sigma_logz=0.2, burst_dlogt=0.3)
+        m.update(model or {})
+        self._keep = [np.ascontiguousarray(ssp[k], dtype=np.float64)
+                      for k in ("log10_met", "log10_age_yr", "wave_A", "lum")]
+        self._keep += [np.ascontiguousarray(filters[k], dtype=np.float64) for k in ("center_A", "sigma_A")]
+        met, age, wave, lum, cen, sig = self._keep
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        sd = _SspDesc(len(met), len(age), len(wave), dp(met), dp(age), dp(wave), dp(lum))
+        fd = _FilterDesc(len(cen), dp(cen), dp(sig))
+        md = _ModelDesc(m["H0"], m["Om"], m["sigma_logz"], m["burst_dlogt"])
+        mask = 0
+        for p in precisions:
+            mask |= 1 << p
+        h = C.c_void_p()
+        _check(_lib.sps_create(C.byref(h), device, C.byref(sd), C.byref(fd), C.byref(md), mask, max_gal))
+        self.h = h
+        self.device = torch.device("cuda", device)
+        self.n_met, self.n_age, self.n_wave, self.n_band = len(met), len(age), len(wave), len(cen)
+        self.max_gal = max_gal
+        self.ztable_spec = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.sps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- setup
+    def reserve(self, max_gal: int):
+        _check(_lib.sps_reserve(self.h, max_gal))
+        self.max_gal = max(self.max_gal, max_gal)
+
+    def build_ztable(self, n_z: int = 64, z_lo: float = 0.1, z_hi: float = 3.0):
+        _check(_lib.sps_build_ztable(self.h, n_z, C.c_double(z_lo), C.c_double(z_hi)))
+        self.ztable_spec = (n_z, z_lo, z_hi)
+
+    def get_ztable(self) -> np.ndarray:
+        n_z = self.ztable_spec[0]
+        q = np.zeros((n_z, self.n_band, self.n_met, self.n_age), np.float32)
+        _check(_lib.sps_get_ztable(self.h, q.ctypes.data_as(C.c_void_p)))
+        return q
+
+    # ---- helpers
+    def _gal(self, params, z, dtype=torch.float32):
+        n = z.shape[0]
+        _dev(params, dtype, (NPARAM, n), "params", self.device)
+        _dev(z, dtype, (n,), "z", self.device)
+        return n
+
+    # ---- entry points (same names as the C ABI)
+    def weights(self, sfh, params, z, out=None, stream=None):
+        n = self._gal(params, z)
+        if out is None:
+            out = torch.empty((n, self.n_met, self.n_age), dtype=torch.float32, device=self.device)
+        _dev(out, torch.float32, (n, self.n_met, self.n_age), "w_out", self.device)
+        _check(_lib.sps_weights(self.h, _stream(stream), n, sfh, _ptr(params), _ptr(z), _ptr(out)))
+        return out
+
+    def phot_approx(self, sfh, params, z, out=None, stream=None):
+        n = self._gal(params, z)
+        if out is None:
+            out = torch.empty((n, self.n_band), dtype=torch.float32, device=self.device)
+        _dev(out, torch.float32, (n, self.n_band), "mag_out", self.device)
+        _check(_lib.sps_phot_approx(self.h, _stream(stream), n, sfh, _ptr(params), _ptr(z), _ptr(out)))
+        return out
+
+    def phot_exact(self, sfh, params, z, prec=SPS_F32, out=None, stream=None):
+        dt = torch.float64 if prec == SPS_F64 else torch.float32
+        n = self._gal(params, z, dt)
+        if out is None:
+            out = torch.empty((n, self.n_band), dtype=dt, device=self.device)
+        _dev(out, dt, (n, self.n_band), "mag_out", self.device)
+        _check(_lib.sps_phot_exact(self.h, _stream(stream), n, sfh, prec, _ptr(params), _ptr(z), _ptr(out)))
+        return out
+
+    def loglike_grad(self, sfh, params, z, obs, sigma, mask, path=SPS_PATH_APPROX, prec=SPS_F32,
+                     grad=True, logl_out=None, grad_out=None, stream=None):
+        n = self._gal(params, z)
+        _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
+        _dev(sigma, torch.float32, (n, self.n_band), "sigma", self.device)
+        _dev(mask, torch.uint8, (n,), "band_mask", self.device)
+        if logl_out is None:
+            logl_out = torch.empty(n, dtype=torch.float32, device=self.device)
+        if grad and grad_out is None:
+            grad_out = torch.empty((NPARAM, n), dtype=torch.float32, device=self.device)
+        _check(_lib.sps_loglike_grad(self.h, _stream(stream), n, sfh, path, prec, _ptr(params), _ptr(z),
+                                     _ptr(obs), _ptr(sigma), _ptr(mask), _ptr(logl_out),
+                                     _ptr(grad_out) if grad else None))
+        return (logl_out, grad_out) if grad else logl_out
+
+    def logpost_grad(self, sfh, x, z, obs, sigma, mask, bounds, prior, stream=None):
+        n = self._gal(x, z)
+        _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
+        _dev(sigma, torch.float32, (n, self.n_band), "sigma", self.device)
+        _dev(mask, torch.uint8, (n,), "band_mask", self.device)
+        _dev(bounds, torch.float32, (NPARAM, 4), "bounds", self.device)
+        _dev(prior, torch.float32, (NPARAM, 3), "prior", self.device)
+        lp = torch.empty(n, dtype=torch.float32, device=self.device)
+        g = torch.empty((NPARAM, n), dtype=torch.float32, device=self.device)
+        _check(_lib.sps_logpost_grad(self.h, _stream(stream), n, sfh, _ptr(x), _ptr(z), _ptr(obs),
+                                     _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(lp), _ptr(g)))
+        return lp, g
+
+    def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
+                n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
+                keep_samples=False, stream=None):
+        n = z.shape[0]
+        _dev(z, torch.float32, (n,), "z", self.device)
+        _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
+        _dev(sigma, torch.float32, (n, self.n_band), "sigma", self.device)
+        _dev(mask, torch.uint8, (n,), "band_mask", self.device)
+        _dev(bounds, torch.float32, (NPARAM, 4), "bounds", self.device)
+        _dev(prior, torch.float32, (NPARAM, 3), "prior", self.device)
+        _dev(theta0, torch.float32, (n_chain, NPARAM, n), "theta0", self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        out = dict(post_mean=torch.empty((NPARAM, n), **f32), post_sd=torch.empty((NPARAM, n), **f32),
+                   rhat=torch.empty((NPARAM, n), **f32), accept=torch.empty(n, **f32),
+                   step=torch.empty((n_chain, n), **f32))
+        samples = torch.empty((n_sample, n_chain, NPARAM, n), **f32) if keep_samples else None
+        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed)
+        _check(_lib.sps_hmc_run(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs),
+                                _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0),
+                                _ptr(samples), _ptr(out["post_mean"]), _ptr(out["post_sd"]),
+                                _ptr(out["rhat"]), _ptr(out["accept"]), _ptr(out["step"])))
+        if keep_samples:
+            out["samples"] = samples
+        return out
+
+
+class LogLike(torch.autograd.Function):
+    """log L(params) per galaxy with the library's hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, params, z, obs, sigma, mask, sps_ctx, sfh, path, prec):
+        logl, grad = sps_ctx.loglike_grad(sfh, params.detach().contiguous(), z, obs, sigma, mask,
+                                          path=path, prec=prec, grad=True)
+        ctx.save_for_backward(grad)
+        return logl
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return grad * gout.unsqueeze(0), None, None, None, None, None, None, None, None
+
+
+def loglike(sps_ctx, params, z, obs, sigma, mask, sfh=SPS_SFH_DPL, path=SPS_PATH_APPROX, prec=SPS_F32):
+    return LogLike.apply(params, z, obs, sigma, mask, sps_ctx, sfh, path, prec)

@@ -1,0 +1,196 @@
+// Approximate photometry, log-likelihood, its adjoint, the log posterior on
+// unbounded parameters, and SSP weights.  One galaxy per lane.
+//
+// Approximate photometry (Sec. 3, Eq. photo_integral_approx):
+//   flux_b = K(z) M F_att(lambda_eff,b / (1+z)) sum_j P_Z(j) sum_i P_age(i) Qz[b][j][i],
+//   Qz = (1-f) Q[k] + f Q[k+1]   (linear interpolation of the c_SSP table in z).
+// Galaxies are ordered by z bucket first (counting sort), so the lanes of a
+// wave share the table slices Q[k], Q[k+1]; their rows are read through the
+// scalar cache (wave-uniform addresses) and feed the FMAs as SGPR operands.
+#include "sps_eval.h"
+
+namespace sps {
+
+// ------------------------------------------------------------------ bucket sort
+__global__ void k_zero_int(int *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_bucket_hist(DevConsts k, int n, const float *__restrict__ z, int *__restrict__ hist) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float f;
+    int kk = z_bucket(k, z[i], &f);
+    atomicAdd(&hist[kk < 0 ? k.n_z - 1 : kk], 1);
+}
+
+// exclusive scan of hist[0..nb) into cursor[0..nb); one block of 1024 threads
+__global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restrict__ hist, int *__restrict__ cursor) {
+    __shared__ int s[1024];
+    int t = threadIdx.x;
+    s[t] = (t < nb) ? hist[t] : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = (t >= o) ? s[t - o] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    if (t < nb) cursor[t] = s[t] - ((t < nb) ? hist[t] : 0);
+}
+
+__global__ void k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z, int *__restrict__ cursor,
+                                 int *__restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float f;
+    int kk = z_bucket(k, z[i], &f);
+    int pos = atomicAdd(&cursor[kk < 0 ? k.n_z - 1 : kk], 1);
+    perm[pos] = i;
+}
+
+// ------------------------------------------------------------------ the one-shot kernel
+struct ApproxArgs {
+    int n, sfh, mode;
+    const float *params;      // [10][n] physical (or unbounded x for MODE_LOGPOST_GRAD)
+    const float *z;
+    const float *obs, *sigma; // [n][nb]
+    const uint8_t *mask;
+    const float *bounds;      // [10][4]
+    const float *prior;       // [10][3]
+    const int *perm;
+    const float *q;           // z table
+    float *mag;               // [n][nb]
+    float *val;               // [n]
+    float *grad;              // [10][n]
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
+    __shared__ float lds[LDS_SLOTS * WAVE];
+    const int lane = threadIdx.x;
+    const int idx = blockIdx.x * WAVE + lane;
+    const bool valid = idx < a.n;
+    const int g = a.perm[valid ? idx : a.n - 1];
+    const int n = a.n, nb = k.n_band;
+    LdsCol col{lds + lane};
+
+    float th[NP], x[NP], dth[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) x[p] = a.params[(size_t)p * n + g];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (MODE == MODE_LOGPOST_GRAD) bound_param(a.bounds + 4 * p, x[p], th[p], dth[p]);
+        else th[p] = x[p];
+    }
+    const float zf = a.z[g];
+    float f;
+    int kk = z_bucket(k, zf, &f);
+    if (!valid) kk = -1;
+    const double t_obs = age_universe_gyr(k, (double)zf);
+    const double m0 = mag_offset(k, (double)zf) - 2.5 * (double)th[0];
+    const int kmin = wave_min_i(kk < 0 ? 1 << 30 : kk);
+    const int kmax = wave_max_i(kk);
+    const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : a.mask[g];
+    const float *obs_g = (MODE == MODE_MAGS) ? nullptr : a.obs + (size_t)g * nb;
+    const float *sig_g = (MODE == MODE_MAGS) ? nullptr : a.sigma + (size_t)g * nb;
+    float mags[NB_MAX], gr[NP];
+    double logl;
+    constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
+    approx_eval<EM>(k, a.sfh, (cfloat *)a.q, col, th, zf, kk, f, t_obs, m0, kmin, kmax, obs_g, sig_g, mask,
+                    mags, logl, gr);
+    if (!valid) return;
+    const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
+    if (MODE == MODE_MAGS) {
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b)
+            if (b < nb) a.mag[(size_t)g * nb + b] = mags[b] + bad;
+        return;
+    }
+    if (MODE == MODE_LOGPOST_GRAD) {
+        double lp = logl;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            float dlp;
+            lp += log_prior_skewnorm(a.prior + 3 * p, x[p], dlp);
+            gr[p] = fmaf(gr[p], dth[p], dlp);
+        }
+        a.val[g] = (float)lp + bad;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) a.grad[(size_t)p * n + g] = gr[p] + bad;
+        return;
+    }
+    a.val[g] = (float)logl + bad;
+    if (MODE == MODE_LOGL_GRAD) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) a.grad[(size_t)p * n + g] = gr[p] + bad;
+    }
+}
+
+// ------------------------------------------------------------------ SSP weights output
+__global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, const float *__restrict__ params,
+                                                  const float *__restrict__ z, float *__restrict__ w) {
+    __shared__ float lds[LDS_SLOTS * WAVE];
+    const int lane = threadIdx.x;
+    const int g0 = blockIdx.x * WAVE;
+    const int g = g0 + lane;
+    const bool valid = g < n;
+    const int gg = valid ? g : n - 1;
+    LdsCol col{lds + lane};
+    float th[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) th[p] = params[(size_t)p * n + gg];
+    const double t_obs = age_universe_gyr(k, (double)z[gg]);
+    float pa[NA], pz[NZ];
+    WeightsState ws;
+    forward_weights(k, sfh, th, t_obs, col, pa, pz, ws);
+    const float mass = exp10f(th[0]);
+    if (!valid) return;
+    float *out = w + (size_t)g * NZ * NA;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        const float mj = mass * pz[j];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) out[j * NA + i] = mj * pa[i];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z) {
+    const int nbk = c->k.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
+    int *hist = c->d_hist, *cursor = c->d_hist + 1025;
+    hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
+    hipLaunchKernelGGL(k_bucket_hist, dim3((n + 255) / 256), dim3(256), 0, s, c->k, n, z, hist);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3((n + 255) / 256), dim3(256), 0, s, c->k, n, z, cursor, c->d_perm);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const float *params, const float *z,
+                  const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+                  const float *prior, float *out_mag, float *out_val, float *out_grad) {
+    int rc = launch_bucket_sort(c, s, n, z);
+    if (rc) return rc;
+    ApproxArgs a{n, sfh, mode, params, z, obs, sigma, mask, bounds, prior, c->d_perm, c->d_q,
+                 out_mag, out_val, out_grad};
+    dim3 grid((n + WAVE - 1) / WAVE), block(WAVE);
+    switch (mode) {
+        case MODE_MAGS: hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, 0, s, c->k, a); break;
+        case MODE_LOGL: hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, 0, s, c->k, a); break;
+        case MODE_LOGL_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, 0, s, c->k, a); break;
+        case MODE_LOGPOST_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, 0, s, c->k, a); break;
+        default: return set_error(SPS_E_INVAL, "bad approx mode");
+    }
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+int launch_weights(sps_ctx *c, hipStream_t s, int n, int sfh, const float *params, const float *z, float *w) {
+    hipLaunchKernelGGL(k_weights, dim3((n + WAVE - 1) / WAVE), dim3(WAVE), 0, s, c->k, n, sfh, params, z, w);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+}  // namespace sps

@@ -1,0 +1,591 @@
+// Exact photometry (Sec. 3, Eq. photo_integral_exact) as a dense contraction on MFMA.
+//
+//   SED[g][l]  = sum_s P_SSP[g][s] L[s][l]                   (galaxies x SSPs) . (SSPs x wavelengths)
+//   num[g][b]  = sum_l SED[g][l] F_att(l; g) T_b((1+z_g) l) l q_l
+//   N[g][b]    = sum_l T_b((1+z_g) l) q_l / l                 (photon-counting AB normaliser)
+//   m[g][b]    = -2.5 log10 K(z_g) - 2.5 log10 M_g - 2.5 log10(num / N)
+//
+// The GEMM runs on MFMA (FP64 16x16x4, FP32 16x16x4, or BF16 16x16x32 with the
+// split W = W_hi + W_lo, L = L_hi + L_lo and three products hi.hi + hi.lo + lo.hi
+// accumulated in FP32).  The attenuation, filter and quadrature weights are
+// generated in the epilogue and reduced over each 64-wavelength tile into
+// per-tile partial sums; a small kernel finishes the sums per galaxy.
+// Gradient (FP32 / BF16X): dlogL/dnum -> Rbar[g][l] -> second GEMM
+// Wbar = Rbar . L^T -> dP_age, dP_Z -> the weights adjoint shared with the
+// approximate path; dust derivatives come from extra epilogue partials.
+#include <type_traits>
+
+#include "sps_eval.h"
+
+namespace sps {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64;
+constexpr int NSSP = NZ * NA;
+constexpr int EPI_PHOT = 0, EPI_PHOT_DUST = 1, EPI_STORE = 2;
+
+template <int P> struct Prec;
+template <> struct Prec<SPS_F64> {
+    typedef double T;
+    typedef double E;   // epilogue arithmetic
+    static constexpr int BK = 16, PAD = 1, KSTEP = 4;
+};
+template <> struct Prec<SPS_F32> {
+    typedef float T;
+    typedef float E;
+    static constexpr int BK = 32, PAD = 1, KSTEP = 4;
+};
+template <> struct Prec<SPS_BF16X> {
+    typedef uint16_t T;
+    typedef float E;
+    static constexpr int BK = 64, PAD = 8, KSTEP = 32;
+};
+
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline float e_exp(float x) { return expf(x); }
+__device__ inline double e_exp(double x) { return exp(x); }
+
+struct FiltConst {
+    float fc[NB_MAX], fs[NB_MAX];
+};
+
+constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
+constexpr int S_PAD = round_up(NSSP, 64);   // 1152: multiple of every BK and of BN
+
+struct GemmArgs {
+    int M, N, K_valid, K_pad;
+    const void *A_hi, *A_lo;   // [M][K_pad] row-major
+    int lda;
+    const void *B_hi, *B_lo;   // L as [S][n_wave]
+    int ldb;
+    bool b_nk;                 // false: B[k][n] = L[k][n] (k = SSP);  true: B[k][n] = L[n][k] (k = wavelength)
+    float *C;                  // EPI_STORE: [M][ldc]
+    int ldc;
+    // photometry epilogue
+    const void *params;        // [10][M] (double for F64, else float)
+    const void *z;
+    const double *wave, *trap;
+    int n_band;
+    double fc[NB_MAX], fs[NB_MAX];
+    float *part;               // [n_tiles_n][M][npart]
+    int npart;
+};
+
+// ------------------------------------------------------------------ GEMM + epilogue
+template <int P, int EPI>
+__global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::E E;
+    constexpr int BK = Prec<P>::BK, LDK = BK + Prec<P>::PAD, KSTEP = Prec<P>::KSTEP;
+    constexpr bool SPLIT = (P == SPS_BF16X);
+    constexpr int NS = SPLIT ? 2 : 1;
+    typedef typename std::conditional<P == SPS_F64, d4v, f4v>::type AccT;
+    typedef typename std::conditional<P == SPS_F64, double, float>::type AccE;
+    // A/B tiles, re-used as the SED tile in the epilogue
+    constexpr int TILE_BYTES = NS * (BM + BN) * LDK * (int)sizeof(T);
+    constexpr int SED_BYTES = BM * (BN + 1) * (int)sizeof(AccE);
+    __shared__ __attribute__((aligned(16))) char smem[TILE_BYTES > SED_BYTES ? TILE_BYTES : SED_BYTES];
+    T (*As)[BM][LDK] = reinterpret_cast<T (*)[BM][LDK]>(smem);
+    T (*Bs)[BN][LDK] = reinterpret_cast<T (*)[BN][LDK]>(smem + NS * BM * LDK * sizeof(T));
+
+    const int tile_m = blockIdx.y * BM, tile_n = blockIdx.x * BN;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    // output row of accumulator register r in lane group lk: FP32 16x16x4 and BF16 16x16x32
+    // hold rows 4*lk + r; FP64 16x16x4 holds rows 4*r + lk
+    auto out_row = [](int lk_, int r) { return (P == SPS_F64) ? 4 * r + lk_ : 4 * lk_ + r; };
+
+    AccT acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = AccT{0, 0, 0, 0};
+
+    const T *Ah = (const T *)a.A_hi, *Al = (const T *)a.A_lo;
+    const T *Bh = (const T *)a.B_hi, *Bl = (const T *)a.B_lo;
+    for (int k0 = 0; k0 < a.K_pad; k0 += BK) {
+        // ---- stage A: rows = galaxies (beyond M: zero); columns padded with zeros in memory
+        for (int e = tid; e < BM * BK; e += 256) {
+            const int r = e / BK, c = e % BK, m = tile_m + r;
+            const bool in = m < a.M;
+            const size_t off = (size_t)m * a.lda + k0 + c;
+            As[0][r][c] = in ? Ah[off] : (T)0;
+            if (SPLIT) As[1][r][c] = in ? Al[off] : (T)0;
+        }
+        // ---- stage B into Bs[n][k]
+        if (!a.b_nk) {
+            for (int e = tid; e < BN * BK; e += 256) {
+                const int r = e % BN, c = e / BN, n = tile_n + r, kq = k0 + c;
+                const bool in = n < a.N && kq < a.K_valid;
+                const size_t off = (size_t)kq * a.ldb + n;
+                Bs[0][r][c] = in ? Bh[off] : (T)0;
+                if (SPLIT) Bs[1][r][c] = in ? Bl[off] : (T)0;
+            }
+        } else {
+            for (int e = tid; e < BN * BK; e += 256) {
+                const int r = e / BK, c = e % BK, n = tile_n + r, kq = k0 + c;
+                const bool in = n < a.N && kq < a.K_valid;
+                const size_t off = (size_t)n * a.ldb + kq;
+                Bs[0][r][c] = in ? Bh[off] : (T)0;
+                if (SPLIT) Bs[1][r][c] = in ? Bl[off] : (T)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += KSTEP) {
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti) {
+                const int ra = wm * 32 + ti * 16 + li;
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) {
+                    const int rb = wn * 32 + tj * 16 + li;
+                    if constexpr (P == SPS_F64) {
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[0][ra][kk + lk], Bs[0][rb][kk + lk],
+                                                                           acc[ti][tj], 0, 0, 0);
+                    } else if constexpr (P == SPS_F32) {
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[0][ra][kk + lk], Bs[0][rb][kk + lk],
+                                                                           acc[ti][tj], 0, 0, 0);
+                    } else {
+                        const int ko = kk + 8 * lk;
+                        const b8v ah = *reinterpret_cast<const b8v *>(&As[0][ra][ko]);
+                        const b8v al = *reinterpret_cast<const b8v *>(&As[1][ra][ko]);
+                        const b8v bh = *reinterpret_cast<const b8v *>(&Bs[0][rb][ko]);
+                        const b8v bl = *reinterpret_cast<const b8v *>(&Bs[1][rb][ko]);
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[ti][tj], 0, 0, 0);
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[ti][tj], 0, 0, 0);
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[ti][tj], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = tile_m + wm * 32 + ti * 16 + out_row(lk, r);
+                    const int n = tile_n + wn * 32 + tj * 16 + li;
+                    if (m < a.M && n < a.ldc) a.C[(size_t)m * a.ldc + n] = (float)acc[ti][tj][r];
+                }
+        return;
+    } else {
+        // ---- SED tile -> LDS, then one galaxy row per 4 threads
+        AccE (*sed)[BN + 1] = reinterpret_cast<AccE (*)[BN + 1]>(smem);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sed[wm * 32 + ti * 16 + out_row(lk, r)][wn * 32 + tj * 16 + li] = acc[ti][tj][r];
+        __syncthreads();
+        const int row = tid >> 2, sub = tid & 3, g = tile_m + row;
+        constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;   // num, N [, dnum/dtauV, dnum/ddelta, dnum/dFfloor]
+        E acc_p[NB_MAX][NPB];
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b)
+#pragma unroll
+            for (int q = 0; q < NPB; ++q) acc_p[b][q] = 0;
+        const int gg = g < a.M ? g : a.M - 1;
+        const E *prm = (const E *)a.params;
+        const E tauv = prm[(size_t)7 * a.M + gg], delta = prm[(size_t)8 * a.M + gg], ffl = prm[(size_t)9 * a.M + gg];
+        const double opz = 1.0 + (double)((const E *)a.z)[gg];
+        for (int c = sub * 16; c < sub * 16 + 16; ++c) {
+            const int l = tile_n + c;
+            if (l >= a.N) break;
+            const double lam = a.wave[l], q = a.trap[l];
+            const E lnx = (E)log(lam * (1.0 / 5500.0));
+            const E xd = e_exp(delta * lnx), ee = e_exp(-tauv * xd);
+            const E F = ffl + (1 - ffl) * ee;
+            const E s = (E)sed[row][c];
+            const E wq = (E)(lam * q), qi = (E)(q / lam);
+#pragma unroll
+            for (int b = 0; b < NB_MAX; ++b) {
+                if (b >= a.n_band) break;
+                const double x = (opz * lam - a.fc[b]) / a.fs[b];
+                const E tb = e_exp((E)(-0.5 * x * x));
+                const E stw = s * tb * wq;
+                acc_p[b][0] += stw * F;
+                acc_p[b][1] += tb * qi;
+                if constexpr (EPI == EPI_PHOT_DUST) {
+                    const E dtv = -(1 - ffl) * xd * ee;
+                    acc_p[b][2] += stw * dtv;
+                    acc_p[b][3] += stw * dtv * tauv * lnx;
+                    acc_p[b][4] += stw * (1 - ee);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b)
+#pragma unroll
+            for (int q = 0; q < NPB; ++q) {
+                E v = acc_p[b][q];
+                v += __shfl_xor(v, 1, 64);
+                v += __shfl_xor(v, 2, 64);
+                acc_p[b][q] = v;
+            }
+        if (sub == 0 && g < a.M) {
+            E *out = (E *)a.part + ((size_t)blockIdx.x * a.M + g) * a.npart;
+#pragma unroll
+            for (int b = 0; b < NB_MAX; ++b) {
+                if (b >= a.n_band) break;
+#pragma unroll
+                for (int q = 0; q < NPB; ++q) out[q * a.n_band + b] = acc_p[b][q];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weights rows P_SSP[g][s]
+template <int P>
+__global__ void __launch_bounds__(64) k_exact_weights(DevConsts k, int n, int sfh, const void *params_v,
+                                                      const void *z_v, const double *edges, void *w_hi, void *w_lo) {
+    __shared__ float lds[LDS_SLOTS * 64];
+    const int lane = threadIdx.x, g = blockIdx.x * 64 + lane;
+    const int gg = g < n ? g : n - 1;
+    if constexpr (P == SPS_F64) {
+        // FP64 weights from FP64 bin edges: closed-form log-normal or 8-point Gauss-Legendre DPL
+        // panels, closed-form triweight and normal CDFs
+        const double *prm = (const double *)params_v;
+        const double *age_lo = edges, *age_hi = edges + NA, *lage_lo = edges + 2 * NA, *lage_hi = edges + 3 * NA;
+        const double *met_lo = edges + 4 * NA, *met_hi = edges + 4 * NA + NZ;
+        double th[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + gg];
+        const double t_obs = age_universe_gyr(k, ((const double *)z_v)[gg]);
+        const double sig_z = k.sigma_logz_d;
+        double pz[NZ];
+        for (int j = 0; j < NZ; ++j) {
+            const double xl = (met_lo[j] - th[6]) / sig_z, xh = (met_hi[j] - th[6]) / sig_z;
+            pz[j] = (xl > 0.0) ? Phic_d(xl) - Phic_d(xh) : Phi_d(xh) - Phi_d(xl);
+        }
+        double S = 0.0, Zb = 0.0;
+        const double l_obs = log10(t_obs * 1e9), s3 = 3.0 * k.burst_sig_d;
+        auto mass = [&](int i) {
+            double m, a0, a1;
+            if (sfh == SPS_SFH_LOGNORMAL) {
+                logn_bin_e<false>(age_lo[i], age_hi[i], t_obs, th[1], th[2], m, a0, a1);
+            } else {
+                m = dpl_bin_f64(k, age_lo[i], age_hi[i], t_obs, th[1], th[2], th[3]);
+            }
+            return m;
+        };
+        auto burst = [&](int i) {
+            const double lo = lage_lo[i];
+            if (!(lo < l_obs)) return 0.0;
+            const double hi = fmin(lage_hi[i], l_obs);
+            auto cdf = [](double u) {
+                u = fmin(fmax(u, -1.0), 1.0);
+                const double u2 = u * u;
+                return 0.5 + 1.09375 * u * (1.0 - u2 + u2 * u2 * (0.6 - u2 / 7.0));
+            };
+            return cdf((hi - th[5]) / s3) - cdf((lo - th[5]) / s3);
+        };
+        for (int i = 0; i < NA; ++i) {
+            S += mass(i);
+            Zb += burst(i);
+        }
+        if (g >= n) return;
+        double *w = (double *)w_hi + (size_t)g * S_PAD;
+        for (int i = 0; i < NA; ++i) {
+            const double pa = (1.0 - th[4]) * mass(i) / S + (Zb > 0.0 ? th[4] * burst(i) / Zb : 0.0);
+            for (int j = 0; j < NZ; ++j) w[j * NA + i] = pz[j] * pa;
+        }
+        for (int s = NSSP; s < S_PAD; ++s) w[s] = 0.0;
+    } else {
+        const float *prm = (const float *)params_v;
+        float th[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + gg];
+        const double t_obs = age_universe_gyr(k, (double)((const float *)z_v)[gg]);
+        float pa[NA], pz[NZ];
+        WeightsState ws;
+        forward_weights(k, sfh, th, t_obs, LdsCol{lds + lane}, pa, pz, ws);
+        if (g >= n) return;
+        if constexpr (P == SPS_F32) {
+            float *w = (float *)w_hi + (size_t)g * S_PAD;
+#pragma unroll
+            for (int j = 0; j < NZ; ++j)
+#pragma unroll
+                for (int i = 0; i < NA; ++i) w[j * NA + i] = pz[j] * pa[i];
+            for (int s = NSSP; s < S_PAD; ++s) w[s] = 0.0f;
+        } else {
+            uint16_t *wh = (uint16_t *)w_hi + (size_t)g * S_PAD, *wl = (uint16_t *)w_lo + (size_t)g * S_PAD;
+#pragma unroll
+            for (int j = 0; j < NZ; ++j)
+#pragma unroll
+                for (int i = 0; i < NA; ++i) {
+                    const float v = pz[j] * pa[i];
+                    const uint16_t h = f2bf(v);
+                    wh[j * NA + i] = h;
+                    wl[j * NA + i] = f2bf(v - bf2f(h));
+                }
+            for (int s = NSSP; s < S_PAD; ++s) wh[s] = wl[s] = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ finish: magnitudes / likelihood
+template <int P>
+__global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *params_v, const void *z_v,
+                               const void *part_v, int npart, void *mag_v, const float *obs, const float *sigma,
+                               const uint8_t *mask, float *logl, float *grad, float *cnum) {
+    typedef typename Prec<P>::E E;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int nb = k.n_band;
+    const E *prm = (const E *)params_v;
+    const double zf = (double)((const E *)z_v)[g];
+    const double m0 = mag_offset(k, zf) - 2.5 * (double)prm[g];
+    const E *part = (const E *)part_v;
+    double num[NB_MAX], nrm[NB_MAX], dd[3][NB_MAX];
+    for (int b = 0; b < nb; ++b) {
+        num[b] = nrm[b] = dd[0][b] = dd[1][b] = dd[2][b] = 0.0;
+        for (int t = 0; t < n_tiles; ++t) {
+            const E *pp = part + ((size_t)t * n + g) * npart;
+            num[b] += (double)pp[b];
+            nrm[b] += (double)pp[nb + b];
+            if (grad) {
+                dd[0][b] += (double)pp[2 * nb + b];
+                dd[1][b] += (double)pp[3 * nb + b];
+                dd[2][b] += (double)pp[4 * nb + b];
+            }
+        }
+    }
+    if (mag_v) {
+        for (int b = 0; b < nb; ++b) {
+            const double m = m0 - 2.5 * log10(num[b] / nrm[b]);
+            if (P == SPS_F64) ((double *)mag_v)[(size_t)g * nb + b] = m;
+            else ((float *)mag_v)[(size_t)g * nb + b] = (float)m;
+        }
+        return;
+    }
+    double ll = 0.0, g0 = 0.0, g7 = 0.0, g8 = 0.0, g9 = 0.0;
+    const uint32_t mk = mask[g];
+    for (int b = 0; b < nb; ++b) {
+        double cb = 0.0;
+        if ((mk >> b) & 1u) {
+            const double m = m0 - 2.5 * log10(num[b] / nrm[b]);
+            const double s = sigma[(size_t)g * nb + b], r = (m - (double)obs[(size_t)g * nb + b]) / s;
+            ll += -0.5 * r * r - log(s * 2.5066282746310002);
+            const double gm = -r / s;
+            g0 += -2.5 * gm;
+            cb = gm * (-2.5 / 2.302585092994046) / num[b];   // d logL / d num_b
+            g7 += cb * dd[0][b];
+            g8 += cb * dd[1][b];
+            g9 += cb * dd[2][b];
+        }
+        if (cnum) cnum[(size_t)g * NB_MAX + b] = (float)cb;
+    }
+    logl[g] = (float)ll;
+    if (grad) {
+        grad[(size_t)0 * n + g] = (float)g0;
+        grad[(size_t)7 * n + g] = (float)g7;
+        grad[(size_t)8 * n + g] = (float)g8;
+        grad[(size_t)9 * n + g] = (float)g9;
+    }
+}
+
+// Rbar[g][l] = sum_b (d logL / d num_b) F_att(l) T_b((1+z) l) l q_l  (zero beyond n_wave)
+template <int P>
+__global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
+                             const float *params, const float *z, const double *wave, const double *trap,
+                             const float *cnum, void *r_hi, void *r_lo) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+    if (l >= ld) return;
+    float v = 0.0f;
+    if (l < n_wave) {
+        const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
+        const double lam = wave[l], opz = 1.0 + (double)z[g];
+        const float lnx = (float)log(lam * (1.0 / 5500.0));
+        const float F = ffl + (1.0f - ffl) * expf(-tauv * expf(delta * lnx));
+        float s = 0.0f;
+        for (int b = 0; b < nb; ++b) {
+            const double x = (opz * lam - (double)fl.fc[b]) / (double)fl.fs[b];
+            s += cnum[(size_t)g * NB_MAX + b] * expf((float)(-0.5 * x * x));
+        }
+        v = s * F * (float)(lam * trap[l]);
+    }
+    if (P == SPS_F32) {
+        ((float *)r_hi)[(size_t)g * ld + l] = v;
+    } else {
+        const uint16_t h = f2bf(v);
+        ((uint16_t *)r_hi)[(size_t)g * ld + l] = h;
+        ((uint16_t *)r_lo)[(size_t)g * ld + l] = f2bf(v - bf2f(h));
+    }
+}
+
+// dP_age, dP_Z from Wbar[g][s] = dlogL/dP_SSP, then the weights adjoint -> grad slots 1..6
+__global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sfh, const float *params,
+                                                      const float *z, const float *wbar, float *grad) {
+    __shared__ float lds[LDS_SLOTS * 64];
+    const int lane = threadIdx.x, g = blockIdx.x * 64 + lane;
+    const int gg = g < n ? g : n - 1;
+    LdsCol col{lds + lane};
+    float th[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) th[p] = params[(size_t)p * n + gg];
+    const double t_obs = age_universe_gyr(k, (double)z[gg]);
+    float pa[NA], pz[NZ];
+    WeightsState ws;
+    forward_weights(k, sfh, th, t_obs, col, pa, pz, ws);
+    const float *wb = wbar + (size_t)gg * S_PAD;
+    float pzbar[NZ];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        float s = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) s = fmaf(pa[i], wb[j * NA + i], s);
+        pzbar[j] = s;
+    }
+    for (int i = 0; i < NA; ++i) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) s = fmaf(pz[j], wb[j * NA + i], s);
+        col[i] = s;
+    }
+    float gr[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) gr[p] = 0.0f;
+    adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);
+    if (g >= n) return;
+#pragma unroll
+    for (int p = 1; p <= 6; ++p) grad[(size_t)p * n + g] = gr[p];
+}
+
+// ------------------------------------------------------------------ launcher
+int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
+                 void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
+                 float *grad) {
+    const int nw = c->n_wave, nb = c->n_band;
+    const int n_tiles = (nw + BN - 1) / BN;
+    const bool want_grad = grad != nullptr;
+    const int npart = (want_grad ? 5 : 2) * nb;
+    const int esz = (prec == SPS_F64) ? 8 : 4;
+    const int tsz = (prec == SPS_F64) ? 8 : (prec == SPS_F32 ? 4 : 2);
+    const int nsplit = (prec == SPS_BF16X) ? 2 : 1;
+    const int lw = round_up(nw, 64);   // padded wavelength stride of Rbar
+    // workspace: weights rows | partial sums | dlogL/dnum | Rbar | Wbar
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t o_w = carve((size_t)nsplit * n * S_PAD * tsz);
+    const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
+    size_t o_cn = 0, o_rb = 0, o_wb = 0;
+    if (logl) {
+        o_cn = carve((size_t)n * NB_MAX * 4);
+        if (want_grad) {
+            o_rb = carve((size_t)nsplit * n * lw * tsz);
+            o_wb = carve((size_t)n * S_PAD * 4);
+        }
+    }
+    if (c->work_bytes < off) {
+        SPS_HIP(hipDeviceSynchronize());
+        hipFree(c->d_work);
+        c->d_work = nullptr;
+        c->work_bytes = 0;
+        SPS_HIP(hipMalloc(&c->d_work, off));
+        c->work_bytes = off;
+    }
+    char *W = (char *)c->d_work;
+    void *w_hi = W + o_w, *w_lo = W + o_w + (size_t)n * S_PAD * tsz;
+    const void *L_hi = (prec == SPS_F64) ? (const void *)c->d_lum64
+                      : (prec == SPS_F32) ? (const void *)c->d_lum32 : (const void *)c->d_lum_hi;
+    const void *L_lo = (prec == SPS_BF16X) ? (const void *)c->d_lum_lo : nullptr;
+
+    dim3 gw((n + 63) / 64), bw(64);
+    switch (prec) {
+        case SPS_F64: hipLaunchKernelGGL(k_exact_weights<SPS_F64>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
+        case SPS_F32: hipLaunchKernelGGL(k_exact_weights<SPS_F32>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
+        default: hipLaunchKernelGGL(k_exact_weights<SPS_BF16X>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
+    }
+    GemmArgs a{};
+    a.M = n;
+    a.N = nw;
+    a.K_valid = NSSP;
+    a.K_pad = S_PAD;
+    a.A_hi = w_hi;
+    a.A_lo = w_lo;
+    a.lda = S_PAD;
+    a.B_hi = L_hi;
+    a.B_lo = L_lo;
+    a.ldb = nw;
+    a.b_nk = false;
+    a.params = params;
+    a.z = z;
+    a.wave = c->d_wave;
+    a.trap = c->d_trap;
+    a.n_band = nb;
+    for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.fs[b] = c->h_fs[b]; }
+    a.part = (float *)(W + o_part);
+    a.npart = npart;
+    dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
+    if (prec == SPS_F64) hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
+    else if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_PHOT>), gg, bg, 0, s, a);
+    else if (prec == SPS_F32) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_PHOT_DUST>), gg, bg, 0, s, a);
+    else if (!want_grad) hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_PHOT>), gg, bg, 0, s, a);
+    else hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_PHOT_DUST>), gg, bg, 0, s, a);
+
+    float *cn = logl ? (float *)(W + o_cn) : nullptr;
+    dim3 gf((n + 127) / 128), bf(128);
+    switch (prec) {
+        case SPS_F64:
+            hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+            break;
+        case SPS_F32:
+            hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+            break;
+        default:
+            hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+            break;
+    }
+    if (want_grad) {
+        void *r_hi = W + o_rb, *r_lo = W + o_rb + (size_t)n * lw * tsz;
+        dim3 gr((lw + 255) / 256, n), br(256);
+        FiltConst fl;
+        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)a.fc[b]; fl.fs[b] = (float)a.fs[b]; }
+        if (prec == SPS_F32)
+            hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
+                               (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
+        else
+            hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
+                               (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
+        GemmArgs b = a;
+        b.M = n;
+        b.N = NSSP;
+        b.K_valid = nw;
+        b.K_pad = lw;
+        b.A_hi = r_hi;
+        b.A_lo = r_lo;
+        b.lda = lw;
+        b.b_nk = true;
+        b.C = (float *)(W + o_wb);
+        b.ldc = S_PAD;
+        dim3 g2(S_PAD / BN, (n + BM - 1) / BM);
+        if (prec == SPS_F32) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_STORE>), g2, bg, 0, s, b);
+        else hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_STORE>), g2, bg, 0, s, b);
+        hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 63) / 64), dim3(64), 0, s, c->k, n, sfh, (const float *)params,
+                           (const float *)z, (const float *)b.C, grad);
+    }
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+}  // namespace sps

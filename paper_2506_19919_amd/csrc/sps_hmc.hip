@@ -1,0 +1,318 @@
+// Batched HMC on the unbounded parameters (Sec. 4; App. C, D.2).  One chain per
+// lane; the n_chain chains of a galaxy sit in adjacent lanes and galaxies are in
+// z-bucket order, so a wave shares its z-table slices.  Each launch advances all
+// chains by a block of iterations; chain state lives in HBM between launches.
+//
+// Per iteration: momentum p ~ N(0, I) from Philox4x32-10 (Box-Muller), n_leapfrog
+// leapfrog steps (half kick, drift, half kick; one value+gradient each),
+// H = -log p + |p|^2 / 2 summed in FP64, Metropolis test log u < H0 - H1 in FP64,
+// divergence (non-finite H1 or H1 - H0 > 1000) = reject.  Warm-up: dual averaging
+// of log step size (Hoffman & Gelman 2014: mu = log(10 eps0), gamma = 0.05,
+// t0 = 10, kappa = 0.75); afterwards the averaged step size is kept.
+// Sampling: Welford mean / M2 of the physical parameters per chain (FP64).
+#include "sps_eval.h"
+
+namespace sps {
+
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// uniform on (0, 1): (w + 1/2) / 2^32
+__device__ inline float u01f(uint32_t w) { return fmaf((float)w, 2.3283064365386963e-10f, 1.1641532182693481e-10f); }
+__device__ inline double u01d(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
+
+struct HmcArgs {
+    int n_gal, C, L, NW, NS, it0, it1, sfh;
+    float target, init_step;
+    uint32_t key0, key1;
+    const float *z, *obs, *sigma;
+    const uint8_t *mask;
+    const float *bounds, *prior, *theta0;
+    const int *perm;
+    const float *q;
+    float *samples;
+    // chain state, indexed by slot = rank * C + chain
+    float *x, *gr, *eps, *hbar, *lebar;
+    int *nacc;
+    double *lp, *wmean, *wm2;
+};
+
+struct LaneCtx {
+    int kk, kmin, kmax;
+    float zf, f;
+    double t_obs, m0base;
+    const float *obs_g, *sig_g;
+    uint32_t mask;
+};
+
+__device__ inline double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc, LdsCol col,
+                                const float (&x)[NP], float (&g)[NP]) {
+    float th[NP], dth[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) bound_param(a.bounds + 4 * p, x[p], th[p], dth[p]);
+    const double m0 = lc.m0base - 2.5 * (double)th[0];
+    double logl;
+    float mags[NB_MAX];
+    approx_eval<MODE_LOGL_GRAD>(k, a.sfh, (cfloat *)a.q, col, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+                                lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
+    double lp = logl;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        float dlp;
+        lp += log_prior_skewnorm(a.prior + 3 * p, x[p], dlp);
+        g[p] = fmaf(g[p], dth[p], dlp);
+    }
+    return lp;
+}
+
+__global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
+    __shared__ float lds[LDS_SLOTS * 64];
+    const int lane = threadIdx.x;
+    const int nslot = a.n_gal * a.C;
+    const int slot = blockIdx.x * 64 + lane;
+    const bool valid = slot < nslot;
+    const int sl = valid ? slot : nslot - 1;
+    const int rank = sl / a.C, ch = sl % a.C;
+    const int g = a.perm[rank];
+    const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
+    LdsCol col{lds + lane};
+
+    LaneCtx lc;
+    lc.zf = a.z[g];
+    lc.kk = z_bucket(k, lc.zf, &lc.f);
+    if (!valid) lc.kk = -1;
+    lc.t_obs = age_universe_gyr(k, (double)lc.zf);
+    lc.m0base = mag_offset(k, (double)lc.zf);
+    lc.kmin = wave_min_i(lc.kk < 0 ? 1 << 30 : lc.kk);
+    lc.kmax = wave_max_i(lc.kk);
+    lc.obs_g = a.obs + (size_t)g * k.n_band;
+    lc.sig_g = a.sigma + (size_t)g * k.n_band;
+    lc.mask = a.mask[g];
+
+    float x[NP], gr[NP], eps, hbar, lebar;
+    double lp;
+    int nacc;
+    double wmean[NP], wm2[NP];
+    if (a.it0 == 0) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
+        lp = logpost(k, a, lc, col, x, gr);
+        eps = a.init_step;
+        hbar = 0.0f;
+        lebar = 0.0f;
+        nacc = 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) wmean[p] = wm2[p] = 0.0;
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            x[p] = a.x[(size_t)p * nslot + sl];
+            gr[p] = a.gr[(size_t)p * nslot + sl];
+            wmean[p] = a.wmean[(size_t)p * nslot + sl];
+            wm2[p] = a.wm2[(size_t)p * nslot + sl];
+        }
+        lp = a.lp[sl];
+        eps = a.eps[sl];
+        hbar = a.hbar[sl];
+        lebar = a.lebar[sl];
+        nacc = a.nacc[sl];
+    }
+    const float mu = logf(10.0f * a.init_step);
+
+    for (int it = a.it0; it < a.it1; ++it) {
+        uint32_t w[12];
+#pragma unroll
+        for (int blk = 0; blk < 3; ++blk) {
+            uint32_t c4[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
+            philox4x32_10(c4, a.key0, a.key1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) w[4 * blk + t] = c4[t];
+        }
+        float p[NP];
+#pragma unroll
+        for (int t = 0; t < NP / 2; ++t) {
+            const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
+            float sn, cs;
+            sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
+            p[2 * t] = r * cs;
+            p[2 * t + 1] = r * sn;
+        }
+        double H0 = -lp;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) H0 += 0.5 * (double)p[t] * (double)p[t];
+        float xn[NP], gn[NP];
+        double lpn = lp;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) { xn[t] = x[t]; gn[t] = gr[t]; }
+        for (int l = 0; l < a.L; ++l) {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                p[t] = fmaf(0.5f * eps, gn[t], p[t]);
+                xn[t] = fmaf(eps, p[t], xn[t]);
+            }
+            lpn = logpost(k, a, lc, col, xn, gn);
+#pragma unroll
+            for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], p[t]);
+        }
+        double H1 = -lpn;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)p[t] * (double)p[t];
+        const double dH = H1 - H0;
+        const bool divergent = !isfinite(H1) || dH > 1000.0;
+        const float alpha = divergent ? 0.0f : (float)fmin(1.0, exp(-dH));
+        const bool acc = !divergent && log(u01d(w[10])) < -dH;
+        if (acc) {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) { x[t] = xn[t]; gr[t] = gn[t]; }
+            lp = lpn;
+        }
+        if (it < a.NW) {
+            const float m = (float)(it + 1), eta = 1.0f / (m + 10.0f);
+            hbar = (1.0f - eta) * hbar + eta * (a.target - alpha);
+            const float leps = mu - sqrtf(m) / 0.05f * hbar, wk = powf(m, -0.75f);
+            lebar = wk * leps + (1.0f - wk) * lebar;
+            eps = expf(it == a.NW - 1 ? lebar : leps);
+        } else {
+            nacc += acc ? 1 : 0;
+            const double nrec = (double)(it - a.NW + 1);
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                float th, dth;
+                bound_param(a.bounds + 4 * t, x[t], th, dth);
+                const double d = (double)th - wmean[t];
+                wmean[t] += d / nrec;
+                wm2[t] += d * ((double)th - wmean[t]);
+                if (a.samples && valid)
+                    a.samples[(((size_t)(it - a.NW) * a.C + ch) * NP + t) * a.n_gal + g] = th;
+            }
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        a.x[(size_t)p * nslot + sl] = x[p];
+        a.gr[(size_t)p * nslot + sl] = gr[p];
+        a.wmean[(size_t)p * nslot + sl] = wmean[p];
+        a.wm2[(size_t)p * nslot + sl] = wm2[p];
+    }
+    a.lp[sl] = lp;
+    a.eps[sl] = eps;
+    a.hbar[sl] = hbar;
+    a.lebar[sl] = lebar;
+    a.nacc[sl] = nacc;
+}
+
+// pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy
+__global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ perm,
+                              const double *__restrict__ wmean, const double *__restrict__ wm2,
+                              const int *__restrict__ nacc, const float *__restrict__ eps, float *post_mean,
+                              float *post_sd, float *rhat, float *accept, float *step) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_gal) return;
+    const int g = perm[r], nslot = n_gal * C;
+    int acc = 0;
+    for (int c = 0; c < C; ++c) {
+        acc += nacc[r * C + c];
+        step[(size_t)c * n_gal + g] = eps[r * C + c];
+    }
+    accept[g] = (float)acc / ((float)C * NS);
+    for (int p = 0; p < NP; ++p) {
+        double gm = 0.0, W = 0.0, B = 0.0, ss = 0.0;
+        for (int c = 0; c < C; ++c) {
+            const size_t o = (size_t)p * nslot + r * C + c;
+            gm += wmean[o];
+            W += wm2[o] / (NS - 1);
+        }
+        gm /= C;
+        W /= C;
+        for (int c = 0; c < C; ++c) {
+            const size_t o = (size_t)p * nslot + r * C + c;
+            const double d = wmean[o] - gm;
+            B += d * d;
+            ss += wm2[o] + NS * d * d;
+        }
+        const double Bn = (C > 1) ? B / (C - 1) : 0.0;
+        const double V = (NS - 1.0) / NS * W + Bn;
+        post_mean[(size_t)p * n_gal + g] = (float)gm;
+        post_sd[(size_t)p * n_gal + g] = (float)sqrt(ss / ((double)C * NS - 1.0));
+        rhat[(size_t)p * n_gal + g] = (C > 1) ? (float)sqrt(V / W) : __int_as_float(0x7fc00000);
+    }
+}
+
+int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
+               const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
+               const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
+               float *step) {
+    const int C = cfg->n_chain, nslot = n_gal * C;
+    // chain state: 10 x + 10 grad + eps, hbar, lebar (float), nacc (int); lp + 20 Welford (double)
+    const size_t fbytes = (size_t)nslot * (2 * NP + 3) * sizeof(float) + (size_t)nslot * sizeof(int);
+    const size_t dofs = (fbytes + 255) & ~(size_t)255;
+    const size_t need = dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double);
+    if (c->work_bytes < need) {
+        SPS_HIP(hipDeviceSynchronize());
+        hipFree(c->d_work);
+        c->d_work = nullptr;
+        c->work_bytes = 0;
+        SPS_HIP(hipMalloc(&c->d_work, need));
+        c->work_bytes = need;
+    }
+    int rc = launch_bucket_sort(c, s, n_gal, z);
+    if (rc) return rc;
+    float *fp = (float *)c->d_work;
+    HmcArgs a{};
+    a.n_gal = n_gal;
+    a.C = C;
+    a.L = cfg->n_leapfrog;
+    a.NW = cfg->n_warmup;
+    a.NS = cfg->n_sample;
+    a.sfh = sfh;
+    a.target = cfg->target_accept;
+    a.init_step = cfg->init_step;
+    a.key0 = (uint32_t)(cfg->seed & 0xffffffffull);
+    a.key1 = (uint32_t)(cfg->seed >> 32);
+    a.z = z;
+    a.obs = obs;
+    a.sigma = sigma;
+    a.mask = mask;
+    a.bounds = bounds;
+    a.prior = prior;
+    a.theta0 = theta0;
+    a.perm = c->d_perm;
+    a.q = c->d_q;
+    a.samples = samples;
+    a.x = fp;
+    a.gr = fp + (size_t)NP * nslot;
+    a.eps = fp + (size_t)2 * NP * nslot;
+    a.hbar = a.eps + nslot;
+    a.lebar = a.hbar + nslot;
+    a.nacc = (int *)(a.lebar + nslot);
+    a.lp = (double *)((char *)c->d_work + dofs);
+    a.wmean = a.lp + nslot;
+    a.wm2 = a.wmean + (size_t)NP * nslot;
+    const int nit = cfg->n_warmup + cfg->n_sample;
+    const int blk_it = 25;
+    dim3 grid((nslot + 63) / 64), block(64);
+    for (int it0 = 0; it0 < nit; it0 += blk_it) {
+        a.it0 = it0;
+        a.it1 = it0 + blk_it < nit ? it0 + blk_it : nit;
+        hipLaunchKernelGGL(k_hmc, grid, block, 0, s, c->k, a);
+    }
+    hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
+                       c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, post_mean, post_sd, rhat, accept, step);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+}  // namespace sps

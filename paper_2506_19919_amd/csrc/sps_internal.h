@@ -1,0 +1,93 @@
+// Internal declarations of the SPS HIP library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sps.h"
+
+namespace sps {
+
+// Compile-time SSP grid tile: per-lane age weights live in registers.
+constexpr int NA = 94;            // ages
+constexpr int NZ = 12;            // metallicities
+constexpr int NB_MAX = SPS_MAX_BAND;
+constexpr int NP = SPS_NPARAM;
+constexpr int NGL_DL = 12;        // half of the 24-point Gauss-Legendre rule for D_L
+
+// Kernel-facing constants, passed by value (kernarg segment).
+struct DevConsts {
+    int n_band, n_wave;
+    int n_z;                      // z table nodes (0 = none)
+    float z_lo, dz;               // z table: node k at z_lo + k dz
+    float sigma_logz, burst_sig;  // dex; burst sigma = (log T_max - log T_peak)/3
+    double sigma_logz_d, burst_sig_d;
+    float age_lo[NA], age_hi[NA]; // stellar-age limits of the bins [Gyr]; last hi = +inf
+    float lage_lo[NA], lage_hi[NA];  // log10(age/yr) limits; -inf / +inf at the ends
+    float met_lo[NZ], met_hi[NZ];    // log10 Z limits; -inf / +inf at the ends
+    float lam_eff[NB_MAX];        // observed-frame effective wavelength of each band [A]
+    float fc[NB_MAX], fs[NB_MAX]; // filter centre and sigma [A]
+    double h0_gyr, om;            // H0 in 1/Gyr, matter density
+    double dh_cm;                 // Hubble distance c/H0 [cm]
+    double kfac;                  // Lsun / (4 pi c[A/s] 3631 Jy)  (AB normalisation)
+    double gl_x[NGL_DL], gl_w[NGL_DL];  // positive Gauss-Legendre nodes/weights (24-point)
+    double gl8_x[4], gl8_w[4];          // positive nodes/weights of the 8-point rule
+};
+
+}  // namespace sps
+
+struct sps_ctx {
+    int device = 0;
+    int n_met = 0, n_age = 0, n_wave = 0, n_band = 0;
+    unsigned prec_mask = 0;
+    sps::DevConsts k{};
+    std::vector<double> h_wave, h_trap;
+    double h_fc[SPS_MAX_BAND] = {0}, h_fs[SPS_MAX_BAND] = {0};   // filter constants (FP64)
+    // device tables
+    double *d_lum64 = nullptr;     // [S][n_wave]
+    float *d_lum32 = nullptr;      // [S][n_wave]
+    uint16_t *d_lum_hi = nullptr;  // BF16 bits, [S][n_wave]
+    uint16_t *d_lum_lo = nullptr;
+    double *d_wave = nullptr, *d_trap = nullptr;
+    double *d_edges = nullptr;     // FP64 bin edges: age_lo, age_hi [Gyr], lage_lo, lage_hi [NA each], met_lo, met_hi [NZ]
+    float *d_q = nullptr;          // [n_z][n_band][n_met][n_age]
+    // per-galaxy workspace
+    int max_gal = 0;
+    int *d_perm = nullptr;         // galaxies ordered by z bucket
+    int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
+    void *d_work = nullptr;        // exact-path weights / partial fluxes
+    size_t work_bytes = 0;
+};
+
+namespace sps {
+
+int set_error(int code, const std::string &msg);
+int hip_check(hipError_t e, const char *what);
+#define SPS_HIP(call)                                           \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return ::sps::hip_check(e_, #call); \
+    } while (0)
+
+// launchers (defined in the kernel sources)
+int launch_ztable(sps_ctx *c, hipStream_t s);
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z);
+int launch_weights(sps_ctx *c, hipStream_t s, int n_gal, int sfh, const float *params, const float *z,
+                   float *w);
+int launch_approx(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int mode, const float *params,
+                  const float *z, const float *obs, const float *sigma, const uint8_t *mask,
+                  const float *bounds, const float *prior, float *out_mag, float *out_val, float *out_grad);
+int launch_exact(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int prec, const void *params,
+                 const void *z, void *mag_out, const float *obs, const float *sigma,
+                 const uint8_t *mask, float *logl, float *grad);
+int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
+               const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+               const float *prior, const float *theta0, float *samples, float *post_mean,
+               float *post_sd, float *rhat, float *accept, float *step);
+
+// modes of the approximate-path kernel
+enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3 };
+
+}  // namespace sps

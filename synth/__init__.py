@@ -152,6 +152,22 @@ def band_masks(n: int, n_band: int, seed: int, lo: int = 3, hi: int = 6):
     return masks
 
 
+# Skew-normal prior (xi, omega, s) on each unbounded parameter: the s = 0 case (a
+# Gaussian of width 1.5 in the unbounded coordinate) for every parameter.
+PRIOR = np.array([[0.0, 1.5, 0.0]] * N_PARAM)
+
+
+def bounds_k_x0() -> np.ndarray:
+    """Bounding-function hyper-parameters [10][4] = (y_lo, y_hi, k = 1, x0 = 0)."""
+    return np.column_stack([BOUNDS, np.ones(N_PARAM), np.zeros(N_PARAM)])
+
+
+def prior_draws(n_chain: int, n: int, seed: int) -> np.ndarray:
+    """Chain starting points drawn from PRIOR: [n_chain][10][n] unbounded values."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(PRIOR[:, 0][None, :, None], PRIOR[:, 1][None, :, None], (n_chain, N_PARAM, n))
+
+
 def soa32(theta: np.ndarray) -> np.ndarray:
     """[n][10] float64 -> [10][n] float32 (the device layout)."""
     return np.ascontiguousarray(theta.T.astype(np.float32))
