@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--hmc-gal", type=int, default=16_384)
     ap.add_argument("--hmc-warmup", type=int, default=200)
     ap.add_argument("--hmc-sample", type=int, default=1000)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="also run 3 plain 1 GiB device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by "
@@ -197,6 +199,14 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} steps)")
+    if args.traffic_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] traffic probe: 3 copies of 1 GiB done")
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()

@@ -220,6 +220,22 @@ class Oracle:
         assert rc in (0, 2)
         return (ll, g) if grad else ll
 
+    def mags_jacobian(self, sfh, theta, z, path=0):
+        """Magnitudes [g][b] and their Jacobian [g][b][10] w.r.t. the physical parameters."""
+        th, zz = _f64(theta), _f64(z)
+        n = len(zz)
+        mags = np.zeros((n, self.n_band))
+        jac = np.zeros((n, self.n_band, N_PARAM))
+        if path == 0:
+            n_z, lo, hi, qp = self._zt()
+        else:
+            n_z, lo, hi, qp = 0, C.c_double(0), C.c_double(0), None
+        rc = self.L.orc_mags_jacobian(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo),
+                                      C.byref(self.model), path, n_z, lo, hi, qp, sfh, n, _p(th), _p(zz),
+                                      _p(mags), _p(jac))
+        assert rc in (0, 2)
+        return mags, jac
+
     # --- bounding / prior
     @staticmethod
     def bound(bnd4, x):
@@ -274,7 +290,7 @@ class Oracle:
     # --- HMC
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
-                keep_samples=False, keep_trace=False, gauss_prec=None):
+                keep_samples=False, keep_trace=False, gauss_prec=None, gal_id=None, n_gal_total=0):
         th0 = _f64(theta0)
         n_gal = th0.shape[1]
         assert th0.shape == (n_chain, n_gal, N_PARAM)
@@ -294,10 +310,11 @@ class Oracle:
         else:
             n_z, lo, hi, qp = 0, C.c_double(0), C.c_double(0), None
             args = (None,) * 6
+        gid = np.ascontiguousarray(gal_id, dtype=np.uint32) if gal_id is not None else None
         rc = self.L.orc_hmc_run(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo),
                                 C.byref(self.model), n_z, lo, hi, qp, sfh, C.byref(cfg), n_gal,
                                 *args, _p(th0), _p(gp), _p(pm), _p(ps), _p(rh), _p(acc), _p(step),
-                                _p(smp), _p(tr))
+                                _p(smp), _p(tr), int(n_gal_total), _p(gid))
         assert rc == 0, rc
         out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step)
         if keep_samples:

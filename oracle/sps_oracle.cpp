@@ -637,6 +637,30 @@ int orc_loglike_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c,
     return bad ? 2 : 0;
 }
 
+int orc_mags_jacobian(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m, int path,
+                      int n_z, double z_lo, double z_hi, const double *q, int sfh, int n_gal, const double *theta,
+                      const double *z, double *mags, double *jac) {
+    if (!check_common(s, f) || n_gal < 0 || (path == 0 && !q) || (n_gal && (!theta || !z || !mags || !jac)))
+        return 1;
+    Model X(s, f, c, m);
+    const int nb = f->n_band;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int g = 0; g < n_gal; ++g) {
+        Dual th[NP], mg[8];
+        for (int p = 0; p < NP; ++p) { th[p] = Dual(theta[(size_t)g * NP + p]); th[p].d[p] = 1.0; }
+        if (path == 0)
+            bad += !mags_approx<Dual>(X.G, X.f, X.c, X.m, n_z, z_lo, z_hi, q, sfh, th, z[g], mg);
+        else
+            mags_exact<Dual>(X.G, X.f, X.c, X.m, sfh, th, z[g], mg);
+        for (int b = 0; b < nb; ++b) {
+            mags[(size_t)g * nb + b] = mg[b].v;
+            for (int p = 0; p < NP; ++p) jac[((size_t)g * nb + b) * NP + p] = mg[b].d[p];
+        }
+    }
+    return bad ? 2 : 0;
+}
+
 double orc_bound(const double *bnd, double x) { return bound<double>(bnd, x); }
 double orc_unbound(const double *bnd, double th) {
     // inverse of the sigmoid: x0 - ln((y_hi - y_lo)/(theta - y_lo) - 1) / k
@@ -714,7 +738,7 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
                 const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                double *samples, double *trace_logp) {
+                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id) {
     if (!cfg || cfg->n_chain < 1 || cfg->n_leapfrog < 1 || cfg->n_warmup < 0 || cfg->n_sample < 2) return 1;
     if (!theta0 || n_gal < 0) return 1;
     if (!gauss_prec && (!check_common(s, f) || !q || !z || !obs || !sigma || !mask || !bounds || !prior))
@@ -733,7 +757,9 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
 #pragma omp parallel for schedule(dynamic, 1)
     for (long cg = 0; cg < (long)C * n_gal; ++cg) {
         const int ch = (int)(cg / n_gal), g = (int)(cg % n_gal);
-        const uint32_t chain_id = (uint32_t)cg;  // = ch * n_gal + g
+        // Philox chain id = chain * (batch size) + galaxy index in the batch; a subset of a
+        // larger batch passes the batch size and its galaxies' indices to reproduce its streams
+        const uint32_t chain_id = gal_id ? (uint32_t)ch * (uint32_t)n_gal_total + gal_id[g] : (uint32_t)cg;
         auto eval = [&](const double *x, double *lp, double *gr) {
             if (gauss_prec) {
                 double v = 0.0;

@@ -86,6 +86,11 @@ int orc_loglike_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c,
                      const double *obs, const double *sigma, const uint8_t *mask,
                      double *logl, double *grad);
 
+/* magnitudes and their Jacobian d m_b / d theta_p: mags[g][b], jac[g][b][10] (path 0 approx, 1 exact) */
+int orc_mags_jacobian(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m, int path,
+                      int n_z, double z_lo, double z_hi, const double *q, int sfh, int n_gal, const double *theta,
+                      const double *z, double *mags, double *jac);
+
 /* ---- bounding function and skew-normal prior ---- */
 /* bounds[p][4] = (y_lo, y_hi, k, x0); prior[p][3] = (xi, omega, s) on the unbounded value */
 double orc_bound(const double *bnd, double x_unbounded);
@@ -123,14 +128,16 @@ typedef struct {
  *   trace_logp [n_warmup+n_sample][c][g] log posterior after each iteration (may be NULL).
  * gauss_prec (may be NULL): if set, the target is the zero-mean Gaussian with this
  * 10x10 precision matrix instead of the SPS posterior (sampler validation mode;
- * then the physical map is the identity). */
+ * then the physical map is the identity).
+ * gal_id (may be NULL): global galaxy indices when these galaxies are a subset of a batch of
+ * n_gal_total galaxies; the Philox chain id is then chain * n_gal_total + gal_id[g]. */
 int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                 int n_z, double z_lo, double z_hi, const double *q, int sfh,
                 const orc_hmc_cfg *cfg, int n_gal, const double *z, const double *obs,
                 const double *sigma, const uint8_t *mask, const double *bounds, const double *prior,
                 const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                double *samples, double *trace_logp);
+                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id);
 
 /* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
 double orc_rhat(int n_chain, int n, const double *x);

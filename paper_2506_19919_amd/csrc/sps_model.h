@@ -1,7 +1,8 @@
 // Device-side forward model, one galaxy (or chain) per lane.
 //
 // SFH bin masses (App. A.1, Eqs. totalMstarFormed, SFRsmooth, smoothPsfh):
-//   double power law: bin integrals by Gauss-Legendre-4 panels in X = ln(t/tau),
+//   double power law: bin integrals by Gauss-Legendre-4 panels in X = ln(t/tau)
+//   (one 2-point panel for bins narrower than 1/8 of the panel width),
 //   where the integrand tau / (e^{(alpha-1)X} + e^{-(beta+1)X}) is analytic with
 //   poles at distance pi/(alpha+beta) from the real axis.  Panel width
 //   min(0.4, 2/(alpha+beta), 1.2/(beta+1)); the oldest bin reaches down to
@@ -71,6 +72,7 @@ __device__ inline float tri_dcdf(float u) {
 // ------------------------------------------------------------------ double power law
 struct Dpl {
     float tau, am1, bp1, ltau, inv_w;
+    float s_l2, b_l2;   // (alpha + beta) log2(e), (beta + 1) log2(e)
 };
 __device__ inline Dpl make_dpl(float tau, float al, float be) {
     Dpl d;
@@ -80,7 +82,33 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
     d.ltau = logf(tau);
     float w = fminf(0.4f, fminf(2.0f / (al + be), 1.2f / d.bp1));
     d.inv_w = 1.0f / w;
+    d.s_l2 = (al + be) * 1.4426950408889634f;
+    d.b_l2 = d.bp1 * 1.4426950408889634f;
     return d;
+}
+
+// 2-point Gauss-Legendre node 1/sqrt(3) (weights 1): bins narrower than 1/8 of the panel
+// width, where the 4-point panel rule would be wasted (error < 1e-7 relative there)
+constexpr float GL2X = 0.57735026918962576f;
+
+// integrand tau / (e^{(alpha-1)X} + e^{-(beta+1)X}) at X, accumulated with weight wg,
+// plus its derivatives w.r.t. (tau, alpha, beta) if DERIV.  Written without overflow:
+//   h = tau fB e^{(beta+1)X},  fB = 1 / (1 + e^{(alpha+beta)X}),  fA = e^{(alpha+beta)X} fB,
+//   dh/dalpha = -h X fA,  dh/dbeta = h X fB,  dh/dtau = (h/tau) (1 + (alpha-1) fA - (beta+1) fB).
+template <bool DERIV>
+__device__ inline void dpl_node(const Dpl &p, float X, float wg, float &s, float &st, float &sa, float &sb) {
+    const float ed = __builtin_amdgcn_exp2f(p.s_l2 * X);
+    const float eb = __builtin_amdgcn_exp2f(p.b_l2 * X);
+    const float fB = __builtin_amdgcn_rcpf(1.0f + ed);
+    const float h = p.tau * fB * eb;
+    s = fmaf(wg, h, s);
+    if (DERIV) {
+        const float fA = (ed < 3.0e38f) ? ed * fB : 1.0f;
+        const float hw = wg * h;
+        st = fmaf(hw, 1.0f + p.am1 * fA - p.bp1 * fB, st);   // times 1/tau after the sum
+        sa = fmaf(-hw * X, fA, sa);
+        sb = fmaf(hw * X, fB, sb);
+    }
 }
 
 // Mass formed in age bin i (rate amplitude 1) and, if DERIV, its derivatives
@@ -101,37 +129,33 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
         // oldest bin: panels down to the cut, analytic leading term below it
         const float xlo = fminf(xhi, 0.0f) - 30.0f / p.bp1;
         span = xhi - xlo;
-        tail = p.tau * expf(p.bp1 * xlo) / p.bp1;
+        tail = p.tau * __builtin_amdgcn_exp2f(p.b_l2 * xlo) / p.bp1;
         if (DERIV) {
             tail_t = -(p.bp1 - 1.0f) * tail / p.tau;
             tail_b = tail * (xlo - 1.0f / p.bp1);
         }
     }
-    int n = (int)ceilf(span * p.inv_w);
-    n = min(max(n, 1), 64);
-    const float hw = 0.5f * span / (float)n;
-    const float xlo = xhi - span;
-    float s = 0.0f, st = 0.0f, sa = 0.0f, sb = 0.0f;
-    for (int q = 0; q < n; ++q) {
-        const float c = xlo + (float)(2 * q + 1) * hw;
+    float s = 0.0f, st = 0.0f, sa = 0.0f, sb = 0.0f, hw;
+    const float npan = span * p.inv_w;
+    if (npan <= 0.125f) {
+        hw = 0.5f * span;
+        const float c = xhi - hw, d = hw * GL2X;
+        dpl_node<DERIV>(p, c - d, 1.0f, s, st, sa, sb);
+        dpl_node<DERIV>(p, c + d, 1.0f, s, st, sa, sb);
+    } else {
+        int n = (int)ceilf(npan);
+        n = min(max(n, 1), 64);
+        hw = 0.5f * span / (float)n;
+        const float xlo = xhi - span;
+        for (int q = 0; q < n; ++q) {
+            const float c = xlo + (float)(2 * q + 1) * hw;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const float X = fmaf(hw, GL4X[g], c);
-            const float A = expf(p.am1 * X), B = expf(-p.bp1 * X);
-            const float inv = 1.0f / (A + B);
-            const float h = p.tau * inv;
-            s = fmaf(GL4W[g], h, s);
-            if (DERIV) {
-                st = fmaf(GL4W[g], inv + (p.am1 * A - p.bp1 * B) * inv * inv, st);
-                const float hx = h * X * inv;
-                sa = fmaf(GL4W[g], -hx * A, sa);
-                sb = fmaf(GL4W[g], hx * B, sb);
-            }
+            for (int g = 0; g < 4; ++g) dpl_node<DERIV>(p, fmaf(hw, GL4X[g], c), GL4W[g], s, st, sa, sb);
         }
     }
     m = fmaf(s, hw, tail);
     if (DERIV) {
-        d_tau = fmaf(st, hw, tail_t);
+        d_tau = fmaf(st * hw, 1.0f / p.tau, tail_t);
         d_al = sa * hw;
         d_be = fmaf(sb, hw, tail_b);
     }

@@ -44,3 +44,22 @@ def grad_close(g, ref, rtol=1e-3, floor=1e-3):
     """|g - ref| <= rtol * max(|ref|, floor * max_p |ref_p|) per galaxy (rows = galaxies)."""
     scale = np.maximum(np.abs(ref), floor * np.abs(ref).max(axis=1, keepdims=True))
     return np.abs(g - ref) <= rtol * scale
+
+
+def grad_tol(orc, sfh, th, z, sig, masks, m_gpu, path=0, rtol=1e-3):
+    """Per-component gradient tolerance: rtol relative, plus the first-order propagation of
+    the measured magnitude difference through the oracle's Jacobian.
+
+    d logL / d theta_p = -sum_b mask_b (m_b - d_b) / s_b^2  dm_b/dtheta_p, so a magnitude error
+    dm_b moves the gradient by sum_b mask_b |dm_b| / s_b^2 |J_bp|; near the posterior mode the
+    band sum cancels and this term, not rtol, bounds the agreement of an FP32 path.  The 2e-6
+    added to |dm_b| is the rounding of an FP32 magnitude near 25 mag."""
+    m_ref, jac = orc.mags_jacobian(sfh, th, z, path=path)
+    bits = (np.asarray(masks)[:, None] >> np.arange(m_ref.shape[1])) & 1
+    dm = (np.abs(np.asarray(m_gpu, np.float64) - m_ref) + 2e-6) * bits / np.asarray(sig) ** 2
+    prop = np.einsum("gb,gbp->gp", dm, np.abs(jac))
+    return prop, m_ref
+
+
+def grad_ok(g, ref, prop, rtol=1e-3):
+    return np.abs(g - ref) <= rtol * np.abs(ref) + prop + 1e-6 * np.abs(ref).max(axis=1, keepdims=True)

@@ -100,7 +100,8 @@ def test_full_size_batch_short_run(ctx, orc):
     out = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
     s = out["samples"].cpu().numpy()
     assert np.isfinite(s).all()
-    ref = orc.hmc_run(1, z[pick], obs[pick], sig[pick], masks[pick], bnd, pri, x0[:, pick], keep_samples=True, **kw)
+    ref = orc.hmc_run(1, z[pick], obs[pick], sig[pick], masks[pick], bnd, pri, x0[:, pick], keep_samples=True,
+                      gal_id=pick, n_gal_total=n, **kw)
     s_pick = s[:, :, :, pick].transpose(0, 1, 3, 2)
     close = np.all(np.abs(s_pick - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0), axis=-1)
     assert close.mean() >= 0.9

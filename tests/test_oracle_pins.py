@@ -412,6 +412,21 @@ def test_dual_gradient_matches_central_differences(orc_small, path):
         np.testing.assert_allclose(g[:, p], fd, rtol=2e-5, atol=1e-7 * np.abs(g).max())
 
 
+@pytest.mark.parametrize("path", [0, 1])
+def test_mags_jacobian_matches_central_differences(orc_small, path):
+    th, z = synth.galaxies_dpl(2, 43)
+    mags, jac = orc_small.mags_jacobian(1, th, z, path=path)
+    ref = orc_small.phot_approx(1, th, z) if path == 0 else orc_small.phot_exact(1, th, z)
+    np.testing.assert_allclose(mags, ref, atol=1e-12)
+    h = 1e-4
+    for p in range(10):
+        t1, t2, t3, t4 = (th.copy() for _ in range(4))
+        t1[:, p] += 2 * h; t2[:, p] += h; t3[:, p] -= h; t4[:, p] -= 2 * h
+        f = (lambda t: orc_small.phot_approx(1, t, z)) if path == 0 else (lambda t: orc_small.phot_exact(1, t, z))
+        fd = (-f(t1) + 8 * f(t2) - 8 * f(t3) + f(t4)) / (12 * h)
+        np.testing.assert_allclose(jac[:, :, p], fd, rtol=1e-5, atol=1e-7)
+
+
 # --------------------------------------------------------------------------
 # bounding function and prior
 # --------------------------------------------------------------------------
