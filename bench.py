@@ -31,8 +31,43 @@ PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s: non-packed FP
 CONTRACTION_FLOP_PER_EVAL = 2 * 27_072
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_approx_logl_grad_1M_traffic.md")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources and headers the kernels are built from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2506_19919_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or None when the
+    summary is missing or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("traffic_") and ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("traffic_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_fetch_bytes_per_launch"]) + float(vals["traffic_write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(ssp, filt, th, z, noise, sig, budget_s=12.0):
@@ -104,8 +139,9 @@ def bench_exact(dev, n=4096, steps=5, warmup=2):
     return res
 
 
-def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10):
-    """Batched HMC: n galaxies x C chains, L leapfrog steps, warm-up + sampling; posteriors/min."""
+def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False):
+    """Batched HMC: n galaxies x C chains, L leapfrog steps, warm-up + sampling; posteriors/min.
+    adapt_metric: identity mass matrix (False) or the windowed diagonal adaptation (True)."""
     import torch
 
     import paper_2506_19919_amd as sps
@@ -125,7 +161,7 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10):
     bounds = torch.as_tensor(synth.bounds_k_x0(), dtype=torch.float32, device=dev)
     prior = torch.as_tensor(synth.PRIOR, dtype=torch.float32, device=dev)
     theta0 = torch.as_tensor(synth.prior_draws(C, n, 304), dtype=torch.float32, device=dev).contiguous()
-    kw = dict(n_chain=C, n_leapfrog=L, n_warmup=n_warm, n_sample=n_samp, seed=404)
+    kw = dict(n_chain=C, n_leapfrog=L, n_warmup=n_warm, n_sample=n_samp, seed=404, adapt_metric=adapt_metric)
     # short untimed run: first-call setup (workspace) and code paths warm
     ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, n_chain=C, n_leapfrog=L,
                 n_warmup=2, n_sample=2, seed=1)
@@ -138,9 +174,10 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10):
     conv = float(np.mean(np.all(rhat < 1.2, axis=0)))
     evals = float(n) * C * (n_warm + n_samp) * L
     ctx.close()
-    log(f"[bench]   HMC wall {wall:.2f} s, converged fraction {conv:.3f}")
+    log(f"[bench]   HMC wall {wall:.2f} s, converged fraction {conv:.3f} (adapt_metric={adapt_metric})")
     return {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, {n_warm} warm-up + {n_samp} samples, "
                         "approximate photometry, 3-6 bands per galaxy, starts drawn from the prior",
+            "mass_matrix": "diagonal, adapted in slow warm-up windows" if adapt_metric else "identity",
             "posteriors_per_min": n / wall * 60.0,
             "converged_posteriors_per_min": conv * n / wall * 60.0,
             "converged_fraction_rhat_lt_1.2": conv,
@@ -248,7 +285,8 @@ def main():
             "peak": PEAK_FP32_VALU,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_approx<MODE_LOGL_GRAD> (+ z-bucket sort), per-launch time from HIP events",
             "flop_per_launch": CONTRACTION_FLOP_PER_EVAL * n,
         },
@@ -259,6 +297,8 @@ def main():
         out["exact"] = bench_exact(dev)
     if not args.no_hmc:
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample)
+        out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
+                                              adapt_metric=True)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ssp, filt, th32, z32, noise, sig)

@@ -146,27 +146,40 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
                      const float *z, const float *obs, const float *sigma, const uint8_t *band_mask,
                      const float *bounds, const float *prior, float *logp_out, float *grad_out);
 
-/* Batched HMC: n_chain chains per galaxy, identity mass matrix, n_leapfrog
- * leapfrog steps per iteration, per-chain step size adapted by dual averaging
- * over n_warmup iterations, then n_sample recorded iterations; momentum and
- * accept draws from Philox4x32-10 keyed by seed with counter (draw block,
- * iteration, chain id = c * n_gal + g, 0).  Hamiltonian and accept test in FP64.
+/* Batched HMC (Sec. 4, App. D.2): n_chain chains per galaxy, n_leapfrog leapfrog
+ * steps per iteration, per-chain step size adapted by dual averaging over n_warmup
+ * iterations, then n_sample recorded iterations; momentum and accept draws from
+ * Philox4x32-10 keyed by seed with counter (draw block, iteration, chain id =
+ * c * n_gal + g, 0).  Hamiltonian and accept test in FP64.
+ * Mass matrix: identity if adapt_metric = 0.  If adapt_metric = 1 (and n_warmup >= 20),
+ * a per-chain diagonal M is adapted in slow warm-up windows (fast buffer of 75
+ * iterations, windows of 25, 50, 100, ... with the last stretched to the end of the
+ * slow phase, final fast buffer of 50; 15 % / 75 % / 10 % of n_warmup when these do
+ * not fit): at each window's end M^-1 = n/(n+5) var(x) + 1e-3 * 5/(n+5) over the
+ * window's n iterates of the unbounded parameters, and dual averaging restarts from
+ * the current step size.  The paper's warm-up tunes its sampler's parameters without
+ * stating the scheme; this is the windowed scheme of the Stan manual.
  * All device pointers:
  *   theta0 [n_chain][10][n_gal] unbounded starting points (required),
  *   samples [n_sample][n_chain][10][n_gal] physical draws or NULL,
  *   post_mean, post_sd, rhat [10][n_gal] (physical parameters, pooled chains),
  *   accept [n_gal] acceptance fraction in the sampling phase,
- *   step [n_chain][n_gal] step size after warm-up. */
+ *   step [n_chain][n_gal] step size after warm-up,
+ *   inv_metric [n_chain][10][n_gal] diagonal M^-1 after warm-up, or NULL.
+ * Needs n_gal * n_chain <= the reserved galaxy count; grows the context's chain-state
+ * workspace (device memory, ~260 B per chain) on first use. */
 typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     float target_accept, init_step;
     unsigned long long seed;
+    int adapt_metric;
 } sps_hmc_cfg;
 
 int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh,
                 const float *z, const float *obs, const float *sigma, const uint8_t *band_mask,
                 const float *bounds, const float *prior, const float *theta0, float *samples,
-                float *post_mean, float *post_sd, float *rhat, float *accept, float *step);
+                float *post_mean, float *post_sd, float *rhat, float *accept, float *step,
+                float *inv_metric);
 
 #ifdef __cplusplus
 }

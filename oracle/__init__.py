@@ -57,7 +57,7 @@ class _Model(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_double), ("init_step", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("adapt_metric", C.c_int)]
 
 
 _lib = None
@@ -290,11 +290,14 @@ class Oracle:
     # --- HMC
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
-                keep_samples=False, keep_trace=False, gauss_prec=None, gal_id=None, n_gal_total=0):
+                keep_samples=False, keep_trace=False, gauss_prec=None, gal_id=None, n_gal_total=0,
+                adapt_metric=False):
         th0 = _f64(theta0)
         n_gal = th0.shape[1]
         assert th0.shape == (n_chain, n_gal, N_PARAM)
-        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed)
+        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
+                      int(bool(adapt_metric)))
+        minv = np.zeros((n_chain, n_gal, N_PARAM))
         pm, ps, rh = (np.zeros((n_gal, N_PARAM)) for _ in range(3))
         acc = np.zeros(n_gal)
         step = np.zeros((n_chain, n_gal))
@@ -314,9 +317,9 @@ class Oracle:
         rc = self.L.orc_hmc_run(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo),
                                 C.byref(self.model), n_z, lo, hi, qp, sfh, C.byref(cfg), n_gal,
                                 *args, _p(th0), _p(gp), _p(pm), _p(ps), _p(rh), _p(acc), _p(step),
-                                _p(smp), _p(tr), int(n_gal_total), _p(gid))
+                                _p(smp), _p(tr), int(n_gal_total), _p(gid), _p(minv))
         assert rc == 0, rc
-        out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step)
+        out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step, inv_metric=minv)
         if keep_samples:
             out["samples"] = smp
         if keep_trace:
@@ -330,6 +333,14 @@ def philox4x32_10(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def hmc_windows(n_warmup):
+    """Slow adaptation windows [(start, end), ...] of a warm-up of n_warmup iterations."""
+    s = np.zeros(64, np.int32)
+    e = np.zeros(64, np.int32)
+    n = lib().orc_hmc_windows(int(n_warmup), 64, _p(s), _p(e))
+    return [(int(s[i]), int(e[i])) for i in range(min(n, 64))]
 
 
 def rhat(x):

@@ -15,7 +15,8 @@
  *   skew-normal prior        App. C, Eq. (SkewNormPrior)
  *   Gaussian likelihood      App. D.1 (diagonal covariance)
  *   HMC + leapfrog           Sec. 4 / App. D.2 (fixed-length trajectories; step size
- *                            adapted in a warm-up phase)
+ *                            and, optionally, a diagonal mass matrix adapted in a
+ *                            warm-up phase)
  *
  * Readings where the paper is silent or garbled are listed in the design doc and
  * restated next to the code they govern.  No blocking, fusion or reordering:
@@ -510,6 +511,33 @@ void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
 
 double u01(uint32_t w) { return (w + 0.5) * (1.0 / 4294967296.0); }
 
+// Warm-up schedule of the windowed metric adaptation (the scheme of the Stan manual,
+// which Blackjax's window adaptation also follows): a fast buffer of 75 iterations
+// (step size only), slow windows that start at 25 iterations and double, a final fast
+// buffer of 50.  When the three defaults do not fit, the buffers are 15 % and 10 % of
+// the warm-up and one window takes the remaining 75 %.  A window is stretched to the
+// end of the slow phase when the next, doubled, window would overrun it.
+int hmc_windows(int nw, int max_win, int *start, int *end) {
+    if (nw < 20) return 0;
+    int init = 75, term = 50, base = 25;
+    if (init + base + term > nw) {
+        init = (int)(0.15 * nw);
+        term = (int)(0.1 * nw);
+        base = nw - init - term;
+    }
+    const int slow_end = nw - term;
+    int n = 0, s = init, w = base;
+    while (s < slow_end) {
+        int e = s + w;
+        if (e + 2 * w > slow_end) e = slow_end;
+        if (n < max_win) { start[n] = s; end[n] = e; }
+        ++n;
+        s = e;
+        w *= 2;
+    }
+    return n;
+}
+
 }  // namespace
 
 // =========================================================================
@@ -714,6 +742,10 @@ int orc_leapfrog(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox(ctr, key, out); }
 
+int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end) {
+    return hmc_windows(n_warmup, max_win, start, end);
+}
+
 double orc_rhat(int n_chain, int n, const double *x) {
     // classic Gelman-Rubin: V = (n-1)/n W + B/n, R = sqrt(V / W)
     std::vector<double> mean(n_chain, 0.0), var(n_chain, 0.0);
@@ -738,7 +770,8 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
                 const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id) {
+                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id,
+                double *inv_metric) {
     if (!cfg || cfg->n_chain < 1 || cfg->n_leapfrog < 1 || cfg->n_warmup < 0 || cfg->n_sample < 2) return 1;
     if (!theta0 || n_gal < 0) return 1;
     if (!gauss_prec && (!check_common(s, f) || !q || !z || !obs || !sigma || !mask || !bounds || !prior))
@@ -753,6 +786,8 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
     const uint32_t key[2] = {(uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32)};
     // dual-averaging constants (Hoffman & Gelman 2014, step-size adaptation)
     const double gamma = 0.05, t0 = 10.0, kappa = 0.75, delta = cfg->target_accept;
+    int w_start[64], w_end[64];
+    const int n_win = cfg->adapt_metric ? std::min(hmc_windows(NW, 64, w_start, w_end), 64) : 0;
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (long cg = 0; cg < (long)C * n_gal; ++cg) {
@@ -780,6 +815,12 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
         for (int p = 0; p < NP; ++p) x[p] = theta0[(size_t)cg * NP + p];
         eval(x, &lp, gr);
         double eps = cfg->init_step, mu = std::log(10.0 * cfg->init_step), hbar = 0.0, leps_bar = 0.0;
+        int da_start = 0;  // iteration at which dual averaging last (re)started
+        // diagonal inverse mass matrix M^-1 (identity unless adapted) and the
+        // Welford statistics of x inside the current slow window
+        double minv[NP], wmu[NP] = {0.0}, wm2[NP] = {0.0};
+        for (int k = 0; k < NP; ++k) minv[k] = 1.0;
+        int win = 0;
         double *mean = &cmean[(size_t)cg * NP], *m2 = &cm2[(size_t)cg * NP];
         int n_rec = 0, n_acc = 0;
         for (int it = 0; it < NIT; ++it) {
@@ -788,24 +829,26 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
                 philox(ctr, key, w + 4 * blk);
             }
+            // momentum p ~ N(0, M): standard normals (Box-Muller pairs) scaled by M^1/2
             double p[NP];
-            for (int k = 0; k < NP / 2; ++k) {  // Box-Muller pairs
+            for (int k = 0; k < NP / 2; ++k) {
                 double r = std::sqrt(-2.0 * std::log(u01(w[2 * k]))), a = 2.0 * PI * u01(w[2 * k + 1]);
-                p[2 * k] = r * std::cos(a);
-                p[2 * k + 1] = r * std::sin(a);
+                p[2 * k] = r * std::cos(a) / std::sqrt(minv[2 * k]);
+                p[2 * k + 1] = r * std::sin(a) / std::sqrt(minv[2 * k + 1]);
             }
+            // H = -log p(x) + p^T M^-1 p / 2
             double H0 = -lp;
-            for (int k = 0; k < NP; ++k) H0 += 0.5 * p[k] * p[k];
+            for (int k = 0; k < NP; ++k) H0 += 0.5 * minv[k] * p[k] * p[k];
             double xn[NP], pn[NP], grn[NP], lpn = lp;
             for (int k = 0; k < NP; ++k) { xn[k] = x[k]; pn[k] = p[k]; grn[k] = gr[k]; }
-            for (int l = 0; l < L; ++l) {  // leapfrog: half kick, drift, half kick
+            for (int l = 0; l < L; ++l) {  // leapfrog: half kick, drift by M^-1 p, half kick
                 for (int k = 0; k < NP; ++k) pn[k] += 0.5 * eps * grn[k];
-                for (int k = 0; k < NP; ++k) xn[k] += eps * pn[k];
+                for (int k = 0; k < NP; ++k) xn[k] += eps * minv[k] * pn[k];
                 eval(xn, &lpn, grn);
                 for (int k = 0; k < NP; ++k) pn[k] += 0.5 * eps * grn[k];
             }
             double H1 = -lpn;
-            for (int k = 0; k < NP; ++k) H1 += 0.5 * pn[k] * pn[k];
+            for (int k = 0; k < NP; ++k) H1 += 0.5 * minv[k] * pn[k] * pn[k];
             double dH = H1 - H0;
             bool divergent = !std::isfinite(H1) || dH > 1000.0;
             double alpha = divergent ? 0.0 : std::min(1.0, std::exp(-dH));
@@ -815,11 +858,31 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 lp = lpn;
             }
             if (it < NW) {
-                double mm = it + 1.0, eta = 1.0 / (mm + t0);
+                double mm = it - da_start + 1.0, eta = 1.0 / (mm + t0);
                 hbar = (1.0 - eta) * hbar + eta * (delta - alpha);
                 double leps = mu - std::sqrt(mm) / gamma * hbar, wk = std::pow(mm, -kappa);
                 leps_bar = wk * leps + (1.0 - wk) * leps_bar;
                 eps = std::exp(it == NW - 1 ? leps_bar : leps);
+                if (win < n_win && it >= w_start[win]) {
+                    // slow window: accumulate x; at its end, set M^-1 to the regularised
+                    // sample variance and restart dual averaging from the current step
+                    const double nn = it - w_start[win] + 1.0;
+                    for (int k = 0; k < NP; ++k) {
+                        double d = x[k] - wmu[k];
+                        wmu[k] += d / nn;
+                        wm2[k] += d * (x[k] - wmu[k]);
+                    }
+                    if (it == w_end[win] - 1) {
+                        for (int k = 0; k < NP; ++k) {
+                            minv[k] = nn / (nn + 5.0) * (wm2[k] / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0);
+                            wmu[k] = wm2[k] = 0.0;
+                        }
+                        mu = std::log(10.0 * eps);
+                        hbar = leps_bar = 0.0;
+                        da_start = it + 1;
+                        ++win;
+                    }
+                }
             } else {
                 n_acc += acc;
                 ++n_rec;
@@ -832,6 +895,8 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             }
             if (trace_logp) trace_logp[((size_t)it * C + ch) * n_gal + g] = lp;
         }
+        if (inv_metric)
+            for (int k = 0; k < NP; ++k) inv_metric[(size_t)cg * NP + k] = minv[k];
         cacc[cg] = n_acc;
         if (step) step[cg] = eps;
     }

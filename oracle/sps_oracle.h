@@ -118,7 +118,13 @@ typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     double target_accept, init_step;
     uint64_t seed;
+    int adapt_metric;   /* 0: identity mass matrix; 1: diagonal, adapted in slow windows */
 } orc_hmc_cfg;
+
+/* Slow adaptation windows of a warm-up of n_warmup iterations: window w covers
+ * iterations [start[w], end[w]).  Returns the number of windows (0 if n_warmup < 20);
+ * at most max_win are written. */
+int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end);
 
 /* theta0[c][g][10] unbounded start; outputs:
  *   post_mean, post_sd, rhat [g][10] (physical parameters),
@@ -130,14 +136,16 @@ typedef struct {
  * 10x10 precision matrix instead of the SPS posterior (sampler validation mode;
  * then the physical map is the identity).
  * gal_id (may be NULL): global galaxy indices when these galaxies are a subset of a batch of
- * n_gal_total galaxies; the Philox chain id is then chain * n_gal_total + gal_id[g]. */
+ * n_gal_total galaxies; the Philox chain id is then chain * n_gal_total + gal_id[g].
+ * inv_metric [c][g][10] (may be NULL): diagonal inverse mass matrix after warm-up. */
 int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                 int n_z, double z_lo, double z_hi, const double *q, int sfh,
                 const orc_hmc_cfg *cfg, int n_gal, const double *z, const double *obs,
                 const double *sigma, const uint8_t *mask, const double *bounds, const double *prior,
                 const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id);
+                double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id,
+                double *inv_metric);
 
 /* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
 double orc_rhat(int n_chain, int n, const double *x);

@@ -54,7 +54,7 @@ class _ModelDesc(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_float), ("init_step", C.c_float),
-                ("seed", C.c_ulonglong)]
+                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int)]
 
 
 def _load():
@@ -77,7 +77,7 @@ def _load():
     lib.sps_loglike_grad.argtypes = [vp, vp, i, i, i, i, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_logpost_grad.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_hmc_run.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp]
+                                vp, vp, vp, vp, vp, vp]
     for name in ABI_FUNCTIONS:
         if name not in ("sps_destroy", "sps_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -235,7 +235,7 @@ class Context:
 
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
-                keep_samples=False, stream=None):
+                keep_samples=False, adapt_metric=False, stream=None):
         n = z.shape[0]
         _dev(z, torch.float32, (n,), "z", self.device)
         _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
@@ -247,13 +247,16 @@ class Context:
         f32 = dict(dtype=torch.float32, device=self.device)
         out = dict(post_mean=torch.empty((NPARAM, n), **f32), post_sd=torch.empty((NPARAM, n), **f32),
                    rhat=torch.empty((NPARAM, n), **f32), accept=torch.empty(n, **f32),
-                   step=torch.empty((n_chain, n), **f32))
+                   step=torch.empty((n_chain, n), **f32),
+                   inv_metric=torch.empty((n_chain, NPARAM, n), **f32))
         samples = torch.empty((n_sample, n_chain, NPARAM, n), **f32) if keep_samples else None
-        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed)
+        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
+                      int(bool(adapt_metric)))
         _check(_lib.sps_hmc_run(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs),
                                 _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0),
                                 _ptr(samples), _ptr(out["post_mean"]), _ptr(out["post_sd"]),
-                                _ptr(out["rhat"]), _ptr(out["accept"]), _ptr(out["step"])))
+                                _ptr(out["rhat"]), _ptr(out["accept"]), _ptr(out["step"]),
+                                _ptr(out["inv_metric"])))
         if keep_samples:
             out["samples"] = samples
         return out

@@ -17,12 +17,27 @@ __global__ void k_zero_int(int *p, int n) {
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_bucket_hist(DevConsts k, int n, const float *__restrict__ z, int *__restrict__ hist) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float f;
-    int kk = z_bucket(k, z[i], &f);
-    atomicAdd(&hist[kk < 0 ? k.n_z - 1 : kk], 1);
+constexpr int SORT_BLOCK = 256, SORT_PER_THREAD = 16, SORT_TILE = SORT_BLOCK * SORT_PER_THREAD;
+
+// per-block histogram in LDS, one global atomic per bucket per block
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_hist(DevConsts k, int n, const float *__restrict__ z,
+                                                           int *__restrict__ hist) {
+    extern __shared__ int sh[];
+    const int nbk = k.n_z;
+    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) sh[b] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * SORT_TILE;
+    for (int t = 0; t < SORT_PER_THREAD; ++t) {
+        const int i = base + t * SORT_BLOCK + threadIdx.x;
+        if (i < n) {
+            float f;
+            const int kk = z_bucket(k, z[i], &f);
+            atomicAdd(&sh[kk < 0 ? nbk - 1 : kk], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK)
+        if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
 // exclusive scan of hist[0..nb) into cursor[0..nb); one block of 1024 threads
@@ -40,14 +55,33 @@ __global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restr
     if (t < nb) cursor[t] = s[t] - ((t < nb) ? hist[t] : 0);
 }
 
-__global__ void k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z, int *__restrict__ cursor,
-                                 int *__restrict__ perm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float f;
-    int kk = z_bucket(k, z[i], &f);
-    int pos = atomicAdd(&cursor[kk < 0 ? k.n_z - 1 : kk], 1);
-    perm[pos] = i;
+// each block reserves a range per bucket in the global cursor, then places its galaxies
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
+                                                              int *__restrict__ cursor, int *__restrict__ perm) {
+    extern __shared__ int sh[];
+    const int nbk = k.n_z;
+    int *cnt = sh, *pos = sh + nbk;
+    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * SORT_TILE;
+    int kk_t[SORT_PER_THREAD];
+    for (int t = 0; t < SORT_PER_THREAD; ++t) {
+        const int i = base + t * SORT_BLOCK + threadIdx.x;
+        kk_t[t] = -2;
+        if (i < n) {
+            float f;
+            const int kk = z_bucket(k, z[i], &f);
+            kk_t[t] = kk < 0 ? nbk - 1 : kk;
+            atomicAdd(&cnt[kk_t[t]], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) pos[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
+    __syncthreads();
+    for (int t = 0; t < SORT_PER_THREAD; ++t) {
+        const int i = base + t * SORT_BLOCK + threadIdx.x;
+        if (kk_t[t] >= 0) perm[atomicAdd(&pos[kk_t[t]], 1)] = i;
+    }
 }
 
 // ------------------------------------------------------------------ the one-shot kernel
@@ -161,9 +195,11 @@ int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z) {
     const int nbk = c->k.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
     int *hist = c->d_hist, *cursor = c->d_hist + 1025;
     hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
-    hipLaunchKernelGGL(k_bucket_hist, dim3((n + 255) / 256), dim3(256), 0, s, c->k, n, z, hist);
+    const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
+    hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, c->k, n, z, hist);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3((n + 255) / 256), dim3(256), 0, s, c->k, n, z, cursor, c->d_perm);
+    hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, c->k, n, z, cursor,
+                       c->d_perm);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }

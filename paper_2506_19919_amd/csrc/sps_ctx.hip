@@ -1,4 +1,5 @@
 // Context lifecycle, table uploads, the z-table build and the C ABI entry points.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -129,9 +130,9 @@ int launch_ztable(sps_ctx *c, hipStream_t st) {
     hipLaunchKernelGGL(k_ztable, dim3(S), dim3(256), nw * sizeof(double), st, S, nkb, nw, c->d_lum64, d_tw, c->d_q);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(d_fc);
-    hipFree(d_fs);
-    hipFree(d_tw);
+    (void)hipFree(d_fc);
+    (void)hipFree(d_fs);
+    (void)hipFree(d_tw);
     if (e != hipSuccess) return hip_check(e, "z-table build");
     return SPS_OK;
 }
@@ -144,18 +145,18 @@ namespace {
 
 void free_ctx(sps_ctx *c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipFree(c->d_lum64);
-    hipFree(c->d_lum32);
-    hipFree(c->d_lum_hi);
-    hipFree(c->d_lum_lo);
-    hipFree(c->d_wave);
-    hipFree(c->d_trap);
-    hipFree(c->d_edges);
-    hipFree(c->d_q);
-    hipFree(c->d_perm);
-    hipFree(c->d_hist);
-    hipFree(c->d_work);
+    (void)hipSetDevice(c->device);
+    (void)hipFree(c->d_lum64);
+    (void)hipFree(c->d_lum32);
+    (void)hipFree(c->d_lum_hi);
+    (void)hipFree(c->d_lum_lo);
+    (void)hipFree(c->d_wave);
+    (void)hipFree(c->d_trap);
+    (void)hipFree(c->d_edges);
+    (void)hipFree(c->d_q);
+    (void)hipFree(c->d_perm);
+    (void)hipFree(c->d_hist);
+    (void)hipFree(c->d_work);
     delete c;
 }
 
@@ -186,7 +187,7 @@ int sps_reserve(sps_ctx *c, int max_gal) {
     if (max_gal < 1) return set_error(SPS_E_INVAL, "max_gal < 1");
     if (max_gal <= c->max_gal) return SPS_OK;
     SPS_HIP(hipDeviceSynchronize());
-    hipFree(c->d_perm);
+    (void)hipFree(c->d_perm);
     c->d_perm = nullptr;
     c->max_gal = 0;
     SPS_HIP(hipMalloc(&c->d_perm, (size_t)max_gal * sizeof(int)));
@@ -245,6 +246,19 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
         k.lage_hi[i] = (float)lhi;
         k.age_lo[i] = (i == 0) ? 0.0f : (float)(std::pow(10.0, llo) * 1e-9);
         k.age_hi[i] = (i == NA - 1) ? INFINITY : (float)(std::pow(10.0, lhi) * 1e-9);
+    }
+    // widest run of age bins a burst window [v, v + 6 sigma] can touch: a window starting in
+    // bin i0 ends below lage_hi[i0] + 6 sigma (padded against FP32 rounding of the edges)
+    {
+        const double win = 2.0 * model->burst_dlogt + 1e-3;
+        int most = 1;
+        for (int i0 = 0; i0 < NA - 1; ++i0) {
+            const double top = (double)k.lage_hi[i0] + win;
+            int cnt = 1;
+            while (i0 + cnt < NA && (double)k.lage_lo[i0 + cnt] < top) ++cnt;
+            most = std::max(most, cnt);
+        }
+        k.burst_nbins = most;
     }
     std::vector<double> edges(4 * NA + 2 * NZ);
     for (int i = 0; i < NA; ++i) {
@@ -332,7 +346,7 @@ int sps_build_ztable(sps_ctx *c, int n_z, double z_lo, double z_hi) {
     if (n_z < 2 || n_z > 1024) return set_error(SPS_E_INVAL, "n_z must be in 2..1024");
     if (!(z_lo >= 0.0) || !(z_hi > z_lo) || !std::isfinite(z_hi)) return set_error(SPS_E_INVAL, "need 0 <= z_lo < z_hi");
     SPS_HIP(hipDeviceSynchronize());
-    hipFree(c->d_q);
+    (void)hipFree(c->d_q);
     c->d_q = nullptr;
     c->k.n_z = 0;
     SPS_HIP(hipMalloc(&c->d_q, (size_t)n_z * c->n_band * NZ * NA * sizeof(float)));
@@ -426,7 +440,7 @@ int sps_logpost_grad(sps_ctx *c, void *stream, int n_gal, int sfh, const float *
 int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                 const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
                 const float *prior, const float *theta0, float *samples, float *post_mean, float *post_sd,
-                float *rhat, float *accept, float *step) {
+                float *rhat, float *accept, float *step, float *inv_metric) {
     int rc = enter(c);
     if (rc) return rc;
     if (!cfg) return set_error(SPS_E_INVAL, "null config");
@@ -435,6 +449,7 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
         return set_error(SPS_E_INVAL, "need 1 <= n_chain <= 64, n_leapfrog >= 1, n_warmup >= 0, n_sample >= 2");
     if (!(cfg->init_step > 0.0f) || !(cfg->target_accept > 0.0f && cfg->target_accept < 1.0f))
         return set_error(SPS_E_INVAL, "need init_step > 0 and 0 < target_accept < 1");
+    if (cfg->adapt_metric != 0 && cfg->adapt_metric != 1) return set_error(SPS_E_INVAL, "adapt_metric must be 0 or 1");
     if ((long long)n_gal * cfg->n_chain > (long long)c->max_gal)
         return set_error(SPS_E_INVAL, "n_gal * n_chain exceeds the reserved workspace (call sps_reserve)");
     if (c->k.n_z == 0) return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
@@ -443,7 +458,7 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
         !accept || !step)
         return set_error(SPS_E_INVAL, "null array");
     return launch_hmc(c, (hipStream_t)stream, cfg, n_gal, sfh, z, obs, sigma, band_mask, bounds, prior, theta0,
-                      samples, post_mean, post_sd, rhat, accept, step);
+                      samples, post_mean, post_sd, rhat, accept, step, inv_metric);
 }
 
 }  // extern "C"

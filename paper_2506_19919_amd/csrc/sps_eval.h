@@ -38,6 +38,7 @@ struct WeightsState {
     double S;      // total smooth mass (FP64 running sum)
     float Zb;      // burst normaliser (1 unless clipped at t_obs)
     float l_obs;   // log10 t_obs [yr]
+    int i0;        // first age bin of the burst window
 };
 
 __device__ inline void forward_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
@@ -60,18 +61,23 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
             S += m;
         }
     }
-    const float l_obs = (float)log10(t_obs * 1e9);
+    // burst: only the bins the triweight window [mu - 3 sigma, mu + 3 sigma] touches
+    const float l_obs = (float)log10(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
+    const int i0 = first_bin_above(k, mu - 3.0f * k.burst_sig);
     float Zb = 0.0f;
-    for (int i = 0; i < NA; ++i) {
+    for (int t = 0; t < k.burst_nbins; ++t) {
         float p, dp;
-        burst_bin(k, i, l_obs, th[5], p, dp);
+        if (i0 + t < NA) burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
+        else p = 0.0f;
         Zb += p;
     }
-    const float fb = th[4], invS = (float)(1.0 / S), invZ = (Zb > 0.0f) ? 1.0f / Zb : 0.0f;
-    for (int i = 0; i < NA; ++i) {
+    const float fb = th[4], sm = (1.0f - fb) * (float)(1.0 / S), bz = (Zb > 0.0f) ? fb / Zb : 0.0f;
+    for (int i = 0; i < NA; ++i) col[i] = col[i] * sm;
+    for (int t = 0; t < k.burst_nbins; ++t) {
+        if (i0 + t >= NA) break;
         float p, dp;
-        burst_bin(k, i, l_obs, th[5], p, dp);
-        col[i] = (1.0f - fb) * (col[i] * invS) + fb * (p * invZ);
+        burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
+        col[i0 + t] = fmaf(bz, p, col[i0 + t]);
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i) pa[i] = col[i];
@@ -83,6 +89,7 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
     ws.S = S;
     ws.Zb = Zb;
     ws.l_obs = l_obs;
+    ws.i0 = i0;
 }
 
 // gradient of the weights: given dP_age (LDS column, slots 0..NA) and dP_Z,
@@ -97,6 +104,7 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     double dA0 = 0.0, dA1 = 0.0, dB0 = 0.0, dB1 = 0.0;
     Dpl p;
     if (sfh == SPS_SFH_DPL) p = make_dpl(th[1], th[2], th[3]);
+    // smooth part: dP_age/dF_burst = P_burst - P_smooth; the P_burst term is added below
     for (int i = 0; i < NA; ++i) {
         const float gbar = col[i];
         float ps;
@@ -109,11 +117,8 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
             logn_bin<true>(k, i, t_obs, (double)th[1], (double)th[2], dm, dmt, dmw);
             ps = (float)(dm / ws.S);
         }
-        float pbr, dpb;
-        burst_bin(k, i, ws.l_obs, th[5], pbr, dpb);
-        const float pb = pbr * invZ;
-        fbar = fmaf(gbar, pb - ps, fbar);
-        const float psbar = (1.0f - fb) * gbar, pbbar = fb * gbar;
+        fbar = fmaf(-gbar, ps, fbar);
+        const float psbar = (1.0f - fb) * gbar;
         cbar = fmaf(psbar, ps, cbar);
         if (sfh == SPS_SFH_DPL) {
             A0 = fmaf(psbar, mt, A0); A1 = fmaf(psbar, ma, A1); A2 = fmaf(psbar, mb, A2);
@@ -122,6 +127,17 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
             dA0 += (double)psbar * dmt; dA1 += (double)psbar * dmw;
             dB0 += dmt; dB1 += dmw;
         }
+    }
+    // burst part over the triweight window
+    const float inv_s3 = 1.0f / (3.0f * k.burst_sig);
+    for (int t = 0; t < k.burst_nbins; ++t) {
+        const int i = ws.i0 + t;
+        if (i >= NA) break;
+        const float gbar = col[i];
+        float pbr, dpb;
+        burst_bin(k, i, ws.l_obs, th[5], inv_s3, pbr, dpb);
+        const float pb = pbr * invZ, pbbar = fb * gbar;
+        fbar = fmaf(gbar, pb, fbar);
         e1 = fmaf(pbbar, dpb, e1);
         e2 = fmaf(pbbar, pb, e2);
         e3 += dpb;

@@ -495,7 +495,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     }
     if (c->work_bytes < off) {
         SPS_HIP(hipDeviceSynchronize());
-        hipFree(c->d_work);
+        (void)hipFree(c->d_work);
         c->d_work = nullptr;
         c->work_bytes = 0;
         SPS_HIP(hipMalloc(&c->d_work, off));

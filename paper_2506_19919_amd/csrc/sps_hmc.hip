@@ -3,13 +3,17 @@
 // z-bucket order, so a wave shares its z-table slices.  Each launch advances all
 // chains by a block of iterations; chain state lives in HBM between launches.
 //
-// Per iteration: momentum p ~ N(0, I) from Philox4x32-10 (Box-Muller), n_leapfrog
-// leapfrog steps (half kick, drift, half kick; one value+gradient each),
-// H = -log p + |p|^2 / 2 summed in FP64, Metropolis test log u < H0 - H1 in FP64,
-// divergence (non-finite H1 or H1 - H0 > 1000) = reject.  Warm-up: dual averaging
-// of log step size (Hoffman & Gelman 2014: mu = log(10 eps0), gamma = 0.05,
-// t0 = 10, kappa = 0.75); afterwards the averaged step size is kept.
-// Sampling: Welford mean / M2 of the physical parameters per chain (FP64).
+// Per iteration: momentum p ~ N(0, M) from Philox4x32-10 (Box-Muller, scaled by
+// M^1/2), n_leapfrog leapfrog steps (half kick, drift by M^-1 p, half kick; one
+// value+gradient each), H = -log p + p^T M^-1 p / 2 summed in FP64, Metropolis test
+// log u < H0 - H1 in FP64, divergence (non-finite H1 or H1 - H0 > 1000) = reject.
+// Warm-up: dual averaging of log step size (Hoffman & Gelman 2014: mu = log(10 eps0),
+// gamma = 0.05, t0 = 10, kappa = 0.75); afterwards the averaged step size is kept.
+// Optional diagonal M (identity otherwise): Welford variance of the unbounded
+// parameters over slow warm-up windows; at a window's end M^-1 = n/(n+5) var +
+// 1e-3 * 5/(n+5) and dual averaging restarts at mu = log(10 eps).
+// Sampling: Welford mean / M2 of the physical parameters per chain (FP64); the same
+// registers hold the window statistics during warm-up.
 #include "sps_eval.h"
 
 namespace sps {
@@ -33,8 +37,12 @@ __device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1)
 __device__ inline float u01f(uint32_t w) { return fmaf((float)w, 2.3283064365386963e-10f, 1.1641532182693481e-10f); }
 __device__ inline double u01d(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
 
+constexpr int MAX_WIN = 24;
+
 struct HmcArgs {
     int n_gal, C, L, NW, NS, it0, it1, sfh;
+    int n_win;                               // slow metric windows (0 = identity metric)
+    int win_s[MAX_WIN], win_e[MAX_WIN];      // window w = iterations [win_s, win_e)
     float target, init_step;
     uint32_t key0, key1;
     const float *z, *obs, *sigma;
@@ -44,8 +52,8 @@ struct HmcArgs {
     const float *q;
     float *samples;
     // chain state, indexed by slot = rank * C + chain
-    float *x, *gr, *eps, *hbar, *lebar;
-    int *nacc;
+    float *x, *gr, *eps, *hbar, *lebar, *mu, *minv;
+    int *nacc, *da0;
     double *lp, *wmean, *wm2;
 };
 
@@ -101,35 +109,42 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     lc.sig_g = a.sigma + (size_t)g * k.n_band;
     lc.mask = a.mask[g];
 
-    float x[NP], gr[NP], eps, hbar, lebar;
+    float x[NP], gr[NP], minv[NP], eps, hbar, lebar, mu;
     double lp;
-    int nacc;
+    int nacc, da0;
     double wmean[NP], wm2[NP];
     if (a.it0 == 0) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
         lp = logpost(k, a, lc, col, x, gr);
         eps = a.init_step;
+        mu = logf(10.0f * a.init_step);
         hbar = 0.0f;
         lebar = 0.0f;
         nacc = 0;
+        da0 = 0;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) wmean[p] = wm2[p] = 0.0;
+        for (int p = 0; p < NP; ++p) {
+            wmean[p] = wm2[p] = 0.0;
+            minv[p] = 1.0f;
+        }
     } else {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             x[p] = a.x[(size_t)p * nslot + sl];
             gr[p] = a.gr[(size_t)p * nslot + sl];
+            minv[p] = a.minv[(size_t)p * nslot + sl];
             wmean[p] = a.wmean[(size_t)p * nslot + sl];
             wm2[p] = a.wm2[(size_t)p * nslot + sl];
         }
         lp = a.lp[sl];
         eps = a.eps[sl];
+        mu = a.mu[sl];
         hbar = a.hbar[sl];
         lebar = a.lebar[sl];
         nacc = a.nacc[sl];
+        da0 = a.da0[sl];
     }
-    const float mu = logf(10.0f * a.init_step);
 
     for (int it = a.it0; it < a.it1; ++it) {
         uint32_t w[12];
@@ -146,21 +161,21 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
             const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
             float sn, cs;
             sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
-            p[2 * t] = r * cs;
-            p[2 * t + 1] = r * sn;
+            p[2 * t] = r * cs / sqrtf(minv[2 * t]);
+            p[2 * t + 1] = r * sn / sqrtf(minv[2 * t + 1]);
         }
         double H0 = -lp;
 #pragma unroll
-        for (int t = 0; t < NP; ++t) H0 += 0.5 * (double)p[t] * (double)p[t];
-        float xn[NP], gn[NP];
+        for (int t = 0; t < NP; ++t) H0 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
+        float xn[NP], gn[NP], em[NP];
         double lpn = lp;
 #pragma unroll
-        for (int t = 0; t < NP; ++t) { xn[t] = x[t]; gn[t] = gr[t]; }
+        for (int t = 0; t < NP; ++t) { xn[t] = x[t]; gn[t] = gr[t]; em[t] = eps * minv[t]; }
         for (int l = 0; l < a.L; ++l) {
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 p[t] = fmaf(0.5f * eps, gn[t], p[t]);
-                xn[t] = fmaf(eps, p[t], xn[t]);
+                xn[t] = fmaf(em[t], p[t], xn[t]);
             }
             lpn = logpost(k, a, lc, col, xn, gn);
 #pragma unroll
@@ -168,7 +183,7 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
         }
         double H1 = -lpn;
 #pragma unroll
-        for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)p[t] * (double)p[t];
+        for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
         const double dH = H1 - H0;
         const bool divergent = !isfinite(H1) || dH > 1000.0;
         const float alpha = divergent ? 0.0f : (float)fmin(1.0, exp(-dH));
@@ -179,11 +194,34 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
             lp = lpn;
         }
         if (it < a.NW) {
-            const float m = (float)(it + 1), eta = 1.0f / (m + 10.0f);
+            const float m = (float)(it - da0 + 1), eta = 1.0f / (m + 10.0f);
             hbar = (1.0f - eta) * hbar + eta * (a.target - alpha);
             const float leps = mu - sqrtf(m) / 0.05f * hbar, wk = powf(m, -0.75f);
             lebar = wk * leps + (1.0f - wk) * lebar;
             eps = expf(it == a.NW - 1 ? lebar : leps);
+            // slow metric window holding iteration it (uniform across the grid)
+            int wi = -1;
+            for (int q = 0; q < a.n_win; ++q)
+                if (it >= a.win_s[q] && it < a.win_e[q]) wi = q;
+            if (wi >= 0) {
+                const double nn = (double)(it - a.win_s[wi] + 1);
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    const double d = (double)x[t] - wmean[t];
+                    wmean[t] += d / nn;
+                    wm2[t] += d * ((double)x[t] - wmean[t]);
+                }
+                if (it == a.win_e[wi] - 1) {
+#pragma unroll
+                    for (int t = 0; t < NP; ++t) {
+                        minv[t] = (float)(nn / (nn + 5.0) * (wm2[t] / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0));
+                        wmean[t] = wm2[t] = 0.0;
+                    }
+                    mu = logf(10.0f * eps);
+                    hbar = lebar = 0.0f;
+                    da0 = it + 1;
+                }
+            }
         } else {
             nacc += acc ? 1 : 0;
             const double nrec = (double)(it - a.NW + 1);
@@ -204,21 +242,25 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     for (int p = 0; p < NP; ++p) {
         a.x[(size_t)p * nslot + sl] = x[p];
         a.gr[(size_t)p * nslot + sl] = gr[p];
+        a.minv[(size_t)p * nslot + sl] = minv[p];
         a.wmean[(size_t)p * nslot + sl] = wmean[p];
         a.wm2[(size_t)p * nslot + sl] = wm2[p];
     }
     a.lp[sl] = lp;
     a.eps[sl] = eps;
+    a.mu[sl] = mu;
     a.hbar[sl] = hbar;
     a.lebar[sl] = lebar;
     a.nacc[sl] = nacc;
+    a.da0[sl] = da0;
 }
 
 // pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy
 __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ perm,
                               const double *__restrict__ wmean, const double *__restrict__ wm2,
-                              const int *__restrict__ nacc, const float *__restrict__ eps, float *post_mean,
-                              float *post_sd, float *rhat, float *accept, float *step) {
+                              const int *__restrict__ nacc, const float *__restrict__ eps,
+                              const float *__restrict__ minv, float *post_mean, float *post_sd, float *rhat,
+                              float *accept, float *step, float *inv_metric) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_gal) return;
     const int g = perm[r], nslot = n_gal * C;
@@ -226,6 +268,9 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
     for (int c = 0; c < C; ++c) {
         acc += nacc[r * C + c];
         step[(size_t)c * n_gal + g] = eps[r * C + c];
+        if (inv_metric)
+            for (int p = 0; p < NP; ++p)
+                inv_metric[((size_t)c * NP + p) * n_gal + g] = minv[(size_t)p * nslot + r * C + c];
     }
     accept[g] = (float)acc / ((float)C * NS);
     for (int p = 0; p < NP; ++p) {
@@ -251,18 +296,52 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
     }
 }
 
+// Slow windows of the metric adaptation over nw warm-up iterations.  Defaults: fast
+// buffers of 75 (first) and 50 (last) iterations around windows of 25, 50, 100, ...;
+// if 75 + 25 + 50 exceeds nw, the buffers are 15 % and 10 % of nw and the first window
+// the rest.  A window that would leave less than twice its length (the next window's
+// size) before the last buffer absorbs that remainder.  Returns the count, or -1 if it
+// exceeds MAX_WIN.  No windows below 20 warm-up iterations.
+static int metric_windows(int nw, int *ws, int *we) {
+    if (nw < 20) return 0;
+    int first = 75, last = 50, len = 25;
+    if (first + len + last > nw) {
+        first = (int)(0.15 * nw);
+        last = (int)(0.1 * nw);
+        len = nw - first - last;
+    }
+    const int stop = nw - last;
+    int n = 0;
+    for (int at = first; at < stop; len *= 2) {
+        if (n == MAX_WIN) return -1;
+        const int end = (at + 3 * len > stop) ? stop : at + len;
+        ws[n] = at;
+        we[n] = end;
+        ++n;
+        at = end;
+    }
+    return n;
+}
+
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
                const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
-               float *step) {
+               float *step, float *inv_metric) {
     const int C = cfg->n_chain, nslot = n_gal * C;
-    // chain state: 10 x + 10 grad + eps, hbar, lebar (float), nacc (int); lp + 20 Welford (double)
-    const size_t fbytes = (size_t)nslot * (2 * NP + 3) * sizeof(float) + (size_t)nslot * sizeof(int);
+    HmcArgs a{};
+    a.n_win = 0;
+    if (cfg->adapt_metric) {
+        a.n_win = metric_windows(cfg->n_warmup, a.win_s, a.win_e);
+        if (a.n_win < 0) return set_error(SPS_E_INVAL, "n_warmup too long for the metric-window table");
+    }
+    // chain state: 10 x + 10 grad + 10 M^-1 + eps, mu, hbar, lebar (float), nacc, da0 (int);
+    // lp + 20 Welford (double)
+    const size_t fbytes = (size_t)nslot * (3 * NP + 4) * sizeof(float) + (size_t)nslot * 2 * sizeof(int);
     const size_t dofs = (fbytes + 255) & ~(size_t)255;
     const size_t need = dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double);
     if (c->work_bytes < need) {
         SPS_HIP(hipDeviceSynchronize());
-        hipFree(c->d_work);
+        (void)hipFree(c->d_work);
         c->d_work = nullptr;
         c->work_bytes = 0;
         SPS_HIP(hipMalloc(&c->d_work, need));
@@ -271,7 +350,6 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     int rc = launch_bucket_sort(c, s, n_gal, z);
     if (rc) return rc;
     float *fp = (float *)c->d_work;
-    HmcArgs a{};
     a.n_gal = n_gal;
     a.C = C;
     a.L = cfg->n_leapfrog;
@@ -294,10 +372,13 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.samples = samples;
     a.x = fp;
     a.gr = fp + (size_t)NP * nslot;
-    a.eps = fp + (size_t)2 * NP * nslot;
-    a.hbar = a.eps + nslot;
+    a.minv = fp + (size_t)2 * NP * nslot;
+    a.eps = fp + (size_t)3 * NP * nslot;
+    a.mu = a.eps + nslot;
+    a.hbar = a.mu + nslot;
     a.lebar = a.hbar + nslot;
     a.nacc = (int *)(a.lebar + nslot);
+    a.da0 = a.nacc + nslot;
     a.lp = (double *)((char *)c->d_work + dofs);
     a.wmean = a.lp + nslot;
     a.wm2 = a.wmean + (size_t)NP * nslot;
@@ -310,7 +391,8 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
         hipLaunchKernelGGL(k_hmc, grid, block, 0, s, c->k, a);
     }
     hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
-                       c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, post_mean, post_sd, rhat, accept, step);
+                       c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                       inv_metric);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }

@@ -23,6 +23,7 @@ struct DevConsts {
     int n_z;                      // z table nodes (0 = none)
     float z_lo, dz;               // z table: node k at z_lo + k dz
     float sigma_logz, burst_sig;  // dex; burst sigma = (log T_max - log T_peak)/3
+    int burst_nbins;              // most age bins a triweight window of width 6 sigma can overlap
     double sigma_logz_d, burst_sig_d;
     float age_lo[NA], age_hi[NA]; // stellar-age limits of the bins [Gyr]; last hi = +inf
     float lage_lo[NA], lage_hi[NA];  // log10(age/yr) limits; -inf / +inf at the ends
@@ -85,7 +86,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int prec, const 
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                const float *prior, const float *theta0, float *samples, float *post_mean,
-               float *post_sd, float *rhat, float *accept, float *step);
+               float *post_sd, float *rhat, float *accept, float *step, float *inv_metric);
 
 // modes of the approximate-path kernel
 enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3 };

@@ -73,6 +73,7 @@ __device__ inline float tri_dcdf(float u) {
 struct Dpl {
     float tau, am1, bp1, ltau, inv_w;
     float s_l2, b_l2;   // (alpha + beta) log2(e), (beta + 1) log2(e)
+    float inv_bp1;
 };
 __device__ inline Dpl make_dpl(float tau, float al, float be) {
     Dpl d;
@@ -84,6 +85,7 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
     d.inv_w = 1.0f / w;
     d.s_l2 = (al + be) * 1.4426950408889634f;
     d.b_l2 = d.bp1 * 1.4426950408889634f;
+    d.inv_bp1 = 1.0f / d.bp1;
     return d;
 }
 
@@ -119,20 +121,24 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     m = d_tau = d_al = d_be = 0.0f;
     const float a_lo = k.age_lo[i], a_hi = k.age_hi[i];
     if (!(a_lo < t_obs)) return;
-    const float xhi = logf(t_obs - a_lo) - p.ltau;
-    // span W of the bin in X is formed directly (log1p of the age-edge difference): young
-    // bins are ~1e-5 wide at |X| ~ 1, where xhi - xlo would cancel in FP32
+    // hardware log2 / reciprocal: ~1 ulp, shifting every node of the bin alike by < 3e-7
+    const float xhi = __builtin_amdgcn_logf(t_obs - a_lo) * 0.69314718055994531f - p.ltau;
+    // span W of the bin in X is formed directly as log1p of the age-edge ratio (young bins
+    // are ~1e-5 wide at |X| ~ 1, where xhi - xlo would cancel in FP32); log1p(d) is
+    // evaluated as log(u) d / (u - 1) with u = 1 + d, which absorbs the rounding of u
     float span, tail = 0.0f, tail_t = 0.0f, tail_b = 0.0f;
     if (a_hi < t_obs) {
-        span = log1pf((a_hi - a_lo) / (t_obs - a_hi));
+        const float d = (a_hi - a_lo) * __builtin_amdgcn_rcpf(t_obs - a_hi);
+        const float u = 1.0f + d;
+        span = (u == 1.0f) ? d : __builtin_amdgcn_logf(u) * 0.69314718055994531f * (d * __builtin_amdgcn_rcpf(u - 1.0f));
     } else {
         // oldest bin: panels down to the cut, analytic leading term below it
-        const float xlo = fminf(xhi, 0.0f) - 30.0f / p.bp1;
+        const float xlo = fminf(xhi, 0.0f) - 30.0f * p.inv_bp1;
         span = xhi - xlo;
-        tail = p.tau * __builtin_amdgcn_exp2f(p.b_l2 * xlo) / p.bp1;
+        tail = p.tau * __builtin_amdgcn_exp2f(p.b_l2 * xlo) * p.inv_bp1;
         if (DERIV) {
             tail_t = -(p.bp1 - 1.0f) * tail / p.tau;
-            tail_b = tail * (xlo - 1.0f / p.bp1);
+            tail_b = tail * (xlo - p.inv_bp1);
         }
     }
     float s = 0.0f, st = 0.0f, sa = 0.0f, sb = 0.0f, hw;
@@ -230,16 +236,28 @@ __device__ inline void logn_bin(const DevConsts &k, int i, double t_obs, double 
 
 // ------------------------------------------------------------------ burst (triweight)
 // unnormalised probability of bin i and its derivative w.r.t. mu = log10 T_peak
-__device__ inline void burst_bin(const DevConsts &k, int i, float l_obs, float mu, float &p, float &dp) {
+// (inv_s3 = 1 / (3 sigma_burst))
+__device__ inline void burst_bin(const DevConsts &k, int i, float l_obs, float mu, float inv_s3, float &p,
+                                 float &dp) {
     p = dp = 0.0f;
     const float lo = k.lage_lo[i];
     if (!(lo < l_obs)) return;
     const float hi = fminf(k.lage_hi[i], l_obs);
-    const float s3 = 3.0f * k.burst_sig;
-    const float u_lo = (lo - mu) / s3, u_hi = (hi - mu) / s3;
+    const float u_lo = (lo - mu) * inv_s3, u_hi = (hi - mu) * inv_s3;
     // the CDF is odd about 1/2: upper-tail bins use 1 - C(u) = C(-u)
     p = (u_lo > 0.0f) ? tri_cdf(-u_lo) - tri_cdf(-u_hi) : tri_cdf(u_hi) - tri_cdf(u_lo);
-    dp = (tri_dcdf(u_lo) - tri_dcdf(u_hi)) / s3;
+    dp = (tri_dcdf(u_lo) - tri_dcdf(u_hi)) * inv_s3;
+}
+
+// first age bin whose upper log-age edge exceeds v (edges increasing, last = +inf)
+__device__ inline int first_bin_above(const DevConsts &k, float v) {
+    int a = 0, b = NA - 1;
+    while (a < b) {
+        const int c = (a + b) >> 1;
+        if (k.lage_hi[c] > v) b = c;
+        else a = c + 1;
+    }
+    return a;
 }
 
 // ------------------------------------------------------------------ metallicity

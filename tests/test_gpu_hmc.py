@@ -105,3 +105,49 @@ def test_full_size_batch_short_run(ctx, orc):
     s_pick = s[:, :, :, pick].transpose(0, 1, 3, 2)
     close = np.all(np.abs(s_pick - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0), axis=-1)
     assert close.mean() >= 0.9
+
+
+def test_metric_adaptation_matches_oracle(ctx, orc):
+    # 20 warm-up iterations: one slow window [3, 18) sets M^-1, dual averaging restarts;
+    # chains that follow the oracle's trajectory draw by draw must end with its M^-1.
+    # One leapfrog step per iteration and a high acceptance target keep FP32 and FP64
+    # trajectories together over the 23 iterations (long trajectories amplify rounding)
+    n, C = 6, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 41, C)
+    kw = dict(n_chain=C, n_leapfrog=1, n_warmup=20, n_sample=3, init_step=0.01, target_accept=0.95, seed=405,
+              adapt_metric=True)
+    out = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)        # [s][c][g][10]
+    same = np.all(np.abs(s_gpu - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0),
+                  axis=(0, -1))                                       # [c][g]
+    assert same.mean() >= 0.6, same
+    mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)       # [c][g][10]
+    assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
+    np.testing.assert_allclose(mi_gpu[same], ref["inv_metric"][same], rtol=2e-3, atol=1e-7)
+    np.testing.assert_allclose(out["step"].cpu().numpy()[same], ref["step"][same], rtol=2e-3)
+
+
+def test_metric_adaptation_off_is_identity(ctx, orc):
+    n, C = 4, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 43, C)
+    kw = dict(n_chain=C, n_leapfrog=5, n_warmup=30, n_sample=4, seed=3, keep_samples=True)
+    a = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, adapt_metric=False, **kw)
+    assert torch.all(a["inv_metric"] == 1.0)
+    b = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, adapt_metric=False, **kw)
+    assert torch.equal(a["samples"], b["samples"])
+
+
+def test_posterior_moments_with_adapted_metric_agree_with_oracle(ctx, orc):
+    n, C = 6, 4
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 51, C)
+    kw = dict(n_chain=C, n_leapfrog=10, n_warmup=200, n_sample=300, seed=8, adapt_metric=True)
+    out = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, **kw)
+    pm, ps = out["post_mean"].cpu().numpy().T, out["post_sd"].cpu().numpy().T
+    scale = np.maximum(ps, ref["post_sd"]) + 1e-6
+    dev_ = np.abs(pm - ref["post_mean"]) / scale
+    assert np.median(dev_) < 0.5 and dev_.max() < 3.0, dev_
+    # adapted step sizes follow the same distribution as the oracle's
+    st, st_ref = out["step"].cpu().numpy(), ref["step"]
+    assert 0.5 < np.median(st) / np.median(st_ref) < 2.0

@@ -541,3 +541,47 @@ def test_hmc_tiny_step_accepts_everything_and_is_deterministic(orc):
     b = orc.hmc_run(1, None, None, None, None, None, None, th0, **kw)
     assert np.all(a["accept"] == 1.0)
     assert np.array_equal(a["samples"], b["samples"])
+
+
+def test_hmc_window_schedule_matches_the_stan_defaults():
+    # the documented defaults: buffers of 75 and 50 around slow windows of 25, 50, 100,
+    # 200 and (stretched to the end of the slow phase) 500 iterations for 1000 warm-up
+    # iterations; 15 % / 75 % / 10 % when the defaults do not fit; none below 20
+    import oracle
+    assert oracle.hmc_windows(1000) == [(75, 100), (100, 150), (150, 250), (250, 450), (450, 950)]
+    assert oracle.hmc_windows(200) == [(75, 100), (100, 150)]
+    assert oracle.hmc_windows(150) == [(75, 100)]
+    assert oracle.hmc_windows(100) == [(15, 90)]
+    assert oracle.hmc_windows(20) == [(3, 18)]
+    assert oracle.hmc_windows(19) == []
+
+
+def test_hmc_metric_adaptation_learns_the_target_variances(orc):
+    # a Gaussian whose scales span three decades: the adapted diagonal M^-1 recovers the
+    # variances (sampling error of a 500-draw window), which lets the step size grow to
+    # the widest direction's scale while the moments stay right.  Once preconditioned the
+    # target is near-isotropic with orbit period 2 pi; 7 steps of ~0.65 keep the
+    # trajectory length away from that period (10 steps of ~0.7 nearly return to start)
+    sd = np.array([0.01, 0.03, 0.1, 0.3, 1.0, 3.0, 10.0, 0.05, 0.5, 5.0])
+    prec = np.diag(1 / sd ** 2)
+    th0 = np.random.default_rng(12).normal(size=(4, 2, 10)) * sd
+    kw = dict(n_chain=4, n_leapfrog=7, n_warmup=1000, n_sample=1000, seed=21, gauss_prec=prec)
+    ad = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric=True, **kw)
+    ratio = ad["inv_metric"] / sd ** 2
+    assert np.all((ratio > 0.5) & (ratio < 2.0)), ratio
+    assert np.all(ad["step"] > 0.3)
+    np.testing.assert_allclose(ad["post_sd"] / sd, 1.0, atol=0.2)
+    assert np.all(ad["rhat"] < 1.05)
+    ident = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric=False, **kw)
+    assert np.all(ident["inv_metric"] == 1.0)
+    assert np.all(ident["step"] < 0.05)
+
+
+def test_hmc_metric_adaptation_off_below_twenty_warmup_iterations(orc):
+    prec = np.diag(1 / GAUSS_SD ** 2)
+    th0 = np.random.default_rng(13).normal(size=(2, 2, 10))
+    kw = dict(n_chain=2, n_warmup=19, n_sample=20, seed=5, gauss_prec=prec, keep_samples=True)
+    a = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric=True, **kw)
+    b = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric=False, **kw)
+    assert np.array_equal(a["samples"], b["samples"])
+    assert np.all(a["inv_metric"] == 1.0)
