@@ -5,8 +5,11 @@
 //   flux_b = K(z) M F_att(lambda_eff,b / (1+z)) sum_j P_Z(j) sum_i P_age(i) Qz[b][j][i],
 //   Qz = (1-f) Q[k] + f Q[k+1]   (linear interpolation of the c_SSP table in z).
 // Galaxies are ordered by z bucket first (counting sort), so the lanes of a
-// wave share the table slices Q[k], Q[k+1]; their rows are read through the
-// scalar cache (wave-uniform addresses) and feed the FMAs as SGPR operands.
+// wave share the table slices Q[k], Q[k+1] and the two contractions over the
+// table run as small wave-wide GEMMs on the matrix cores.  The sort also
+// gathers each galaxy's inputs into a 128-byte record in that order, so the
+// kernel reads them coalesced; results are written in the same order and put
+// back into the caller's order by a coalescing pass.
 #include "sps_eval.h"
 
 namespace sps {
@@ -55,11 +58,13 @@ __global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restr
     if (t < nb) cursor[t] = s[t] - ((t < nb) ? hist[t] : 0);
 }
 
-// each block reserves a range per bucket in the global cursor, then places its galaxies
+// each block reserves a range per bucket in the global cursor, then places its galaxies;
+// with ga.rec set it also writes each galaxy's input record at its new position
 __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
-                                                              int *__restrict__ cursor, int *__restrict__ perm) {
+                                                              int *__restrict__ cursor, int *__restrict__ perm,
+                                                              GatherArgs ga) {
     extern __shared__ int sh[];
-    const int nbk = k.n_z;
+    const int nbk = k.n_z, nb = k.n_band;
     int *cnt = sh, *pos = sh + nbk;
     for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
     __syncthreads();
@@ -80,24 +85,39 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
     __syncthreads();
     for (int t = 0; t < SORT_PER_THREAD; ++t) {
         const int i = base + t * SORT_BLOCK + threadIdx.x;
-        if (kk_t[t] >= 0) perm[atomicAdd(&pos[kk_t[t]], 1)] = i;
+        if (kk_t[t] < 0) continue;
+        const int at = atomicAdd(&pos[kk_t[t]], 1);
+        perm[at] = i;
+        if (!ga.rec) continue;
+        float r[REC];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) r[p] = ga.params[(size_t)p * n + i];
+        r[REC_Z] = z[i];
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b) {
+            r[REC_OBS + b] = (ga.obs && b < nb) ? ga.obs[(size_t)i * nb + b] : 0.0f;
+            r[REC_SIG + b] = (ga.sigma && b < nb) ? ga.sigma[(size_t)i * nb + b] : 1.0f;
+        }
+        r[REC_MASK] = __int_as_float(ga.mask ? (int)ga.mask[i] : 0xff);
+        r[REC_ORIG] = __int_as_float(i);
+#pragma unroll
+        for (int q = REC_ORIG + 1; q < REC; ++q) r[q] = 0.0f;
+        v4f *dst = (v4f *)(ga.rec + (size_t)at * REC);
+#pragma unroll
+        for (int q = 0; q < REC / 4; ++q) dst[q] = v4f{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
+        ga.inv[i] = at;
     }
 }
 
 // ------------------------------------------------------------------ the one-shot kernel
 struct ApproxArgs {
     int n, sfh, mode;
-    const float *params;      // [10][n] physical (or unbounded x for MODE_LOGPOST_GRAD)
-    const float *z;
-    const float *obs, *sigma; // [n][nb]
-    const uint8_t *mask;
+    const float *rec;         // input records in z-bucket order (params physical, or unbounded x
+                              // for MODE_LOGPOST_GRAD)
     const float *bounds;      // [10][4]
     const float *prior;       // [10][3]
-    const int *perm;
-    const float *q;           // z table
-    float *mag;               // [n][nb]
-    float *val;               // [n]
-    float *grad;              // [10][n]
+    const float *qf, *qa;     // z table in fragment order (forward, adjoint contraction)
+    float *orec;              // output records in z-bucket order
 };
 
 template <int MODE>
@@ -106,19 +126,26 @@ __global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
-    const int g = a.perm[valid ? idx : a.n - 1];
-    const int n = a.n, nb = k.n_band;
-    LdsCol col{lds + lane};
-
+    float r[REC];
+    {
+        const v4f *src = (const v4f *)(a.rec + (size_t)(valid ? idx : a.n - 1) * REC);
+#pragma unroll
+        for (int q = 0; q < REC / 4; ++q) {
+            const v4f v = src[q];
+            r[4 * q] = v[0];
+            r[4 * q + 1] = v[1];
+            r[4 * q + 2] = v[2];
+            r[4 * q + 3] = v[3];
+        }
+    }
     float th[NP], x[NP], dth[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) x[p] = a.params[(size_t)p * n + g];
-#pragma unroll
     for (int p = 0; p < NP; ++p) {
+        x[p] = r[p];
         if (MODE == MODE_LOGPOST_GRAD) bound_param(a.bounds + 4 * p, x[p], th[p], dth[p]);
         else th[p] = x[p];
     }
-    const float zf = a.z[g];
+    const float zf = r[REC_Z];
     float f;
     int kk = z_bucket(k, zf, &f);
     if (!valid) kk = -1;
@@ -126,22 +153,21 @@ __global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
     const double m0 = mag_offset(k, (double)zf) - 2.5 * (double)th[0];
     const int kmin = wave_min_i(kk < 0 ? 1 << 30 : kk);
     const int kmax = wave_max_i(kk);
-    const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : a.mask[g];
-    const float *obs_g = (MODE == MODE_MAGS) ? nullptr : a.obs + (size_t)g * nb;
-    const float *sig_g = (MODE == MODE_MAGS) ? nullptr : a.sigma + (size_t)g * nb;
-    float mags[NB_MAX], gr[NP];
+    const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : (uint32_t)__float_as_int(r[REC_MASK]);
+    float mags[NB_MAX] = {}, gr[NP];
     double logl;
     constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
-    approx_eval<EM>(k, a.sfh, (cfloat *)a.q, col, th, zf, kk, f, t_obs, m0, kmin, kmax, obs_g, sig_g, mask,
-                    mags, logl, gr);
+    approx_eval<EM>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, r + REC_OBS, r + REC_SIG,
+                    mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
+    v4f *dst = (v4f *)(a.orec + (size_t)idx * OREC);
     if (MODE == MODE_MAGS) {
-#pragma unroll
-        for (int b = 0; b < NB_MAX; ++b)
-            if (b < nb) a.mag[(size_t)g * nb + b] = mags[b] + bad;
+        dst[0] = v4f{mags[0] + bad, mags[1] + bad, mags[2] + bad, mags[3] + bad};
+        dst[1] = v4f{mags[4] + bad, mags[5] + bad, mags[6] + bad, mags[7] + bad};
         return;
     }
+    float val = (float)logl;
     if (MODE == MODE_LOGPOST_GRAD) {
         double lp = logl;
 #pragma unroll
@@ -150,15 +176,34 @@ __global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
             lp += log_prior_skewnorm(a.prior + 3 * p, x[p], dlp);
             gr[p] = fmaf(gr[p], dth[p], dlp);
         }
-        a.val[g] = (float)lp + bad;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) a.grad[(size_t)p * n + g] = gr[p] + bad;
+        val = (float)lp;
+    }
+    if (MODE == MODE_LOGL) {
+        dst[0] = v4f{val + bad, 0.f, 0.f, 0.f};
         return;
     }
-    a.val[g] = (float)logl + bad;
-    if (MODE == MODE_LOGL_GRAD) {
+    dst[0] = v4f{val + bad, gr[0] + bad, gr[1] + bad, gr[2] + bad};
+    dst[1] = v4f{gr[3] + bad, gr[4] + bad, gr[5] + bad, gr[6] + bad};
+    dst[2] = v4f{gr[7] + bad, gr[8] + bad, gr[9] + bad, 0.f};
+}
+
+// results back into the caller's order: thread i reads its galaxy's record (one line)
+// and writes coalesced outputs
+template <int MODE>
+__global__ void __launch_bounds__(256) k_unpermute(int n, int nb, const int *__restrict__ inv,
+                                                   const float *__restrict__ orec, float *__restrict__ mag,
+                                                   float *__restrict__ val, float *__restrict__ grad) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float *o = orec + (size_t)inv[i] * OREC;
+    if (MODE == MODE_MAGS) {
+        for (int b = 0; b < nb; ++b) mag[(size_t)i * nb + b] = o[b];
+        return;
+    }
+    val[i] = o[0];
+    if (MODE != MODE_LOGL && grad) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) a.grad[(size_t)p * n + g] = gr[p] + bad;
+        for (int p = 0; p < NP; ++p) grad[(size_t)p * n + i] = o[1 + p];
     }
 }
 
@@ -178,7 +223,9 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
     const double t_obs = age_universe_gyr(k, (double)z[gg]);
     float pa[NA], pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pa, pz, ws);
+    forward_weights(k, sfh, th, t_obs, col, pz, ws);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) pa[i] = col[i];
     const float mass = exp10f(th[0]);
     if (!valid) return;
     float *out = w + (size_t)g * NZ * NA;
@@ -191,15 +238,16 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z) {
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga) {
     const int nbk = c->k.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
     int *hist = c->d_hist, *cursor = c->d_hist + 1025;
     hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
     const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
     hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, c->k, n, z, hist);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
+    const GatherArgs none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, c->k, n, z, cursor,
-                       c->d_perm);
+                       c->d_perm, ga ? *ga : none);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }
@@ -207,16 +255,34 @@ int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z) {
 int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const float *params, const float *z,
                   const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                   const float *prior, float *out_mag, float *out_val, float *out_grad) {
-    int rc = launch_bucket_sort(c, s, n, z);
+    const GatherArgs ga{params, mode == MODE_MAGS ? nullptr : obs, mode == MODE_MAGS ? nullptr : sigma,
+                        mode == MODE_MAGS ? nullptr : mask, c->d_rec, c->d_inv};
+    int rc = launch_bucket_sort(c, s, n, z, &ga);
     if (rc) return rc;
-    ApproxArgs a{n, sfh, mode, params, z, obs, sigma, mask, bounds, prior, c->d_perm, c->d_q,
-                 out_mag, out_val, out_grad};
-    dim3 grid((n + WAVE - 1) / WAVE), block(WAVE);
+    ApproxArgs a{n, sfh, mode, c->d_rec, bounds, prior, c->d_qf, c->d_qa, c->d_orec};
+    const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE), ug((n + 255) / 256), ub(256);
+    const int nb = c->n_band;
     switch (mode) {
-        case MODE_MAGS: hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, 0, s, c->k, a); break;
-        case MODE_LOGL: hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, 0, s, c->k, a); break;
-        case MODE_LOGL_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, 0, s, c->k, a); break;
-        case MODE_LOGPOST_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, 0, s, c->k, a); break;
+        case MODE_MAGS:
+            hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
+                               out_grad);
+            break;
+        case MODE_LOGL:
+            hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
+                               out_grad);
+            break;
+        case MODE_LOGL_GRAD:
+            hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
+                               out_val, out_grad);
+            break;
+        case MODE_LOGPOST_GRAD:
+            hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
+                               out_val, out_grad);
+            break;
         default: return set_error(SPS_E_INVAL, "bad approx mode");
     }
     SPS_HIP(hipGetLastError());

@@ -115,6 +115,28 @@ __global__ void __launch_bounds__(256) k_ztable(int n_ssp, int nkb, int nw, cons
     }
 }
 
+// fragment-order copies of the z table (layouts in sps_internal.h); one thread per float
+__global__ void __launch_bounds__(256) k_qswizzle(int n_z, int R, int nrb, const float *__restrict__ q,
+                                                  float *__restrict__ qf, float *__restrict__ qa) {
+    const size_t per_node = (size_t)nrb * QF_NODE_PER_NRB;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)n_z * per_node) return;
+    const int node = (int)(t / per_node);
+    const int rem = (int)(t % per_node);
+    const int e = rem & 3, lane = (rem >> 2) & 63, blk = rem >> 8;   // blk = outer * kq_count + kq
+    const float *qn = q + (size_t)node * R * NA;
+    {   // forward: blk = nb * AGE_BLK + kq
+        const int nb = blk / AGE_BLK, kq = blk % AGE_BLK;
+        const int r = 16 * nb + (lane & 15), i = 16 * kq + 4 * e + (lane >> 4);
+        qf[t] = (r < R && i < NA) ? qn[(size_t)r * NA + i] : 0.0f;
+    }
+    {   // adjoint: blk = na * nrb + kq
+        const int na = blk / nrb, kq = blk % nrb;
+        const int r = 16 * kq + 4 * e + (lane >> 4), i = 16 * na + (lane & 15);
+        qa[t] = (r < R && i < NA) ? qn[(size_t)r * NA + i] : 0.0f;
+    }
+}
+
 int launch_ztable(sps_ctx *c, hipStream_t st) {
     const int nb = c->n_band, nw = c->n_wave, nkb = c->k.n_z * nb, S = c->n_met * c->n_age;
     double *d_fc = nullptr, *d_fs = nullptr, *d_tw = nullptr;
@@ -128,6 +150,12 @@ int launch_ztable(sps_ctx *c, hipStream_t st) {
     hipLaunchKernelGGL(k_filter_weights, dim3(nkb), dim3(256), 0, st, nb, nw, (double)c->k.z_lo,
                        (double)c->k.dz, d_fc, d_fs, c->d_wave, c->d_trap, d_tw);
     hipLaunchKernelGGL(k_ztable, dim3(S), dim3(256), nw * sizeof(double), st, S, nkb, nw, c->d_lum64, d_tw, c->d_q);
+    {
+        const int nrb = row_blocks(nb);
+        const size_t total = (size_t)c->k.n_z * nrb * QF_NODE_PER_NRB;
+        hipLaunchKernelGGL(k_qswizzle, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, c->k.n_z, nb * NZ,
+                           nrb, c->d_q, c->d_qf, c->d_qa);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d_fc);
@@ -154,7 +182,12 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_trap);
     (void)hipFree(c->d_edges);
     (void)hipFree(c->d_q);
+    (void)hipFree(c->d_qf);
+    (void)hipFree(c->d_qa);
     (void)hipFree(c->d_perm);
+    (void)hipFree(c->d_inv);
+    (void)hipFree(c->d_rec);
+    (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hist);
     (void)hipFree(c->d_work);
     delete c;
@@ -188,9 +221,16 @@ int sps_reserve(sps_ctx *c, int max_gal) {
     if (max_gal <= c->max_gal) return SPS_OK;
     SPS_HIP(hipDeviceSynchronize());
     (void)hipFree(c->d_perm);
-    c->d_perm = nullptr;
+    (void)hipFree(c->d_inv);
+    (void)hipFree(c->d_rec);
+    (void)hipFree(c->d_orec);
+    c->d_perm = c->d_inv = nullptr;
+    c->d_rec = c->d_orec = nullptr;
     c->max_gal = 0;
     SPS_HIP(hipMalloc(&c->d_perm, (size_t)max_gal * sizeof(int)));
+    SPS_HIP(hipMalloc(&c->d_inv, (size_t)max_gal * sizeof(int)));
+    SPS_HIP(hipMalloc(&c->d_rec, (size_t)max_gal * REC * sizeof(float)));
+    SPS_HIP(hipMalloc(&c->d_orec, (size_t)max_gal * OREC * sizeof(float)));
     c->max_gal = max_gal;
     return SPS_OK;
 }
@@ -347,9 +387,14 @@ int sps_build_ztable(sps_ctx *c, int n_z, double z_lo, double z_hi) {
     if (!(z_lo >= 0.0) || !(z_hi > z_lo) || !std::isfinite(z_hi)) return set_error(SPS_E_INVAL, "need 0 <= z_lo < z_hi");
     SPS_HIP(hipDeviceSynchronize());
     (void)hipFree(c->d_q);
-    c->d_q = nullptr;
+    (void)hipFree(c->d_qf);
+    (void)hipFree(c->d_qa);
+    c->d_q = c->d_qf = c->d_qa = nullptr;
     c->k.n_z = 0;
     SPS_HIP(hipMalloc(&c->d_q, (size_t)n_z * c->n_band * NZ * NA * sizeof(float)));
+    const size_t frag = (size_t)n_z * row_blocks(c->n_band) * QF_NODE_PER_NRB * sizeof(float);
+    SPS_HIP(hipMalloc(&c->d_qf, frag));
+    SPS_HIP(hipMalloc(&c->d_qa, frag));
     c->k.z_lo = (float)z_lo;
     c->k.dz = (float)((z_hi - z_lo) / (n_z - 1));
     c->k.n_z = n_z;

@@ -5,10 +5,14 @@
 
 namespace sps {
 
-typedef const float __attribute__((address_space(4))) cfloat;
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
-constexpr int LDS_SLOTS = (NA > NB_MAX * NZ + NB_MAX) ? NA : NB_MAX * NZ + NB_MAX;
+// per-lane LDS column: 96 slots for P_age (padded), the table row sums T, the adjoint
+// row coefficients or dP_age, then two slots for the lane's z-slice weights
+constexpr int SLOT_W = 16 * AGE_BLK;
+constexpr int LDS_SLOTS = SLOT_W + 2;
+static_assert(NB_MAX * NZ <= SLOT_W, "table rows must fit the LDS column");
 
 // ------------------------------------------------------------------ bucket sort
 // bucket of a galaxy: interval k of the z table, or n_z - 1 for z outside the table
@@ -32,8 +36,7 @@ struct LdsCol {
 };
 
 // ------------------------------------------------------------------ forward weights
-// Leaves P_age in registers (pa), P_Z in registers (pz); returns the burst
-// normaliser and the total smooth mass (needed by the adjoint).
+// Returns the burst normaliser and the total smooth mass (needed by the adjoint).
 struct WeightsState {
     double S;      // total smooth mass (FP64 running sum)
     float Zb;      // burst normaliser (1 unless clipped at t_obs)
@@ -41,8 +44,9 @@ struct WeightsState {
     int i0;        // first age bin of the burst window
 };
 
+// P_age is left in the LDS column (slots 0..NA-1), P_Z in registers.
 __device__ inline void forward_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
-                                       LdsCol col, float (&pa)[NA], float (&pz)[NZ], WeightsState &ws) {
+                                       LdsCol col, float (&pz)[NZ], WeightsState &ws) {
     const float t_obs_f = (float)t_obs;
     double S = 0.0;
     if (sfh == SPS_SFH_DPL) {
@@ -79,8 +83,6 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
         burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
         col[i0 + t] = fmaf(bz, p, col[i0 + t]);
     }
-#pragma unroll
-    for (int i = 0; i < NA; ++i) pa[i] = col[i];
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
         float dp;
@@ -163,48 +165,172 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
 }
 
 
+// ------------------------------------------------------------------ contractions on the matrix cores
+// The wave's 64 galaxies are the M dimension of two small GEMMs per z bucket kb (all lanes
+// take part; a galaxy contributes only in its own bucket's pass, with weight (1 - f) on
+// node kb and f on node kb + 1).  v_mfma_f32_16x16x4f32 fragments: lane l supplies
+// A[m = l % 16][k = l / 16] and B[k = l / 16][n = l % 16]; accumulator register j holds
+// D[m = 4 (l / 16) + j][n = l % 16].  A comes from the LDS columns (slot k of galaxy m),
+// B from the fragment-order tables, D goes back to the LDS columns.
+
+// Slice weights of the current pass for the accumulator rows this lane holds: galaxy
+// 16 mb + 4 (l / 16) + j in register j.  A galaxy outside the pass's bucket gets 0.
+__device__ inline void pass_weights(float *wl, int lane, bool act, float f, v4f (&w0)[4], v4f (&w1)[4]) {
+    wl[SLOT_W * WAVE + lane] = act ? 1.0f - f : 0.0f;
+    wl[(SLOT_W + 1) * WAVE + lane] = act ? f : 0.0f;
+    __syncthreads();
+    const int lk = lane >> 4;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        w0[mb] = *(const v4f *)(wl + SLOT_W * WAVE + 16 * mb + 4 * lk);
+        w1[mb] = *(const v4f *)(wl + (SLOT_W + 1) * WAVE + 16 * mb + 4 * lk);
+    }
+}
+
+// out += w0 d0 + w1 d1 row by row; rows with zero weight are left untouched (a NaN
+// product of an inactive galaxy cannot leak in)
+__device__ inline void blend(v4f &out, const v4f &w0, const v4f &d0, const v4f &w1, const v4f &d1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (w0[j] != 0.0f) out[j] = fmaf(w0[j], d0[j], out[j]);
+        if (w1[j] != 0.0f) out[j] = fmaf(w1[j], d1[j], out[j]);
+    }
+}
+
+// One row block (16 output columns) of D_s = A B_s for the galaxy pair of blocks (2h, 2h+1),
+// s = 0, 1 (z nodes kb, kb + 1), K = 16 nk; A from LDS slots 0..16 nk - 1 of those galaxies,
+// B fragments at b0 (node kb) / b1 (node kb + 1), one float4 per k-step group of 4 at
+// stride 256 floats.
+__device__ inline void mfma_block(const float *wl, int lane, int h, int nk, const float *b0, const float *b1,
+                                  size_t kstride, v4f (&d0)[2], v4f (&d1)[2]) {
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) d0[m] = d1[m] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int kq = 0; kq < nk; ++kq) {
+        float a[4][2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) a[e][m] = wl[(16 * kq + 4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
+        const v4f q0 = *(const v4f *)(b0 + kq * kstride);
+        const v4f q1 = *(const v4f *)(b1 + kq * kstride);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                d0[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e][m], q0[e], d0[m], 0, 0, 0);
+                d1[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e][m], q1[e], d1[m], 0, 0, 0);
+            }
+    }
+}
+
+// T[g][r] = (1 - f) sum_i P_age[g][i] Qk[r][i] + f sum_i P_age[g][i] Qk+1[r][i]; P_age in
+// slots 0..95 (94, 95 zero), T written to slots 0..R-1.  Galaxies 0..31 and 32..63 in
+// turn: a half's row sums overwrite only its own P_age columns.
+__device__ inline void contract_forward(const DevConsts &k, const float *qf, float *wl, int lane, int kk, float f,
+                                        int kmin, int kmax) {
+    const int nrb = row_blocks(k.n_band), R = k.n_band * NZ;
+    const int li = lane & 15, lk = lane >> 4;
+    const size_t node = (size_t)nrb * QF_NODE_PER_NRB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        v4f out[6][2];
+#pragma unroll
+        for (int nb = 0; nb < 6; ++nb)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) out[nb][m] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int kb = kmin; kb <= kmax; ++kb) {
+            const bool act = (kk == kb);
+            if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
+            v4f w0[4], w1[4];
+            pass_weights(wl, lane, act, f, w0, w1);
+            const float *b0 = qf + (size_t)kb * node + lane * 4;
+#pragma unroll
+            for (int nb = 0; nb < 6; ++nb) {
+                if (nb >= nrb) break;
+                v4f d0[2], d1[2];
+                const float *bb = b0 + (size_t)nb * AGE_BLK * 256;
+                mfma_block(wl, lane, h, AGE_BLK, bb, bb + node, 256, d0, d1);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) blend(out[nb][m], w0[2 * h + m], d0[m], w1[2 * h + m], d1[m]);
+            }
+            __syncthreads();   // the next pass rewrites the weight slots
+        }
+#pragma unroll
+        for (int nb = 0; nb < 6; ++nb)
+            if (nb < nrb && 16 * nb + li < R) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    *(v4f *)(wl + (16 * nb + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = out[nb][m];
+            }
+        __syncthreads();
+    }
+}
+
+// dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..16 NRB - 1
+// (zero from R on), dP_age written to slots 0..NA-1.  Galaxy halves as above.
+__device__ inline void contract_adjoint(const DevConsts &k, const float *qa, float *wl, int lane, int kk, float f,
+                                        int kmin, int kmax) {
+    const int nrb = row_blocks(k.n_band);
+    const int li = lane & 15, lk = lane >> 4;
+    const size_t node = (size_t)nrb * QF_NODE_PER_NRB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        v4f out[6][2];
+#pragma unroll
+        for (int na = 0; na < 6; ++na)
+#pragma unroll
+            for (int m = 0; m < 2; ++m) out[na][m] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int kb = kmin; kb <= kmax; ++kb) {
+            const bool act = (kk == kb);
+            if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
+            v4f w0[4], w1[4];
+            pass_weights(wl, lane, act, f, w0, w1);
+            const float *b0 = qa + (size_t)kb * node + lane * 4;
+#pragma unroll
+            for (int na = 0; na < 6; ++na) {
+                v4f d0[2], d1[2];
+                const float *bb = b0 + (size_t)na * nrb * 256;
+                mfma_block(wl, lane, h, nrb, bb, bb + node, 256, d0, d1);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) blend(out[na][m], w0[2 * h + m], d0[m], w1[2 * h + m], d1[m]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int na = 0; na < 6; ++na)
+            if (16 * na + li < NA) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    *(v4f *)(wl + (16 * na + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = out[na][m];
+            }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ one evaluation
 // Magnitudes (MODE_MAGS) or log-likelihood with its gradient w.r.t. the physical
-// parameters (MODE_LOGL_GRAD) for the lane's galaxy.  Every lane of the wave
-// must call it (the z-bucket loop is wave-uniform); lanes with kk < 0 take part
-// without contributing.  kmin/kmax: wave-uniform range of the lanes' buckets.
+// parameters (MODE_LOGL_GRAD) for the lane's galaxy.  Every lane of the (single-wave)
+// workgroup must call it: the contractions are wave-wide and synchronise the workgroup.
+// Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
+// the lanes' buckets.  wl: the wave's LDS block (LDS_SLOTS x 64 floats).
 template <int MODE>
-__device__ inline void approx_eval(const DevConsts &k, int sfh, cfloat *qc, LdsCol col, const float (&th)[NP],
-                                   float zf, int kk, float f, double t_obs, double m0, int kmin, int kmax,
-                                   const float *obs_g, const float *sig_g, uint32_t mask, float *mag_out,
-                                   double &logl, float (&gr)[NP]) {
+__device__ inline void approx_eval(const DevConsts &k, int sfh, const float *qf, const float *qa, float *wl,
+                                   const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
+                                   int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
+                                   float *mag_out, double &logl, float (&gr)[NP]) {
     const int nb = k.n_band;
-    float pa[NA], pz[NZ];
+    const int lane = threadIdx.x & (WAVE - 1);
+    LdsCol col{wl + lane};
+    float pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pa, pz, ws);
+    forward_weights(k, sfh, th, t_obs, col, pz, ws);
+    col[NA] = 0.0f;
+    col[NA + 1] = 0.0f;
 
     // ---- contraction: T[b][j] = sum_i P_age(i) Qz[b][j][i]
-    const int rows = nb * NZ;
-    for (int kb = kmin; kb <= kmax; ++kb) {
-        const bool act = (kk == kb);
-        if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-        cfloat *q0 = qc + (size_t)kb * rows * NA;
-        cfloat *q1 = q0 + (size_t)rows * NA;
-        for (int r = 0; r < rows; ++r) {
-            cfloat *r0 = q0 + r * NA;
-            cfloat *r1 = q1 + r * NA;
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-#pragma unroll
-            for (int i = 0; i + 3 < NA; i += 4) {
-                a0 = fmaf(pa[i], r0[i], a0); c0 = fmaf(pa[i], r1[i], c0);
-                a1 = fmaf(pa[i + 1], r0[i + 1], a1); c1 = fmaf(pa[i + 1], r1[i + 1], c1);
-                a2 = fmaf(pa[i + 2], r0[i + 2], a2); c2 = fmaf(pa[i + 2], r1[i + 2], c2);
-                a3 = fmaf(pa[i + 3], r0[i + 3], a3); c3 = fmaf(pa[i + 3], r1[i + 3], c3);
-            }
-#pragma unroll
-            for (int i = NA & ~3; i < NA; ++i) {
-                a0 = fmaf(pa[i], r0[i], a0);
-                c0 = fmaf(pa[i], r1[i], c0);
-            }
-            const float t = (1.0f - f) * ((a0 + a1) + (a2 + a3)) + f * ((c0 + c1) + (c2 + c3));
-            if (act) col[r] = t;
-        }
-    }
+    contract_forward(k, qf, wl, lane, kk, f, kmin, kmax);
 
     // ---- magnitudes, likelihood.  The band sums, magnitudes and residuals are formed in
     // FP64 from the FP32 row sums: an FP32 magnitude near 25 carries ~2e-6 of rounding,
@@ -259,30 +385,12 @@ __device__ inline void approx_eval(const DevConsts &k, int sfh, cfloat *qc, LdsC
     }
 #pragma unroll
     for (int b = 0; b < NB_MAX; ++b)
-        if (b < nb) {
 #pragma unroll
-            for (int j = 0; j < NZ; ++j) col[b * NZ + j] = sbar[b] * pz[j];
-        }
+        for (int j = 0; j < NZ; ++j)
+            if (b < nb) col[b * NZ + j] = sbar[b] * pz[j];
+    for (int r = nb * NZ; r < 16 * row_blocks(nb); ++r) col[r] = 0.0f;
     // dP_age(i) = sum_{b,j} sbar_b P_Z(j) Qz[b][j][i]
-    float pbar[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) pbar[i] = 0.0f;
-    for (int kb = kmin; kb <= kmax; ++kb) {
-        const bool act = (kk == kb);
-        if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-        cfloat *q0 = qc + (size_t)kb * rows * NA;
-        cfloat *q1 = q0 + (size_t)rows * NA;
-        for (int r = 0; r < rows; ++r) {
-            cfloat *r0 = q0 + r * NA;
-            cfloat *r1 = q1 + r * NA;
-            const float c = act ? col[r] : 0.0f;
-            const float c0 = (1.0f - f) * c, c1 = f * c;
-#pragma unroll
-            for (int i = 0; i < NA; ++i) pbar[i] = fmaf(c0, r0[i], fmaf(c1, r1[i], pbar[i]));
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NA; ++i) col[i] = pbar[i];
+    contract_adjoint(k, qa, wl, lane, kk, f, kmin, kmax);
     adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);
 }
 

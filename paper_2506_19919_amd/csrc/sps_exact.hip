@@ -315,7 +315,9 @@ __global__ void __launch_bounds__(64) k_exact_weights(DevConsts k, int n, int sf
         const double t_obs = age_universe_gyr(k, (double)((const float *)z_v)[gg]);
         float pa[NA], pz[NZ];
         WeightsState ws;
-        forward_weights(k, sfh, th, t_obs, LdsCol{lds + lane}, pa, pz, ws);
+        forward_weights(k, sfh, th, t_obs, LdsCol{lds + lane}, pz, ws);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) pa[i] = lds[i * 64 + lane];
         if (g >= n) return;
         if constexpr (P == SPS_F32) {
             float *w = (float *)w_hi + (size_t)g * S_PAD;
@@ -443,7 +445,9 @@ __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sf
     const double t_obs = age_universe_gyr(k, (double)z[gg]);
     float pa[NA], pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pa, pz, ws);
+    forward_weights(k, sfh, th, t_obs, col, pz, ws);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) pa[i] = col[i];
     const float *wb = wbar + (size_t)gg * S_PAD;
     float pzbar[NZ];
 #pragma unroll

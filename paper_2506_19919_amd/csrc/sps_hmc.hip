@@ -49,7 +49,7 @@ struct HmcArgs {
     const uint8_t *mask;
     const float *bounds, *prior, *theta0;
     const int *perm;
-    const float *q;
+    const float *qf, *qa;
     float *samples;
     // chain state, indexed by slot = rank * C + chain
     float *x, *gr, *eps, *hbar, *lebar, *mu, *minv;
@@ -65,26 +65,33 @@ struct LaneCtx {
     uint32_t mask;
 };
 
-__device__ inline double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc, LdsCol col,
+__device__ inline double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc, float *wl,
                                 const float (&x)[NP], float (&g)[NP]) {
-    float th[NP], dth[NP];
+    float th[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) bound_param(a.bounds + 4 * p, x[p], th[p], dth[p]);
+    for (int p = 0; p < NP; ++p) {
+        float dth;
+        bound_param(a.bounds + 4 * p, x[p], th[p], dth);
+    }
     const double m0 = lc.m0base - 2.5 * (double)th[0];
     double logl;
     float mags[NB_MAX];
-    approx_eval<MODE_LOGL_GRAD>(k, a.sfh, (cfloat *)a.q, col, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+    approx_eval<MODE_LOGL_GRAD>(k, a.sfh, a.qf, a.qa, wl, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
                                 lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
     double lp = logl;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        float dlp;
+        float dlp, t, dth;
+        bound_param(a.bounds + 4 * p, x[p], t, dth);   // recomputed: not kept live across the model
         lp += log_prior_skewnorm(a.prior + 3 * p, x[p], dlp);
-        g[p] = fmaf(g[p], dth[p], dlp);
+        g[p] = fmaf(g[p], dth, dlp);
     }
     return lp;
 }
 
+// Chain state lives in HBM (SoA [quantity][slot], coalesced across the wave) and is read
+// where it is used, so that only the trajectory (x, p, M^-1 and the scalars of the
+// step-size adaptation) stays in registers across the model evaluations.
 __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     __shared__ float lds[LDS_SLOTS * 64];
     const int lane = threadIdx.x;
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     const int rank = sl / a.C, ch = sl % a.C;
     const int g = a.perm[rank];
     const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
-    LdsCol col{lds + lane};
+#define ST(arr, p) (arr)[(size_t)(p) * nslot + sl]
 
     LaneCtx lc;
     lc.zf = a.z[g];
@@ -109,34 +116,29 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     lc.sig_g = a.sigma + (size_t)g * k.n_band;
     lc.mask = a.mask[g];
 
-    float x[NP], gr[NP], minv[NP], eps, hbar, lebar, mu;
+    float eps, hbar, lebar, mu;
     double lp;
     int nacc, da0;
-    double wmean[NP], wm2[NP];
     if (a.it0 == 0) {
+        float x[NP], gr[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
-        lp = logpost(k, a, lc, col, x, gr);
+        lp = logpost(k, a, lc, lds, x, gr);
         eps = a.init_step;
         mu = logf(10.0f * a.init_step);
-        hbar = 0.0f;
-        lebar = 0.0f;
-        nacc = 0;
-        da0 = 0;
+        hbar = lebar = 0.0f;
+        nacc = da0 = 0;
+        if (valid) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            wmean[p] = wm2[p] = 0.0;
-            minv[p] = 1.0f;
+            for (int p = 0; p < NP; ++p) {
+                ST(a.x, p) = x[p];
+                ST(a.gr, p) = gr[p];
+                ST(a.minv, p) = 1.0f;
+                ST(a.wmean, p) = 0.0;
+                ST(a.wm2, p) = 0.0;
+            }
         }
     } else {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            x[p] = a.x[(size_t)p * nslot + sl];
-            gr[p] = a.gr[(size_t)p * nslot + sl];
-            minv[p] = a.minv[(size_t)p * nslot + sl];
-            wmean[p] = a.wmean[(size_t)p * nslot + sl];
-            wm2[p] = a.wm2[(size_t)p * nslot + sl];
-        }
         lp = a.lp[sl];
         eps = a.eps[sl];
         mu = a.mu[sl];
@@ -147,37 +149,43 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     }
 
     for (int it = a.it0; it < a.it1; ++it) {
-        uint32_t w[12];
+        float p[NP], xn[NP], gn[NP], minv[NP];
 #pragma unroll
-        for (int blk = 0; blk < 3; ++blk) {
-            uint32_t c4[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
-            philox4x32_10(c4, a.key0, a.key1);
+        for (int t = 0; t < NP; ++t) minv[t] = ST(a.minv, t);
+        {
+            uint32_t w[NP];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) w[4 * blk + t] = c4[t];
-        }
-        float p[NP];
+            for (int blk = 0; blk < 3; ++blk) {
+                uint32_t c4[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
+                philox4x32_10(c4, a.key0, a.key1);
 #pragma unroll
-        for (int t = 0; t < NP / 2; ++t) {
-            const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
-            float sn, cs;
-            sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
-            p[2 * t] = r * cs / sqrtf(minv[2 * t]);
-            p[2 * t + 1] = r * sn / sqrtf(minv[2 * t + 1]);
+                for (int t = 0; t < 4; ++t)
+                    if (4 * blk + t < NP) w[4 * blk + t] = c4[t];
+            }
+#pragma unroll
+            for (int t = 0; t < NP / 2; ++t) {
+                const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
+                float sn, cs;
+                sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
+                p[2 * t] = r * cs / sqrtf(minv[2 * t]);
+                p[2 * t + 1] = r * sn / sqrtf(minv[2 * t + 1]);
+            }
         }
         double H0 = -lp;
 #pragma unroll
-        for (int t = 0; t < NP; ++t) H0 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
-        float xn[NP], gn[NP], em[NP];
+        for (int t = 0; t < NP; ++t) {
+            H0 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
+            xn[t] = ST(a.x, t);
+            gn[t] = ST(a.gr, t);
+        }
         double lpn = lp;
-#pragma unroll
-        for (int t = 0; t < NP; ++t) { xn[t] = x[t]; gn[t] = gr[t]; em[t] = eps * minv[t]; }
         for (int l = 0; l < a.L; ++l) {
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 p[t] = fmaf(0.5f * eps, gn[t], p[t]);
-                xn[t] = fmaf(em[t], p[t], xn[t]);
+                xn[t] = fmaf(eps * minv[t], p[t], xn[t]);
             }
-            lpn = logpost(k, a, lc, col, xn, gn);
+            lpn = logpost(k, a, lc, lds, xn, gn);
 #pragma unroll
             for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], p[t]);
         }
@@ -187,11 +195,22 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
         const double dH = H1 - H0;
         const bool divergent = !isfinite(H1) || dH > 1000.0;
         const float alpha = divergent ? 0.0f : (float)fmin(1.0, exp(-dH));
-        const bool acc = !divergent && log(u01d(w[10])) < -dH;
+        uint32_t c4[4] = {2u, (uint32_t)it, chain_id, 0u};   // the accept draw: word 2 of block 2
+        philox4x32_10(c4, a.key0, a.key1);
+        const bool acc = !divergent && log(u01d(c4[2])) < -dH;
+        // xn now holds the chain's position after this iteration
         if (acc) {
-#pragma unroll
-            for (int t = 0; t < NP; ++t) { x[t] = xn[t]; gr[t] = gn[t]; }
             lp = lpn;
+            if (valid) {
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    ST(a.x, t) = xn[t];
+                    ST(a.gr, t) = gn[t];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) xn[t] = ST(a.x, t);
         }
         if (it < a.NW) {
             const float m = (float)(it - da0 + 1), eta = 1.0f / (m + 10.0f);
@@ -205,18 +224,23 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
                 if (it >= a.win_s[q] && it < a.win_e[q]) wi = q;
             if (wi >= 0) {
                 const double nn = (double)(it - a.win_s[wi] + 1);
+                const bool last = (it == a.win_e[wi] - 1);
 #pragma unroll
                 for (int t = 0; t < NP; ++t) {
-                    const double d = (double)x[t] - wmean[t];
-                    wmean[t] += d / nn;
-                    wm2[t] += d * ((double)x[t] - wmean[t]);
-                }
-                if (it == a.win_e[wi] - 1) {
-#pragma unroll
-                    for (int t = 0; t < NP; ++t) {
-                        minv[t] = (float)(nn / (nn + 5.0) * (wm2[t] / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0));
-                        wmean[t] = wm2[t] = 0.0;
+                    double wmean = ST(a.wmean, t), wm2 = ST(a.wm2, t);
+                    const double d = (double)xn[t] - wmean;
+                    wmean += d / nn;
+                    wm2 += d * ((double)xn[t] - wmean);
+                    if (last) {
+                        if (valid) ST(a.minv, t) = (float)(nn / (nn + 5.0) * (wm2 / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0));
+                        wmean = wm2 = 0.0;
                     }
+                    if (valid) {
+                        ST(a.wmean, t) = wmean;
+                        ST(a.wm2, t) = wm2;
+                    }
+                }
+                if (last) {
                     mu = logf(10.0f * eps);
                     hbar = lebar = 0.0f;
                     da0 = it + 1;
@@ -228,24 +252,21 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 float th, dth;
-                bound_param(a.bounds + 4 * t, x[t], th, dth);
-                const double d = (double)th - wmean[t];
-                wmean[t] += d / nrec;
-                wm2[t] += d * ((double)th - wmean[t]);
-                if (a.samples && valid)
-                    a.samples[(((size_t)(it - a.NW) * a.C + ch) * NP + t) * a.n_gal + g] = th;
+                bound_param(a.bounds + 4 * t, xn[t], th, dth);
+                double wmean = ST(a.wmean, t), wm2 = ST(a.wm2, t);
+                const double d = (double)th - wmean;
+                wmean += d / nrec;
+                wm2 += d * ((double)th - wmean);
+                if (valid) {
+                    ST(a.wmean, t) = wmean;
+                    ST(a.wm2, t) = wm2;
+                    if (a.samples) a.samples[(((size_t)(it - a.NW) * a.C + ch) * NP + t) * a.n_gal + g] = th;
+                }
             }
         }
     }
+#undef ST
     if (!valid) return;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        a.x[(size_t)p * nslot + sl] = x[p];
-        a.gr[(size_t)p * nslot + sl] = gr[p];
-        a.minv[(size_t)p * nslot + sl] = minv[p];
-        a.wmean[(size_t)p * nslot + sl] = wmean[p];
-        a.wm2[(size_t)p * nslot + sl] = wm2[p];
-    }
     a.lp[sl] = lp;
     a.eps[sl] = eps;
     a.mu[sl] = mu;
@@ -368,7 +389,8 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.prior = prior;
     a.theta0 = theta0;
     a.perm = c->d_perm;
-    a.q = c->d_q;
+    a.qf = c->d_qf;
+    a.qa = c->d_qa;
     a.samples = samples;
     a.x = fp;
     a.gr = fp + (size_t)NP * nslot;

@@ -17,6 +17,16 @@ constexpr int NB_MAX = SPS_MAX_BAND;
 constexpr int NP = SPS_NPARAM;
 constexpr int NGL_DL = 12;        // half of the 24-point Gauss-Legendre rule for D_L
 
+// Matrix-core fragment tables of the z table (v_mfma_f32_16x16x4f32 B operands).
+// With R = n_band * NZ table rows (r = b * NZ + j) and NRB = ceil(R / 16) row blocks,
+// per z node (node stride QF_NODE(NRB) floats in both):
+//   qf[nb][kq][lane][e] = Q[r = 16 nb + lane % 16][i = 16 kq + 4 e + lane / 16]   nb < NRB, kq < 6
+//   qa[na][kq][lane][e] = Q[r = 16 kq + 4 e + lane / 16][i = 16 na + lane % 16]   na < 6,   kq < NRB
+// zero where r >= R or i >= NA; one float4 per lane covers 4 consecutive k-steps of 4.
+constexpr int AGE_BLK = 6;        // 96 padded ages = 6 blocks of 16
+constexpr int QF_NODE_PER_NRB = AGE_BLK * 64 * 4;
+__host__ __device__ inline int row_blocks(int n_band) { return (n_band * NZ + 15) / 16; }
+
 // Kernel-facing constants, passed by value (kernarg segment).
 struct DevConsts {
     int n_band, n_wave;
@@ -54,9 +64,14 @@ struct sps_ctx {
     double *d_wave = nullptr, *d_trap = nullptr;
     double *d_edges = nullptr;     // FP64 bin edges: age_lo, age_hi [Gyr], lage_lo, lage_hi [NA each], met_lo, met_hi [NZ]
     float *d_q = nullptr;          // [n_z][n_band][n_met][n_age]
+    float *d_qf = nullptr;         // z table in matrix-core fragment order, forward contraction
+    float *d_qa = nullptr;         // z table in matrix-core fragment order, adjoint contraction
     // per-galaxy workspace
     int max_gal = 0;
     int *d_perm = nullptr;         // galaxies ordered by z bucket
+    int *d_inv = nullptr;          // position of each galaxy in that order
+    float *d_rec = nullptr;        // inputs in z-bucket order, one 128-byte record per galaxy
+    float *d_orec = nullptr;       // outputs in z-bucket order, 64 bytes per galaxy
     int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
     void *d_work = nullptr;        // exact-path weights / partial fluxes
     size_t work_bytes = 0;
@@ -73,8 +88,19 @@ int hip_check(hipError_t e, const char *what);
     } while (0)
 
 // launchers (defined in the kernel sources)
-int launch_ztable(sps_ctx *c, hipStream_t s);
-int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z);
+int launch_ztable(sps_ctx *c, hipStream_t s);   // also fills d_qf, d_qa
+// Inputs gathered into z-bucket order by the sort (coalesced reads in the caller's order,
+// one full-line record write per galaxy): record layout, REC floats per galaxy.
+constexpr int REC = 32;
+enum { REC_Z = 10, REC_OBS = 11, REC_SIG = 19, REC_MASK = 27, REC_ORIG = 28 };
+constexpr int OREC = 16;          // output record: mags[8] or (value, grad[10])
+struct GatherArgs {
+    const float *params, *obs, *sigma;  // obs, sigma may be null (magnitudes only)
+    const uint8_t *mask;                // may be null (all bands)
+    float *rec;                         // null: sort only
+    int *inv;
+};
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z, const GatherArgs *ga = nullptr);
 int launch_weights(sps_ctx *c, hipStream_t s, int n_gal, int sfh, const float *params, const float *z,
                    float *w);
 int launch_approx(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int mode, const float *params,
