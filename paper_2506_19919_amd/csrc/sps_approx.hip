@@ -121,16 +121,19 @@ struct ApproxArgs {
 };
 
 template <int MODE>
-__global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
+__global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     __shared__ float lds[LDS_SLOTS * WAVE];
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
-    float r[REC];
+    // parameters, z and mask from the record now; observations and sigma are read from it
+    // where the likelihood needs them (not held in registers through the model)
+    const float *rec = a.rec + (size_t)(valid ? idx : a.n - 1) * REC;
+    float r[12];
     {
-        const v4f *src = (const v4f *)(a.rec + (size_t)(valid ? idx : a.n - 1) * REC);
+        const v4f *src = (const v4f *)rec;
 #pragma unroll
-        for (int q = 0; q < REC / 4; ++q) {
+        for (int q = 0; q < 3; ++q) {
             const v4f v = src[q];
             r[4 * q] = v[0];
             r[4 * q + 1] = v[1];
@@ -153,11 +156,11 @@ __global__ void __launch_bounds__(WAVE) k_approx(DevConsts k, ApproxArgs a) {
     const double m0 = mag_offset(k, (double)zf) - 2.5 * (double)th[0];
     const int kmin = wave_min_i(kk < 0 ? 1 << 30 : kk);
     const int kmax = wave_max_i(kk);
-    const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : (uint32_t)__float_as_int(r[REC_MASK]);
+    const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : (uint32_t)__float_as_int(rec[REC_MASK]);
     float mags[NB_MAX] = {}, gr[NP];
     double logl;
     constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
-    approx_eval<EM>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, r + REC_OBS, r + REC_SIG,
+    approx_eval<EM>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);

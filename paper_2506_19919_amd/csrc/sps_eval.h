@@ -173,17 +173,18 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
 // D[m = 4 (l / 16) + j][n = l % 16].  A comes from the LDS columns (slot k of galaxy m),
 // B from the fragment-order tables, D goes back to the LDS columns.
 
-// Slice weights of the current pass for the accumulator rows this lane holds: galaxy
-// 16 mb + 4 (l / 16) + j in register j.  A galaxy outside the pass's bucket gets 0.
-__device__ inline void pass_weights(float *wl, int lane, bool act, float f, v4f (&w0)[4], v4f (&w1)[4]) {
+// Slice weights of the current pass for the accumulator rows this lane holds in the galaxy
+// half h: galaxy 16 (2h + m) + 4 (l / 16) + j in register j.  A galaxy outside the pass's
+// bucket gets 0.
+__device__ inline void pass_weights(float *wl, int lane, int h, bool act, float f, v4f (&w0)[2], v4f (&w1)[2]) {
     wl[SLOT_W * WAVE + lane] = act ? 1.0f - f : 0.0f;
     wl[(SLOT_W + 1) * WAVE + lane] = act ? f : 0.0f;
     __syncthreads();
     const int lk = lane >> 4;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        w0[mb] = *(const v4f *)(wl + SLOT_W * WAVE + 16 * mb + 4 * lk);
-        w1[mb] = *(const v4f *)(wl + (SLOT_W + 1) * WAVE + 16 * mb + 4 * lk);
+    for (int m = 0; m < 2; ++m) {
+        w0[m] = *(const v4f *)(wl + SLOT_W * WAVE + 16 * (2 * h + m) + 4 * lk);
+        w1[m] = *(const v4f *)(wl + (SLOT_W + 1) * WAVE + 16 * (2 * h + m) + 4 * lk);
     }
 }
 
@@ -206,15 +207,23 @@ __device__ inline void mfma_block(const float *wl, int lane, int h, int nk, cons
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int m = 0; m < 2; ++m) d0[m] = d1[m] = v4f{0.f, 0.f, 0.f, 0.f};
+    // the B fragments of step kq + 1 are in flight while step kq's products issue (the
+    // table comes from L2, whose latency one step of 16 products covers); the scheduling
+    // fence keeps the compiler from hoisting the loads of later blocks (registers)
+    __builtin_amdgcn_sched_barrier(0);
+    v4f n0 = *(const v4f *)b0, n1 = *(const v4f *)b1;
 #pragma unroll 1
     for (int kq = 0; kq < nk; ++kq) {
+        const v4f q0 = n0, q1 = n1;
+        if (kq + 1 < nk) {
+            n0 = *(const v4f *)(b0 + (kq + 1) * kstride);
+            n1 = *(const v4f *)(b1 + (kq + 1) * kstride);
+        }
         float a[4][2];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
             for (int m = 0; m < 2; ++m) a[e][m] = wl[(16 * kq + 4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
-        const v4f q0 = *(const v4f *)(b0 + kq * kstride);
-        const v4f q1 = *(const v4f *)(b1 + kq * kstride);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -243,8 +252,8 @@ __device__ inline void contract_forward(const DevConsts &k, const float *qf, flo
         for (int kb = kmin; kb <= kmax; ++kb) {
             const bool act = (kk == kb);
             if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-            v4f w0[4], w1[4];
-            pass_weights(wl, lane, act, f, w0, w1);
+            v4f w0[2], w1[2];
+            pass_weights(wl, lane, h, act, f, w0, w1);
             const float *b0 = qf + (size_t)kb * node + lane * 4;
 #pragma unroll
             for (int nb = 0; nb < 6; ++nb) {
@@ -253,7 +262,7 @@ __device__ inline void contract_forward(const DevConsts &k, const float *qf, flo
                 const float *bb = b0 + (size_t)nb * AGE_BLK * 256;
                 mfma_block(wl, lane, h, AGE_BLK, bb, bb + node, 256, d0, d1);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) blend(out[nb][m], w0[2 * h + m], d0[m], w1[2 * h + m], d1[m]);
+                for (int m = 0; m < 2; ++m) blend(out[nb][m], w0[m], d0[m], w1[m], d1[m]);
             }
             __syncthreads();   // the next pass rewrites the weight slots
         }
@@ -285,8 +294,8 @@ __device__ inline void contract_adjoint(const DevConsts &k, const float *qa, flo
         for (int kb = kmin; kb <= kmax; ++kb) {
             const bool act = (kk == kb);
             if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-            v4f w0[4], w1[4];
-            pass_weights(wl, lane, act, f, w0, w1);
+            v4f w0[2], w1[2];
+            pass_weights(wl, lane, h, act, f, w0, w1);
             const float *b0 = qa + (size_t)kb * node + lane * 4;
 #pragma unroll
             for (int na = 0; na < 6; ++na) {
@@ -294,7 +303,7 @@ __device__ inline void contract_adjoint(const DevConsts &k, const float *qa, flo
                 const float *bb = b0 + (size_t)na * nrb * 256;
                 mfma_block(wl, lane, h, nrb, bb, bb + node, 256, d0, d1);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) blend(out[na][m], w0[2 * h + m], d0[m], w1[2 * h + m], d1[m]);
+                for (int m = 0; m < 2; ++m) blend(out[na][m], w0[m], d0[m], w1[m], d1[m]);
             }
             __syncthreads();
         }
