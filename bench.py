@@ -126,14 +126,21 @@ def bench_exact(dev, n=4096, steps=5, warmup=2):
     res = {"workload": f"exact photometry value+gradient, {n} galaxies, 1128 SSPs x 5000 wavelengths x 6 bands",
            "unit": "evals/s"}
     gemm_flop = 2.0 * n * 1128 * 5000
+    # dense matrix-core peaks of MI355X: FP32 157.3 TFLOP/s; BF16 2.5 PFLOP/s, of which the
+    # hi/lo split spends three products per algorithmic one
+    peaks = {"f32": (157.3, 1), "bf16x": (2500.0, 3)}
     for name, prec in (("f32", sps.SPS_F32), ("bf16x", sps.SPS_BF16X)):
         fwd = timed(lambda: ctx.phot_exact(synth.SFH_DPL, params, zt, prec=prec), steps, warmup)
         vg = timed(lambda: ctx.loglike_grad(synth.SFH_DPL, params, zt, obs, sigma, mask,
                                             path=sps.SPS_PATH_EXACT, prec=prec), steps, warmup)
+        peak, mult = peaks[name]
         res[name] = {"value_grad_evals_per_s": n / vg, "forward_evals_per_s": n / fwd,
                      "ms_value_grad": vg * 1e3, "ms_forward": fwd * 1e3,
                      "algorithmic_gemm_tflops_forward": gemm_flop / fwd / 1e12,
-                     "algorithmic_gemm_tflops_value_grad": 2 * gemm_flop / vg / 1e12}
+                     "algorithmic_gemm_tflops_value_grad": 2 * gemm_flop / vg / 1e12,
+                     "mfma_peak_tflops": peak,
+                     "executed_frac_of_peak_forward": mult * gemm_flop / fwd / 1e12 / peak,
+                     "executed_frac_of_peak_value_grad": mult * 2 * gemm_flop / vg / 1e12 / peak}
         log(f"[bench]   {name}: fwd {fwd * 1e3:.3f} ms, value+grad {vg * 1e3:.3f} ms")
     ctx.close()
     return res

@@ -296,7 +296,7 @@ class Oracle:
         n_gal = th0.shape[1]
         assert th0.shape == (n_chain, n_gal, N_PARAM)
         cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
-                      int(bool(adapt_metric)))
+                      {False: 0, True: 1, "diag": 1, "dense": 2}[adapt_metric])
         minv = np.zeros((n_chain, n_gal, N_PARAM))
         pm, ps, rh = (np.zeros((n_gal, N_PARAM)) for _ in range(3))
         acc = np.zeros(n_gal)

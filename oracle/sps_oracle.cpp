@@ -820,6 +820,10 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
         // Welford statistics of x inside the current slow window
         double minv[NP], wmu[NP] = {0.0}, wm2[NP] = {0.0};
         for (int k = 0; k < NP; ++k) minv[k] = 1.0;
+        // dense metric (adapt_metric = 2): M^-1 = Mi, Mi = Lc Lc^T, co-moments of the window
+        const bool dense = cfg->adapt_metric == 2;
+        double Mi[NP][NP] = {{0.0}}, Lc[NP][NP] = {{0.0}}, wcm[NP][NP] = {{0.0}};
+        for (int k = 0; k < NP; ++k) Mi[k][k] = Lc[k][k] = 1.0;
         int win = 0;
         double *mean = &cmean[(size_t)cg * NP], *m2 = &cm2[(size_t)cg * NP];
         int n_rec = 0, n_acc = 0;
@@ -836,19 +840,44 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 p[2 * k] = r * std::cos(a) / std::sqrt(minv[2 * k]);
                 p[2 * k + 1] = r * std::sin(a) / std::sqrt(minv[2 * k + 1]);
             }
+            if (dense) {  // p = Lc^-T z solves Lc^T p = z, so that p^T Mi p = |z|^2
+                double zv[NP];
+                for (int k = 0; k < NP; ++k) zv[k] = p[k] * std::sqrt(minv[k]);
+                for (int k = NP - 1; k >= 0; --k) {
+                    double v = zv[k];
+                    for (int j = k + 1; j < NP; ++j) v -= Lc[j][k] * p[j];
+                    p[k] = v / Lc[k][k];
+                }
+            }
+            auto kinetic = [&](const double *q) {
+                double e = 0.0;
+                if (dense) {
+                    for (int i = 0; i < NP; ++i)
+                        for (int j = 0; j < NP; ++j) e += 0.5 * q[i] * Mi[i][j] * q[j];
+                } else {
+                    for (int k = 0; k < NP; ++k) e += 0.5 * minv[k] * q[k] * q[k];
+                }
+                return e;
+            };
             // H = -log p(x) + p^T M^-1 p / 2
-            double H0 = -lp;
-            for (int k = 0; k < NP; ++k) H0 += 0.5 * minv[k] * p[k] * p[k];
+            double H0 = -lp + kinetic(p);
             double xn[NP], pn[NP], grn[NP], lpn = lp;
             for (int k = 0; k < NP; ++k) { xn[k] = x[k]; pn[k] = p[k]; grn[k] = gr[k]; }
             for (int l = 0; l < L; ++l) {  // leapfrog: half kick, drift by M^-1 p, half kick
                 for (int k = 0; k < NP; ++k) pn[k] += 0.5 * eps * grn[k];
-                for (int k = 0; k < NP; ++k) xn[k] += eps * minv[k] * pn[k];
+                if (dense) {
+                    for (int i = 0; i < NP; ++i) {
+                        double v = 0.0;
+                        for (int j = 0; j < NP; ++j) v += Mi[i][j] * pn[j];
+                        xn[i] += eps * v;
+                    }
+                } else {
+                    for (int k = 0; k < NP; ++k) xn[k] += eps * minv[k] * pn[k];
+                }
                 eval(xn, &lpn, grn);
                 for (int k = 0; k < NP; ++k) pn[k] += 0.5 * eps * grn[k];
             }
-            double H1 = -lpn;
-            for (int k = 0; k < NP; ++k) H1 += 0.5 * minv[k] * pn[k] * pn[k];
+            double H1 = -lpn + kinetic(pn);
             double dH = H1 - H0;
             bool divergent = !std::isfinite(H1) || dH > 1000.0;
             double alpha = divergent ? 0.0 : std::min(1.0, std::exp(-dH));
@@ -867,15 +896,40 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                     // slow window: accumulate x; at its end, set M^-1 to the regularised
                     // sample variance and restart dual averaging from the current step
                     const double nn = it - w_start[win] + 1.0;
+                    double d[NP];
                     for (int k = 0; k < NP; ++k) {
-                        double d = x[k] - wmu[k];
-                        wmu[k] += d / nn;
-                        wm2[k] += d * (x[k] - wmu[k]);
+                        d[k] = x[k] - wmu[k];
+                        wmu[k] += d[k] / nn;
+                        wm2[k] += d[k] * (x[k] - wmu[k]);
                     }
+                    if (dense)
+                        for (int i = 0; i < NP; ++i)
+                            for (int j = 0; j < NP; ++j) wcm[i][j] += d[i] * (x[j] - wmu[j]);
                     if (it == w_end[win] - 1) {
                         for (int k = 0; k < NP; ++k) {
                             minv[k] = nn / (nn + 5.0) * (wm2[k] / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0);
                             wmu[k] = wm2[k] = 0.0;
+                        }
+                        if (dense) {
+                            // regularised sample covariance and its Cholesky factor
+                            for (int i = 0; i < NP; ++i)
+                                for (int j = 0; j < NP; ++j) {
+                                    Mi[i][j] = nn / (nn + 5.0) * (wcm[i][j] / (nn - 1.0)) +
+                                               (i == j ? 1e-3 * 5.0 / (nn + 5.0) : 0.0);
+                                    wcm[i][j] = 0.0;
+                                }
+                            for (int j = 0; j < NP; ++j) {
+                                double v = Mi[j][j];
+                                for (int k = 0; k < j; ++k) v -= Lc[j][k] * Lc[j][k];
+                                Lc[j][j] = std::sqrt(v);
+                                for (int i = j + 1; i < NP; ++i) {
+                                    double u = Mi[i][j];
+                                    for (int k = 0; k < j; ++k) u -= Lc[i][k] * Lc[j][k];
+                                    Lc[i][j] = u / Lc[j][j];
+                                }
+                            }
+                            // the momentum scaling above then uses unit variances
+                            for (int k = 0; k < NP; ++k) minv[k] = 1.0;
                         }
                         mu = std::log(10.0 * eps);
                         hbar = leps_bar = 0.0;
@@ -896,7 +950,7 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             if (trace_logp) trace_logp[((size_t)it * C + ch) * n_gal + g] = lp;
         }
         if (inv_metric)
-            for (int k = 0; k < NP; ++k) inv_metric[(size_t)cg * NP + k] = minv[k];
+            for (int k = 0; k < NP; ++k) inv_metric[(size_t)cg * NP + k] = dense ? Mi[k][k] : minv[k];
         cacc[cg] = n_acc;
         if (step) step[cg] = eps;
     }

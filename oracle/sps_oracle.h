@@ -118,7 +118,7 @@ typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     double target_accept, init_step;
     uint64_t seed;
-    int adapt_metric;   /* 0: identity mass matrix; 1: diagonal, adapted in slow windows */
+    int adapt_metric;   /* 0: identity mass matrix; 1: diagonal, 2: dense, adapted in slow windows */
 } orc_hmc_cfg;
 
 /* Slow adaptation windows of a warm-up of n_warmup iterations: window w covers
@@ -137,7 +137,7 @@ int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end);
  * then the physical map is the identity).
  * gal_id (may be NULL): global galaxy indices when these galaxies are a subset of a batch of
  * n_gal_total galaxies; the Philox chain id is then chain * n_gal_total + gal_id[g].
- * inv_metric [c][g][10] (may be NULL): diagonal inverse mass matrix after warm-up. */
+ * inv_metric [c][g][10] (may be NULL): diagonal of the inverse mass matrix after warm-up. */
 int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                 int n_z, double z_lo, double z_hi, const double *q, int sfh,
                 const orc_hmc_cfg *cfg, int n_gal, const double *z, const double *obs,

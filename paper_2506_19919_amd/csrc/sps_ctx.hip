@@ -175,9 +175,13 @@ void free_ctx(sps_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipFree(c->d_lum64);
-    (void)hipFree(c->d_lum32);
-    (void)hipFree(c->d_lum_hi);
-    (void)hipFree(c->d_lum_lo);
+    (void)hipFree(c->d_ls32);
+    (void)hipFree(c->d_lt32);
+    (void)hipFree(c->d_ls_hi);
+    (void)hipFree(c->d_ls_lo);
+    (void)hipFree(c->d_lt_hi);
+    (void)hipFree(c->d_lt_lo);
+    (void)hipFree(c->d_wc);
     (void)hipFree(c->d_wave);
     (void)hipFree(c->d_trap);
     (void)hipFree(c->d_edges);
@@ -356,20 +360,46 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
     if ((rc = upload((void **)&c->d_wave, c->h_wave.data(), nw * sizeof(double)))) return fail(rc);
     if ((rc = upload((void **)&c->d_trap, c->h_trap.data(), nw * sizeof(double)))) return fail(rc);
     if ((rc = upload((void **)&c->d_edges, edges.data(), edges.size() * sizeof(double)))) return fail(rc);
+    // matrix-core copies of the SSP table (see sps_internal.h), zero padded
+    const int lw = (nw + 127) / 128 * 128;
+    c->lw = lw;
+    const size_t np = (size_t)S_PAD * lw;
     if (prec_mask & (1u << SPS_F32)) {
-        std::vector<float> v(nl);
-        for (size_t i = 0; i < nl; ++i) v[i] = (float)ssp->lum[i];
-        if ((rc = upload((void **)&c->d_lum32, v.data(), nl * sizeof(float)))) return fail(rc);
+        std::vector<float> ls(np, 0.0f), lt(np, 0.0f);
+        for (size_t s = 0; s < S; ++s)
+            for (int l = 0; l < nw; ++l) {
+                const float f = (float)ssp->lum[s * nw + l];
+                ls[s * lw + l] = f;
+                lt[(size_t)l * S_PAD + s] = f;
+            }
+        if ((rc = upload((void **)&c->d_ls32, ls.data(), np * sizeof(float)))) return fail(rc);
+        if ((rc = upload((void **)&c->d_lt32, lt.data(), np * sizeof(float)))) return fail(rc);
     }
     if (prec_mask & (1u << SPS_BF16X)) {
-        std::vector<uint16_t> hi(nl), lo(nl);
-        for (size_t i = 0; i < nl; ++i) {
-            float f = (float)ssp->lum[i];
-            hi[i] = bf16_rne(f);
-            lo[i] = bf16_rne(f - bf16_to_f(hi[i]));
+        std::vector<uint16_t> ls_h(np, 0), ls_l(np, 0), lt_h(np, 0), lt_l(np, 0);
+        for (size_t s = 0; s < S; ++s)
+            for (int l = 0; l < nw; ++l) {
+                const float f = (float)ssp->lum[s * nw + l];
+                const uint16_t h = bf16_rne(f), lo = bf16_rne(f - bf16_to_f(h));
+                ls_h[s * lw + l] = h;
+                ls_l[s * lw + l] = lo;
+                lt_h[(size_t)l * S_PAD + s] = h;
+                lt_l[(size_t)l * S_PAD + s] = lo;
+            }
+        if ((rc = upload((void **)&c->d_ls_hi, ls_h.data(), np * 2))) return fail(rc);
+        if ((rc = upload((void **)&c->d_ls_lo, ls_l.data(), np * 2))) return fail(rc);
+        if ((rc = upload((void **)&c->d_lt_hi, lt_h.data(), np * 2))) return fail(rc);
+        if ((rc = upload((void **)&c->d_lt_lo, lt_l.data(), np * 2))) return fail(rc);
+    }
+    {
+        std::vector<float> wc((size_t)lw * 4, 0.0f);
+        for (int l = 0; l < nw; ++l) {
+            const double lam = c->h_wave[l], q = c->h_trap[l];
+            wc[4 * l] = (float)std::log(lam / 5500.0);
+            wc[4 * l + 1] = (float)(lam * q);
+            wc[4 * l + 2] = (float)(q / lam);
         }
-        if ((rc = upload((void **)&c->d_lum_hi, hi.data(), nl * 2))) return fail(rc);
-        if ((rc = upload((void **)&c->d_lum_lo, lo.data(), nl * 2))) return fail(rc);
+        if ((rc = upload((void **)&c->d_wc, wc.data(), wc.size() * sizeof(float)))) return fail(rc);
     }
     if (hipMalloc(&c->d_hist, 2 * 1025 * sizeof(int)) != hipSuccess)
         return fail(set_error(SPS_E_NOMEM, "workspace allocation failed"));

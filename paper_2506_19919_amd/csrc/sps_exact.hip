@@ -60,7 +60,7 @@ struct FiltConst {
 };
 
 constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
-constexpr int S_PAD = round_up(NSSP, 64);   // 1152: multiple of every BK and of BN
+static_assert(S_PAD % 128 == 0 && S_PAD >= NSSP, "SSP padding");
 
 struct GemmArgs {
     int M, N, K_valid, K_pad;
@@ -246,6 +246,216 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
                 if (b >= a.n_band) break;
 #pragma unroll
                 for (int q = 0; q < NPB; ++q) out[q * a.n_band + b] = acc_p[b][q];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ FP32 / BF16-split GEMM (gfx950)
+// C = A . B^T with A [M][K] and B [N][K], both k-contiguous (row strides lda, ldb), K a
+// multiple of 32, N a multiple of 128, A allocated to a multiple of 128 rows.  Block tile
+// 128 x 128, 256 threads as 2 x 2 waves of 64 x 64 (4 x 4 MFMA tiles of 16 x 16); k-tiles
+// of 32 staged through LDS with double buffering (the next tile's global loads are in
+// flight while the current tile's products issue).  LDS rows are 144 bytes: 32 FP32, or
+// 32 BF16 hi then 32 BF16 lo, then padding.
+//   FP32: v_mfma_f32_16x16x4f32.  The four k-slots of one product are taken as
+//         k = 4 (l / 16) + s in step s, so one 16-byte LDS read per lane feeds four steps.
+//   BF16X: v_mfma_f32_16x16x32_bf16, lane l supplying k = 8 (l / 16) .. + 7; three products
+//         lo.hi + hi.lo + hi.hi per tile pair, FP32 accumulation.
+// Blocks are mapped XCD-aware: consecutive dispatch slots go round-robin over the 8 XCDs, so
+// slot b is remapped to tile (b % 8) * T / 8 + b / 8 and each XCD works through one
+// contiguous run of tiles, M fastest (its A rows stay in that XCD's L2).
+constexpr int XBM = 128, XBN = 128, XBK = 32, XROW = 144;   // XROW in bytes
+constexpr int XSTAGE = (XBM + XBN) * XROW;                   // 36,864 bytes per stage
+
+struct XArgs {
+    int M, N, K;
+    const void *A_hi, *A_lo;
+    int lda;
+    const void *B_hi, *B_lo;
+    int ldb;
+    int n_mt, n_nt;
+    float *C;                  // EPI_STORE: [M][ldc], columns < n_store
+    int ldc, n_store;
+    const float *params, *z;   // photometry epilogue
+    const double *wave;
+    const float *wc;           // [N][4]: ln(l / 5500), l q, q / l
+    int n_wave, n_band;
+    double fc[NB_MAX], inv_fs[NB_MAX];
+    float *part;               // [n_nt][M][npart]
+    int npart;
+};
+
+template <int P>
+__device__ inline void x_load(const XArgs &a, int tile_m, int tile_n, int k0, int tid, v4f (&r)[8]) {
+    // 8 chunks of 16 bytes per thread: chunks 0..3 of A, 4..7 of B; chunk c of an operand
+    // tile covers row (tid + 256 c) / 8 ... see x_store for the matching placement
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int e = tid + 256 * (c & 3);      // 0..1023 within the operand tile
+        const int row = e >> 3, q = e & 7;       // 8 chunks of 16 B per row
+        const bool isA = c < 4;
+        const int ld = isA ? a.lda : a.ldb;
+        const size_t grow = (size_t)(isA ? tile_m : tile_n) + row;
+        if constexpr (P == SPS_F32) {
+            const float *base = (const float *)(isA ? a.A_hi : a.B_hi);
+            r[c] = *(const v4f *)(base + grow * ld + k0 + 4 * q);
+        } else {
+            // q < 4: hi, 8 bf16 each; q >= 4: lo
+            const uint16_t *base = (const uint16_t *)(q < 4 ? (isA ? a.A_hi : a.B_hi) : (isA ? a.A_lo : a.B_lo));
+            r[c] = *(const v4f *)(base + grow * ld + k0 + 8 * (q & 3));
+        }
+    }
+}
+
+__device__ inline void x_store(char *stage, int tid, const v4f (&r)[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int e = tid + 256 * (c & 3);
+        const int row = e >> 3, q = e & 7;
+        const int orow = (c < 4) ? row : XBM + row;
+        *(v4f *)(stage + orow * XROW + 16 * q) = r[c];
+    }
+}
+
+template <int P, int EPI>
+__global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * XSTAGE];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    // XCD-aware tile order
+    const int T = a.n_mt * a.n_nt, b = blockIdx.x;
+    int t = b;
+    if (T % 8 == 0) t = (b % 8) * (T / 8) + b / 8;
+    const int tile_m = (t % a.n_mt) * XBM, tile_n = (t / a.n_mt) * XBN;
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = a.K / XBK;
+    v4f r[8];
+    x_load<P>(a, tile_m, tile_n, 0, tid, r);
+    x_store(smem, tid, r);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        char *cur = smem + (kt & 1) * XSTAGE;
+        if (kt + 1 < nk) x_load<P>(a, tile_m, tile_n, (kt + 1) * XBK, tid, r);
+        const char *As = cur, *Bs = cur + XBM * XROW;
+        if constexpr (P == SPS_F32) {
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {   // two groups of 16 k
+                v4f af[4], bf[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    af[i] = *(const v4f *)(As + (wm * 64 + i * 16 + li) * XROW + 64 * g + 16 * lk);
+                    bf[i] = *(const v4f *)(Bs + (wn * 64 + i * 16 + li) * XROW + 64 * g + 16 * lk);
+                }
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][st], bf[j][st], acc[i][j], 0, 0, 0);
+            }
+        } else {
+            b8v ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const char *ar = As + (wm * 64 + i * 16 + li) * XROW + 16 * lk;
+                const char *br = Bs + (wn * 64 + i * 16 + li) * XROW + 16 * lk;
+                ah[i] = *(const b8v *)ar;
+                al[i] = *(const b8v *)(ar + 64);
+                bh[i] = *(const b8v *)br;
+                bl[i] = *(const b8v *)(br + 64);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        if (kt + 1 < nk) x_store(smem + ((kt + 1) & 1) * XSTAGE, tid, r);
+        __syncthreads();
+    }
+
+    if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int m = tile_m + wm * 64 + i * 16 + 4 * lk + q;
+                    const int n = tile_n + wn * 64 + j * 16 + li;
+                    if (m < a.M && n < a.n_store) a.C[(size_t)m * a.ldc + n] = acc[i][j][q];
+                }
+        return;
+    } else {
+        // SED tile [128 galaxies][128 wavelengths] -> LDS (stride 129), then two threads per
+        // galaxy reduce 64 wavelengths each into the band sums
+        float(*sed)[XBN + 1] = reinterpret_cast<float(*)[XBN + 1]>(smem);
+        static_assert(XBM * (XBN + 1) * 4 <= 2 * XSTAGE, "SED tile fits the staging buffers");
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sed[wm * 64 + i * 16 + 4 * lk + q][wn * 64 + j * 16 + li] = acc[i][j][q];
+        __syncthreads();
+        const int row = tid >> 1, half = tid & 1, g = tile_m + row;
+        constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;   // num, N [, dnum/dtauV, dnum/ddelta, dnum/dFfloor]
+        float accp[NB_MAX][NPB];
+#pragma unroll
+        for (int bb = 0; bb < NB_MAX; ++bb)
+#pragma unroll
+            for (int q = 0; q < NPB; ++q) accp[bb][q] = 0.0f;
+        const int gg = g < a.M ? g : a.M - 1;
+        const float tauv = a.params[(size_t)7 * a.M + gg], delta = a.params[(size_t)8 * a.M + gg];
+        const float ffl = a.params[(size_t)9 * a.M + gg];
+        const double opz = 1.0 + (double)a.z[gg];
+        for (int cc = 0; cc < 64; ++cc) {
+            const int c = half * 64 + cc, l = tile_n + c;
+            if (l >= a.n_wave) break;
+            const v4f w = *(const v4f *)(a.wc + 4 * (size_t)l);   // ln x, l q, q / l
+            const float xd = __expf(delta * w[0]), ee = __expf(-tauv * xd);
+            const float F = ffl + (1.0f - ffl) * ee;
+            const float sw = sed[row][c] * w[1];
+            const double lo = opz * a.wave[l];
+#pragma unroll
+            for (int bb = 0; bb < NB_MAX; ++bb) {
+                if (bb >= a.n_band) break;
+                const float x = (float)((lo - a.fc[bb]) * a.inv_fs[bb]);
+                const float tb = __expf(-0.5f * x * x);
+                const float stw = sw * tb;
+                accp[bb][0] = fmaf(stw, F, accp[bb][0]);
+                accp[bb][1] = fmaf(tb, w[2], accp[bb][1]);
+                if constexpr (EPI == EPI_PHOT_DUST) {
+                    const float dtv = -(1.0f - ffl) * xd * ee;
+                    accp[bb][2] = fmaf(stw, dtv, accp[bb][2]);
+                    accp[bb][3] = fmaf(stw * dtv, tauv * w[0], accp[bb][3]);
+                    accp[bb][4] = fmaf(stw, 1.0f - ee, accp[bb][4]);
+                }
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < NB_MAX; ++bb)
+#pragma unroll
+            for (int q = 0; q < NPB; ++q) accp[bb][q] += __shfl_xor(accp[bb][q], 1, 64);
+        if (half == 0 && g < a.M) {
+            float *out = a.part + ((size_t)(tile_n / XBN) * a.M + g) * a.npart;
+#pragma unroll
+            for (int bb = 0; bb < NB_MAX; ++bb) {
+                if (bb >= a.n_band) break;
+#pragma unroll
+                for (int q = 0; q < NPB; ++q) out[q * a.n_band + bb] = accp[bb][q];
             }
         }
     }
@@ -477,23 +687,27 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
                  void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
                  float *grad) {
     const int nw = c->n_wave, nb = c->n_band;
-    const int n_tiles = (nw + BN - 1) / BN;
+    const bool f64 = (prec == SPS_F64);
+    const int TN = f64 ? BN : XBN;                // wavelengths per tile of the forward GEMM
+    const int n_tiles = f64 ? (nw + BN - 1) / BN : c->lw / XBN;
+    const int mp = round_up(n, XBM);              // A operands are read in whole 128-row tiles
     const bool want_grad = grad != nullptr;
     const int npart = (want_grad ? 5 : 2) * nb;
-    const int esz = (prec == SPS_F64) ? 8 : 4;
-    const int tsz = (prec == SPS_F64) ? 8 : (prec == SPS_F32 ? 4 : 2);
+    const int esz = f64 ? 8 : 4;
+    const int tsz = f64 ? 8 : (prec == SPS_F32 ? 4 : 2);
     const int nsplit = (prec == SPS_BF16X) ? 2 : 1;
-    const int lw = round_up(nw, 64);   // padded wavelength stride of Rbar
+    const int lw = c->lw;                         // padded wavelength stride of Rbar
+    (void)TN;
     // workspace: weights rows | partial sums | dlogL/dnum | Rbar | Wbar
     size_t off = 0;
     auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    const size_t o_w = carve((size_t)nsplit * n * S_PAD * tsz);
+    const size_t o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
     const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
     size_t o_cn = 0, o_rb = 0, o_wb = 0;
     if (logl) {
         o_cn = carve((size_t)n * NB_MAX * 4);
         if (want_grad) {
-            o_rb = carve((size_t)nsplit * n * lw * tsz);
+            o_rb = carve((size_t)nsplit * mp * lw * tsz);
             o_wb = carve((size_t)n * S_PAD * 4);
         }
     }
@@ -506,10 +720,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         c->work_bytes = off;
     }
     char *W = (char *)c->d_work;
-    void *w_hi = W + o_w, *w_lo = W + o_w + (size_t)n * S_PAD * tsz;
-    const void *L_hi = (prec == SPS_F64) ? (const void *)c->d_lum64
-                      : (prec == SPS_F32) ? (const void *)c->d_lum32 : (const void *)c->d_lum_hi;
-    const void *L_lo = (prec == SPS_BF16X) ? (const void *)c->d_lum_lo : nullptr;
+    void *w_hi = W + o_w, *w_lo = W + o_w + (size_t)mp * S_PAD * tsz;
 
     dim3 gw((n + 63) / 64), bw(64);
     switch (prec) {
@@ -517,74 +728,105 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         case SPS_F32: hipLaunchKernelGGL(k_exact_weights<SPS_F32>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
         default: hipLaunchKernelGGL(k_exact_weights<SPS_BF16X>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
     }
-    GemmArgs a{};
-    a.M = n;
-    a.N = nw;
-    a.K_valid = NSSP;
-    a.K_pad = S_PAD;
-    a.A_hi = w_hi;
-    a.A_lo = w_lo;
-    a.lda = S_PAD;
-    a.B_hi = L_hi;
-    a.B_lo = L_lo;
-    a.ldb = nw;
-    a.b_nk = false;
-    a.params = params;
-    a.z = z;
-    a.wave = c->d_wave;
-    a.trap = c->d_trap;
-    a.n_band = nb;
-    for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.fs[b] = c->h_fs[b]; }
-    a.part = (float *)(W + o_part);
-    a.npart = npart;
-    dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
-    if (prec == SPS_F64) hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
-    else if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_PHOT>), gg, bg, 0, s, a);
-    else if (prec == SPS_F32) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_PHOT_DUST>), gg, bg, 0, s, a);
-    else if (!want_grad) hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_PHOT>), gg, bg, 0, s, a);
-    else hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_PHOT_DUST>), gg, bg, 0, s, a);
+    float *part = (float *)(W + o_part);
+    if (f64) {
+        // FP64 parity path: the generic 64 x 64 tile kernel on the FP64 table
+        GemmArgs a{};
+        a.M = n;
+        a.N = nw;
+        a.K_valid = NSSP;
+        a.K_pad = S_PAD;
+        a.A_hi = w_hi;
+        a.A_lo = w_lo;
+        a.lda = S_PAD;
+        a.B_hi = c->d_lum64;
+        a.B_lo = nullptr;
+        a.ldb = nw;
+        a.b_nk = false;
+        a.params = params;
+        a.z = z;
+        a.wave = c->d_wave;
+        a.trap = c->d_trap;
+        a.n_band = nb;
+        for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.fs[b] = c->h_fs[b]; }
+        a.part = part;
+        a.npart = npart;
+        dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
+        hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
+    } else {
+        XArgs a{};
+        a.M = n;
+        a.N = lw;
+        a.K = S_PAD;
+        a.A_hi = w_hi;
+        a.A_lo = w_lo;
+        a.lda = S_PAD;
+        a.B_hi = (prec == SPS_F32) ? (const void *)c->d_lt32 : (const void *)c->d_lt_hi;
+        a.B_lo = (prec == SPS_F32) ? nullptr : (const void *)c->d_lt_lo;
+        a.ldb = S_PAD;
+        a.n_mt = mp / XBM;
+        a.n_nt = lw / XBN;
+        a.params = (const float *)params;
+        a.z = (const float *)z;
+        a.wave = c->d_wave;
+        a.wc = c->d_wc;
+        a.n_wave = nw;
+        a.n_band = nb;
+        for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.inv_fs[b] = 1.0 / c->h_fs[b]; }
+        a.part = part;
+        a.npart = npart;
+        const dim3 gx(a.n_mt * a.n_nt), bx(256);
+        if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT>), gx, bx, 0, s, a);
+        else if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT_DUST>), gx, bx, 0, s, a);
+        else if (!want_grad) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT>), gx, bx, 0, s, a);
+        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT_DUST>), gx, bx, 0, s, a);
+    }
 
     float *cn = logl ? (float *)(W + o_cn) : nullptr;
     dim3 gf((n + 127) / 128), bf(128);
     switch (prec) {
         case SPS_F64:
-            hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
         case SPS_F32:
-            hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
         default:
-            hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)a.part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
     }
     if (want_grad) {
-        void *r_hi = W + o_rb, *r_lo = W + o_rb + (size_t)n * lw * tsz;
+        void *r_hi = W + o_rb, *r_lo = W + o_rb + (size_t)mp * lw * tsz;
         dim3 gr((lw + 255) / 256, n), br(256);
         FiltConst fl;
-        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)a.fc[b]; fl.fs[b] = (float)a.fs[b]; }
+        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)c->h_fc[b]; fl.fs[b] = (float)c->h_fs[b]; }
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
                                (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
         else
             hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
                                (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
-        GemmArgs b = a;
+        XArgs b{};
         b.M = n;
-        b.N = NSSP;
-        b.K_valid = nw;
-        b.K_pad = lw;
+        b.N = S_PAD;
+        b.K = lw;
         b.A_hi = r_hi;
         b.A_lo = r_lo;
         b.lda = lw;
-        b.b_nk = true;
+        b.B_hi = (prec == SPS_F32) ? (const void *)c->d_ls32 : (const void *)c->d_ls_hi;
+        b.B_lo = (prec == SPS_F32) ? nullptr : (const void *)c->d_ls_lo;
+        b.ldb = lw;
+        b.n_mt = mp / XBM;
+        b.n_nt = S_PAD / XBN;
         b.C = (float *)(W + o_wb);
         b.ldc = S_PAD;
-        dim3 g2(S_PAD / BN, (n + BM - 1) / BM);
-        if (prec == SPS_F32) hipLaunchKernelGGL((k_exact_gemm<SPS_F32, EPI_STORE>), g2, bg, 0, s, b);
-        else hipLaunchKernelGGL((k_exact_gemm<SPS_BF16X, EPI_STORE>), g2, bg, 0, s, b);
+        b.n_store = S_PAD;
+        const dim3 g2(b.n_mt * b.n_nt), b2(256);
+        if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
+        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE>), g2, b2, 0, s, b);
         hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 63) / 64), dim3(64), 0, s, c->k, n, sfh, (const float *)params,
                            (const float *)z, (const float *)b.C, grad);
     }

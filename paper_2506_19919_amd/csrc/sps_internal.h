@@ -24,6 +24,7 @@ constexpr int NGL_DL = 12;        // half of the 24-point Gauss-Legendre rule fo
 //   qa[na][kq][lane][e] = Q[r = 16 kq + 4 e + lane / 16][i = 16 na + lane % 16]   na < 6,   kq < NRB
 // zero where r >= R or i >= NA; one float4 per lane covers 4 consecutive k-steps of 4.
 constexpr int AGE_BLK = 6;        // 96 padded ages = 6 blocks of 16
+constexpr int S_PAD = 1152;       // SSP rows padded to a multiple of 128
 constexpr int QF_NODE_PER_NRB = AGE_BLK * 64 * 4;
 __host__ __device__ inline int row_blocks(int n_band) { return (n_band * NZ + 15) / 16; }
 
@@ -58,9 +59,14 @@ struct sps_ctx {
     double h_fc[SPS_MAX_BAND] = {0}, h_fs[SPS_MAX_BAND] = {0};   // filter constants (FP64)
     // device tables
     double *d_lum64 = nullptr;     // [S][n_wave]
-    float *d_lum32 = nullptr;      // [S][n_wave]
-    uint16_t *d_lum_hi = nullptr;  // BF16 bits, [S][n_wave]
-    uint16_t *d_lum_lo = nullptr;
+    // FP32 / BF16 hi+lo copies for the matrix-core GEMMs, zero-padded to S_PAD SSP rows and
+    // LW = round_up(n_wave, 128) wavelengths, in both orientations (k contiguous):
+    //   ls: [S_PAD][LW]  (B of the gradient GEMM, k = wavelength)
+    //   lt: [LW][S_PAD]  (B of the forward GEMM, k = SSP)
+    int lw = 0;
+    float *d_ls32 = nullptr, *d_lt32 = nullptr;
+    uint16_t *d_ls_hi = nullptr, *d_ls_lo = nullptr, *d_lt_hi = nullptr, *d_lt_lo = nullptr;
+    float *d_wc = nullptr;         // per wavelength [LW][4]: ln(l / 5500 A), l q_l, q_l / l, 0
     double *d_wave = nullptr, *d_trap = nullptr;
     double *d_edges = nullptr;     // FP64 bin edges: age_lo, age_hi [Gyr], lage_lo, lage_hi [NA each], met_lo, met_hi [NZ]
     float *d_q = nullptr;          // [n_z][n_band][n_met][n_age]
