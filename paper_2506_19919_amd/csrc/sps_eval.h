@@ -30,10 +30,20 @@ __device__ inline int z_bucket(const DevConsts &k, float z, float *frac) {
 }
 
 // ------------------------------------------------------------------ per-lane LDS column
-struct LdsCol {
-    float *base;  // &lds[lane]; slot s at base[s * WAVE]
-    __device__ float &operator[](int s) const { return base[s * WAVE]; }
+template <int STRIDE>
+struct LdsColT {
+    float *base;  // slot s at base[s * STRIDE]
+    __device__ float &operator[](int s) const { return base[s * STRIDE]; }
 };
+typedef LdsColT<WAVE> LdsCol;   // one column per lane: base = &lds[lane]
+
+// sum over the G adjacent lanes that share one galaxy (G = 1, 2, 4, ...)
+template <int G, typename T>
+__device__ inline T group_sum(T v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
 
 // ------------------------------------------------------------------ forward weights
 // Returns the burst normaliser and the total smooth mass (needed by the adjoint).
@@ -44,41 +54,49 @@ struct WeightsState {
     int i0;        // first age bin of the burst window
 };
 
-// P_age is left in the LDS column (slots 0..NA-1), P_Z in registers.
+// P_age is left in the LDS column (slots 0..NA-1), P_Z in registers.  G adjacent lanes may
+// share one galaxy (and one column): lane q of the group takes the age bins i = q mod G,
+// and the sums over bins are combined across the group.
+template <int G = 1, int STRIDE = WAVE>
 __device__ inline void forward_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
-                                       LdsCol col, float (&pz)[NZ], WeightsState &ws) {
+                                       LdsColT<STRIDE> col, float (&pz)[NZ], WeightsState &ws, int q = 0) {
     const float t_obs_f = (float)t_obs;
     double S = 0.0;
     if (sfh == SPS_SFH_DPL) {
         const Dpl p = make_dpl(th[1], th[2], th[3]);
-        for (int i = 0; i < NA; ++i) {
+        for (int i = q; i < NA; i += G) {
             float m, a, b, c;
             dpl_bin<false>(k, i, t_obs_f, p, m, a, b, c);
             col[i] = m;
             S += (double)m;
         }
     } else {
-        for (int i = 0; i < NA; ++i) {
+        for (int i = q; i < NA; i += G) {
             double m, a, b;
             logn_bin<false>(k, i, t_obs, (double)th[1], (double)th[2], m, a, b);
             col[i] = (float)m;
             S += m;
         }
     }
-    // burst: only the bins the triweight window [mu - 3 sigma, mu + 3 sigma] touches
+    S = group_sum<G>(S);
+    // burst: only the bins the triweight window [mu - 3 sigma, mu + 3 sigma] touches; a bin
+    // is handled by the lane that owns it
     const float l_obs = (float)log10(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
     const int i0 = first_bin_above(k, mu - 3.0f * k.burst_sig);
     float Zb = 0.0f;
     for (int t = 0; t < k.burst_nbins; ++t) {
+        if (G > 1 && (i0 + t) % G != q) continue;
         float p, dp;
         if (i0 + t < NA) burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
         else p = 0.0f;
         Zb += p;
     }
+    Zb = group_sum<G>(Zb);
     const float fb = th[4], sm = (1.0f - fb) * (float)(1.0 / S), bz = (Zb > 0.0f) ? fb / Zb : 0.0f;
-    for (int i = 0; i < NA; ++i) col[i] = col[i] * sm;
+    for (int i = q; i < NA; i += G) col[i] = col[i] * sm;
     for (int t = 0; t < k.burst_nbins; ++t) {
         if (i0 + t >= NA) break;
+        if (G > 1 && (i0 + t) % G != q) continue;
         float p, dp;
         burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
         col[i0 + t] = fmaf(bz, p, col[i0 + t]);
@@ -95,10 +113,12 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
 }
 
 // gradient of the weights: given dP_age (LDS column, slots 0..NA) and dP_Z,
-// accumulate d/d(theta_1..6)
+// accumulate d/d(theta_1..6).  With G lanes per galaxy, lane q takes the bins i = q mod G;
+// every lane of the group ends with the same totals.
+template <int G = 1, int STRIDE = WAVE>
 __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
-                                       const WeightsState &ws, LdsCol col, const float (&pzbar)[NZ],
-                                       float *g) {
+                                       const WeightsState &ws, LdsColT<STRIDE> col, const float (&pzbar)[NZ],
+                                       float *g, int q = 0) {
     const float t_obs_f = (float)t_obs, fb = th[4];
     const float invS = (float)(1.0 / ws.S), invZ = (ws.Zb > 0.0f) ? 1.0f / ws.Zb : 0.0f;
     float fbar = 0.0f, cbar = 0.0f, e1 = 0.0f, e2 = 0.0f, e3 = 0.0f;
@@ -107,7 +127,7 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     Dpl p;
     if (sfh == SPS_SFH_DPL) p = make_dpl(th[1], th[2], th[3]);
     // smooth part: dP_age/dF_burst = P_burst - P_smooth; the P_burst term is added below
-    for (int i = 0; i < NA; ++i) {
+    for (int i = q; i < NA; i += G) {
         const float gbar = col[i];
         float ps;
         float m, mt, ma, mb;
@@ -135,6 +155,7 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     for (int t = 0; t < k.burst_nbins; ++t) {
         const int i = ws.i0 + t;
         if (i >= NA) break;
+        if (G > 1 && i % G != q) continue;
         const float gbar = col[i];
         float pbr, dpb;
         burst_bin(k, i, ws.l_obs, th[5], inv_s3, pbr, dpb);
@@ -143,6 +164,13 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
         e1 = fmaf(pbbar, dpb, e1);
         e2 = fmaf(pbbar, pb, e2);
         e3 += dpb;
+    }
+    if (G > 1) {
+        fbar = group_sum<G>(fbar); cbar = group_sum<G>(cbar);
+        e1 = group_sum<G>(e1); e2 = group_sum<G>(e2); e3 = group_sum<G>(e3);
+        A0 = group_sum<G>(A0); A1 = group_sum<G>(A1); A2 = group_sum<G>(A2);
+        B0 = group_sum<G>(B0); B1 = group_sum<G>(B1); B2 = group_sum<G>(B2);
+        dA0 = group_sum<G>(dA0); dA1 = group_sum<G>(dA1); dB0 = group_sum<G>(dB0); dB1 = group_sum<G>(dB1);
     }
     if (sfh == SPS_SFH_DPL) {
         g[1] += (A0 - cbar * B0) * invS;
@@ -163,7 +191,6 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     }
     g[6] += mbar;
 }
-
 
 // ------------------------------------------------------------------ contractions on the matrix cores
 // The wave's 64 galaxies are the M dimension of two small GEMMs per z bucket kb (all lanes

@@ -275,7 +275,7 @@ struct XArgs {
     const void *B_hi, *B_lo;
     int ldb;
     int n_mt, n_nt;
-    float *C;                  // EPI_STORE: [M][ldc], columns < n_store
+    float *C;                  // EPI_STORE: transposed, [n_store][ldc] (ldc >= 128-padded M)
     int ldc, n_store;
     const float *params, *z;   // photometry epilogue
     const double *wave;
@@ -387,16 +387,16 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     }
 
     if constexpr (EPI == EPI_STORE) {
+        // C stored transposed, C[n][m] with row stride ldc >= the 128-padded M: a lane's four
+        // accumulator rows are consecutive m, one 16-byte store
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int m = tile_m + wm * 64 + i * 16 + 4 * lk + q;
-                    const int n = tile_n + wn * 64 + j * 16 + li;
-                    if (m < a.M && n < a.n_store) a.C[(size_t)m * a.ldc + n] = acc[i][j][q];
-                }
+            for (int j = 0; j < 4; ++j) {
+                const int m = tile_m + wm * 64 + i * 16 + 4 * lk;
+                const int n = tile_n + wn * 64 + j * 16 + li;
+                if (n < a.n_store) *(v4f *)(a.C + (size_t)n * a.ldc + m) = acc[i][j];
+            }
         return;
     } else {
         // SED tile [128 galaxies][128 wavelengths] -> LDS (stride 129), then two threads per
@@ -461,23 +461,21 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     }
 }
 
-// ------------------------------------------------------------------ weights rows P_SSP[g][s]
-template <int P>
-__global__ void __launch_bounds__(64) k_exact_weights(DevConsts k, int n, int sfh, const void *params_v,
-                                                      const void *z_v, const double *edges, void *w_hi, void *w_lo) {
-    __shared__ float lds[LDS_SLOTS * 64];
+// ------------------------------------------------------------------ FP64 weights rows P_SSP[g][s]
+// FP64 weights from FP64 bin edges: closed-form log-normal or 8-point Gauss-Legendre DPL
+// panels, closed-form triweight and normal CDFs (the FP64 parity path)
+__global__ void __launch_bounds__(64) k_exact_weights64(DevConsts k, int n, int sfh, const double *params_v,
+                                                        const double *z_v, const double *edges, double *w_out) {
     const int lane = threadIdx.x, g = blockIdx.x * 64 + lane;
     const int gg = g < n ? g : n - 1;
-    if constexpr (P == SPS_F64) {
-        // FP64 weights from FP64 bin edges: closed-form log-normal or 8-point Gauss-Legendre DPL
-        // panels, closed-form triweight and normal CDFs
-        const double *prm = (const double *)params_v;
+    {
+        const double *prm = params_v;
         const double *age_lo = edges, *age_hi = edges + NA, *lage_lo = edges + 2 * NA, *lage_hi = edges + 3 * NA;
         const double *met_lo = edges + 4 * NA, *met_hi = edges + 4 * NA + NZ;
         double th[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + gg];
-        const double t_obs = age_universe_gyr(k, ((const double *)z_v)[gg]);
+        const double t_obs = age_universe_gyr(k, z_v[gg]);
         const double sig_z = k.sigma_logz_d;
         double pz[NZ];
         for (int j = 0; j < NZ; ++j) {
@@ -511,44 +509,66 @@ __global__ void __launch_bounds__(64) k_exact_weights(DevConsts k, int n, int sf
             Zb += burst(i);
         }
         if (g >= n) return;
-        double *w = (double *)w_hi + (size_t)g * S_PAD;
+        double *w = w_out + (size_t)g * S_PAD;
         for (int i = 0; i < NA; ++i) {
             const double pa = (1.0 - th[4]) * mass(i) / S + (Zb > 0.0 ? th[4] * burst(i) / Zb : 0.0);
             for (int j = 0; j < NZ; ++j) w[j * NA + i] = pz[j] * pa;
         }
         for (int s = NSSP; s < S_PAD; ++s) w[s] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ FP32 / BF16X weights, four lanes per galaxy
+// The exact path runs a few thousand galaxies, too few waves for one lane per galaxy; here
+// four adjacent lanes share a galaxy (and its LDS column) and split its age bins.
+// Per-galaxy results, SoA [slot][n]: slots 0..93 P_age, 96..107 P_Z, 108/109 the FP64 total
+// smooth mass (low/high words), 110 the burst normaliser, 111 log10 t_obs, 112 the first
+// burst bin (int bits).
+constexpr int PW_SLOTS = 128, PW_PZ = 96, PW_S = 108, PW_ZB = 110, PW_LOBS = 111, PW_I0 = 112;
+constexpr int GPL = 4;   // lanes per galaxy
+
+__global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, const float *params, const float *z,
+                                                 float *pw) {
+    __shared__ float lds[LDS_SLOTS * (64 / GPL)];
+    const int lane = threadIdx.x, slot = lane / GPL, q = lane % GPL;
+    const int g = blockIdx.x * (64 / GPL) + slot, gg = g < n ? g : n - 1;
+    LdsColT<64 / GPL> col{lds + slot};
+    float th[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) th[p] = params[(size_t)p * n + gg];
+    const double t_obs = age_universe_gyr(k, (double)z[gg]);
+    float pz[NZ];
+    WeightsState ws;
+    forward_weights<GPL>(k, sfh, th, t_obs, col, pz, ws, q);
+    if (g >= n) return;
+    for (int i = q; i < NA; i += GPL) pw[(size_t)i * n + g] = col[i];
+    if (q == 0) {
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) pw[(size_t)(PW_PZ + j) * n + g] = pz[j];
+        pw[(size_t)PW_S * n + g] = __int_as_float(__double2loint(ws.S));
+        pw[(size_t)(PW_S + 1) * n + g] = __int_as_float(__double2hiint(ws.S));
+        pw[(size_t)PW_ZB * n + g] = ws.Zb;
+        pw[(size_t)PW_LOBS * n + g] = ws.l_obs;
+        pw[(size_t)PW_I0 * n + g] = __int_as_float(ws.i0);
+    }
+}
+
+// weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP (coalesced rows)
+template <int P>
+__global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w_hi, void *w_lo) {
+    const int sidx = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+    if (sidx >= S_PAD) return;
+    float v = 0.0f;
+    if (sidx < NSSP) {
+        const int j = sidx / NA, i = sidx - j * NA;
+        v = pw[(size_t)(PW_PZ + j) * n + g] * pw[(size_t)i * n + g];
+    }
+    if constexpr (P == SPS_F32) {
+        ((float *)w_hi)[(size_t)g * S_PAD + sidx] = v;
     } else {
-        const float *prm = (const float *)params_v;
-        float th[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + gg];
-        const double t_obs = age_universe_gyr(k, (double)((const float *)z_v)[gg]);
-        float pa[NA], pz[NZ];
-        WeightsState ws;
-        forward_weights(k, sfh, th, t_obs, LdsCol{lds + lane}, pz, ws);
-#pragma unroll
-        for (int i = 0; i < NA; ++i) pa[i] = lds[i * 64 + lane];
-        if (g >= n) return;
-        if constexpr (P == SPS_F32) {
-            float *w = (float *)w_hi + (size_t)g * S_PAD;
-#pragma unroll
-            for (int j = 0; j < NZ; ++j)
-#pragma unroll
-                for (int i = 0; i < NA; ++i) w[j * NA + i] = pz[j] * pa[i];
-            for (int s = NSSP; s < S_PAD; ++s) w[s] = 0.0f;
-        } else {
-            uint16_t *wh = (uint16_t *)w_hi + (size_t)g * S_PAD, *wl = (uint16_t *)w_lo + (size_t)g * S_PAD;
-#pragma unroll
-            for (int j = 0; j < NZ; ++j)
-#pragma unroll
-                for (int i = 0; i < NA; ++i) {
-                    const float v = pz[j] * pa[i];
-                    const uint16_t h = f2bf(v);
-                    wh[j * NA + i] = h;
-                    wl[j * NA + i] = f2bf(v - bf2f(h));
-                }
-            for (int s = NSSP; s < S_PAD; ++s) wh[s] = wl[s] = 0;
-        }
+        const uint16_t h = f2bf(v);
+        ((uint16_t *)w_hi)[(size_t)g * S_PAD + sidx] = h;
+        ((uint16_t *)w_lo)[(size_t)g * S_PAD + sidx] = f2bf(v - bf2f(h));
     }
 }
 
@@ -613,25 +633,27 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
     }
 }
 
-// Rbar[g][l] = sum_b (d logL / d num_b) F_att(l) T_b((1+z) l) l q_l  (zero beyond n_wave)
+// Rbar[g][l] = sum_b (d logL / d num_b) F_att(l) T_b((1+z) l) l q_l  (zero beyond n_wave);
+// bands more than 8 sigma from the redshifted wavelength contribute below FP32 resolution
 template <int P>
-__global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
-                             const float *params, const float *z, const double *wave, const double *trap,
-                             const float *cnum, void *r_hi, void *r_lo) {
+__global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, const float *params, const float *z,
+                             const double *wave, const float *wc, const float *cnum, void *r_hi, void *r_lo) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
     if (l >= ld) return;
     float v = 0.0f;
     if (l < n_wave) {
         const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
-        const double lam = wave[l], opz = 1.0 + (double)z[g];
-        const float lnx = (float)log(lam * (1.0 / 5500.0));
-        const float F = ffl + (1.0f - ffl) * expf(-tauv * expf(delta * lnx));
+        const double lo = (1.0 + (double)z[g]) * wave[l];
+        const v4f w = *(const v4f *)(wc + 4 * (size_t)l);   // ln x, l q, q / l
         float s = 0.0f;
         for (int b = 0; b < nb; ++b) {
-            const double x = (opz * lam - (double)fl.fc[b]) / (double)fl.fs[b];
-            s += cnum[(size_t)g * NB_MAX + b] * expf((float)(-0.5 * x * x));
+            const float x = (float)((lo - (double)fl.fc[b]) / (double)fl.fs[b]);
+            if (fabsf(x) < 8.0f) s = fmaf(cnum[(size_t)g * NB_MAX + b], __expf(-0.5f * x * x), s);
         }
-        v = s * F * (float)(lam * trap[l]);
+        if (s != 0.0f) {
+            const float F = ffl + (1.0f - ffl) * __expf(-tauv * __expf(delta * w[0]));
+            v = s * F * w[1];
+        }
     }
     if (P == SPS_F32) {
         ((float *)r_hi)[(size_t)g * ld + l] = v;
@@ -642,42 +664,50 @@ __global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
     }
 }
 
-// dP_age, dP_Z from Wbar[g][s] = dlogL/dP_SSP, then the weights adjoint -> grad slots 1..6
+// dP_age and dP_Z from Wbar = dlogL/dP_SSP (stored [s][ld], galaxies contiguous):
+//   dP_age(i) = sum_j P_Z(j) Wbar[j NA + i],  dP_Z(j) = sum_i P_age(i) Wbar[j NA + i]
+// one thread per (galaxy, output), written SoA pb[r][n] (r < NA: dP_age, then dP_Z)
+__global__ void __launch_bounds__(256) k_wbar_reduce(int n, const float *pw, const float *wbar, int ld,
+                                                     float *pb) {
+    const int g = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (g >= n) return;
+    float s = 0.0f;
+    if (r < NA) {
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) s = fmaf(pw[(size_t)(PW_PZ + j) * n + g], wbar[(size_t)(j * NA + r) * ld + g], s);
+    } else {
+        const int j = r - NA;
+        for (int i = 0; i < NA; ++i) s = fmaf(pw[(size_t)i * n + g], wbar[(size_t)(j * NA + i) * ld + g], s);
+    }
+    pb[(size_t)r * n + g] = s;
+}
+
+// the weights adjoint -> grad slots 1..6, four lanes per galaxy
 __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sfh, const float *params,
-                                                      const float *z, const float *wbar, float *grad) {
-    __shared__ float lds[LDS_SLOTS * 64];
-    const int lane = threadIdx.x, g = blockIdx.x * 64 + lane;
-    const int gg = g < n ? g : n - 1;
-    LdsCol col{lds + lane};
+                                                      const float *z, const float *pw, const float *pb,
+                                                      float *grad) {
+    __shared__ float lds[LDS_SLOTS * (64 / GPL)];
+    const int lane = threadIdx.x, slot = lane / GPL, q = lane % GPL;
+    const int g = blockIdx.x * (64 / GPL) + slot, gg = g < n ? g : n - 1;
+    LdsColT<64 / GPL> col{lds + slot};
     float th[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) th[p] = params[(size_t)p * n + gg];
     const double t_obs = age_universe_gyr(k, (double)z[gg]);
-    float pa[NA], pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pz, ws);
-#pragma unroll
-    for (int i = 0; i < NA; ++i) pa[i] = col[i];
-    const float *wb = wbar + (size_t)gg * S_PAD;
+    ws.S = __hiloint2double(__float_as_int(pw[(size_t)(PW_S + 1) * n + gg]), __float_as_int(pw[(size_t)PW_S * n + gg]));
+    ws.Zb = pw[(size_t)PW_ZB * n + gg];
+    ws.l_obs = pw[(size_t)PW_LOBS * n + gg];
+    ws.i0 = __float_as_int(pw[(size_t)PW_I0 * n + gg]);
+    for (int i = q; i < NA; i += GPL) col[i] = pb[(size_t)i * n + gg];
     float pzbar[NZ];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        float s = 0.0f;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) s = fmaf(pa[i], wb[j * NA + i], s);
-        pzbar[j] = s;
-    }
-    for (int i = 0; i < NA; ++i) {
-        float s = 0.0f;
-#pragma unroll
-        for (int j = 0; j < NZ; ++j) s = fmaf(pz[j], wb[j * NA + i], s);
-        col[i] = s;
-    }
+    for (int j = 0; j < NZ; ++j) pzbar[j] = pb[(size_t)(NA + j) * n + gg];
     float gr[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) gr[p] = 0.0f;
-    adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);
-    if (g >= n) return;
+    adjoint_weights<GPL>(k, sfh, th, t_obs, ws, col, pzbar, gr, q);
+    if (g >= n || q != 0) return;
 #pragma unroll
     for (int p = 1; p <= 6; ++p) grad[(size_t)p * n + g] = gr[p];
 }
@@ -698,17 +728,19 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     const int nsplit = (prec == SPS_BF16X) ? 2 : 1;
     const int lw = c->lw;                         // padded wavelength stride of Rbar
     (void)TN;
-    // workspace: weights rows | partial sums | dlogL/dnum | Rbar | Wbar
+    // workspace: weights rows | per-galaxy weights | partial sums | dlogL/dnum | Rbar | Wbar | dP
     size_t off = 0;
     auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
     const size_t o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
+    const size_t o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
     const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
-    size_t o_cn = 0, o_rb = 0, o_wb = 0;
+    size_t o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
     if (logl) {
         o_cn = carve((size_t)n * NB_MAX * 4);
         if (want_grad) {
             o_rb = carve((size_t)nsplit * mp * lw * tsz);
-            o_wb = carve((size_t)n * S_PAD * 4);
+            o_wb = carve((size_t)S_PAD * mp * 4);
+            o_pb = carve((size_t)(NA + NZ) * n * 4);
         }
     }
     if (c->work_bytes < off) {
@@ -722,11 +754,16 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     char *W = (char *)c->d_work;
     void *w_hi = W + o_w, *w_lo = W + o_w + (size_t)mp * S_PAD * tsz;
 
-    dim3 gw((n + 63) / 64), bw(64);
-    switch (prec) {
-        case SPS_F64: hipLaunchKernelGGL(k_exact_weights<SPS_F64>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
-        case SPS_F32: hipLaunchKernelGGL(k_exact_weights<SPS_F32>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
-        default: hipLaunchKernelGGL(k_exact_weights<SPS_BF16X>, gw, bw, 0, s, c->k, n, sfh, params, z, c->d_edges, w_hi, w_lo); break;
+    float *pw = f64 ? nullptr : (float *)(W + o_pw);
+    if (f64) {
+        hipLaunchKernelGGL(k_exact_weights64, dim3((n + 63) / 64), dim3(64), 0, s, c->k, n, sfh,
+                           (const double *)params, (const double *)z, c->d_edges, (double *)w_hi);
+    } else {
+        hipLaunchKernelGGL(k_exact_pw, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
+                           (const float *)params, (const float *)z, pw);
+        const dim3 ge((S_PAD + 255) / 256, n), be(256);
+        if (prec == SPS_F32) hipLaunchKernelGGL(k_expand<SPS_F32>, ge, be, 0, s, n, (const float *)pw, w_hi, w_lo);
+        else hipLaunchKernelGGL(k_expand<SPS_BF16X>, ge, be, 0, s, n, (const float *)pw, w_hi, w_lo);
     }
     float *part = (float *)(W + o_part);
     if (f64) {
@@ -805,10 +842,10 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)c->h_fc[b]; fl.fs[b] = (float)c->h_fs[b]; }
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi, r_lo);
         else
             hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_trap, cn, r_hi, r_lo);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi, r_lo);
         XArgs b{};
         b.M = n;
         b.N = S_PAD;
@@ -822,13 +859,16 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         b.n_mt = mp / XBM;
         b.n_nt = S_PAD / XBN;
         b.C = (float *)(W + o_wb);
-        b.ldc = S_PAD;
+        b.ldc = mp;
         b.n_store = S_PAD;
         const dim3 g2(b.n_mt * b.n_nt), b2(256);
         if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
         else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE>), g2, b2, 0, s, b);
-        hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 63) / 64), dim3(64), 0, s, c->k, n, sfh, (const float *)params,
-                           (const float *)z, (const float *)b.C, grad);
+        float *pb = (float *)(W + o_pb);
+        hipLaunchKernelGGL(k_wbar_reduce, dim3((n + 255) / 256, NA + NZ), dim3(256), 0, s, n, (const float *)pw,
+                           (const float *)b.C, mp, pb);
+        hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
+                           (const float *)params, (const float *)z, (const float *)pw, (const float *)pb, grad);
     }
     SPS_HIP(hipGetLastError());
     return SPS_OK;
