@@ -234,23 +234,32 @@ __device__ inline void mfma_block(const float *wl, int lane, int h, int nk, cons
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int m = 0; m < 2; ++m) d0[m] = d1[m] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the B fragments of step kq + 1 are in flight while step kq's products issue (the
-    // table comes from L2, whose latency one step of 16 products covers); the scheduling
-    // fence keeps the compiler from hoisting the loads of later blocks (registers)
+    // the A and B fragments of step kq + 1 are in flight while step kq's products issue (B
+    // comes from L2, whose latency one step of 16 products covers); the scheduling fence
+    // keeps the compiler from hoisting the loads of later blocks (registers)
     __builtin_amdgcn_sched_barrier(0);
     v4f n0 = *(const v4f *)b0, n1 = *(const v4f *)b1;
+    float na[4][2];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) na[e][m] = wl[(4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
 #pragma unroll 1
     for (int kq = 0; kq < nk; ++kq) {
         const v4f q0 = n0, q1 = n1;
-        if (kq + 1 < nk) {
-            n0 = *(const v4f *)(b0 + (kq + 1) * kstride);
-            n1 = *(const v4f *)(b1 + (kq + 1) * kstride);
-        }
         float a[4][2];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int m = 0; m < 2; ++m) a[e][m] = wl[(16 * kq + 4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
+            for (int m = 0; m < 2; ++m) a[e][m] = na[e][m];
+        if (kq + 1 < nk) {
+            n0 = *(const v4f *)(b0 + (kq + 1) * kstride);
+            n1 = *(const v4f *)(b1 + (kq + 1) * kstride);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int m = 0; m < 2; ++m) na[e][m] = wl[(16 * (kq + 1) + 4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll

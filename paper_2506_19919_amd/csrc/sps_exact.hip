@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
 // contiguous run of tiles, M fastest (its A rows stay in that XCD's L2).
 constexpr int XBM = 128, XBN = 128, XBK = 32, XROW = 144;   // XROW in bytes
 constexpr int XSTAGE = (XBM + XBN) * XROW;                   // 36,864 bytes per stage
+constexpr int XSPLIT = 4;                                    // K ranges of the gradient GEMM
 
 struct XArgs {
     int M, N, K;
@@ -275,6 +276,8 @@ struct XArgs {
     const void *B_hi, *B_lo;
     int ldb;
     int n_mt, n_nt;
+    int k_splits;              // EPI_STORE: K is split into this many ranges, one partial C each
+    size_t c_split;            // floats between the partial C of consecutive K ranges
     float *C;                  // EPI_STORE: transposed, [n_store][ldc] (ldc >= 128-padded M)
     int ldc, n_store;
     const float *params, *z;   // photometry epilogue
@@ -282,7 +285,7 @@ struct XArgs {
     const float *wc;           // [N][4]: ln(l / 5500), l q, q / l
     int n_wave, n_band;
     double fc[NB_MAX], inv_fs[NB_MAX];
-    float *part;               // [n_nt][M][npart]
+    float *part;               // [n_nt][npart][M] (quantity-major: the finish reads it coalesced)
     int npart;
 };
 
@@ -324,11 +327,14 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
-    // XCD-aware tile order
-    const int T = a.n_mt * a.n_nt, b = blockIdx.x;
+    // XCD-aware tile order; with a split K the slot also names the K range
+    const int T = a.n_mt * a.n_nt, nsp = (EPI == EPI_STORE) ? a.k_splits : 1, total = T * nsp, b = blockIdx.x;
     int t = b;
-    if (T % 8 == 0) t = (b % 8) * (T / 8) + b / 8;
+    if (total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
+    const int sp = t / T;
+    t -= sp * T;
     const int tile_m = (t % a.n_mt) * XBM, tile_n = (t / a.n_mt) * XBN;
+    const int klen = a.K / nsp, kbeg = sp * klen;
 
     v4f acc[4][4];
 #pragma unroll
@@ -336,14 +342,14 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = a.K / XBK;
+    const int nk = klen / XBK;
     v4f r[8];
-    x_load<P>(a, tile_m, tile_n, 0, tid, r);
+    x_load<P>(a, tile_m, tile_n, kbeg, tid, r);
     x_store(smem, tid, r);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         char *cur = smem + (kt & 1) * XSTAGE;
-        if (kt + 1 < nk) x_load<P>(a, tile_m, tile_n, (kt + 1) * XBK, tid, r);
+        if (kt + 1 < nk) x_load<P>(a, tile_m, tile_n, kbeg + (kt + 1) * XBK, tid, r);
         const char *As = cur, *Bs = cur + XBM * XROW;
         if constexpr (P == SPS_F32) {
 #pragma unroll
@@ -395,7 +401,7 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
             for (int j = 0; j < 4; ++j) {
                 const int m = tile_m + wm * 64 + i * 16 + 4 * lk;
                 const int n = tile_n + wn * 64 + j * 16 + li;
-                if (n < a.n_store) *(v4f *)(a.C + (size_t)n * a.ldc + m) = acc[i][j];
+                if (n < a.n_store) *(v4f *)(a.C + sp * a.c_split + (size_t)n * a.ldc + m) = acc[i][j];
             }
         return;
     } else {
@@ -450,12 +456,12 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
 #pragma unroll
             for (int q = 0; q < NPB; ++q) accp[bb][q] += __shfl_xor(accp[bb][q], 1, 64);
         if (half == 0 && g < a.M) {
-            float *out = a.part + ((size_t)(tile_n / XBN) * a.M + g) * a.npart;
+            float *out = a.part + (size_t)(tile_n / XBN) * a.npart * a.M + g;
 #pragma unroll
             for (int bb = 0; bb < NB_MAX; ++bb) {
                 if (bb >= a.n_band) break;
 #pragma unroll
-                for (int q = 0; q < NPB; ++q) out[q * a.n_band + bb] = accp[bb][q];
+                for (int q = 0; q < NPB; ++q) out[(size_t)(q * a.n_band + bb) * a.M] = accp[bb][q];
             }
         }
     }
@@ -518,14 +524,14 @@ __global__ void __launch_bounds__(64) k_exact_weights64(DevConsts k, int n, int 
     }
 }
 
-// ------------------------------------------------------------------ FP32 / BF16X weights, four lanes per galaxy
+// ------------------------------------------------------------------ FP32 / BF16X weights, GPL lanes per galaxy
 // The exact path runs a few thousand galaxies, too few waves for one lane per galaxy; here
-// four adjacent lanes share a galaxy (and its LDS column) and split its age bins.
+// GPL adjacent lanes share a galaxy (and its LDS column) and split its age bins.
 // Per-galaxy results, SoA [slot][n]: slots 0..93 P_age, 96..107 P_Z, 108/109 the FP64 total
 // smooth mass (low/high words), 110 the burst normaliser, 111 log10 t_obs, 112 the first
 // burst bin (int bits).
 constexpr int PW_SLOTS = 128, PW_PZ = 96, PW_S = 108, PW_ZB = 110, PW_LOBS = 111, PW_I0 = 112;
-constexpr int GPL = 4;   // lanes per galaxy
+constexpr int GPL = 8;   // lanes per galaxy
 
 __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, const float *params, const float *z,
                                                  float *pw) {
@@ -589,13 +595,15 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
     for (int b = 0; b < nb; ++b) {
         num[b] = nrm[b] = dd[0][b] = dd[1][b] = dd[2][b] = 0.0;
         for (int t = 0; t < n_tiles; ++t) {
-            const E *pp = part + ((size_t)t * n + g) * npart;
-            num[b] += (double)pp[b];
-            nrm[b] += (double)pp[nb + b];
+            // FP64 partials are [tile][galaxy][quantity]; FP32 ones [tile][quantity][galaxy]
+            const E *pp = (P == SPS_F64) ? part + ((size_t)t * n + g) * npart : part + (size_t)t * npart * n + g;
+            const size_t st = (P == SPS_F64) ? 1 : (size_t)n;
+            num[b] += (double)pp[b * st];
+            nrm[b] += (double)pp[(nb + b) * st];
             if (grad) {
-                dd[0][b] += (double)pp[2 * nb + b];
-                dd[1][b] += (double)pp[3 * nb + b];
-                dd[2][b] += (double)pp[4 * nb + b];
+                dd[0][b] += (double)pp[(2 * nb + b) * st];
+                dd[1][b] += (double)pp[(3 * nb + b) * st];
+                dd[2][b] += (double)pp[(4 * nb + b) * st];
             }
         }
     }
@@ -682,7 +690,25 @@ __global__ void __launch_bounds__(256) k_wbar_reduce(int n, const float *pw, con
     pb[(size_t)r * n + g] = s;
 }
 
-// the weights adjoint -> grad slots 1..6, four lanes per galaxy
+// sum of the K-range partial products into the first one (float4 per thread)
+__global__ void __launch_bounds__(256) k_sum_splits(size_t n4, int n_split, size_t split4, v4f *c) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n4) return;
+    v4f v = c[i];
+    for (int q = 1; q < n_split; ++q) v += c[q * split4 + i];
+    c[i] = v;
+}
+
+// per-tile photometry partials summed over the wavelength tiles: out[q][g] = sum_t part[t][q][g]
+__global__ void __launch_bounds__(256) k_sum_tiles(int n, int npart, int n_tiles, const float *part, float *out) {
+    const int g = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
+    if (g >= n) return;
+    float v = 0.0f;
+    for (int t = 0; t < n_tiles; ++t) v += part[((size_t)t * npart + q) * n + g];
+    out[(size_t)q * n + g] = v;
+}
+
+// the weights adjoint -> grad slots 1..6, GPL lanes per galaxy
 __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sfh, const float *params,
                                                       const float *z, const float *pw, const float *pb,
                                                       float *grad) {
@@ -734,12 +760,13 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     const size_t o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
     const size_t o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
     const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
+    const size_t o_psum = f64 ? 0 : carve((size_t)n * npart * 4);
     size_t o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
     if (logl) {
         o_cn = carve((size_t)n * NB_MAX * 4);
         if (want_grad) {
             o_rb = carve((size_t)nsplit * mp * lw * tsz);
-            o_wb = carve((size_t)S_PAD * mp * 4);
+            o_wb = carve((size_t)XSPLIT * S_PAD * mp * 4);
             o_pb = carve((size_t)(NA + NZ) * n * 4);
         }
     }
@@ -821,17 +848,25 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
 
     float *cn = logl ? (float *)(W + o_cn) : nullptr;
     dim3 gf((n + 127) / 128), bf(128);
+    int n_fin = n_tiles;   // tiles the finish kernel sums (1 once they are pre-summed)
+    if (!f64) {
+        float *psum = (float *)(W + o_psum);
+        hipLaunchKernelGGL(k_sum_tiles, dim3((n + 255) / 256, npart), dim3(256), 0, s, n, npart, n_tiles,
+                           (const float *)part, psum);
+        part = psum;
+        n_fin = 1;
+    }
     switch (prec) {
         case SPS_F64:
-            hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
         case SPS_F32:
-            hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
         default:
-            hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_tiles, params, z, (const void *)part,
+            hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
                                npart, mag_out, obs, sigma, mask, logl, grad, cn);
             break;
     }
@@ -861,10 +896,19 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         b.C = (float *)(W + o_wb);
         b.ldc = mp;
         b.n_store = S_PAD;
-        const dim3 g2(b.n_mt * b.n_nt), b2(256);
+        // the gradient GEMM has few output tiles (n_mt x 9): split K into XSPLIT ranges whose
+        // partial products are summed by the reduction that reads them anyway
+        b.k_splits = (lw % (XSPLIT * XBK) == 0) ? XSPLIT : 1;
+        b.c_split = (size_t)S_PAD * mp;
+        const dim3 g2(b.n_mt * b.n_nt * b.k_splits), b2(256);
         if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
         else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE>), g2, b2, 0, s, b);
         float *pb = (float *)(W + o_pb);
+        if (b.k_splits > 1) {
+            const size_t n4 = b.c_split / 4;
+            hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, n4, b.k_splits, n4,
+                               (v4f *)b.C);
+        }
         hipLaunchKernelGGL(k_wbar_reduce, dim3((n + 255) / 256, NA + NZ), dim3(256), 0, s, n, (const float *)pw,
                            (const float *)b.C, mp, pb);
         hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,

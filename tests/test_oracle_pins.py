@@ -585,3 +585,24 @@ def test_hmc_metric_adaptation_off_below_twenty_warmup_iterations(orc):
     b = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric=False, **kw)
     assert np.array_equal(a["samples"], b["samples"])
     assert np.all(a["inv_metric"] == 1.0)
+
+
+def test_hmc_dense_metric_adaptation_learns_a_correlated_covariance(orc):
+    # correlated Gaussian (correlation 0.9 between neighbours in two pairs, scales spanning
+    # a decade): the dense adaptation's M^-1 diagonal recovers the variances and the
+    # moments stay right; the diagonal adaptation, which cannot rotate, ends with a smaller
+    # step on the same target
+    sd = np.array([0.1, 0.1, 1.0, 1.0, 0.3, 3.0, 0.5, 2.0, 1.0, 0.2])
+    cor = np.eye(10)
+    cor[0, 1] = cor[1, 0] = 0.9
+    cor[2, 3] = cor[3, 2] = -0.9
+    cov = cor * np.outer(sd, sd)
+    prec = np.linalg.inv(cov)
+    th0 = np.random.default_rng(14).normal(size=(4, 2, 10)) * sd
+    kw = dict(n_chain=4, n_leapfrog=7, n_warmup=1000, n_sample=1000, seed=23, gauss_prec=prec)
+    dn = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric="dense", **kw)
+    ratio = dn["inv_metric"] / sd ** 2
+    assert np.all((ratio > 0.5) & (ratio < 2.0)), ratio
+    np.testing.assert_allclose(dn["post_sd"] / sd, 1.0, atol=0.2)
+    dg = orc.hmc_run(1, None, None, None, None, None, None, th0, adapt_metric="diag", **kw)
+    assert np.median(dn["step"]) > 1.5 * np.median(dg["step"])
