@@ -116,7 +116,7 @@ struct ApproxArgs {
                               // for MODE_LOGPOST_GRAD)
     const float *bounds;      // [10][4]
     const float *prior;       // [10][3]
-    const float *qf, *qa;     // z table in fragment order (forward, adjoint contraction)
+    const uint16_t *qf, *qa;  // z table fragments (forward, adjoint contraction)
     float *orec;              // output records in z-bucket order
 };
 

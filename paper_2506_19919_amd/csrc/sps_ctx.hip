@@ -115,26 +115,32 @@ __global__ void __launch_bounds__(256) k_ztable(int n_ssp, int nkb, int nw, cons
     }
 }
 
-// fragment-order copies of the z table (layouts in sps_internal.h); one thread per float
-__global__ void __launch_bounds__(256) k_qswizzle(int n_z, int R, int nrb, const float *__restrict__ q,
-                                                  float *__restrict__ qf, float *__restrict__ qa) {
-    const size_t per_node = (size_t)nrb * QF_NODE_PER_NRB;
+__device__ inline uint16_t bf16_bits(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// fragment-order BF16 hi/lo copies of the z table (layouts in sps_internal.h); one thread
+// per table value of each layout
+__global__ void __launch_bounds__(256) k_qswizzle(int n_z, int R, const float *__restrict__ q,
+                                                  uint16_t *__restrict__ qf, uint16_t *__restrict__ qa) {
     const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (size_t)n_z * per_node) return;
-    const int node = (int)(t / per_node);
-    const int rem = (int)(t % per_node);
-    const int e = rem & 3, lane = (rem >> 2) & 63, blk = rem >> 8;   // blk = outer * kq_count + kq
+    const size_t total = (size_t)n_z * QB_NODE;
+    if (t >= total) return;
+    const int node = (int)(t / QB_NODE);
+    const int rem = (int)(t % QB_NODE);
+    const int e = rem & 7, lane = (rem >> 3) & 63, blk = rem >> 9;   // blk = outer * KSTEPS + ks
+    const int outer = blk / KSTEPS, ks = blk % KSTEPS;
     const float *qn = q + (size_t)node * R * NA;
-    {   // forward: blk = nb * AGE_BLK + kq
-        const int nb = blk / AGE_BLK, kq = blk % AGE_BLK;
-        const int r = 16 * nb + (lane & 15), i = 16 * kq + 4 * e + (lane >> 4);
-        qf[t] = (r < R && i < NA) ? qn[(size_t)r * NA + i] : 0.0f;
-    }
-    {   // adjoint: blk = na * nrb + kq
-        const int na = blk / nrb, kq = blk % nrb;
-        const int r = 16 * kq + 4 * e + (lane >> 4), i = 16 * na + (lane & 15);
-        qa[t] = (r < R && i < NA) ? qn[(size_t)r * NA + i] : 0.0f;
-    }
+    auto put = [&](uint16_t *dst, int r, int i) {
+        const float v = (r < R && i < NA) ? qn[(size_t)r * NA + i] : 0.0f;
+        const uint16_t hb = bf16_bits(v);
+        dst[t] = hb;
+        dst[total + t] = bf16_bits(v - __uint_as_float((uint32_t)hb << 16));
+    };
+    put(qf, 16 * outer + (lane & 15), 32 * ks + 8 * (lane >> 4) + e);
+    put(qa, 32 * ks + 8 * (lane >> 4) + e, 16 * outer + (lane & 15));
 }
 
 int launch_ztable(sps_ctx *c, hipStream_t st) {
@@ -151,10 +157,9 @@ int launch_ztable(sps_ctx *c, hipStream_t st) {
                        (double)c->k.dz, d_fc, d_fs, c->d_wave, c->d_trap, d_tw);
     hipLaunchKernelGGL(k_ztable, dim3(S), dim3(256), nw * sizeof(double), st, S, nkb, nw, c->d_lum64, d_tw, c->d_q);
     {
-        const int nrb = row_blocks(nb);
-        const size_t total = (size_t)c->k.n_z * nrb * QF_NODE_PER_NRB;
+        const size_t total = (size_t)c->k.n_z * QB_NODE;
         hipLaunchKernelGGL(k_qswizzle, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, c->k.n_z, nb * NZ,
-                           nrb, c->d_q, c->d_qf, c->d_qa);
+                           c->d_q, c->d_qf, c->d_qa);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -419,10 +424,11 @@ int sps_build_ztable(sps_ctx *c, int n_z, double z_lo, double z_hi) {
     (void)hipFree(c->d_q);
     (void)hipFree(c->d_qf);
     (void)hipFree(c->d_qa);
-    c->d_q = c->d_qf = c->d_qa = nullptr;
+    c->d_q = nullptr;
+    c->d_qf = c->d_qa = nullptr;
     c->k.n_z = 0;
     SPS_HIP(hipMalloc(&c->d_q, (size_t)n_z * c->n_band * NZ * NA * sizeof(float)));
-    const size_t frag = (size_t)n_z * row_blocks(c->n_band) * QF_NODE_PER_NRB * sizeof(float);
+    const size_t frag = (size_t)2 * n_z * QB_NODE * sizeof(uint16_t);   // hi and lo
     SPS_HIP(hipMalloc(&c->d_qf, frag));
     SPS_HIP(hipMalloc(&c->d_qa, frag));
     c->k.z_lo = (float)z_lo;

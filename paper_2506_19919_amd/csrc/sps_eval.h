@@ -195,163 +195,119 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
 // ------------------------------------------------------------------ contractions on the matrix cores
 // The wave's 64 galaxies are the M dimension of two small GEMMs per z bucket kb (all lanes
 // take part; a galaxy contributes only in its own bucket's pass, with weight (1 - f) on
-// node kb and f on node kb + 1).  v_mfma_f32_16x16x4f32 fragments: lane l supplies
-// A[m = l % 16][k = l / 16] and B[k = l / 16][n = l % 16]; accumulator register j holds
-// D[m = 4 (l / 16) + j][n = l % 16].  A comes from the LDS columns (slot k of galaxy m),
-// B from the fragment-order tables, D goes back to the LDS columns.
+// node kb and f on node kb + 1).  v_mfma_f32_16x16x32_bf16 with both operands split as BF16
+// hi + lo and three products lo.hi + hi.lo + hi.hi accumulated in FP32 (the dropped lo.lo
+// term and the rounding of lo leave ~2^-16 relative per product; every T term is positive).
+// Fragments: lane l supplies A[m = l % 16][k = 8 (l / 16) + e] and B[k = 8 (l / 16) + e]
+// [n = l % 16], e = 0..7; accumulator register j holds D[m = 4 (l / 16) + j][n = l % 16].
+// A comes from the LDS columns (slot k of galaxy m), scaled by the galaxy's slice weight and
+// split in registers; B from the fragment tables.  Galaxies 0..31 and 32..63 are done in
+// turn, so a half's results overwrite only its own LDS columns.
 
-// Slice weights of the current pass for the accumulator rows this lane holds in the galaxy
-// half h: galaxy 16 (2h + m) + 4 (l / 16) + j in register j.  A galaxy outside the pass's
-// bucket gets 0.
-__device__ inline void pass_weights(float *wl, int lane, int h, bool act, float f, v4f (&w0)[2], v4f (&w1)[2]) {
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+
+// the pass's slice weights of the A rows 16 (2h + m) + l % 16 (0 outside the pass's bucket)
+__device__ inline void pass_weights(float *wl, int lane, int h, bool act, float f, float (&w0)[2], float (&w1)[2]) {
     wl[SLOT_W * WAVE + lane] = act ? 1.0f - f : 0.0f;
     wl[(SLOT_W + 1) * WAVE + lane] = act ? f : 0.0f;
     __syncthreads();
-    const int lk = lane >> 4;
+    const int li = lane & 15;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-        w0[m] = *(const v4f *)(wl + SLOT_W * WAVE + 16 * (2 * h + m) + 4 * lk);
-        w1[m] = *(const v4f *)(wl + (SLOT_W + 1) * WAVE + 16 * (2 * h + m) + 4 * lk);
+        w0[m] = wl[SLOT_W * WAVE + 16 * (2 * h + m) + li];
+        w1[m] = wl[(SLOT_W + 1) * WAVE + 16 * (2 * h + m) + li];
     }
 }
 
-// out += w0 d0 + w1 d1 row by row; rows with zero weight are left untouched (a NaN
-// product of an inactive galaxy cannot leak in)
-__device__ inline void blend(v4f &out, const v4f &w0, const v4f &d0, const v4f &w1, const v4f &d1) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (w0[j] != 0.0f) out[j] = fmaf(w0[j], d0[j], out[j]);
-        if (w1[j] != 0.0f) out[j] = fmaf(w1[j], d1[j], out[j]);
-    }
-}
-
-// One row block (16 output columns) of D_s = A B_s for the galaxy pair of blocks (2h, 2h+1),
-// s = 0, 1 (z nodes kb, kb + 1), K = 16 nk; A from LDS slots 0..16 nk - 1 of those galaxies,
-// B fragments at b0 (node kb) / b1 (node kb + 1), one float4 per k-step group of 4 at
-// stride 256 floats.
-__device__ inline void mfma_block(const float *wl, int lane, int h, int nk, const float *b0, const float *b1,
-                                  size_t kstride, v4f (&d0)[2], v4f (&d1)[2]) {
+// A fragments of k-step ks for the galaxy pair of blocks of half h: w0- and w1-scaled, split
+__device__ inline void a_frags(const float *wl, int lane, int h, int ks, const float (&w0)[2], const float (&w1)[2],
+                               b8v (&a0h)[2], b8v (&a0l)[2], b8v (&a1h)[2], b8v (&a1l)[2]) {
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) d0[m] = d1[m] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the A and B fragments of step kq + 1 are in flight while step kq's products issue (B
-    // comes from L2, whose latency one step of 16 products covers); the scheduling fence
-    // keeps the compiler from hoisting the loads of later blocks (registers)
-    __builtin_amdgcn_sched_barrier(0);
-    v4f n0 = *(const v4f *)b0, n1 = *(const v4f *)b1;
-    float na[4][2];
+    for (int m = 0; m < 2; ++m) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int m = 0; m < 2; ++m) na[e][m] = wl[(4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
-#pragma unroll 1
-    for (int kq = 0; kq < nk; ++kq) {
-        const v4f q0 = n0, q1 = n1;
-        float a[4][2];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int m = 0; m < 2; ++m) a[e][m] = na[e][m];
-        if (kq + 1 < nk) {
-            n0 = *(const v4f *)(b0 + (kq + 1) * kstride);
-            n1 = *(const v4f *)(b1 + (kq + 1) * kstride);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int m = 0; m < 2; ++m) na[e][m] = wl[(16 * (kq + 1) + 4 * e + lk) * WAVE + 16 * (2 * h + m) + li];
+        for (int e = 0; e < 8; ++e) {
+            const float v = wl[(32 * ks + 8 * lk + e) * WAVE + 16 * (2 * h + m) + li];
+            // a zero weight gives an exact zero (a NaN column of an inactive galaxy stays out)
+            const float x0 = (w0[m] != 0.0f) ? v * w0[m] : 0.0f, x1 = (w1[m] != 0.0f) ? v * w1[m] : 0.0f;
+            const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+            a0h[m][e] = h0;
+            a0l[m][e] = (__bf16)(x0 - (float)h0);
+            a1h[m][e] = h1;
+            a1l[m][e] = (__bf16)(x1 - (float)h1);
         }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                d0[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e][m], q0[e], d0[m], 0, 0, 0);
-                d1[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e][m], q1[e], d1[m], 0, 0, 0);
-            }
     }
 }
 
-// T[g][r] = (1 - f) sum_i P_age[g][i] Qk[r][i] + f sum_i P_age[g][i] Qk+1[r][i]; P_age in
-// slots 0..95 (94, 95 zero), T written to slots 0..R-1.  Galaxies 0..31 and 32..63 in
-// turn: a half's row sums overwrite only its own P_age columns.
-__device__ inline void contract_forward(const DevConsts &k, const float *qf, float *wl, int lane, int kk, float f,
-                                        int kmin, int kmax) {
-    const int nrb = row_blocks(k.n_band), R = k.n_band * NZ;
+__device__ inline v4f mfma3(const b8v &ah, const b8v &al, const b8v &bh, const b8v &bl, v4f acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+// one contraction: D[g][n] = sum_s w_s(g) sum_k A[g][k] B_s[k][n] over K = 96 (3 k-steps),
+// N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo)
+template <int MODE_ADJ>
+__device__ inline void contract(const DevConsts &k, const uint16_t *q, float *wl, int lane, int kk, float f,
+                                int kmin, int kmax, int nbk, int n_out) {
     const int li = lane & 15, lk = lane >> 4;
-    const size_t node = (size_t)nrb * QF_NODE_PER_NRB;
+    const size_t lo_off = (size_t)k.n_z * QB_NODE;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        v4f out[6][2];
+        v4f acc[6][2];
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
 #pragma unroll
-            for (int m = 0; m < 2; ++m) out[nb][m] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int m = 0; m < 2; ++m) acc[nb][m] = v4f{0.f, 0.f, 0.f, 0.f};
         for (int kb = kmin; kb <= kmax; ++kb) {
             const bool act = (kk == kb);
             if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-            v4f w0[2], w1[2];
+            float w0[2], w1[2];
             pass_weights(wl, lane, h, act, f, w0, w1);
-            const float *b0 = qf + (size_t)kb * node + lane * 4;
+            const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
+#pragma unroll 1
+            for (int ks = 0; ks < KSTEPS; ++ks) {
+                b8v a0h[2], a0l[2], a1h[2], a1l[2];
+                a_frags(wl, lane, h, ks, w0, w1, a0h, a0l, a1h, a1l);
 #pragma unroll
-            for (int nb = 0; nb < 6; ++nb) {
-                if (nb >= nrb) break;
-                v4f d0[2], d1[2];
-                const float *bb = b0 + (size_t)nb * AGE_BLK * 256;
-                mfma_block(wl, lane, h, AGE_BLK, bb, bb + node, 256, d0, d1);
+                for (int nb = 0; nb < 6; ++nb) {
+                    if (nb >= nbk) break;
+                    const size_t o = (size_t)(nb * KSTEPS + ks) * 512;
+                    const b8v q0h = *(const b8v *)(b0 + o), q0l = *(const b8v *)(b0 + lo_off + o);
+                    const b8v q1h = *(const b8v *)(b1 + o), q1l = *(const b8v *)(b1 + lo_off + o);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) blend(out[nb][m], w0[m], d0[m], w1[m], d1[m]);
+                    for (int m = 0; m < 2; ++m) {
+                        acc[nb][m] = mfma3(a0h[m], a0l[m], q0h, q0l, acc[nb][m]);
+                        acc[nb][m] = mfma3(a1h[m], a1l[m], q1h, q1l, acc[nb][m]);
+                    }
+                }
             }
             __syncthreads();   // the next pass rewrites the weight slots
         }
+        // all of this half's A reads are done: its results overwrite its own columns
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
-            if (nb < nrb && 16 * nb + li < R) {
+            if (nb < nbk && 16 * nb + li < n_out) {
 #pragma unroll
                 for (int m = 0; m < 2; ++m)
-                    *(v4f *)(wl + (16 * nb + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = out[nb][m];
+                    *(v4f *)(wl + (16 * nb + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = acc[nb][m];
             }
         __syncthreads();
     }
 }
 
-// dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..16 NRB - 1
-// (zero from R on), dP_age written to slots 0..NA-1.  Galaxy halves as above.
-__device__ inline void contract_adjoint(const DevConsts &k, const float *qa, float *wl, int lane, int kk, float f,
+// T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]); P_age in slots 0..95
+// (94, 95 zero), T written to slots 0..R-1
+__device__ inline void contract_forward(const DevConsts &k, const uint16_t *qf, float *wl, int lane, int kk, float f,
                                         int kmin, int kmax) {
-    const int nrb = row_blocks(k.n_band);
-    const int li = lane & 15, lk = lane >> 4;
-    const size_t node = (size_t)nrb * QF_NODE_PER_NRB;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        v4f out[6][2];
-#pragma unroll
-        for (int na = 0; na < 6; ++na)
-#pragma unroll
-            for (int m = 0; m < 2; ++m) out[na][m] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int kb = kmin; kb <= kmax; ++kb) {
-            const bool act = (kk == kb);
-            if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-            v4f w0[2], w1[2];
-            pass_weights(wl, lane, h, act, f, w0, w1);
-            const float *b0 = qa + (size_t)kb * node + lane * 4;
-#pragma unroll
-            for (int na = 0; na < 6; ++na) {
-                v4f d0[2], d1[2];
-                const float *bb = b0 + (size_t)na * nrb * 256;
-                mfma_block(wl, lane, h, nrb, bb, bb + node, 256, d0, d1);
-#pragma unroll
-                for (int m = 0; m < 2; ++m) blend(out[na][m], w0[m], d0[m], w1[m], d1[m]);
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int na = 0; na < 6; ++na)
-            if (16 * na + li < NA) {
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    *(v4f *)(wl + (16 * na + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = out[na][m];
-            }
-        __syncthreads();
-    }
+    contract<0>(k, qf, wl, lane, kk, f, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
+}
+
+// dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..95 (zero
+// from R on), dP_age written to slots 0..NA-1
+__device__ inline void contract_adjoint(const DevConsts &k, const uint16_t *qa, float *wl, int lane, int kk, float f,
+                                        int kmin, int kmax) {
+    contract<1>(k, qa, wl, lane, kk, f, kmin, kmax, AGE_BLK, NA);
 }
 
 // ------------------------------------------------------------------ one evaluation
@@ -361,7 +317,7 @@ __device__ inline void contract_adjoint(const DevConsts &k, const float *qa, flo
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
 // the lanes' buckets.  wl: the wave's LDS block (LDS_SLOTS x 64 floats).
 template <int MODE>
-__device__ inline void approx_eval(const DevConsts &k, int sfh, const float *qf, const float *qa, float *wl,
+__device__ inline void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa, float *wl,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
@@ -433,7 +389,7 @@ __device__ inline void approx_eval(const DevConsts &k, int sfh, const float *qf,
 #pragma unroll
         for (int j = 0; j < NZ; ++j)
             if (b < nb) col[b * NZ + j] = sbar[b] * pz[j];
-    for (int r = nb * NZ; r < 16 * row_blocks(nb); ++r) col[r] = 0.0f;
+    for (int r = nb * NZ; r < 32 * KSTEPS; ++r) col[r] = 0.0f;
     // dP_age(i) = sum_{b,j} sbar_b P_Z(j) Qz[b][j][i]
     contract_adjoint(k, qa, wl, lane, kk, f, kmin, kmax);
     adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);

@@ -49,7 +49,7 @@ struct HmcArgs {
     const uint8_t *mask;
     const float *bounds, *prior, *theta0;
     const int *perm;
-    const float *qf, *qa;
+    const uint16_t *qf, *qa;
     float *samples;
     // chain state, indexed by slot = rank * C + chain
     float *x, *gr, *eps, *hbar, *lebar, *mu, *minv;

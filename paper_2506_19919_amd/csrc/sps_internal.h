@@ -17,16 +17,17 @@ constexpr int NB_MAX = SPS_MAX_BAND;
 constexpr int NP = SPS_NPARAM;
 constexpr int NGL_DL = 12;        // half of the 24-point Gauss-Legendre rule for D_L
 
-// Matrix-core fragment tables of the z table (v_mfma_f32_16x16x4f32 B operands).
-// With R = n_band * NZ table rows (r = b * NZ + j) and NRB = ceil(R / 16) row blocks,
-// per z node (node stride QF_NODE(NRB) floats in both):
-//   qf[nb][kq][lane][e] = Q[r = 16 nb + lane % 16][i = 16 kq + 4 e + lane / 16]   nb < NRB, kq < 6
-//   qa[na][kq][lane][e] = Q[r = 16 kq + 4 e + lane / 16][i = 16 na + lane % 16]   na < 6,   kq < NRB
-// zero where r >= R or i >= NA; one float4 per lane covers 4 consecutive k-steps of 4.
+// Matrix-core fragment tables of the z table: B operands of v_mfma_f32_16x16x32_bf16, the
+// table split as BF16 hi + lo (hi = bf16(Q), lo = bf16(Q - hi)).  With R = n_band * NZ table
+// rows (r = b * NZ + j), per z node (QB_NODE bf16 values in each of the four arrays):
+//   qf[nb][ks][lane][e] = Q[r = 16 nb + lane % 16][i = 32 ks + 8 (lane / 16) + e]   nb < 6, ks < 3
+//   qa[na][ks][lane][e] = Q[r = 32 ks + 8 (lane / 16) + e][i = 16 na + lane % 16]   na < 6, ks < 3
+// zero where r >= R or i >= NA; one 16-byte load per lane per fragment.
 constexpr int AGE_BLK = 6;        // 96 padded ages = 6 blocks of 16
-constexpr int S_PAD = 1152;       // SSP rows padded to a multiple of 128
-constexpr int QF_NODE_PER_NRB = AGE_BLK * 64 * 4;
+constexpr int KSTEPS = 3;         // 96 padded ages or rows = 3 k-steps of 32
+constexpr int QB_NODE = 6 * KSTEPS * 64 * 8;
 __host__ __device__ inline int row_blocks(int n_band) { return (n_band * NZ + 15) / 16; }
+constexpr int S_PAD = 1152;       // SSP rows padded to a multiple of 128
 
 // Kernel-facing constants, passed by value (kernarg segment).
 struct DevConsts {
@@ -70,8 +71,8 @@ struct sps_ctx {
     double *d_wave = nullptr, *d_trap = nullptr;
     double *d_edges = nullptr;     // FP64 bin edges: age_lo, age_hi [Gyr], lage_lo, lage_hi [NA each], met_lo, met_hi [NZ]
     float *d_q = nullptr;          // [n_z][n_band][n_met][n_age]
-    float *d_qf = nullptr;         // z table in matrix-core fragment order, forward contraction
-    float *d_qa = nullptr;         // z table in matrix-core fragment order, adjoint contraction
+    uint16_t *d_qf = nullptr;      // z table fragments, forward contraction: hi [n_z][QB_NODE], then lo
+    uint16_t *d_qa = nullptr;      // z table fragments, adjoint contraction: hi, then lo
     // per-galaxy workspace
     int max_gal = 0;
     int *d_perm = nullptr;         // galaxies ordered by z bucket

@@ -73,7 +73,7 @@ __device__ inline float tri_dcdf(float u) {
 struct Dpl {
     float tau, am1, bp1, ltau, inv_w;
     float s_l2, b_l2;   // (alpha + beta) log2(e), (beta + 1) log2(e)
-    float inv_bp1;
+    float inv_bp1, inv_tau;
 };
 __device__ inline Dpl make_dpl(float tau, float al, float be) {
     Dpl d;
@@ -86,6 +86,7 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
     d.s_l2 = (al + be) * 1.4426950408889634f;
     d.b_l2 = d.bp1 * 1.4426950408889634f;
     d.inv_bp1 = 1.0f / d.bp1;
+    d.inv_tau = 1.0f / tau;
     return d;
 }
 
@@ -137,7 +138,7 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
         span = xhi - xlo;
         tail = p.tau * __builtin_amdgcn_exp2f(p.b_l2 * xlo) * p.inv_bp1;
         if (DERIV) {
-            tail_t = -(p.bp1 - 1.0f) * tail / p.tau;
+            tail_t = -(p.bp1 - 1.0f) * tail * p.inv_tau;
             tail_b = tail * (xlo - p.inv_bp1);
         }
     }
@@ -151,7 +152,7 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     } else {
         int n = (int)ceilf(npan);
         n = min(max(n, 1), 64);
-        hw = 0.5f * span / (float)n;
+        hw = 0.5f * span * __builtin_amdgcn_rcpf((float)n);   // n is a small integer
         const float xlo = xhi - span;
         for (int q = 0; q < n; ++q) {
             const float c = xlo + (float)(2 * q + 1) * hw;
@@ -161,7 +162,7 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     }
     m = fmaf(s, hw, tail);
     if (DERIV) {
-        d_tau = fmaf(st * hw, 1.0f / p.tau, tail_t);
+        d_tau = fmaf(st * hw, p.inv_tau, tail_t);
         d_al = sa * hw;
         d_be = fmaf(sb, hw, tail_b);
     }
