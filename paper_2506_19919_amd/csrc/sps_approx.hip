@@ -99,9 +99,12 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
             r[REC_SIG + b] = (ga.sigma && b < nb) ? ga.sigma[(size_t)i * nb + b] : 1.0f;
         }
         r[REC_MASK] = __int_as_float(ga.mask ? (int)ga.mask[i] : 0xff);
-        r[REC_ORIG] = __int_as_float(i);
-#pragma unroll
-        for (int q = REC_ORIG + 1; q < REC; ++q) r[q] = 0.0f;
+        // per-galaxy cosmology, once per call here rather than in the model kernel
+        const double t_obs = age_universe_gyr(k, (double)z[i]), m0 = mag_offset(k, (double)z[i]);
+        r[REC_TOBS] = __int_as_float(__double2loint(t_obs));
+        r[REC_TOBS + 1] = __int_as_float(__double2hiint(t_obs));
+        r[REC_M0] = __int_as_float(__double2loint(m0));
+        r[REC_M0 + 1] = __int_as_float(__double2hiint(m0));
         v4f *dst = (v4f *)(ga.rec + (size_t)at * REC);
 #pragma unroll
         for (int q = 0; q < REC / 4; ++q) dst[q] = v4f{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
@@ -126,10 +129,11 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
-    // parameters, z and mask from the record now; observations and sigma are read from it
-    // where the likelihood needs them (not held in registers through the model)
+    // parameters, z, mask and the cosmology from the record now; observations and sigma are
+    // read from it where the likelihood needs them (not held in registers through the model)
     const float *rec = a.rec + (size_t)(valid ? idx : a.n - 1) * REC;
     float r[12];
+    const v4f cosmo = *(const v4f *)(rec + REC_TOBS);
     {
         const v4f *src = (const v4f *)rec;
 #pragma unroll
@@ -152,8 +156,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     float f;
     int kk = z_bucket(k, zf, &f);
     if (!valid) kk = -1;
-    const double t_obs = age_universe_gyr(k, (double)zf);
-    const double m0 = mag_offset(k, (double)zf) - 2.5 * (double)th[0];
+    const double t_obs = __hiloint2double(__float_as_int(cosmo[1]), __float_as_int(cosmo[0]));
+    const double m0 = __hiloint2double(__float_as_int(cosmo[3]), __float_as_int(cosmo[2])) - 2.5 * (double)th[0];
     const int kmin = wave_min_i(kk < 0 ? 1 << 30 : kk);
     const int kmax = wave_max_i(kk);
     const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : (uint32_t)__float_as_int(rec[REC_MASK]);

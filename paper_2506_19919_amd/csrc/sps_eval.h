@@ -63,7 +63,8 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
     const float t_obs_f = (float)t_obs;
     double S = 0.0;
     if (sfh == SPS_SFH_DPL) {
-        const Dpl p = make_dpl(th[1], th[2], th[3]);
+        Dpl p = make_dpl(th[1], th[2], th[3]);
+        dpl_at_obs(p, t_obs_f);
         for (int i = q; i < NA; i += G) {
             float m, a, b, c;
             dpl_bin<false>(k, i, t_obs_f, p, m, a, b, c);
@@ -125,7 +126,10 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     float A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
     double dA0 = 0.0, dA1 = 0.0, dB0 = 0.0, dB1 = 0.0;
     Dpl p;
-    if (sfh == SPS_SFH_DPL) p = make_dpl(th[1], th[2], th[3]);
+    if (sfh == SPS_SFH_DPL) {
+        p = make_dpl(th[1], th[2], th[3]);
+        dpl_at_obs(p, t_obs_f);
+    }
     // smooth part: dP_age/dF_burst = P_burst - P_smooth; the P_burst term is added below
     for (int i = q; i < NA; i += G) {
         const float gbar = col[i];
@@ -310,6 +314,14 @@ __device__ inline void contract_adjoint(const DevConsts &k, const uint16_t *qa, 
     contract<1>(k, qa, wl, lane, kk, f, kmin, kmax, AGE_BLK, NA);
 }
 
+// log10 of a positive double to ~3e-8 absolute: the binary exponent exactly, the mantissa
+// in [0.5, 1) by the FP32 logarithm
+__device__ inline double log10_split(double x) {
+    int e;
+    const double mt = frexp(x, &e);
+    return (double)e * 0.30102999566398120 + (double)log10f((float)mt);
+}
+
 // ------------------------------------------------------------------ one evaluation
 // Magnitudes (MODE_MAGS) or log-likelihood with its gradient w.r.t. the physical
 // parameters (MODE_LOGL_GRAD) for the lane's galaxy.  Every lane of the (single-wave)
@@ -350,7 +362,7 @@ __device__ inline void approx_eval(const DevConsts &k, int sfh, const uint16_t *
 #pragma unroll
         for (int j = 0; j < NZ; ++j) sb += (double)pz[j] * (double)col[b * NZ + j];
         const DustVal d = dust_at(k.lam_eff[b] / (opz * 5500.0f), tauv, delta, ffl);
-        const double mag = m0 - 2.5 * log10((double)d.F * sb);
+        const double mag = m0 - 2.5 * log10_split((double)d.F * sb);
         if (MODE == MODE_MAGS) {
             mag_out[b] = (float)mag;
             continue;
@@ -358,7 +370,7 @@ __device__ inline void approx_eval(const DevConsts &k, int sfh, const uint16_t *
         if ((mask >> b) & 1u) {
             const double s = sig_g[b];
             const double r = (mag - (double)obs_g[b]) / s;
-            logl_d += -0.5 * r * r - log(s * 2.5066282746310002);
+            logl_d += -0.5 * r * r - (double)logf(sig_g[b] * 2.5066282746310002f);
             if (MODE != MODE_LOGL) {
                 const float gm = (float)(-r / s);            // d logL / d m_b
                 const float c = gm * (-2.5f / LN10F);        // d logL / d ln(F S)

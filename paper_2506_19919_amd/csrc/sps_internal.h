@@ -99,7 +99,9 @@ int launch_ztable(sps_ctx *c, hipStream_t s);   // also fills d_qf, d_qa
 // Inputs gathered into z-bucket order by the sort (coalesced reads in the caller's order,
 // one full-line record write per galaxy): record layout, REC floats per galaxy.
 constexpr int REC = 32;
-enum { REC_Z = 10, REC_OBS = 11, REC_SIG = 19, REC_MASK = 27, REC_ORIG = 28 };
+// slots 28..31: age of the universe at z [Gyr] and the distance part of the magnitude
+// offset, each as an FP64 value in two words (low, high)
+enum { REC_Z = 10, REC_OBS = 11, REC_SIG = 19, REC_MASK = 27, REC_TOBS = 28, REC_M0 = 30 };
 constexpr int OREC = 16;          // output record: mags[8] or (value, grad[10])
 struct GatherArgs {
     const float *params, *obs, *sigma;  // obs, sigma may be null (magnitudes only)
