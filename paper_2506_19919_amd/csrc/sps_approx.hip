@@ -168,10 +168,14 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
+    // whole 64-byte records (full-line writes)
     v4f *dst = (v4f *)(a.orec + (size_t)idx * OREC);
+    const v4f zero4 = v4f{0.f, 0.f, 0.f, 0.f};
     if (MODE == MODE_MAGS) {
         dst[0] = v4f{mags[0] + bad, mags[1] + bad, mags[2] + bad, mags[3] + bad};
         dst[1] = v4f{mags[4] + bad, mags[5] + bad, mags[6] + bad, mags[7] + bad};
+        dst[2] = zero4;
+        dst[3] = zero4;
         return;
     }
     float val = (float)logl;
@@ -187,11 +191,15 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     }
     if (MODE == MODE_LOGL) {
         dst[0] = v4f{val + bad, 0.f, 0.f, 0.f};
+        dst[1] = zero4;
+        dst[2] = zero4;
+        dst[3] = zero4;
         return;
     }
     dst[0] = v4f{val + bad, gr[0] + bad, gr[1] + bad, gr[2] + bad};
     dst[1] = v4f{gr[3] + bad, gr[4] + bad, gr[5] + bad, gr[6] + bad};
     dst[2] = v4f{gr[7] + bad, gr[8] + bad, gr[9] + bad, 0.f};
+    dst[3] = zero4;
 }
 
 // results back into the caller's order: thread i reads its galaxy's record (one line)

@@ -102,10 +102,9 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
         burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
         col[i0 + t] = fmaf(bz, p, col[i0 + t]);
     }
-#pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        float dp;
-        met_bin(k, j, th[6], pz[j], dp);
+    {
+        float unused[NZ];
+        met_weights<false>(k, th[6], pz, unused);
     }
     ws.S = S;
     ws.Zb = Zb;
@@ -187,11 +186,11 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
     g[4] += fbar;
     g[5] += (e1 - e2 * e3) * invZ;
     float mbar = 0.0f;
+    {
+        float pzj[NZ], dpz[NZ];
+        met_weights<true>(k, th[6], pzj, dpz);
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-        float pzj, dpz;
-        met_bin(k, j, th[6], pzj, dpz);
-        mbar = fmaf(pzbar[j], dpz, mbar);
+        for (int j = 0; j < NZ; ++j) mbar = fmaf(pzbar[j], dpz[j], mbar);
     }
     g[6] += mbar;
 }

@@ -282,11 +282,28 @@ __device__ inline int first_bin_above(const DevConsts &k, float v) {
 }
 
 // ------------------------------------------------------------------ metallicity
-__device__ inline void met_bin(const DevConsts &k, int j, float mu, float &p, float &dp) {
-    const float xl = (k.met_lo[j] - mu) / k.sigma_logz, xh = (k.met_hi[j] - mu) / k.sigma_logz;
-    // upper-tail bins by the complementary CDF (no cancellation against 1)
-    p = (xl > 0.0f) ? Phi_f(-xl) - Phi_f(-xh) : Phi_f(xh) - Phi_f(xl);
-    dp = (phi_f(xl) - phi_f(xh)) / k.sigma_logz;
+// All NZ metallicity weights (normal CDF differences over the bin edges) and, if DERIV, their
+// derivatives w.r.t. mu; each interior edge is evaluated once.  An edge at standardised
+// x carries the tail value T = 0.5 erfc(|x| / sqrt 2) (Phi(x) for x <= 0, 1 - Phi(x) for
+// x > 0) so that no bin difference cancels against 1.
+template <bool DERIV>
+__device__ inline void met_weights(const DevConsts &k, float mu, float (&pz)[NZ], float (&dpz)[NZ]) {
+    const float inv_s = 1.0f / k.sigma_logz;
+    float xp = -INFINITY, tp = 0.0f, dp = 0.0f;   // the open lower edge
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        float x = INFINITY, t = 0.0f, d = 0.0f;    // the open upper edge of the last bin
+        if (j < NZ - 1) {
+            x = (k.met_hi[j] - mu) * inv_s;
+            t = 0.5f * erfcf(0.7071067811865475f * fabsf(x));
+            d = phi_f(x);
+        }
+        pz[j] = (xp > 0.0f) ? tp - t : ((x <= 0.0f) ? t - tp : 1.0f - tp - t);
+        if (DERIV) dpz[j] = (dp - d) * inv_s;
+        xp = x;
+        tp = t;
+        dp = d;
+    }
 }
 
 // ------------------------------------------------------------------ dust at one wavelength

@@ -172,3 +172,49 @@ def test_full_size_loglike_sampled(ctx, orc):
     assert np.abs(m_all[pick] - m_ref).max() <= 1e-4
     assert np.all(np.abs(ll - rl) < 0.05 + 1e-4 * np.abs(rl))
     assert grad_ok(g, rg, prop).all()
+
+
+def test_parameter_box_corners_match_oracle(ctx, orc):
+    # every parameter at its bounds (or at the edge of the workload ranges) one at a time on
+    # top of a mid-range galaxy: flat and steep double power laws, tau at both ends, bursts
+    # older and younger than the whole age grid, no / maximal dust, grey dust, full floor,
+    # and a galaxy with no band in its mask (log L = 0, zero gradient)
+    base = np.array([10.0, 3.0, 2.0, 2.0, 0.05, 7.0, -0.5, 1.0, -0.7, 0.1])
+    cases = [(1, 0.1), (1, 14.0), (2, 0.1), (2, 8.0), (3, 0.1), (3, 8.0), (4, 0.0), (4, 0.2),
+             (5, 4.5), (5, 8.5), (6, -2.0), (6, 0.4), (7, 0.0), (7, 4.0), (8, 0.0), (8, -1.5),
+             (9, 0.0), (9, 0.5)]
+    th = np.tile(base, (len(cases) + 1, 1))
+    for r, (p, v) in enumerate(cases):
+        th[r, p] = v
+    th, n = f32(th), len(th)
+    z = f32(np.linspace(0.12, 2.9, n))
+    sfh = synth.SFH_DPL
+    m = ctx.phot_approx(sfh, soa(th), dev(z)).cpu().numpy()
+    m_ref = orc.phot_approx(sfh, th, z)
+    assert np.abs(m - m_ref).max() <= MAG_TOL, np.abs(m - m_ref).max(axis=1)
+    obs, sig, masks = _obs(orc, sfh, th, z, 21)
+    masks[-1] = 0
+    ll, g = ctx.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8))
+    ll, g = ll.cpu().numpy().astype(np.float64), g.cpu().numpy().T.astype(np.float64)
+    rl, rg = orc.loglike_grad(sfh, th, z, obs, sig, masks)
+    prop, _ = grad_tol(orc, sfh, th, z, sig, masks, m)
+    assert ll[-1] == 0.0 and np.all(g[-1] == 0.0)
+    assert np.all(np.abs(ll - rl) <= 1e-3 * np.abs(rl) + 1e-4)
+    ok = grad_ok(g, rg, prop)
+    assert ok.all(), (np.argwhere(~ok)[:10], g[~ok][:10], rg[~ok][:10])
+
+
+def test_weights_at_parameter_box_corners(ctx, orc):
+    base = np.array([10.0, 3.0, 2.0, 2.0, 0.05, 7.0, -0.5, 1.0, -0.7, 0.1])
+    rows = []
+    for p, v in [(1, 0.1), (1, 14.0), (2, 8.0), (3, 8.0), (4, 0.2), (5, 4.5), (5, 8.5), (6, -2.0), (6, 0.4)]:
+        t = base.copy()
+        t[p] = v
+        rows.append(t)
+    th = f32(np.array(rows))
+    z = f32(np.linspace(0.1, 3.0, len(th)))
+    w = ctx.weights(synth.SFH_DPL, soa(th), dev(z)).cpu().numpy().astype(np.float64)
+    ref = orc.weights(synth.SFH_DPL, th, z)
+    for g in range(len(th)):
+        np.testing.assert_allclose(w[g].sum(), 10 ** th[g, 0], rtol=2e-5)
+        np.testing.assert_allclose(w[g], ref[g], rtol=1e-4, atol=1e-7 * 10 ** th[g, 0])
