@@ -74,6 +74,7 @@ struct Dpl {
     float tau, am1, bp1, ltau, inv_w;
     float s_l2, b_l2;   // (alpha + beta) log2(e), (beta + 1) log2(e)
     float inv_bp1, inv_tau;
+    float alpha, ab;         // alpha, alpha + beta
     float x_obs, inv_tobs;   // ln(t_obs / tau), 1 / t_obs: set by dpl_at_obs
 };
 
@@ -99,6 +100,8 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
     d.b_l2 = d.bp1 * 1.4426950408889634f;
     d.inv_bp1 = 1.0f / d.bp1;
     d.inv_tau = 1.0f / tau;
+    d.alpha = al;
+    d.ab = al + be;
     return d;
 }
 
@@ -108,23 +111,26 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
 // derivatives within ~8e-5, over tau 0.1-14 Gyr, alpha, beta 0.1-8, z 0.1-3
 constexpr float GL2X = 0.57735026918962576f;
 
-// integrand tau / (e^{(alpha-1)X} + e^{-(beta+1)X}) at X, accumulated with weight wg,
-// plus its derivatives w.r.t. (tau, alpha, beta) if DERIV.  Written without overflow:
-//   h = tau fB e^{(beta+1)X},  fB = 1 / (1 + e^{(alpha+beta)X}),  fA = e^{(alpha+beta)X} fB,
-//   dh/dalpha = -h X fA,  dh/dbeta = h X fB,  dh/dtau = (h/tau) (1 + (alpha-1) fA - (beta+1) fB).
+// integrand h = tau g(X), g = 1 / (e^{(alpha-1)X} + e^{-(beta+1)X}), at X with weight wg.
+// Written without overflow as g = fB e^{(beta+1)X}, fB = 1 / (1 + e^{(alpha+beta)X}), and
+// with fA = 1 - fB:
+//   dh/dtau = g (alpha - (alpha+beta) fB)   (X = ln(t/tau) moves with tau),
+//   dh/dalpha = -tau g X (1 - fB),  dh/dbeta = tau g X fB,
+// so four sums carry the derivatives: s = sum w g, sf = sum w g fB, sa = sum w g X fA and
+// sb = sum w g X fB (tau is applied once per bin; fA is formed as e fB, not 1 - fB, which
+// would lose its relative precision where it is small).
 template <bool DERIV>
-__device__ inline void dpl_node(const Dpl &p, float X, float wg, float &s, float &st, float &sa, float &sb) {
+__device__ inline void dpl_node(const Dpl &p, float X, float wg, float &s, float &sf, float &sa, float &sb) {
     const float ed = __builtin_amdgcn_exp2f(p.s_l2 * X);
     const float eb = __builtin_amdgcn_exp2f(p.b_l2 * X);
     const float fB = __builtin_amdgcn_rcpf(1.0f + ed);
-    const float h = p.tau * fB * eb;
-    s = fmaf(wg, h, s);
+    const float t = wg * fB * eb;
+    s += t;
     if (DERIV) {
-        const float fA = (ed < 3.0e38f) ? ed * fB : 1.0f;
-        const float hw = wg * h;
-        st = fmaf(hw, 1.0f + p.am1 * fA - p.bp1 * fB, st);   // times 1/tau after the sum
-        sa = fmaf(-hw * X, fA, sa);
-        sb = fmaf(hw * X, fB, sb);
+        const float tx = t * X, fA = (ed < 3.0e38f) ? ed * fB : 1.0f;
+        sf = fmaf(t, fB, sf);
+        sa = fmaf(tx, fA, sa);
+        sb = fmaf(tx, fB, sb);
     }
 }
 
@@ -162,13 +168,13 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
             tail_b = tail * (xlo - p.inv_bp1);
         }
     }
-    float s = 0.0f, st = 0.0f, sa = 0.0f, sb = 0.0f, hw;
+    float s = 0.0f, sf = 0.0f, sa = 0.0f, sb = 0.0f, hw;
     const float npan = span * p.inv_w;
     if (npan <= 0.25f) {
         hw = 0.5f * span;
         const float c = xhi - hw, d = hw * GL2X;
-        dpl_node<DERIV>(p, c - d, 1.0f, s, st, sa, sb);
-        dpl_node<DERIV>(p, c + d, 1.0f, s, st, sa, sb);
+        dpl_node<DERIV>(p, c - d, 1.0f, s, sf, sa, sb);
+        dpl_node<DERIV>(p, c + d, 1.0f, s, sf, sa, sb);
     } else {
         int n = (int)ceilf(npan);
         n = min(max(n, 1), 64);
@@ -177,14 +183,15 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
         for (int q = 0; q < n; ++q) {
             const float c = xlo + (float)(2 * q + 1) * hw;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) dpl_node<DERIV>(p, fmaf(hw, GL4X[g], c), GL4W[g], s, st, sa, sb);
+            for (int g = 0; g < 4; ++g) dpl_node<DERIV>(p, fmaf(hw, GL4X[g], c), GL4W[g], s, sf, sa, sb);
         }
     }
-    m = fmaf(s, hw, tail);
+    const float th = p.tau * hw;
+    m = fmaf(s, th, tail);
     if (DERIV) {
-        d_tau = fmaf(st * hw, p.inv_tau, tail_t);
-        d_al = sa * hw;
-        d_be = fmaf(sb, hw, tail_b);
+        d_tau = fmaf(hw, p.alpha * s - p.ab * sf, tail_t);
+        d_al = -th * sa;
+        d_be = fmaf(sb, th, tail_b);
     }
 }
 
