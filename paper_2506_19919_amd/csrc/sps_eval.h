@@ -45,6 +45,14 @@ __device__ inline T group_sum(T v) {
     return v;
 }
 
+// log10 of a positive double to ~3e-8 absolute: the binary exponent exactly, the mantissa
+// in [0.5, 1) by the FP32 logarithm
+__device__ inline double log10_split(double x) {
+    int e;
+    const double mt = frexp(x, &e);
+    return (double)e * 0.30102999566398120 + (double)log10f((float)mt);
+}
+
 // ------------------------------------------------------------------ forward weights
 // Returns the burst normaliser and the total smooth mass (needed by the adjoint).
 struct WeightsState {
@@ -82,7 +90,7 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
     S = group_sum<G>(S);
     // burst: only the bins the triweight window [mu - 3 sigma, mu + 3 sigma] touches; a bin
     // is handled by the lane that owns it
-    const float l_obs = (float)log10(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
+    const float l_obs = (float)log10_split(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
     const int i0 = first_bin_above(k, mu - 3.0f * k.burst_sig);
     float Zb = 0.0f;
     for (int t = 0; t < k.burst_nbins; ++t) {
@@ -251,7 +259,7 @@ __device__ inline v4f mfma3(const b8v &ah, const b8v &al, const b8v &bh, const b
 // one contraction: D[g][n] = sum_s w_s(g) sum_k A[g][k] B_s[k][n] over K = 96 (3 k-steps),
 // N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo)
 template <int MODE_ADJ>
-__device__ inline void contract(const DevConsts &k, const uint16_t *q, float *wl, int lane, int kk, float f,
+__device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, float *wl, int lane, int kk, float f,
                                 int kmin, int kmax, int nbk, int n_out) {
     const int li = lane & 15, lk = lane >> 4;
     const size_t lo_off = (size_t)k.n_z * QB_NODE;
@@ -301,24 +309,16 @@ __device__ inline void contract(const DevConsts &k, const uint16_t *q, float *wl
 
 // T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]); P_age in slots 0..95
 // (94, 95 zero), T written to slots 0..R-1
-__device__ inline void contract_forward(const DevConsts &k, const uint16_t *qf, float *wl, int lane, int kk, float f,
+__device__ __forceinline__ void contract_forward(const DevConsts &k, const uint16_t *qf, float *wl, int lane, int kk, float f,
                                         int kmin, int kmax) {
     contract<0>(k, qf, wl, lane, kk, f, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
 }
 
 // dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..95 (zero
 // from R on), dP_age written to slots 0..NA-1
-__device__ inline void contract_adjoint(const DevConsts &k, const uint16_t *qa, float *wl, int lane, int kk, float f,
+__device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint16_t *qa, float *wl, int lane, int kk, float f,
                                         int kmin, int kmax) {
     contract<1>(k, qa, wl, lane, kk, f, kmin, kmax, AGE_BLK, NA);
-}
-
-// log10 of a positive double to ~3e-8 absolute: the binary exponent exactly, the mantissa
-// in [0.5, 1) by the FP32 logarithm
-__device__ inline double log10_split(double x) {
-    int e;
-    const double mt = frexp(x, &e);
-    return (double)e * 0.30102999566398120 + (double)log10f((float)mt);
 }
 
 // ------------------------------------------------------------------ one evaluation
@@ -328,7 +328,7 @@ __device__ inline double log10_split(double x) {
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
 // the lanes' buckets.  wl: the wave's LDS block (LDS_SLOTS x 64 floats).
 template <int MODE>
-__device__ inline void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa, float *wl,
+__device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa, float *wl,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
@@ -419,7 +419,10 @@ __device__ inline double log_prior_skewnorm(const float *pri, float x, float &dl
     const double xi = pri[0], om = pri[1], sk = pri[2];
     const double y = ((double)x - xi) / om, v = sk * y;
     double lphi, ratio;
-    if (v < -5.0) {  // scaled complementary error function keeps log Phi finite in the far tail
+    if (sk == 0.0) {   // the normal member: Phi(0) = 1/2, phi(0) / Phi(0) = sqrt(2 / pi)
+        lphi = -0.69314718055994531;
+        ratio = 0.79788456080286536;
+    } else if (v < -5.0) {  // scaled complementary error function keeps log Phi finite in the far tail
         const double e = erfcx(-v * 0.7071067811865475);
         lphi = log(0.5 * e) - 0.5 * v * v;
         ratio = 0.7978845608028654 / e;

@@ -65,8 +65,42 @@ struct LaneCtx {
     uint32_t mask;
 };
 
-__device__ inline double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc, float *wl,
+// The FP64 pieces of an iteration (the prior and the Metropolis test) are out-of-line calls:
+// inlined, their constants would be hoisted out of the iteration loop and held in registers
+// across the model evaluations.
+__device__ __noinline__ double log_prior_all(const float *prior, const float (&x)[NP], float (&dlp)[NP]) {
+    double lp = 0.0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) lp += log_prior_skewnorm(prior + 3 * p, x[p], dlp[p]);
+    return lp;
+}
+
+// Metropolis test of a proposal with energy change dH (FP64) against the uniform word w;
+// alpha = min(1, exp(-dH)), 0 for a divergent proposal (non-finite H1 or dH > 1000).
+__device__ __noinline__ bool metropolis(double H1, double dH, uint32_t w, float &alpha) {
+    const bool divergent = !isfinite(H1) || dH > 1000.0;
+    alpha = divergent ? 0.0f : (float)fmin(1.0, exp(-dH));
+    return !divergent && log(u01d(w)) < -dH;
+}
+
+// Opaque copy: values derived from the galaxy alone are then recomputed in each evaluation
+// instead of being hoisted out of the leapfrog loop and held in registers across it.
+template <typename T>
+__device__ inline T opaque(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Inlined at its one call site per kernel: as an out-of-line call the model would reach the
+// kernel-argument constants through a stack copy.
+template <int SFH>
+__device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc0, float *wl,
                                 const float (&x)[NP], float (&g)[NP]) {
+    LaneCtx lc = lc0;
+    lc.zf = opaque(lc0.zf);
+    lc.f = opaque(lc0.f);
+    lc.t_obs = opaque(lc0.t_obs);
+    lc.m0base = opaque(lc0.m0base);
     float th[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -76,77 +110,104 @@ __device__ inline double logpost(const DevConsts &k, const HmcArgs &a, const Lan
     const double m0 = lc.m0base - 2.5 * (double)th[0];
     double logl;
     float mags[NB_MAX];
-    approx_eval<MODE_LOGL_GRAD>(k, a.sfh, a.qf, a.qa, wl, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+    approx_eval<MODE_LOGL_GRAD>(k, SFH, a.qf, a.qa, wl, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
                                 lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
-    double lp = logl;
+    float dlp[NP];
+    const double lp = logl + log_prior_all(a.prior, x, dlp);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        float dlp, t, dth;
+        float t, dth;
         bound_param(a.bounds + 4 * p, x[p], t, dth);   // recomputed: not kept live across the model
-        lp += log_prior_skewnorm(a.prior + 3 * p, x[p], dlp);
-        g[p] = fmaf(g[p], dth, dlp);
+        g[p] = fmaf(g[p], dth, dlp[p]);
     }
     return lp;
 }
 
-// Chain state lives in HBM (SoA [quantity][slot], coalesced across the wave) and is read
-// where it is used, so that only the trajectory (x, p, M^-1 and the scalars of the
-// step-size adaptation) stays in registers across the model evaluations.
-__global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
-    __shared__ float lds[LDS_SLOTS * 64];
-    const int lane = threadIdx.x;
-    const int nslot = a.n_gal * a.C;
-    const int slot = blockIdx.x * 64 + lane;
-    const bool valid = slot < nslot;
-    const int sl = valid ? slot : nslot - 1;
-    const int rank = sl / a.C, ch = sl % a.C;
-    const int g = a.perm[rank];
-    const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
-#define ST(arr, p) (arr)[(size_t)(p) * nslot + sl]
+// Chain slot of this lane (slot = rank * C + chain; ranks in z-bucket order) and the
+// per-galaxy constants of the model evaluation.
+struct SlotInfo {
+    int nslot, sl, ch, g;
+    bool valid;
+    uint32_t chain_id;
+};
 
+__device__ inline SlotInfo slot_info(const HmcArgs &a) {
+    SlotInfo si;
+    si.nslot = a.n_gal * a.C;
+    const int slot = blockIdx.x * 64 + (int)threadIdx.x;
+    si.valid = slot < si.nslot;
+    si.sl = si.valid ? slot : si.nslot - 1;
+    const int rank = si.sl / a.C;
+    si.ch = si.sl % a.C;
+    si.g = a.perm[rank];
+    si.chain_id = (uint32_t)(si.ch * a.n_gal + si.g);
+    return si;
+}
+
+__device__ inline LaneCtx lane_ctx(const DevConsts &k, const HmcArgs &a, const SlotInfo &si) {
     LaneCtx lc;
-    lc.zf = a.z[g];
+    lc.zf = a.z[si.g];
     lc.kk = z_bucket(k, lc.zf, &lc.f);
-    if (!valid) lc.kk = -1;
+    if (!si.valid) lc.kk = -1;
     lc.t_obs = age_universe_gyr(k, (double)lc.zf);
     lc.m0base = mag_offset(k, (double)lc.zf);
     lc.kmin = wave_min_i(lc.kk < 0 ? 1 << 30 : lc.kk);
     lc.kmax = wave_max_i(lc.kk);
-    lc.obs_g = a.obs + (size_t)g * k.n_band;
-    lc.sig_g = a.sigma + (size_t)g * k.n_band;
-    lc.mask = a.mask[g];
+    lc.obs_g = a.obs + (size_t)si.g * k.n_band;
+    lc.sig_g = a.sigma + (size_t)si.g * k.n_band;
+    lc.mask = a.mask[si.g];
+    return lc;
+}
 
-    float eps, hbar, lebar, mu;
-    double lp;
-    int nacc, da0;
-    if (a.it0 == 0) {
-        float x[NP], gr[NP];
+// element p of the lane's slot in a state array; the slot index is made opaque at each use so
+// that the addresses are formed where they are used, not hoisted and held across the loop
+#define ST(arr, p) (arr)[(size_t)(p) * si.nslot + opaque(si.sl)]
+
+// Chain start: log posterior and gradient at the initial point, unit metric, step-size
+// adaptation state.
+template <int SFH>
+__global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
+    __shared__ float lds[LDS_SLOTS * 64];
+    const SlotInfo si = slot_info(a);
+    const LaneCtx lc = lane_ctx(k, a, si);
+    float x[NP], gr[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
-        lp = logpost(k, a, lc, lds, x, gr);
-        eps = a.init_step;
-        mu = logf(10.0f * a.init_step);
-        hbar = lebar = 0.0f;
-        nacc = da0 = 0;
-        if (valid) {
+    for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
+    const double lp = logpost<SFH>(k, a, lc, lds, x, gr);
+    if (!si.valid) return;
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                ST(a.x, p) = x[p];
-                ST(a.gr, p) = gr[p];
-                ST(a.minv, p) = 1.0f;
-                ST(a.wmean, p) = 0.0;
-                ST(a.wm2, p) = 0.0;
-            }
-        }
-    } else {
-        lp = a.lp[sl];
-        eps = a.eps[sl];
-        mu = a.mu[sl];
-        hbar = a.hbar[sl];
-        lebar = a.lebar[sl];
-        nacc = a.nacc[sl];
-        da0 = a.da0[sl];
+    for (int p = 0; p < NP; ++p) {
+        ST(a.x, p) = x[p];
+        ST(a.gr, p) = gr[p];
+        ST(a.minv, p) = 1.0f;
+        ST(a.wmean, p) = 0.0;
+        ST(a.wm2, p) = 0.0;
     }
+    a.lp[si.sl] = lp;
+    a.eps[si.sl] = a.init_step;
+    a.mu[si.sl] = logf(10.0f * a.init_step);
+    a.hbar[si.sl] = 0.0f;
+    a.lebar[si.sl] = 0.0f;
+    a.nacc[si.sl] = 0;
+    a.da0[si.sl] = 0;
+}
+
+// Iterations [it0, it1) of every chain.  Chain state lives in HBM (SoA [quantity][slot],
+// coalesced across the wave) and is read where it is used, so that only the trajectory
+// (x, p, M^-1 and the scalars of the step-size adaptation) stays in registers across the
+// model evaluations.
+template <int SFH>
+__global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
+    __shared__ float lds[LDS_SLOTS * 64];
+    const SlotInfo si = slot_info(a);
+    const LaneCtx lc = lane_ctx(k, a, si);
+    const bool valid = si.valid;
+    const int ch = si.ch, g = si.g, sl = si.sl;
+    const uint32_t chain_id = si.chain_id;
+
+    double lp = a.lp[sl];
+    float eps = a.eps[sl], mu = a.mu[sl], hbar = a.hbar[sl], lebar = a.lebar[sl];
+    int nacc = a.nacc[sl], da0 = a.da0[sl];
 
     for (int it = a.it0; it < a.it1; ++it) {
         float p[NP], xn[NP], gn[NP], minv[NP];
@@ -185,19 +246,17 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
                 p[t] = fmaf(0.5f * eps, gn[t], p[t]);
                 xn[t] = fmaf(eps * minv[t], p[t], xn[t]);
             }
-            lpn = logpost(k, a, lc, lds, xn, gn);
+            lpn = logpost<SFH>(k, a, lc, lds, xn, gn);
 #pragma unroll
             for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], p[t]);
         }
         double H1 = -lpn;
 #pragma unroll
         for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
-        const double dH = H1 - H0;
-        const bool divergent = !isfinite(H1) || dH > 1000.0;
-        const float alpha = divergent ? 0.0f : (float)fmin(1.0, exp(-dH));
         uint32_t c4[4] = {2u, (uint32_t)it, chain_id, 0u};   // the accept draw: word 2 of block 2
         philox4x32_10(c4, a.key0, a.key1);
-        const bool acc = !divergent && log(u01d(c4[2])) < -dH;
+        float alpha;
+        const bool acc = metropolis(H1, H1 - H0, c4[2], alpha);
         // xn now holds the chain's position after this iteration
         if (acc) {
             lp = lpn;
@@ -265,7 +324,6 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
             }
         }
     }
-#undef ST
     if (!valid) return;
     a.lp[sl] = lp;
     a.eps[sl] = eps;
@@ -275,6 +333,7 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     a.nacc[sl] = nacc;
     a.da0[sl] = da0;
 }
+#undef ST
 
 // pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy
 __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ perm,
@@ -407,10 +466,14 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     const int nit = cfg->n_warmup + cfg->n_sample;
     const int blk_it = 25;
     dim3 grid((nslot + 63) / 64), block(64);
+    const bool dpl = (sfh == SPS_SFH_DPL);
+    if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, 0, s, c->k, a);
+    else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, 0, s, c->k, a);
     for (int it0 = 0; it0 < nit; it0 += blk_it) {
         a.it0 = it0;
         a.it1 = it0 + blk_it < nit ? it0 + blk_it : nit;
-        hipLaunchKernelGGL(k_hmc, grid, block, 0, s, c->k, a);
+        if (dpl) hipLaunchKernelGGL(k_hmc<SPS_SFH_DPL>, grid, block, 0, s, c->k, a);
+        else hipLaunchKernelGGL(k_hmc<SPS_SFH_LOGNORMAL>, grid, block, 0, s, c->k, a);
     }
     hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
                        c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
