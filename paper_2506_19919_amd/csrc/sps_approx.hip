@@ -125,7 +125,8 @@ struct ApproxArgs {
 
 template <int MODE>
 __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
-    __shared__ float lds[LDS_SLOTS * WAVE];
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, true)
+    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, true)};
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
@@ -164,7 +165,7 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     float mags[NB_MAX] = {}, gr[NP];
     double logl;
     constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
-    approx_eval<EM>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
+    approx_eval<EM, true>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
@@ -277,24 +278,25 @@ int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const flo
     ApproxArgs a{n, sfh, mode, c->d_rec, bounds, prior, c->d_qf, c->d_qa, c->d_orec};
     const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE), ug((n + 255) / 256), ub(256);
     const int nb = c->n_band;
+    const size_t lds_bytes = approx_lds_bytes(nb, true);
     switch (mode) {
         case MODE_MAGS:
-            hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, lds_bytes, s, c->k, a);
             hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL:
-            hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, lds_bytes, s, c->k, a);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL_GRAD:
-            hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, lds_bytes, s, c->k, a);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
                                out_val, out_grad);
             break;
         case MODE_LOGPOST_GRAD:
-            hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, 0, s, c->k, a);
+            hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, lds_bytes, s, c->k, a);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
                                out_val, out_grad);
             break;

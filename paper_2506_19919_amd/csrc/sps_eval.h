@@ -3,16 +3,27 @@
 #pragma once
 #include "sps_model.h"
 
+#include <type_traits>
+
 namespace sps {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
 // per-lane LDS column: 96 slots for P_age (padded), the table row sums T, the adjoint
-// row coefficients or dP_age, then two slots for the lane's z-slice weights
+// row coefficients or dP_age; the FP32 columns of the exact path carry two more slots
 constexpr int SLOT_W = 16 * AGE_BLK;
 constexpr int LDS_SLOTS = SLOT_W + 2;
 static_assert(NB_MAX * NZ <= SLOT_W, "table rows must fit the LDS column");
+
+// Opaque copy: what is derived from it is computed where it is used.  Inside a loop this
+// keeps per-lane constants (LDS addresses, per-galaxy values) from being hoisted out and
+// held in registers across the loop body.
+template <typename T>
+__device__ inline T opaque(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // ------------------------------------------------------------------ bucket sort
 // bucket of a galaxy: interval k of the z table, or n_z - 1 for z outside the table
@@ -37,12 +48,78 @@ struct LdsColT {
 };
 typedef LdsColT<WAVE> LdsCol;   // one column per lane: base = &lds[lane]
 
+// 24-bit storage: FP32 rounded to nearest (ties to even) at a 16-bit significand and kept as
+// its top 16 bits plus the next 8 (relative rounding error <= 2^-16, well below the 2^-16
+// per product that the BF16 hi + lo contraction already carries)
+__device__ inline uint32_t round24(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return b + 0x7Fu + ((b >> 8) & 1u);
+}
+__device__ inline float unpack24(uint16_t h, uint8_t l) {
+    return __uint_as_float(((uint32_t)h << 16) | ((uint32_t)l << 8));
+}
+
+// Per-wave LDS of the approximate path, sized at launch.  Each half of the wave (lanes
+// 32h .. 32h + 31) owns a region of half_bytes: its lanes' columns of SLOT_W 24-bit values
+// (slot s of lane l at hi[s * HALF + l % HALF] and lo[s * HALF + l % HALF]), overlaid by
+// the FP32 table row sums T of the same lanes (row r at t[r * HALF + l % HALF]) once the
+// half's forward contraction has read its columns.  T stays in FP32: the metallicity
+// gradient is a difference of these sums (the weights' derivatives sum to zero over Z).
+// Then the two z-slice weights of every lane in FP32.  Up to 6 bands 18,944 bytes, so that
+// eight single-wave workgroups fit in a CU's 160 KiB.
+constexpr int HALF = WAVE / 2;
+constexpr int PK_BYTES = SLOT_W * HALF * 3;
+// PK = false: the columns in FP32 as well (SLOT_W x HALF floats per half), for kernels whose
+// occupancy the LDS does not limit
+__host__ __device__ inline int approx_half_bytes(int n_band, bool pk) {
+    const int t = n_band * NZ * HALF * 4;
+    return pk ? (t > PK_BYTES ? t : PK_BYTES) : SLOT_W * HALF * 4;
+}
+__host__ __device__ inline int approx_lds_bytes(int n_band, bool pk) {
+    return 2 * approx_half_bytes(n_band, pk) + 2 * WAVE * 4;
+}
+
+struct ApproxLds {
+    char *base;
+    int half_bytes;
+    __device__ uint16_t *hi(int h) const { return (uint16_t *)(base + h * half_bytes); }
+    __device__ uint8_t *lo(int h) const { return (uint8_t *)(base + h * half_bytes + SLOT_W * HALF * 2); }
+    __device__ float *t(int h) const { return (float *)(base + h * half_bytes); }
+    __device__ float *w() const { return (float *)(base + 2 * half_bytes); }
+};
+
+// one lane's 24-bit column
+struct Col24 {
+    uint16_t *hi;
+    uint8_t *lo;
+    struct Ref {
+        uint16_t *h;
+        uint8_t *l;
+        __device__ operator float() const { return unpack24(*h, *l); }
+        __device__ Ref &operator=(float v) {
+            const uint32_t r = round24(v);
+            *h = (uint16_t)(r >> 16);
+            *l = (uint8_t)(r >> 8);
+            return *this;
+        }
+        __device__ Ref &operator=(const Ref &o) { return *this = (float)o; }
+    };
+    __device__ Ref operator[](int s) const { return Ref{hi + s * HALF, lo + s * HALF}; }
+};
+
 // sum over the G adjacent lanes that share one galaxy (G = 1, 2, 4, ...)
 template <int G, typename T>
 __device__ inline T group_sum(T v) {
 #pragma unroll
     for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, WAVE);
     return v;
+}
+
+// lane ll of half hl: its column in the layout PK selects
+template <bool PK>
+__device__ inline typename std::conditional<PK, Col24, LdsColT<HALF>>::type make_col(const ApproxLds &L, int hl, int ll) {
+    if constexpr (PK) return Col24{L.hi(hl) + ll, L.lo(hl) + ll};
+    else return LdsColT<HALF>{L.t(hl) + ll};
 }
 
 // log10 of a positive double to ~3e-8 absolute: the binary exponent exactly, the mantissa
@@ -60,14 +137,17 @@ struct WeightsState {
     float Zb;      // burst normaliser (1 unless clipped at t_obs)
     float l_obs;   // log10 t_obs [yr]
     int i0;        // first age bin of the burst window
+    float scale;   // P_age = scale x column (1 unless the normalisation is folded out)
 };
 
 // P_age is left in the LDS column (slots 0..NA-1), P_Z in registers.  G adjacent lanes may
 // share one galaxy (and one column): lane q of the group takes the age bins i = q mod G,
-// and the sums over bins are combined across the group.
-template <int G = 1, int STRIDE = WAVE>
+// and the sums over bins are combined across the group.  FOLD: the column holds P_age /
+// ws.scale (the smooth masses as computed, the burst added in proportion), which saves a
+// pass over the column; the contraction applies the scale.
+template <int G = 1, bool FOLD = false, typename Col>
 __device__ inline void forward_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
-                                       LdsColT<STRIDE> col, float (&pz)[NZ], WeightsState &ws, int q = 0) {
+                                       Col col, float (&pz)[NZ], WeightsState &ws, int q = 0) {
     const float t_obs_f = (float)t_obs;
     double S = 0.0;
     if (sfh == SPS_SFH_DPL) {
@@ -102,13 +182,22 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
     }
     Zb = group_sum<G>(Zb);
     const float fb = th[4], sm = (1.0f - fb) * (float)(1.0 / S), bz = (Zb > 0.0f) ? fb / Zb : 0.0f;
-    for (int i = q; i < NA; i += G) col[i] = col[i] * sm;
+    float cb = bz;   // coefficient of the burst profile in the column
+    ws.scale = 1.0f;
+    if (!FOLD) {
+        for (int i = q; i < NA; i += G) col[i] = col[i] * sm;
+    } else if (sm > 0.0f) {
+        cb = bz / sm;
+        ws.scale = sm;
+    } else {   // no smooth part (F_burst = 1)
+        for (int i = q; i < NA; i += G) col[i] = 0.0f;
+    }
     for (int t = 0; t < k.burst_nbins; ++t) {
         if (i0 + t >= NA) break;
         if (G > 1 && (i0 + t) % G != q) continue;
         float p, dp;
         burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
-        col[i0 + t] = fmaf(bz, p, col[i0 + t]);
+        col[i0 + t] = fmaf(cb, p, col[i0 + t]);
     }
     {
         float unused[NZ];
@@ -123,9 +212,9 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
 // gradient of the weights: given dP_age (LDS column, slots 0..NA) and dP_Z,
 // accumulate d/d(theta_1..6).  With G lanes per galaxy, lane q takes the bins i = q mod G;
 // every lane of the group ends with the same totals.
-template <int G = 1, int STRIDE = WAVE>
+template <int G = 1, typename Col>
 __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
-                                       const WeightsState &ws, LdsColT<STRIDE> col, const float (&pzbar)[NZ],
+                                       const WeightsState &ws, Col col, const float (&pzbar)[NZ],
                                        float *g, int q = 0) {
     const float t_obs_f = (float)t_obs, fb = th[4];
     const float invS = (float)(1.0 / ws.S), invZ = (ws.Zb > 0.0f) ? 1.0f / ws.Zb : 0.0f;
@@ -217,28 +306,35 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
 
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 
-// the pass's slice weights of the A rows 16 (2h + m) + l % 16 (0 outside the pass's bucket)
-__device__ inline void pass_weights(float *wl, int lane, int h, bool act, float f, float (&w0)[2], float (&w1)[2]) {
-    wl[SLOT_W * WAVE + lane] = act ? 1.0f - f : 0.0f;
-    wl[(SLOT_W + 1) * WAVE + lane] = act ? f : 0.0f;
+// the pass's slice weights of the A rows 16 (2h + m) + l % 16 (0 outside the pass's bucket),
+// times the column scale
+__device__ inline void pass_weights(const ApproxLds &L, int lane, int h, bool act, float f, float scale,
+                                    float (&w0)[2], float (&w1)[2]) {
+    float *w = L.w();
+    w[lane] = act ? (1.0f - f) * scale : 0.0f;
+    w[WAVE + lane] = act ? f * scale : 0.0f;
     __syncthreads();
     const int li = lane & 15;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-        w0[m] = wl[SLOT_W * WAVE + 16 * (2 * h + m) + li];
-        w1[m] = wl[(SLOT_W + 1) * WAVE + 16 * (2 * h + m) + li];
+        w0[m] = w[16 * (2 * h + m) + li];
+        w1[m] = w[WAVE + 16 * (2 * h + m) + li];
     }
 }
 
 // A fragments of k-step ks for the galaxy pair of blocks of half h: w0- and w1-scaled, split
-__device__ inline void a_frags(const float *wl, int lane, int h, int ks, const float (&w0)[2], const float (&w1)[2],
-                               b8v (&a0h)[2], b8v (&a0l)[2], b8v (&a1h)[2], b8v (&a1l)[2]) {
+template <bool PK>
+__device__ inline void a_frags(const ApproxLds &L, int lane, int h, int ks, const float (&w0)[2],
+                               const float (&w1)[2], b8v (&a0h)[2], b8v (&a0l)[2], b8v (&a1h)[2], b8v (&a1l)[2]) {
     const int li = lane & 15, lk = lane >> 4;
+    const uint16_t *hi = L.hi(h);
+    const uint8_t *lo = L.lo(h);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float v = wl[(32 * ks + 8 * lk + e) * WAVE + 16 * (2 * h + m) + li];
+            const int o = (32 * ks + 8 * lk + e) * HALF + 16 * m + li;
+            const float v = PK ? unpack24(hi[o], lo[o]) : L.t(h)[o];
             // a zero weight gives an exact zero (a NaN column of an inactive galaxy stays out)
             const float x0 = (w0[m] != 0.0f) ? v * w0[m] : 0.0f, x1 = (w1[m] != 0.0f) ? v * w1[m] : 0.0f;
             const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
@@ -250,17 +346,28 @@ __device__ inline void a_frags(const float *wl, int lane, int h, int ks, const f
     }
 }
 
+// four results of consecutive lanes' columns (o = slot * HALF + lane % HALF, a multiple of 4)
+// stored in 24 bits: one 8-byte and one 4-byte LDS write
+__device__ inline void store4_24(uint16_t *hi, uint8_t *lo, int o, const v4f &v) {
+    const uint32_t r0 = round24(v[0]), r1 = round24(v[1]), r2 = round24(v[2]), r3 = round24(v[3]);
+    uint2 h;
+    h.x = (r0 >> 16) | (r1 & 0xffff0000u);
+    h.y = (r2 >> 16) | (r3 & 0xffff0000u);
+    *(uint2 *)(hi + o) = h;
+    *(uint32_t *)(lo + o) = ((r0 >> 8) & 0xffu) | (r1 & 0xff00u) | ((r2 & 0xff00u) << 8) | ((r3 & 0xff00u) << 16);
+}
+
 __device__ inline v4f mfma3(const b8v &ah, const b8v &al, const b8v &bh, const b8v &bl, v4f acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
 }
 
-// one contraction: D[g][n] = sum_s w_s(g) sum_k A[g][k] B_s[k][n] over K = 96 (3 k-steps),
-// N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo)
-template <int MODE_ADJ>
-__device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, float *wl, int lane, int kk, float f,
-                                int kmin, int kmax, int nbk, int n_out) {
+// one contraction: D[g][n] = scale(g) sum_s w_s(g) sum_k A[g][k] B_s[k][n] over K = 96
+// (3 k-steps), N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo)
+template <int MODE_ADJ, bool PK>
+__device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, const ApproxLds &L, int lane, int kk,
+                                         float f, float scale, int kmin, int kmax, int nbk, int n_out) {
     const int li = lane & 15, lk = lane >> 4;
     const size_t lo_off = (size_t)k.n_z * QB_NODE;
 #pragma unroll
@@ -274,12 +381,12 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
             const bool act = (kk == kb);
             if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
             float w0[2], w1[2];
-            pass_weights(wl, lane, h, act, f, w0, w1);
+            pass_weights(L, lane, h, act, f, scale, w0, w1);
             const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
 #pragma unroll 1
             for (int ks = 0; ks < KSTEPS; ++ks) {
                 b8v a0h[2], a0l[2], a1h[2], a1l[2];
-                a_frags(wl, lane, h, ks, w0, w1, a0h, a0l, a1h, a1l);
+                a_frags<PK>(L, lane, h, ks, w0, w1, a0h, a0l, a1h, a1l);
 #pragma unroll
                 for (int nb = 0; nb < 6; ++nb) {
                     if (nb >= nbk) break;
@@ -295,30 +402,36 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
             }
             __syncthreads();   // the next pass rewrites the weight slots
         }
-        // all of this half's A reads are done: its results overwrite its own columns
+        // all of this half's A reads are done: its results overwrite its own region (T in
+        // FP32, dP_age in 24 bits)
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
             if (nb < nbk && 16 * nb + li < n_out) {
 #pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    *(v4f *)(wl + (16 * nb + li) * WAVE + 16 * (2 * h + m) + 4 * lk) = acc[nb][m];
+                for (int m = 0; m < 2; ++m) {
+                    const int o = (16 * nb + li) * HALF + 16 * m + 4 * lk;
+                    if (MODE_ADJ && PK) store4_24(L.hi(h), L.lo(h), o, acc[nb][m]);
+                    else *(v4f *)(L.t(h) + o) = acc[nb][m];
+                }
             }
         __syncthreads();
     }
 }
 
-// T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]); P_age in slots 0..95
-// (94, 95 zero), T written to slots 0..R-1
-__device__ __forceinline__ void contract_forward(const DevConsts &k, const uint16_t *qf, float *wl, int lane, int kk, float f,
-                                        int kmin, int kmax) {
-    contract<0>(k, qf, wl, lane, kk, f, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
+// T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]), P_age = scale x the column
+// (slots 0..95; 94, 95 zero); T written in FP32, rows 0..R-1
+template <bool PK>
+__device__ __forceinline__ void contract_forward(const DevConsts &k, const uint16_t *qf, const ApproxLds &L, int lane,
+                                                 int kk, float f, float scale, int kmin, int kmax) {
+    contract<0, PK>(k, qf, L, lane, kk, f, scale, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
 }
 
 // dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..95 (zero
 // from R on), dP_age written to slots 0..NA-1
-__device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint16_t *qa, float *wl, int lane, int kk, float f,
-                                        int kmin, int kmax) {
-    contract<1>(k, qa, wl, lane, kk, f, kmin, kmax, AGE_BLK, NA);
+template <bool PK>
+__device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint16_t *qa, const ApproxLds &L, int lane,
+                                                 int kk, float f, int kmin, int kmax) {
+    contract<1, PK>(k, qa, L, lane, kk, f, 1.0f, kmin, kmax, AGE_BLK, NA);
 }
 
 // ------------------------------------------------------------------ one evaluation
@@ -326,23 +439,28 @@ __device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint1
 // parameters (MODE_LOGL_GRAD) for the lane's galaxy.  Every lane of the (single-wave)
 // workgroup must call it: the contractions are wave-wide and synchronise the workgroup.
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
-// the lanes' buckets.  wl: the wave's LDS block (LDS_SLOTS x 64 floats).
-template <int MODE>
-__device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa, float *wl,
+// the lanes' buckets.  L: the wave's LDS block.
+template <int MODE, bool PK>
+__device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa,
+                                            const ApproxLds &L0,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
     const int nb = k.n_band;
-    const int lane = threadIdx.x & (WAVE - 1);
-    LdsCol col{wl + lane};
+    const int lane = opaque((int)threadIdx.x & (WAVE - 1));
+    const ApproxLds L{L0.base, opaque(L0.half_bytes)};
+    const int hl = lane / HALF, ll = lane % HALF;
+    using Col = typename std::conditional<PK, Col24, LdsColT<HALF>>::type;
+    Col col = make_col<PK>(L, hl, ll);
+    const float *tcol = L.t(hl) + ll;   // T rows of this lane: tcol[r * HALF]
     float pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pz, ws);
+    forward_weights<1, true>(k, sfh, th, t_obs, col, pz, ws);
     col[NA] = 0.0f;
     col[NA + 1] = 0.0f;
 
     // ---- contraction: T[b][j] = sum_i P_age(i) Qz[b][j][i]
-    contract_forward(k, qf, wl, lane, kk, f, kmin, kmax);
+    contract_forward<PK>(k, qf, L, lane, kk, f, ws.scale, kmin, kmax);
 
     // ---- magnitudes, likelihood.  The band sums, magnitudes and residuals are formed in
     // FP64 from the FP32 row sums: an FP32 magnitude near 25 carries ~2e-6 of rounding,
@@ -359,7 +477,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const u
         if (b >= nb) continue;
         double sb = 0.0;
 #pragma unroll
-        for (int j = 0; j < NZ; ++j) sb += (double)pz[j] * (double)col[b * NZ + j];
+        for (int j = 0; j < NZ; ++j) sb += (double)pz[j] * (double)tcol[(b * NZ + j) * HALF];
         const DustVal d = dust_at(k.lam_eff[b] / (opz * 5500.0f), tauv, delta, ffl);
         const double mag = m0 - 2.5 * log10_split((double)d.F * sb);
         if (MODE == MODE_MAGS) {
@@ -392,9 +510,10 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const u
         float s = 0.0f;
 #pragma unroll
         for (int b = 0; b < NB_MAX; ++b)
-            if (b < nb) s = fmaf(sbar[b], col[b * NZ + j], s);
+            if (b < nb) s = fmaf(sbar[b], tcol[(b * NZ + j) * HALF], s);
         pzbar[j] = s;
     }
+    __syncthreads();   // T is read: the rows of C overwrite it
 #pragma unroll
     for (int b = 0; b < NB_MAX; ++b)
 #pragma unroll
@@ -402,7 +521,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const u
             if (b < nb) col[b * NZ + j] = sbar[b] * pz[j];
     for (int r = nb * NZ; r < 32 * KSTEPS; ++r) col[r] = 0.0f;
     // dP_age(i) = sum_{b,j} sbar_b P_Z(j) Qz[b][j][i]
-    contract_adjoint(k, qa, wl, lane, kk, f, kmin, kmax);
+    contract_adjoint<PK>(k, qa, L, lane, kk, f, kmin, kmax);
     adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);
 }
 

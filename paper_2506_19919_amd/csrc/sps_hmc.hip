@@ -55,6 +55,10 @@ struct HmcArgs {
     float *x, *gr, *eps, *hbar, *lebar, *mu, *minv;
     int *nacc, *da0;
     double *lp, *wmean, *wm2;
+    // trajectory scratch (momentum, position) per lane of the grid, [p][ntmp]: the model
+    // evaluation runs with these in memory instead of registers
+    float *pm, *xt;
+    int ntmp;
 };
 
 struct LaneCtx {
@@ -83,19 +87,18 @@ __device__ __noinline__ bool metropolis(double H1, double dH, uint32_t w, float 
     return !divergent && log(u01d(w)) < -dH;
 }
 
-// Opaque copy: values derived from the galaxy alone are then recomputed in each evaluation
-// instead of being hoisted out of the leapfrog loop and held in registers across it.
-template <typename T>
-__device__ inline T opaque(T v) {
-    asm volatile("" : "+v"(v));
-    return v;
-}
-
 // Inlined at its one call site per kernel: as an out-of-line call the model would reach the
 // kernel-argument constants through a stack copy.
+// element p of this lane's trajectory scratch
+#define TMP(arr, p) (arr)[(size_t)(p) * a.ntmp + opaque((int)(blockIdx.x * 64 + threadIdx.x))]
+
+// log posterior and its gradient at the position held in the lane's trajectory scratch
 template <int SFH>
-__device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc0, float *wl,
-                                const float (&x)[NP], float (&g)[NP]) {
+__device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc0, const ApproxLds &L,
+                                float (&g)[NP]) {
+    float x[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) x[p] = TMP(a.xt, p);
     LaneCtx lc = lc0;
     lc.zf = opaque(lc0.zf);
     lc.f = opaque(lc0.f);
@@ -110,8 +113,11 @@ __device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, 
     const double m0 = lc.m0base - 2.5 * (double)th[0];
     double logl;
     float mags[NB_MAX];
-    approx_eval<MODE_LOGL_GRAD>(k, SFH, a.qf, a.qa, wl, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+    approx_eval<MODE_LOGL_GRAD, false>(k, SFH, a.qf, a.qa, L, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
                                 lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
+    asm volatile("" ::: "memory");   // the position is read again, not held through the model
+#pragma unroll
+    for (int p = 0; p < NP; ++p) x[p] = TMP(a.xt, p);
     float dlp[NP];
     const double lp = logl + log_prior_all(a.prior, x, dlp);
 #pragma unroll
@@ -167,13 +173,17 @@ __device__ inline LaneCtx lane_ctx(const DevConsts &k, const HmcArgs &a, const S
 // adaptation state.
 template <int SFH>
 __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
-    __shared__ float lds[LDS_SLOTS * 64];
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
+    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     float x[NP], gr[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
-    const double lp = logpost<SFH>(k, a, lc, lds, x, gr);
+    for (int p = 0; p < NP; ++p) {
+        x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
+        TMP(a.xt, p) = x[p];
+    }
+    const double lp = logpost<SFH>(k, a, lc, lds, gr);
     if (!si.valid) return;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -198,7 +208,8 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
 // model evaluations.
 template <int SFH>
 __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
-    __shared__ float lds[LDS_SLOTS * 64];
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
+    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     const bool valid = si.valid;
@@ -210,9 +221,7 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     int nacc = a.nacc[sl], da0 = a.da0[sl];
 
     for (int it = a.it0; it < a.it1; ++it) {
-        float p[NP], xn[NP], gn[NP], minv[NP];
-#pragma unroll
-        for (int t = 0; t < NP; ++t) minv[t] = ST(a.minv, t);
+        float p[NP], xn[NP], gn[NP];
         {
             uint32_t w[NP];
 #pragma unroll
@@ -228,31 +237,38 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
                 const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
                 float sn, cs;
                 sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
-                p[2 * t] = r * cs / sqrtf(minv[2 * t]);
-                p[2 * t + 1] = r * sn / sqrtf(minv[2 * t + 1]);
+                p[2 * t] = r * cs / sqrtf(ST(a.minv, 2 * t));
+                p[2 * t + 1] = r * sn / sqrtf(ST(a.minv, 2 * t + 1));
             }
         }
         double H0 = -lp;
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
-            H0 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
-            xn[t] = ST(a.x, t);
+            H0 += 0.5 * (double)ST(a.minv, t) * (double)p[t] * (double)p[t];
+            TMP(a.xt, t) = ST(a.x, t);
             gn[t] = ST(a.gr, t);
         }
         double lpn = lp;
         for (int l = 0; l < a.L; ++l) {
+            // half kick and drift; momentum and position go to the trajectory scratch for the
+            // model evaluation
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 p[t] = fmaf(0.5f * eps, gn[t], p[t]);
-                xn[t] = fmaf(eps * minv[t], p[t], xn[t]);
+                TMP(a.pm, t) = p[t];
+                TMP(a.xt, t) = fmaf(eps * ST(a.minv, t), p[t], TMP(a.xt, t));
             }
-            lpn = logpost<SFH>(k, a, lc, lds, xn, gn);
+            asm volatile("" ::: "memory");
+            lpn = logpost<SFH>(k, a, lc, lds, gn);
+            asm volatile("" ::: "memory");
 #pragma unroll
-            for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], p[t]);
+            for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], TMP(a.pm, t));
         }
+#pragma unroll
+        for (int t = 0; t < NP; ++t) xn[t] = TMP(a.xt, t);
         double H1 = -lpn;
 #pragma unroll
-        for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)minv[t] * (double)p[t] * (double)p[t];
+        for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)ST(a.minv, t) * (double)p[t] * (double)p[t];
         uint32_t c4[4] = {2u, (uint32_t)it, chain_id, 0u};   // the accept draw: word 2 of block 2
         philox4x32_10(c4, a.key0, a.key1);
         float alpha;
@@ -418,7 +434,9 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     // lp + 20 Welford (double)
     const size_t fbytes = (size_t)nslot * (3 * NP + 4) * sizeof(float) + (size_t)nslot * 2 * sizeof(int);
     const size_t dofs = (fbytes + 255) & ~(size_t)255;
-    const size_t need = dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double);
+    const int ntmp = (nslot + 63) / 64 * 64;   // every lane of the grid
+    const size_t tofs = (dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double) + 255) & ~(size_t)255;
+    const size_t need = tofs + (size_t)2 * NP * ntmp * sizeof(float);
     if (c->work_bytes < need) {
         SPS_HIP(hipDeviceSynchronize());
         (void)hipFree(c->d_work);
@@ -461,19 +479,23 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.nacc = (int *)(a.lebar + nslot);
     a.da0 = a.nacc + nslot;
     a.lp = (double *)((char *)c->d_work + dofs);
+    a.pm = (float *)((char *)c->d_work + tofs);
+    a.xt = a.pm + (size_t)NP * ntmp;
+    a.ntmp = ntmp;
     a.wmean = a.lp + nslot;
     a.wm2 = a.wmean + (size_t)NP * nslot;
     const int nit = cfg->n_warmup + cfg->n_sample;
     const int blk_it = 25;
     dim3 grid((nslot + 63) / 64), block(64);
     const bool dpl = (sfh == SPS_SFH_DPL);
-    if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, 0, s, c->k, a);
-    else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, 0, s, c->k, a);
+    const size_t lds_bytes = approx_lds_bytes(c->n_band, false);
+    if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
+    else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
     for (int it0 = 0; it0 < nit; it0 += blk_it) {
         a.it0 = it0;
         a.it1 = it0 + blk_it < nit ? it0 + blk_it : nit;
-        if (dpl) hipLaunchKernelGGL(k_hmc<SPS_SFH_DPL>, grid, block, 0, s, c->k, a);
-        else hipLaunchKernelGGL(k_hmc<SPS_SFH_LOGNORMAL>, grid, block, 0, s, c->k, a);
+        if (dpl) hipLaunchKernelGGL(k_hmc<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
+        else hipLaunchKernelGGL(k_hmc<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
     }
     hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
                        c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
