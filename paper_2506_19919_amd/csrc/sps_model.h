@@ -71,9 +71,8 @@ __device__ inline float tri_dcdf(float u) {
 
 // ------------------------------------------------------------------ double power law
 struct Dpl {
-    float tau, am1, bp1, ltau, inv_w;
+    float tau, bp1, ltau, inv_w;
     float s_l2, b_l2;   // (alpha + beta) log2(e), (beta + 1) log2(e)
-    float inv_bp1, inv_tau;
     float alpha, ab;         // alpha, alpha + beta
     float x_obs, inv_tobs;   // ln(t_obs / tau), 1 / t_obs: set by dpl_at_obs
 };
@@ -91,15 +90,12 @@ __device__ inline float log1p_small(float x) {
 __device__ inline Dpl make_dpl(float tau, float al, float be) {
     Dpl d;
     d.tau = tau;
-    d.am1 = al - 1.0f;
     d.bp1 = be + 1.0f;
     d.ltau = logf(tau);
     float w = fminf(0.56f, fminf(2.8f / (al + be), 1.68f / d.bp1));
     d.inv_w = 1.0f / w;
     d.s_l2 = (al + be) * 1.4426950408889634f;
     d.b_l2 = d.bp1 * 1.4426950408889634f;
-    d.inv_bp1 = 1.0f / d.bp1;
-    d.inv_tau = 1.0f / tau;
     d.alpha = al;
     d.ab = al + be;
     return d;
@@ -110,6 +106,11 @@ __device__ inline Dpl make_dpl(float tau, float al, float be) {
 // bin masses within ~4e-6 of the exact integral in total and their tau/alpha/beta
 // derivatives within ~8e-5, over tau 0.1-14 Gyr, alpha, beta 0.1-8, z 0.1-3
 constexpr float GL2X = 0.57735026918962576f;
+
+// oldest age bin: quadrature panels cover X down to TAIL_CUT / (alpha + beta) below
+// min(X_obs, 0); the series below that cut takes TAIL_TERMS terms
+constexpr float TAIL_CUT = 4.0f;
+constexpr int TAIL_TERMS = 4;
 
 // integrand h = tau g(X), g = 1 / (e^{(alpha-1)X} + e^{-(beta+1)X}), at X with weight wg.
 // Written without overflow as g = fB e^{(beta+1)X}, fB = 1 / (1 + e^{(alpha+beta)X}), and
@@ -144,7 +145,7 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     if (!(a_lo < t_obs)) return;
     // span W of the bin in X is formed directly as log1p of the age-edge ratio (young bins
     // are ~1e-5 wide at |X| ~ 1, where xhi - xlo would cancel in FP32)
-    float xhi, span, tail = 0.0f, tail_t = 0.0f, tail_b = 0.0f;
+    float xhi, span, tail = 0.0f, tail_t = 0.0f, tail_a = 0.0f, tail_b = 0.0f;
     if (a_hi <= 0.0078125f * t_obs) {
         // young bin (older edge within 2^-7 of t_obs): X_hi = X_obs + ln(1 - a_lo / t_obs) and
         // W = ln(1 + d) by series, no transcendental beyond one reciprocal
@@ -159,13 +160,32 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
         span = (u == 1.0f) ? d : __builtin_amdgcn_logf(u) * 0.69314718055994531f * (d * __builtin_amdgcn_rcpf(u - 1.0f));
     } else {
         xhi = __builtin_amdgcn_logf(t_obs - a_lo) * 0.69314718055994531f - p.ltau;
-        // oldest bin: panels down to the cut, analytic leading term below it
-        const float xlo = fminf(xhi, 0.0f) - 30.0f * p.inv_bp1;
-        span = xhi - xlo;
-        tail = p.tau * __builtin_amdgcn_exp2f(p.b_l2 * xlo) * p.inv_bp1;
+        // oldest bin: panels down to the cut xc, where u = e^{(alpha+beta) X} <= e^-4; below
+        // it g = e^{(beta+1) X} sum_n (-1)^n u^n integrates term by term, with k_n =
+        // beta + 1 + n (alpha + beta):  int e^{kX} = e^{k xc} / k,  int X e^{kX} =
+        // (e^{k xc} / k) (xc - 1 / k);  g fB carries the factor n + 1 and g fA the factor
+        // -n.  Four terms leave < 1e-7 of the tail.
+        const float xc = fminf(xhi, 0.0f) - TAIL_CUT * __builtin_amdgcn_rcpf(p.ab);
+        span = xhi - xc;
+        const float u = __builtin_amdgcn_exp2f(p.s_l2 * xc);
+        float term = __builtin_amdgcn_exp2f(p.b_l2 * xc), sv = 0.0f, st = 0.0f, sa = 0.0f, sb = 0.0f;
+#pragma unroll
+        for (int n = 0; n < TAIL_TERMS; ++n) {
+            const float ik = __builtin_amdgcn_rcpf(p.bp1 + (float)n * p.ab);
+            const float I = ((n & 1) ? -term : term) * ik, g1 = xc - ik;
+            sv += I;
+            if (DERIV) {
+                st = fmaf(I, p.alpha - p.ab * (float)(n + 1), st);
+                sa = fmaf(-(float)n * I, g1, sa);
+                sb = fmaf((float)(n + 1) * I, g1, sb);
+            }
+            term *= u;
+        }
+        tail = p.tau * sv;
         if (DERIV) {
-            tail_t = -(p.bp1 - 1.0f) * tail * p.inv_tau;
-            tail_b = tail * (xlo - p.inv_bp1);
+            tail_t = st;
+            tail_a = -p.tau * sa;
+            tail_b = p.tau * sb;
         }
     }
     float s = 0.0f, sf = 0.0f, sa = 0.0f, sb = 0.0f, hw;
@@ -190,7 +210,7 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     m = fmaf(s, th, tail);
     if (DERIV) {
         d_tau = fmaf(hw, p.alpha * s - p.ab * sf, tail_t);
-        d_al = -th * sa;
+        d_al = fmaf(-th, sa, tail_a);
         d_be = fmaf(sb, th, tail_b);
     }
 }
