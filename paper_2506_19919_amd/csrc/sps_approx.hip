@@ -127,6 +127,8 @@ template <int MODE>
 __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, true)
     const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, true)};
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     float mags[NB_MAX] = {}, gr[NP];
     double logl;
     constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
-    approx_eval<EM, true>(k, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
+    approx_eval<EM, true>(k, ledge, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
@@ -227,6 +229,8 @@ __global__ void __launch_bounds__(256) k_unpermute(int n, int nb, const int *__r
 __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, const float *__restrict__ params,
                                                   const float *__restrict__ z, float *__restrict__ w) {
     __shared__ float lds[LDS_SLOTS * WAVE];
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const int lane = threadIdx.x;
     const int g0 = blockIdx.x * WAVE;
     const int g = g0 + lane;
@@ -239,7 +243,7 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
     const double t_obs = age_universe_gyr(k, (double)z[gg]);
     float pa[NA], pz[NZ];
     WeightsState ws;
-    forward_weights(k, sfh, th, t_obs, col, pz, ws);
+    forward_weights(k, ledge, sfh, th, t_obs, col, pz, ws);
 #pragma unroll
     for (int i = 0; i < NA; ++i) pa[i] = col[i];
     const float mass = exp10f(th[0]);

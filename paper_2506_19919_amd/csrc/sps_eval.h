@@ -146,7 +146,7 @@ struct WeightsState {
 // ws.scale (the smooth masses as computed, the burst added in proportion), which saves a
 // pass over the column; the contraction applies the scale.
 template <int G = 1, bool FOLD = false, typename Col>
-__device__ inline void forward_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
+__device__ inline void forward_weights(const DevConsts &k, const float *ledge, int sfh, const float *th, double t_obs,
                                        Col col, float (&pz)[NZ], WeightsState &ws, int q = 0) {
     const float t_obs_f = (float)t_obs;
     double S = 0.0;
@@ -171,12 +171,12 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
     // burst: only the bins the triweight window [mu - 3 sigma, mu + 3 sigma] touches; a bin
     // is handled by the lane that owns it
     const float l_obs = (float)log10_split(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
-    const int i0 = first_bin_above(k, mu - 3.0f * k.burst_sig);
+    const int i0 = first_bin_above(ledge, mu - 3.0f * k.burst_sig);
     float Zb = 0.0f;
     for (int t = 0; t < k.burst_nbins; ++t) {
         if (G > 1 && (i0 + t) % G != q) continue;
         float p, dp;
-        if (i0 + t < NA) burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
+        if (i0 + t < NA) burst_bin(ledge, i0 + t, l_obs, mu, inv_s3, p, dp);
         else p = 0.0f;
         Zb += p;
     }
@@ -196,7 +196,7 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
         if (i0 + t >= NA) break;
         if (G > 1 && (i0 + t) % G != q) continue;
         float p, dp;
-        burst_bin(k, i0 + t, l_obs, mu, inv_s3, p, dp);
+        burst_bin(ledge, i0 + t, l_obs, mu, inv_s3, p, dp);
         col[i0 + t] = fmaf(cb, p, col[i0 + t]);
     }
     {
@@ -213,7 +213,7 @@ __device__ inline void forward_weights(const DevConsts &k, int sfh, const float 
 // accumulate d/d(theta_1..6).  With G lanes per galaxy, lane q takes the bins i = q mod G;
 // every lane of the group ends with the same totals.
 template <int G = 1, typename Col>
-__device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float *th, double t_obs,
+__device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, int sfh, const float *th, double t_obs,
                                        const WeightsState &ws, Col col, const float (&pzbar)[NZ],
                                        float *g, int q = 0) {
     const float t_obs_f = (float)t_obs, fb = th[4];
@@ -258,7 +258,7 @@ __device__ inline void adjoint_weights(const DevConsts &k, int sfh, const float 
         if (G > 1 && i % G != q) continue;
         const float gbar = col[i];
         float pbr, dpb;
-        burst_bin(k, i, ws.l_obs, th[5], inv_s3, pbr, dpb);
+        burst_bin(ledge, i, ws.l_obs, th[5], inv_s3, pbr, dpb);
         const float pb = pbr * invZ, pbbar = fb * gbar;
         fbar = fmaf(gbar, pb, fbar);
         e1 = fmaf(pbbar, dpb, e1);
@@ -441,8 +441,8 @@ __device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint1
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
 // the lanes' buckets.  L: the wave's LDS block.
 template <int MODE, bool PK>
-__device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const uint16_t *qf, const uint16_t *qa,
-                                            const ApproxLds &L0,
+__device__ __forceinline__ void approx_eval(const DevConsts &k, const float *ledge, int sfh, const uint16_t *qf,
+                                            const uint16_t *qa, const ApproxLds &L0,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
@@ -455,7 +455,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const u
     const float *tcol = L.t(hl) + ll;   // T rows of this lane: tcol[r * HALF]
     float pz[NZ];
     WeightsState ws;
-    forward_weights<1, true>(k, sfh, th, t_obs, col, pz, ws);
+    forward_weights<1, true>(k, ledge, sfh, th, t_obs, col, pz, ws);
     col[NA] = 0.0f;
     col[NA + 1] = 0.0f;
 
@@ -522,7 +522,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, int sfh, const u
     for (int r = nb * NZ; r < 32 * KSTEPS; ++r) col[r] = 0.0f;
     // dP_age(i) = sum_{b,j} sbar_b P_Z(j) Qz[b][j][i]
     contract_adjoint<PK>(k, qa, L, lane, kk, f, kmin, kmax);
-    adjoint_weights(k, sfh, th, t_obs, ws, col, pzbar, gr);
+    adjoint_weights(k, ledge, sfh, th, t_obs, ws, col, pzbar, gr);
 }
 
 // bounding function (App. C): theta = lo + (hi - lo) sigmoid(k (x - x0)) and d theta / d x

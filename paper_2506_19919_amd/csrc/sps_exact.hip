@@ -536,6 +536,8 @@ constexpr int GPL = 8;   // lanes per galaxy
 __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, const float *params, const float *z,
                                                  float *pw) {
     __shared__ float lds[LDS_SLOTS * (64 / GPL)];
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const int lane = threadIdx.x, slot = lane / GPL, q = lane % GPL;
     const int g = blockIdx.x * (64 / GPL) + slot, gg = g < n ? g : n - 1;
     LdsColT<64 / GPL> col{lds + slot};
@@ -545,7 +547,7 @@ __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, co
     const double t_obs = age_universe_gyr(k, (double)z[gg]);
     float pz[NZ];
     WeightsState ws;
-    forward_weights<GPL>(k, sfh, th, t_obs, col, pz, ws, q);
+    forward_weights<GPL>(k, ledge, sfh, th, t_obs, col, pz, ws, q);
     if (g >= n) return;
     for (int i = q; i < NA; i += GPL) pw[(size_t)i * n + g] = col[i];
     if (q == 0) {
@@ -713,6 +715,8 @@ __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sf
                                                       const float *z, const float *pw, const float *pb,
                                                       float *grad) {
     __shared__ float lds[LDS_SLOTS * (64 / GPL)];
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const int lane = threadIdx.x, slot = lane / GPL, q = lane % GPL;
     const int g = blockIdx.x * (64 / GPL) + slot, gg = g < n ? g : n - 1;
     LdsColT<64 / GPL> col{lds + slot};
@@ -732,7 +736,7 @@ __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sf
     float gr[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) gr[p] = 0.0f;
-    adjoint_weights<GPL>(k, sfh, th, t_obs, ws, col, pzbar, gr, q);
+    adjoint_weights<GPL>(k, ledge, sfh, th, t_obs, ws, col, pzbar, gr, q);
     if (g >= n || q != 0) return;
 #pragma unroll
     for (int p = 1; p <= 6; ++p) grad[(size_t)p * n + g] = gr[p];

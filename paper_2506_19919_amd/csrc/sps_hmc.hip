@@ -94,7 +94,8 @@ __device__ __noinline__ bool metropolis(double H1, double dH, uint32_t w, float 
 
 // log posterior and its gradient at the position held in the lane's trajectory scratch
 template <int SFH>
-__device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, const LaneCtx &lc0, const ApproxLds &L,
+__device__ __forceinline__ double logpost(const DevConsts &k, const float *ledge, const HmcArgs &a, const LaneCtx &lc0,
+                                          const ApproxLds &L,
                                 float (&g)[NP]) {
     float x[NP];
 #pragma unroll
@@ -113,7 +114,7 @@ __device__ __forceinline__ double logpost(const DevConsts &k, const HmcArgs &a, 
     const double m0 = lc.m0base - 2.5 * (double)th[0];
     double logl;
     float mags[NB_MAX];
-    approx_eval<MODE_LOGL_GRAD, false>(k, SFH, a.qf, a.qa, L, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+    approx_eval<MODE_LOGL_GRAD, false>(k, ledge, SFH, a.qf, a.qa, L, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
                                 lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
     asm volatile("" ::: "memory");   // the position is read again, not held through the model
 #pragma unroll
@@ -175,6 +176,8 @@ template <int SFH>
 __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
     const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     float x[NP], gr[NP];
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
         x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
         TMP(a.xt, p) = x[p];
     }
-    const double lp = logpost<SFH>(k, a, lc, lds, gr);
+    const double lp = logpost<SFH>(k, ledge, a, lc, lds, gr);
     if (!si.valid) return;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -210,6 +213,8 @@ template <int SFH>
 __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
     const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     const bool valid = si.valid;
@@ -259,7 +264,7 @@ __global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
                 TMP(a.xt, t) = fmaf(eps * ST(a.minv, t), p[t], TMP(a.xt, t));
             }
             asm volatile("" ::: "memory");
-            lpn = logpost<SFH>(k, a, lc, lds, gn);
+            lpn = logpost<SFH>(k, ledge, a, lc, lds, gn);
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], TMP(a.pm, t));

@@ -285,12 +285,19 @@ __device__ inline void logn_bin(const DevConsts &k, int i, double t_obs, double 
 // ------------------------------------------------------------------ burst (triweight)
 // unnormalised probability of bin i and its derivative w.r.t. mu = log10 T_peak
 // (inv_s3 = 1 / (3 sigma_burst))
-__device__ inline void burst_bin(const DevConsts &k, int i, float l_obs, float mu, float inv_s3, float &p,
+// The burst and its window use the log-age bin edges e_0 .. e_NA (bin i spans [e_i, e_i+1];
+// -inf and +inf at the ends), read at lane-dependent bins: the kernels keep a copy in LDS.
+__device__ inline void stage_log_age_edges(const DevConsts &k, float *ledge) {
+    for (int i = threadIdx.x; i <= NA; i += blockDim.x) ledge[i] = (i < NA) ? k.lage_lo[i] : k.lage_hi[NA - 1];
+    __syncthreads();
+}
+
+__device__ inline void burst_bin(const float *ledge, int i, float l_obs, float mu, float inv_s3, float &p,
                                  float &dp) {
     p = dp = 0.0f;
-    const float lo = k.lage_lo[i];
+    const float lo = ledge[i];
     if (!(lo < l_obs)) return;
-    const float hi = fminf(k.lage_hi[i], l_obs);
+    const float hi = fminf(ledge[i + 1], l_obs);
     const float u_lo = (lo - mu) * inv_s3, u_hi = (hi - mu) * inv_s3;
     // the CDF is odd about 1/2: upper-tail bins use 1 - C(u) = C(-u)
     p = (u_lo > 0.0f) ? tri_cdf(-u_lo) - tri_cdf(-u_hi) : tri_cdf(u_hi) - tri_cdf(u_lo);
@@ -298,11 +305,11 @@ __device__ inline void burst_bin(const DevConsts &k, int i, float l_obs, float m
 }
 
 // first age bin whose upper log-age edge exceeds v (edges increasing, last = +inf)
-__device__ inline int first_bin_above(const DevConsts &k, float v) {
+__device__ inline int first_bin_above(const float *ledge, float v) {
     int a = 0, b = NA - 1;
     while (a < b) {
         const int c = (a + b) >> 1;
-        if (k.lage_hi[c] > v) b = c;
+        if (ledge[c + 1] > v) b = c;
         else a = c + 1;
     }
     return a;
