@@ -173,12 +173,13 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
     const float l_obs = (float)log10_split(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
     const int i0 = first_bin_above(ledge, mu - 3.0f * k.burst_sig);
     float Zb = 0.0f;
-    for (int t = 0; t < k.burst_nbins; ++t) {
-        if (G > 1 && (i0 + t) % G != q) continue;
-        float p, dp;
-        if (i0 + t < NA) burst_bin(ledge, i0 + t, l_obs, mu, inv_s3, p, dp);
-        else p = 0.0f;
-        Zb += p;
+    {
+        BurstEdge lo = burst_edge<false>(ledge, i0, l_obs, mu, inv_s3);
+        for (int t = 0; t < k.burst_nbins; ++t) {
+            const BurstEdge hi = burst_edge<false>(ledge, i0 + t + 1, l_obs, mu, inv_s3);
+            if (G == 1 || (i0 + t) % G == q) Zb += burst_mass(lo, hi);
+            lo = hi;
+        }
     }
     Zb = group_sum<G>(Zb);
     const float fb = th[4], sm = (1.0f - fb) * (float)(1.0 / S), bz = (Zb > 0.0f) ? fb / Zb : 0.0f;
@@ -192,12 +193,13 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
     } else {   // no smooth part (F_burst = 1)
         for (int i = q; i < NA; i += G) col[i] = 0.0f;
     }
-    for (int t = 0; t < k.burst_nbins; ++t) {
-        if (i0 + t >= NA) break;
-        if (G > 1 && (i0 + t) % G != q) continue;
-        float p, dp;
-        burst_bin(ledge, i0 + t, l_obs, mu, inv_s3, p, dp);
-        col[i0 + t] = fmaf(cb, p, col[i0 + t]);
+    {
+        BurstEdge lo = burst_edge<false>(ledge, i0, l_obs, mu, inv_s3);
+        for (int t = 0; t < k.burst_nbins && i0 + t < NA; ++t) {
+            const BurstEdge hi = burst_edge<false>(ledge, i0 + t + 1, l_obs, mu, inv_s3);
+            if (G == 1 || (i0 + t) % G == q) col[i0 + t] = fmaf(cb, burst_mass(lo, hi), col[i0 + t]);
+            lo = hi;
+        }
     }
     {
         float unused[NZ];
@@ -252,18 +254,21 @@ __device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, i
     }
     // burst part over the triweight window
     const float inv_s3 = 1.0f / (3.0f * k.burst_sig);
-    for (int t = 0; t < k.burst_nbins; ++t) {
-        const int i = ws.i0 + t;
-        if (i >= NA) break;
-        if (G > 1 && i % G != q) continue;
-        const float gbar = col[i];
-        float pbr, dpb;
-        burst_bin(ledge, i, ws.l_obs, th[5], inv_s3, pbr, dpb);
-        const float pb = pbr * invZ, pbbar = fb * gbar;
-        fbar = fmaf(gbar, pb, fbar);
-        e1 = fmaf(pbbar, dpb, e1);
-        e2 = fmaf(pbbar, pb, e2);
-        e3 += dpb;
+    {
+        BurstEdge lo = burst_edge<true>(ledge, ws.i0, ws.l_obs, th[5], inv_s3);
+        for (int t = 0; t < k.burst_nbins && ws.i0 + t < NA; ++t) {
+            const int i = ws.i0 + t;
+            const BurstEdge hi = burst_edge<true>(ledge, i + 1, ws.l_obs, th[5], inv_s3);
+            if (G == 1 || i % G == q) {
+                const float gbar = col[i];
+                const float pb = burst_mass(lo, hi) * invZ, dpb = (lo.d - hi.d) * inv_s3, pbbar = fb * gbar;
+                fbar = fmaf(gbar, pb, fbar);
+                e1 = fmaf(pbbar, dpb, e1);
+                e2 = fmaf(pbbar, pb, e2);
+                e3 += dpb;
+            }
+            lo = hi;
+        }
     }
     if (G > 1) {
         fbar = group_sum<G>(fbar); cbar = group_sum<G>(cbar);

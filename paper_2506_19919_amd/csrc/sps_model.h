@@ -292,16 +292,24 @@ __device__ inline void stage_log_age_edges(const DevConsts &k, float *ledge) {
     __syncthreads();
 }
 
-__device__ inline void burst_bin(const float *ledge, int i, float l_obs, float mu, float inv_s3, float &p,
-                                 float &dp) {
-    p = dp = 0.0f;
-    const float lo = ledge[i];
-    if (!(lo < l_obs)) return;
-    const float hi = fminf(ledge[i + 1], l_obs);
-    const float u_lo = (lo - mu) * inv_s3, u_hi = (hi - mu) * inv_s3;
-    // the CDF is odd about 1/2: upper-tail bins use 1 - C(u) = C(-u)
-    p = (u_lo > 0.0f) ? tri_cdf(-u_lo) - tri_cdf(-u_hi) : tri_cdf(u_hi) - tri_cdf(u_lo);
-    dp = (tri_dcdf(u_lo) - tri_dcdf(u_hi)) * inv_s3;
+// The window is walked edge by edge: an edge at standardised log age u keeps the tail value
+// C(-|u|) (no difference near 1 cancels) and, if DERIV, the density C'(u); each edge serves
+// the two bins it bounds.  Edges are clipped to log10 t_obs, so bins past t_obs (and past
+// the last bin) come out empty.
+struct BurstEdge {
+    float u, tail, d;
+};
+template <bool DERIV>
+__device__ inline BurstEdge burst_edge(const float *ledge, int e, float l_obs, float mu, float inv_s3) {
+    BurstEdge r;
+    r.u = (fminf(ledge[min(e, NA)], l_obs) - mu) * inv_s3;
+    r.tail = tri_cdf(-fabsf(r.u));
+    r.d = DERIV ? tri_dcdf(r.u) : 0.0f;
+    return r;
+}
+// profile mass between two edges (the derivative w.r.t. mu is (lo.d - hi.d) / (3 sigma))
+__device__ inline float burst_mass(const BurstEdge &lo, const BurstEdge &hi) {
+    return (lo.u > 0.0f) ? lo.tail - hi.tail : ((hi.u <= 0.0f) ? hi.tail - lo.tail : 1.0f - hi.tail - lo.tail);
 }
 
 // first age bin whose upper log-age edge exceeds v (edges increasing, last = +inf)
