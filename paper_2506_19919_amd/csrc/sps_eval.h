@@ -172,16 +172,10 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
     // is handled by the lane that owns it
     const float l_obs = (float)log10_split(t_obs * 1e9), mu = th[5], inv_s3 = 1.0f / (3.0f * k.burst_sig);
     const int i0 = first_bin_above(ledge, mu - 3.0f * k.burst_sig);
-    float Zb = 0.0f;
-    {
-        BurstEdge lo = burst_edge<false>(ledge, i0, l_obs, mu, inv_s3);
-        for (int t = 0; t < k.burst_nbins; ++t) {
-            const BurstEdge hi = burst_edge<false>(ledge, i0 + t + 1, l_obs, mu, inv_s3);
-            if (G == 1 || (i0 + t) % G == q) Zb += burst_mass(lo, hi);
-            lo = hi;
-        }
-    }
-    Zb = group_sum<G>(Zb);
+    // the window's bin masses telescope: their sum is the profile mass between its first
+    // edge and its last (clipped at t_obs)
+    const float Zb = burst_mass(burst_edge<false>(ledge, i0, l_obs, mu, inv_s3),
+                                burst_edge<false>(ledge, i0 + k.burst_nbins, l_obs, mu, inv_s3));
     const float fb = th[4], sm = (1.0f - fb) * (float)(1.0 / S), bz = (Zb > 0.0f) ? fb / Zb : 0.0f;
     float cb = bz;   // coefficient of the burst profile in the column
     ws.scale = 1.0f;
@@ -340,8 +334,8 @@ __device__ inline void a_frags(const ApproxLds &L, int lane, int h, int ks, cons
         for (int e = 0; e < 8; ++e) {
             const int o = (32 * ks + 8 * lk + e) * HALF + 16 * m + li;
             const float v = PK ? unpack24(hi[o], lo[o]) : L.t(h)[o];
-            // a zero weight gives an exact zero (a NaN column of an inactive galaxy stays out)
-            const float x0 = (w0[m] != 0.0f) ? v * w0[m] : 0.0f, x1 = (w1[m] != 0.0f) ? v * w1[m] : 0.0f;
+            // rows outside the pass get weight 0; a row only ever feeds its own galaxy's results
+            const float x0 = v * w0[m], x1 = v * w1[m];
             const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
             a0h[m][e] = h0;
             a0l[m][e] = (__bf16)(x0 - (float)h0);
