@@ -109,6 +109,18 @@ int sps_get_ztable(sps_ctx *ctx, float *q_host);
 void sps_destroy(sps_ctx *ctx);
 const char *sps_last_error(void);
 
+/* Instrumentation of the approximate path's model kernel (no part of the model).  With
+ * n_pairs > 0 every later approximate-path call (sps_phot_approx, sps_loglike_grad with
+ * SPS_PATH_APPROX, sps_logpost_grad) records a pair of HIP events on its stream right before
+ * and after that kernel, cycling through n_pairs pairs; 0 turns this off and frees the
+ * events.  Calls cost one extra event pair each while on.  n_pairs <= 4096. */
+int sps_set_kernel_timing(sps_ctx *ctx, int n_pairs);
+
+/* Elapsed milliseconds of the last min(n_pairs, calls since timing was set) recorded
+ * launches, oldest first, into ms_out[0 .. max) (waits for those events); *count receives
+ * the number written.  SPS_E_INVAL if timing is off. */
+int sps_kernel_times(sps_ctx *ctx, float *ms_out, int max, int *count);
+
 /* SSP weights W[g][j][i] = M_formed P_met(j) P_age(i) (Eq. galSED_decomposed;
  * sums to 10^params[0]).  params [10][n_gal], z [n_gal], w_out [n_gal][n_met][n_age]. */
 int sps_weights(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float *params, const float *z,

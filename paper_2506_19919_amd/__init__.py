@@ -26,7 +26,8 @@ MAX_BAND = 8
 
 ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_build_ztable", "sps_get_ztable", "sps_destroy",
                  "sps_last_error", "sps_weights", "sps_phot_approx", "sps_phot_exact",
-                 "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run")
+                 "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_set_kernel_timing",
+                 "sps_kernel_times")
 
 
 class SpsError(RuntimeError):
@@ -78,6 +79,8 @@ def _load():
     lib.sps_logpost_grad.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_hmc_run.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp]
+    lib.sps_set_kernel_timing.argtypes = [vp, i]
+    lib.sps_kernel_times.argtypes = [vp, vp, i, C.POINTER(i)]
     for name in ABI_FUNCTIONS:
         if name not in ("sps_destroy", "sps_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -171,6 +174,21 @@ class Context:
         q = np.zeros((n_z, self.n_band, self.n_met, self.n_age), np.float32)
         _check(_lib.sps_get_ztable(self.h, q.ctypes.data_as(C.c_void_p)))
         return q
+
+    # ---- instrumentation
+    def set_kernel_timing(self, n_pairs: int):
+        """Record HIP events around the approximate path's model kernel in the next calls
+        (cycling through n_pairs pairs; 0 turns it off)."""
+        _check(_lib.sps_set_kernel_timing(self.h, n_pairs))
+        self.timing_pairs = n_pairs
+
+    def kernel_times(self) -> np.ndarray:
+        """Milliseconds of the last recorded model-kernel launches, oldest first."""
+        n = max(getattr(self, "timing_pairs", 0), 1)
+        ms = np.zeros(n, np.float32)
+        cnt = C.c_int(0)
+        _check(_lib.sps_kernel_times(self.h, ms.ctypes.data_as(C.c_void_p), n, C.byref(cnt)))
+        return ms[:cnt.value].copy()
 
     # ---- helpers
     def _gal(self, params, z, dtype=torch.float32):

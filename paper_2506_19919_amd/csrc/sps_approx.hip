@@ -283,24 +283,33 @@ int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const flo
     const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE), ug((n + 255) / 256), ub(256);
     const int nb = c->n_band;
     const size_t lds_bytes = approx_lds_bytes(nb, true);
+    hipEvent_t *tev = timing_pair(c);
     switch (mode) {
         case MODE_MAGS:
+            if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, lds_bytes, s, c->k, a);
+            if (tev) (void)hipEventRecord(tev[1], s);
             hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL:
+            if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, lds_bytes, s, c->k, a);
+            if (tev) (void)hipEventRecord(tev[1], s);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL_GRAD:
+            if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, lds_bytes, s, c->k, a);
+            if (tev) (void)hipEventRecord(tev[1], s);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
                                out_val, out_grad);
             break;
         case MODE_LOGPOST_GRAD:
+            if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, lds_bytes, s, c->k, a);
+            if (tev) (void)hipEventRecord(tev[1], s);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
                                out_val, out_grad);
             break;

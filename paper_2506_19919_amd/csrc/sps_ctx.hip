@@ -176,9 +176,16 @@ using namespace sps;
 
 namespace {
 
+static void free_timing(sps_ctx *c) {
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
+    c->tev_calls = 0;
+}
+
 void free_ctx(sps_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    free_timing(c);
     (void)hipFree(c->d_lum64);
     (void)hipFree(c->d_ls32);
     (void)hipFree(c->d_lt32);
@@ -218,6 +225,15 @@ int check_gal(sps_ctx *c, int n_gal, int sfh) {
 }
 
 }  // namespace
+
+namespace sps {
+hipEvent_t *timing_pair(sps_ctx *c) {
+    if (c->tev.empty()) return nullptr;
+    const size_t np = c->tev.size() / 2, i = (size_t)(c->tev_calls++ % (long long)np);
+    return &c->tev[2 * i];
+}
+}  // namespace sps
+
 
 extern "C" {
 
@@ -414,6 +430,38 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
 }
 
 void sps_destroy(sps_ctx *c) { free_ctx(c); }
+
+int sps_set_kernel_timing(sps_ctx *c, int n_pairs) {
+    if (!c || n_pairs < 0 || n_pairs > 4096) return set_error(SPS_E_INVAL, "sps_set_kernel_timing: bad arguments");
+    SPS_HIP(hipSetDevice(c->device));
+    SPS_HIP(hipDeviceSynchronize());
+    free_timing(c);
+    c->tev.resize(2 * (size_t)n_pairs, nullptr);
+    for (auto &e : c->tev) {
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            e = nullptr;
+            free_timing(c);
+            return hip_check(r, "hipEventCreate");
+        }
+    }
+    return SPS_OK;
+}
+
+int sps_kernel_times(sps_ctx *c, float *ms_out, int max, int *count) {
+    if (!c || !ms_out || !count || max < 0) return set_error(SPS_E_INVAL, "sps_kernel_times: bad arguments");
+    if (c->tev.empty()) return set_error(SPS_E_INVAL, "sps_kernel_times: kernel timing is off");
+    SPS_HIP(hipSetDevice(c->device));
+    const long long np = (long long)(c->tev.size() / 2);
+    const long long k = std::min<long long>(std::min<long long>(np, c->tev_calls), max);
+    for (long long j = 0; j < k; ++j) {
+        const size_t i = (size_t)((c->tev_calls - k + j) % np);
+        SPS_HIP(hipEventSynchronize(c->tev[2 * i + 1]));
+        SPS_HIP(hipEventElapsedTime(&ms_out[j], c->tev[2 * i], c->tev[2 * i + 1]));
+    }
+    *count = (int)k;
+    return SPS_OK;
+}
 
 int sps_build_ztable(sps_ctx *c, int n_z, double z_lo, double z_hi) {
     int rc = enter(c);

@@ -82,11 +82,16 @@ struct sps_ctx {
     int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
     void *d_work = nullptr;        // exact-path weights / partial fluxes
     size_t work_bytes = 0;
+    // kernel timing (sps_set_kernel_timing): 2 events per pair, pairs used cyclically
+    std::vector<hipEvent_t> tev;
+    long long tev_calls = 0;
 };
 
 namespace sps {
 
 int set_error(int code, const std::string &msg);
+// the next timing event pair (start, stop) if kernel timing is on, else nullptr
+hipEvent_t *timing_pair(sps_ctx *c);
 int hip_check(hipError_t e, const char *what);
 #define SPS_HIP(call)                                           \
     do {                                                        \

@@ -141,6 +141,27 @@ def test_deterministic_across_runs(ctx, orc):
     np.testing.assert_array_equal(a[1], b[1])
 
 
+def test_kernel_timing_records_the_model_kernel(ctx, orc):
+    import paper_2506_19919_amd as sps
+    sfh, th, z = gal_inputs("dpl", 300, 43)
+    obs, sig, masks = _obs(orc, sfh, th, z, 8)
+    args = (sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8))
+    ref = [t.cpu().numpy() for t in ctx.loglike_grad(*args)]
+    ctx.set_kernel_timing(3)
+    try:
+        for _ in range(5):
+            out = [t.cpu().numpy() for t in ctx.loglike_grad(*args)]
+        ms = ctx.kernel_times()
+    finally:
+        ctx.set_kernel_timing(0)
+    # the last three launches, each a positive duration; results unchanged by the events
+    assert ms.shape == (3,) and np.all(ms > 0.0) and np.all(ms < 1e3)
+    np.testing.assert_array_equal(out[0], ref[0])
+    np.testing.assert_array_equal(out[1], ref[1])
+    with pytest.raises(sps.SpsError):
+        ctx.kernel_times()
+
+
 def test_autograd_function_uses_the_adjoint(ctx, orc):
     import paper_2506_19919_amd as sps
     sfh, th, z = gal_inputs("dpl", 50, 51)
