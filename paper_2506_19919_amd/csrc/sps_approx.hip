@@ -126,7 +126,7 @@ struct ApproxArgs {
 template <int MODE>
 __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, true)
-    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, true)};
+    const ApproxLds lds = approx_lds(lds_dyn, k.n_band, true, 1);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
     const int lane = threadIdx.x;

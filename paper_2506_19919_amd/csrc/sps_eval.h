@@ -75,18 +75,26 @@ __host__ __device__ inline int approx_half_bytes(int n_band, bool pk) {
     const int t = n_band * NZ * HALF * 4;
     return pk ? (t > PK_BYTES ? t : PK_BYTES) : SLOT_W * HALF * 4;
 }
-__host__ __device__ inline int approx_lds_bytes(int n_band, bool pk) {
-    return 2 * approx_half_bytes(n_band, pk) + 2 * WAVE * 4;
+// G lanes per galaxy: 64 / G galaxies per wave, 2 / G half regions
+__host__ __device__ inline int approx_lds_bytes(int n_band, bool pk, int G = 1) {
+    return (2 / G) * approx_half_bytes(n_band, pk) + 2 * WAVE * 4;
 }
 
 struct ApproxLds {
     char *base;
     int half_bytes;
+    int w_off;   // the slice weights: after the 2 / G half regions
     __device__ uint16_t *hi(int h) const { return (uint16_t *)(base + h * half_bytes); }
     __device__ uint8_t *lo(int h) const { return (uint8_t *)(base + h * half_bytes + SLOT_W * HALF * 2); }
     __device__ float *t(int h) const { return (float *)(base + h * half_bytes); }
-    __device__ float *w() const { return (float *)(base + 2 * half_bytes); }
+    __device__ float *w() const { return (float *)(base + w_off); }
 };
+
+// the layout of a wave's block of approx_lds_bytes(n_band, pk, G) bytes at base
+__device__ inline ApproxLds approx_lds(char *base, int n_band, bool pk, int G) {
+    const int hb = approx_half_bytes(n_band, pk);
+    return ApproxLds{base, hb, (2 / G) * hb};
+}
 
 // one lane's 24-bit column
 struct Col24 {
@@ -306,12 +314,12 @@ __device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, i
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 
 // the pass's slice weights of the A rows 16 (2h + m) + l % 16 (0 outside the pass's bucket),
-// times the column scale
-__device__ inline void pass_weights(const ApproxLds &L, int lane, int h, bool act, float f, float scale,
+// times the column scale; row: the lane's galaxy row
+__device__ inline void pass_weights(const ApproxLds &L, int lane, int row, int h, bool act, float f, float scale,
                                     float (&w0)[2], float (&w1)[2]) {
     float *w = L.w();
-    w[lane] = act ? (1.0f - f) * scale : 0.0f;
-    w[WAVE + lane] = act ? f * scale : 0.0f;
+    w[row] = act ? (1.0f - f) * scale : 0.0f;
+    w[WAVE + row] = act ? f * scale : 0.0f;
     __syncthreads();
     const int li = lane & 15;
 #pragma unroll
@@ -363,14 +371,15 @@ __device__ inline v4f mfma3(const b8v &ah, const b8v &al, const b8v &bh, const b
 }
 
 // one contraction: D[g][n] = scale(g) sum_s w_s(g) sum_k A[g][k] B_s[k][n] over K = 96
-// (3 k-steps), N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo)
-template <int MODE_ADJ, bool PK>
+// (3 k-steps), N = 16 nbk; B fragments of node kb at q + kb QB_NODE (hi) and + n_z QB_NODE (lo).
+// M = 64 / G galaxies (G lanes per galaxy), in 2 / G halves of 32.
+template <int MODE_ADJ, bool PK, int G>
 __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, const ApproxLds &L, int lane, int kk,
                                          float f, float scale, int kmin, int kmax, int nbk, int n_out) {
     const int li = lane & 15, lk = lane >> 4;
     const size_t lo_off = (size_t)k.n_z * QB_NODE;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < 2 / G; ++h) {
         v4f acc[6][2];
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
@@ -380,7 +389,7 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
             const bool act = (kk == kb);
             if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
             float w0[2], w1[2];
-            pass_weights(L, lane, h, act, f, scale, w0, w1);
+            pass_weights(L, lane, lane / G, h, act, f, scale, w0, w1);
             const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
 #pragma unroll 1
             for (int ks = 0; ks < KSTEPS; ++ks) {
@@ -419,18 +428,18 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
 
 // T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]), P_age = scale x the column
 // (slots 0..95; 94, 95 zero); T written in FP32, rows 0..R-1
-template <bool PK>
+template <bool PK, int G>
 __device__ __forceinline__ void contract_forward(const DevConsts &k, const uint16_t *qf, const ApproxLds &L, int lane,
                                                  int kk, float f, float scale, int kmin, int kmax) {
-    contract<0, PK>(k, qf, L, lane, kk, f, scale, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
+    contract<0, PK, G>(k, qf, L, lane, kk, f, scale, kmin, kmax, row_blocks(k.n_band), k.n_band * NZ);
 }
 
 // dP_age[g][i] = sum_r C[g][r] ((1 - f) Qk[r][i] + f Qk+1[r][i]); C in slots 0..95 (zero
 // from R on), dP_age written to slots 0..NA-1
-template <bool PK>
+template <bool PK, int G>
 __device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint16_t *qa, const ApproxLds &L, int lane,
                                                  int kk, float f, int kmin, int kmax) {
-    contract<1, PK>(k, qa, L, lane, kk, f, 1.0f, kmin, kmax, AGE_BLK, NA);
+    contract<1, PK, G>(k, qa, L, lane, kk, f, 1.0f, kmin, kmax, AGE_BLK, NA);
 }
 
 // ------------------------------------------------------------------ one evaluation
@@ -438,28 +447,33 @@ __device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint1
 // parameters (MODE_LOGL_GRAD) for the lane's galaxy.  Every lane of the (single-wave)
 // workgroup must call it: the contractions are wave-wide and synchronise the workgroup.
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
-// the lanes' buckets.  L: the wave's LDS block.
-template <int MODE, bool PK>
+// the lanes' buckets.  L: the wave's LDS block.  G adjacent lanes may share a galaxy (value
+// and gradient only): they split its age bins and bands, and all end with the same results.
+template <int MODE, bool PK, int G = 1>
 __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *ledge, int sfh, const uint16_t *qf,
                                             const uint16_t *qa, const ApproxLds &L0,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
+    static_assert(G == 1 || MODE == MODE_LOGL_GRAD, "shared galaxies: value and gradient only");
     const int nb = k.n_band;
     const int lane = opaque((int)threadIdx.x & (WAVE - 1));
-    const ApproxLds L{L0.base, opaque(L0.half_bytes)};
-    const int hl = lane / HALF, ll = lane % HALF;
+    const ApproxLds L{L0.base, opaque(L0.half_bytes), opaque(L0.w_off)};
+    const int row = lane / G, q = lane % G;   // the galaxy's row in the wave, the lane's part
+    const int hl = row / HALF, ll = row % HALF;
     using Col = typename std::conditional<PK, Col24, LdsColT<HALF>>::type;
     Col col = make_col<PK>(L, hl, ll);
     const float *tcol = L.t(hl) + ll;   // T rows of this lane: tcol[r * HALF]
     float pz[NZ];
     WeightsState ws;
-    forward_weights<1, true>(k, ledge, sfh, th, t_obs, col, pz, ws);
-    col[NA] = 0.0f;
-    col[NA + 1] = 0.0f;
+    forward_weights<G, true>(k, ledge, sfh, th, t_obs, col, pz, ws, q);
+    if (q == 0) {
+        col[NA] = 0.0f;
+        col[NA + 1] = 0.0f;
+    }
 
     // ---- contraction: T[b][j] = sum_i P_age(i) Qz[b][j][i]
-    contract_forward<PK>(k, qf, L, lane, kk, f, ws.scale, kmin, kmax);
+    contract_forward<PK, G>(k, qf, L, lane, kk, f, ws.scale, kmin, kmax);
 
     // ---- magnitudes, likelihood.  The band sums, magnitudes and residuals are formed in
     // FP64 from the FP32 row sums: an FP32 magnitude near 25 carries ~2e-6 of rounding,
@@ -473,7 +487,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *led
 #pragma unroll
     for (int b = 0; b < NB_MAX; ++b) {
         sbar[b] = 0.0f;
-        if (b >= nb) continue;
+        if (b >= nb || (G > 1 && b % G != q)) continue;
         double sb = 0.0;
 #pragma unroll
         for (int j = 0; j < NZ; ++j) sb += (double)pz[j] * (double)tcol[(b * NZ + j) * HALF];
@@ -499,6 +513,13 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *led
             }
         }
     }
+    if (G > 1) {
+        logl_d = group_sum<G>(logl_d);
+        gr[0] = group_sum<G>(gr[0]);
+        gr[7] = group_sum<G>(gr[7]);
+        gr[8] = group_sum<G>(gr[8]);
+        gr[9] = group_sum<G>(gr[9]);
+    }
     logl = logl_d;
     if (MODE != MODE_LOGL_GRAD) return;
 
@@ -510,18 +531,18 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *led
 #pragma unroll
         for (int b = 0; b < NB_MAX; ++b)
             if (b < nb) s = fmaf(sbar[b], tcol[(b * NZ + j) * HALF], s);
-        pzbar[j] = s;
+        pzbar[j] = group_sum<G>(s);
     }
     __syncthreads();   // T is read: the rows of C overwrite it
 #pragma unroll
     for (int b = 0; b < NB_MAX; ++b)
 #pragma unroll
         for (int j = 0; j < NZ; ++j)
-            if (b < nb) col[b * NZ + j] = sbar[b] * pz[j];
-    for (int r = nb * NZ; r < 32 * KSTEPS; ++r) col[r] = 0.0f;
+            if (b < nb && (G == 1 || b % G == q)) col[b * NZ + j] = sbar[b] * pz[j];
+    for (int r = nb * NZ + q; r < 32 * KSTEPS; r += G) col[r] = 0.0f;
     // dP_age(i) = sum_{b,j} sbar_b P_Z(j) Qz[b][j][i]
-    contract_adjoint<PK>(k, qa, L, lane, kk, f, kmin, kmax);
-    adjoint_weights(k, ledge, sfh, th, t_obs, ws, col, pzbar, gr);
+    contract_adjoint<PK, G>(k, qa, L, lane, kk, f, kmin, kmax);
+    adjoint_weights<G>(k, ledge, sfh, th, t_obs, ws, col, pzbar, gr, q);
 }
 
 // bounding function (App. C): theta = lo + (hi - lo) sigmoid(k (x - x0)) and d theta / d x

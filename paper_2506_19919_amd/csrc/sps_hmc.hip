@@ -39,6 +39,12 @@ __device__ inline double u01d(uint32_t w) { return ((double)w + 0.5) * 2.3283064
 
 constexpr int MAX_WIN = 24;
 
+// lanes per chain: two adjacent lanes share a chain's model evaluations (each takes half of
+// the age bins and bands), so the 65,536 chains of a 16,384-galaxy batch make 2,048 waves,
+// two per SIMD.  Both lanes carry the whole chain state, bit for bit the same (every shared
+// sum is formed symmetrically), and both write it: each lane only reads back its own writes.
+constexpr int HG = 2;
+
 struct HmcArgs {
     int n_gal, C, L, NW, NS, it0, it1, sfh;
     int n_win;                               // slow metric windows (0 = identity metric)
@@ -114,7 +120,7 @@ __device__ __forceinline__ double logpost(const DevConsts &k, const float *ledge
     const double m0 = lc.m0base - 2.5 * (double)th[0];
     double logl;
     float mags[NB_MAX];
-    approx_eval<MODE_LOGL_GRAD, false>(k, ledge, SFH, a.qf, a.qa, L, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
+    approx_eval<MODE_LOGL_GRAD, false, HG>(k, ledge, SFH, a.qf, a.qa, L, th, lc.zf, lc.kk, lc.f, lc.t_obs, m0, lc.kmin,
                                 lc.kmax, lc.obs_g, lc.sig_g, lc.mask, mags, logl, g);
     asm volatile("" ::: "memory");   // the position is read again, not held through the model
 #pragma unroll
@@ -141,7 +147,7 @@ struct SlotInfo {
 __device__ inline SlotInfo slot_info(const HmcArgs &a) {
     SlotInfo si;
     si.nslot = a.n_gal * a.C;
-    const int slot = blockIdx.x * 64 + (int)threadIdx.x;
+    const int slot = (blockIdx.x * 64 + (int)threadIdx.x) / HG;
     si.valid = slot < si.nslot;
     si.sl = si.valid ? slot : si.nslot - 1;
     const int rank = si.sl / a.C;
@@ -174,8 +180,8 @@ __device__ inline LaneCtx lane_ctx(const DevConsts &k, const HmcArgs &a, const S
 // adaptation state.
 template <int SFH>
 __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
-    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
-    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false, HG)
+    const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
     const SlotInfo si = slot_info(a);
@@ -210,9 +216,9 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
 // (x, p, M^-1 and the scalars of the step-size adaptation) stays in registers across the
 // model evaluations.
 template <int SFH>
-__global__ void __launch_bounds__(64) k_hmc(DevConsts k, HmcArgs a) {
-    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false)
-    const ApproxLds lds{lds_dyn, approx_half_bytes(k.n_band, false)};
+__global__ void __launch_bounds__(64, 2) k_hmc(DevConsts k, HmcArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false, HG)
+    const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
     const SlotInfo si = slot_info(a);
@@ -439,7 +445,7 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     // lp + 20 Welford (double)
     const size_t fbytes = (size_t)nslot * (3 * NP + 4) * sizeof(float) + (size_t)nslot * 2 * sizeof(int);
     const size_t dofs = (fbytes + 255) & ~(size_t)255;
-    const int ntmp = (nslot + 63) / 64 * 64;   // every lane of the grid
+    const int ntmp = (nslot * HG + 63) / 64 * 64;   // every lane of the grid
     const size_t tofs = (dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double) + 255) & ~(size_t)255;
     const size_t need = tofs + (size_t)2 * NP * ntmp * sizeof(float);
     if (c->work_bytes < need) {
@@ -491,9 +497,9 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.wm2 = a.wmean + (size_t)NP * nslot;
     const int nit = cfg->n_warmup + cfg->n_sample;
     const int blk_it = 25;
-    dim3 grid((nslot + 63) / 64), block(64);
+    dim3 grid((nslot * HG + 63) / 64), block(64);
     const bool dpl = (sfh == SPS_SFH_DPL);
-    const size_t lds_bytes = approx_lds_bytes(c->n_band, false);
+    const size_t lds_bytes = approx_lds_bytes(c->n_band, false, HG);
     if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
     else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
     for (int it0 = 0; it0 < nit; it0 += blk_it) {
