@@ -100,7 +100,8 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
         }
         r[REC_MASK] = __int_as_float(ga.mask ? (int)ga.mask[i] : 0xff);
         // per-galaxy cosmology, once per call here rather than in the model kernel
-        const double t_obs = age_universe_gyr(k, (double)z[i]), m0 = mag_offset(k, (double)z[i]);
+        double t_obs, m0;
+        cosmo_at(k, (double)z[i], t_obs, m0);
         r[REC_TOBS] = __int_as_float(__double2loint(t_obs));
         r[REC_TOBS + 1] = __int_as_float(__double2hiint(t_obs));
         r[REC_M0] = __int_as_float(__double2loint(m0));

@@ -143,6 +143,19 @@ __global__ void __launch_bounds__(256) k_qswizzle(int n_z, int R, const float *_
     put(qa, 32 * ks + 8 * (lane >> 4) + e, 16 * outer + (lane & 15));
 }
 
+// cosmology table rows: t_obs, dt/dz, mag_offset, dm/dz at z = lo + i dz
+__global__ void __launch_bounds__(256) k_cosmo_table(DevConsts k, int n, double lo, double dz, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double z = lo + dz * (double)i, dl = lum_distance_cm(k, z);
+    double dt, dm;
+    cosmo_derivs(k, z, dl, dt, dm);
+    out[4 * i] = age_universe_gyr(k, z);
+    out[4 * i + 1] = dt;
+    out[4 * i + 2] = -2.5 * log10((1.0 + z) * k.kfac) + 5.0 * log10(dl);
+    out[4 * i + 3] = dm;
+}
+
 int launch_ztable(sps_ctx *c, hipStream_t st) {
     const int nb = c->n_band, nw = c->n_wave, nkb = c->k.n_z * nb, S = c->n_met * c->n_age;
     double *d_fc = nullptr, *d_fs = nullptr, *d_tw = nullptr;
@@ -156,6 +169,12 @@ int launch_ztable(sps_ctx *c, hipStream_t st) {
     hipLaunchKernelGGL(k_filter_weights, dim3(nkb), dim3(256), 0, st, nb, nw, (double)c->k.z_lo,
                        (double)c->k.dz, d_fc, d_fs, c->d_wave, c->d_trap, d_tw);
     hipLaunchKernelGGL(k_ztable, dim3(S), dim3(256), nw * sizeof(double), st, S, nkb, nw, c->d_lum64, d_tw, c->d_q);
+    {
+        DevConsts k0 = c->k;
+        k0.ctab = nullptr;
+        hipLaunchKernelGGL(k_cosmo_table, dim3((CT_N + 255) / 256), dim3(256), 0, st, k0, CT_N, c->k.ct_lo,
+                           c->k.ct_dz, c->d_ctab);
+    }
     {
         const size_t total = (size_t)c->k.n_z * QB_NODE;
         hipLaunchKernelGGL(k_qswizzle, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, c->k.n_z, nb * NZ,
@@ -200,6 +219,7 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_q);
     (void)hipFree(c->d_qf);
     (void)hipFree(c->d_qa);
+    (void)hipFree(c->d_ctab);
     (void)hipFree(c->d_perm);
     (void)hipFree(c->d_inv);
     (void)hipFree(c->d_rec);
@@ -472,18 +492,26 @@ int sps_build_ztable(sps_ctx *c, int n_z, double z_lo, double z_hi) {
     (void)hipFree(c->d_q);
     (void)hipFree(c->d_qf);
     (void)hipFree(c->d_qa);
+    (void)hipFree(c->d_ctab);
     c->d_q = nullptr;
     c->d_qf = c->d_qa = nullptr;
+    c->d_ctab = nullptr;
+    c->k.ctab = nullptr;
     c->k.n_z = 0;
     SPS_HIP(hipMalloc(&c->d_q, (size_t)n_z * c->n_band * NZ * NA * sizeof(float)));
     const size_t frag = (size_t)2 * n_z * QB_NODE * sizeof(uint16_t);   // hi and lo
     SPS_HIP(hipMalloc(&c->d_qf, frag));
     SPS_HIP(hipMalloc(&c->d_qa, frag));
+    SPS_HIP(hipMalloc(&c->d_ctab, (size_t)4 * CT_N * sizeof(double)));
     c->k.z_lo = (float)z_lo;
     c->k.dz = (float)((z_hi - z_lo) / (n_z - 1));
     c->k.n_z = n_z;
+    c->k.ct_lo = z_lo;
+    c->k.ct_dz = (z_hi - z_lo) / (CT_N - 1);
+    c->k.ct_inv_dz = 1.0 / c->k.ct_dz;
     rc = launch_ztable(c, nullptr);
     if (rc) c->k.n_z = 0;
+    else c->k.ctab = c->d_ctab;
     return rc;
 }
 

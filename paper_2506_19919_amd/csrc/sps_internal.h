@@ -47,7 +47,13 @@ struct DevConsts {
     double kfac;                  // Lsun / (4 pi c[A/s] 3631 Jy)  (AB normalisation)
     double gl_x[NGL_DL], gl_w[NGL_DL];  // positive Gauss-Legendre nodes/weights (24-point)
     double gl8_x[4], gl8_w[4];          // positive nodes/weights of the 8-point rule
+    // t_obs(z) and the distance part of the magnitude offset, with their z derivatives, on
+    // CT_N nodes over the z table's range: [CT_N][4] FP64 in device memory (null until a z
+    // table is built)
+    const double *ctab;
+    double ct_lo, ct_dz, ct_inv_dz;
 };
+constexpr int CT_N = 1025;
 
 }  // namespace sps
 
@@ -73,6 +79,7 @@ struct sps_ctx {
     float *d_q = nullptr;          // [n_z][n_band][n_met][n_age]
     uint16_t *d_qf = nullptr;      // z table fragments, forward contraction: hi [n_z][QB_NODE], then lo
     uint16_t *d_qa = nullptr;      // z table fragments, adjoint contraction: hi, then lo
+    double *d_ctab = nullptr;      // cosmology table (DevConsts::ctab)
     // per-galaxy workspace
     int max_gal = 0;
     int *d_perm = nullptr;         // galaxies ordered by z bucket
