@@ -58,13 +58,12 @@ __global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restr
     if (t < nb) cursor[t] = s[t] - ((t < nb) ? hist[t] : 0);
 }
 
-// each block reserves a range per bucket in the global cursor, then places its galaxies;
-// with ga.rec set it also writes each galaxy's input record at its new position
+// each block reserves a range per bucket in the global cursor, then places its galaxies
+// (the order only: k_bucket_gather places them with their input records)
 __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
-                                                              int *__restrict__ cursor, int *__restrict__ perm,
-                                                              GatherArgs ga) {
+                                                              int *__restrict__ cursor, int *__restrict__ perm) {
     extern __shared__ int sh[];
-    const int nbk = k.n_z, nb = k.n_band;
+    const int nbk = k.n_z;
     int *cnt = sh, *pos = sh + nbk;
     for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
     __syncthreads();
@@ -86,9 +85,80 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
     for (int t = 0; t < SORT_PER_THREAD; ++t) {
         const int i = base + t * SORT_BLOCK + threadIdx.x;
         if (kk_t[t] < 0) continue;
-        const int at = atomicAdd(&pos[kk_t[t]], 1);
-        perm[at] = i;
-        if (!ga.rec) continue;
+        perm[atomicAdd(&pos[kk_t[t]], 1)] = i;
+    }
+}
+
+// exclusive prefix sum of v[0..n) into out[0..n), n <= 4 SORT_BLOCK; every thread of the block
+// calls it (part: SORT_BLOCK ints of LDS)
+__device__ inline void block_exclusive_scan(const int *v, int *out, int n, int *part) {
+    const int tid = threadIdx.x, per = (n + SORT_BLOCK - 1) / SORT_BLOCK, b0 = tid * per;
+    int s = 0;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < n) s += v[b0 + j];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < SORT_BLOCK; o <<= 1) {
+        const int x = (tid >= o) ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int j = 0; j < per; ++j)
+        if (b0 + j < n) {
+            out[b0 + j] = run;
+            run += v[b0 + j];
+        }
+    __syncthreads();
+}
+
+// The sort's placement with the record gather, staged through LDS so that the record writes
+// are whole, contiguous lines: a block's galaxies are laid out in LDS in sorted order (one run
+// per bucket, each run contiguous at its destination too) and the block then copies the runs
+// out as consecutive 16-byte chunks.  LDS: GATHER_TILE records of RSTRIDE floats, their
+// destinations and sources, and the per-bucket counts, global offsets and local starts.
+constexpr int GATHER_PER_THREAD = 2, GATHER_TILE = SORT_BLOCK * GATHER_PER_THREAD;
+constexpr int RSTRIDE = REC + 4;   // 144-byte LDS rows: 16-byte writes of different rows spread over the banks
+__host__ __device__ inline size_t gather_lds_bytes(int nbk) {
+    return ((size_t)GATHER_TILE * RSTRIDE + 2 * GATHER_TILE + 3 * (size_t)nbk) * sizeof(int);
+}
+
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_gather(DevConsts k, int n, const float *__restrict__ z,
+                                                             int *__restrict__ cursor, int *__restrict__ perm,
+                                                             GatherArgs ga) {
+    extern __shared__ __attribute__((aligned(16))) int gsh[];
+    __shared__ int part[SORT_BLOCK];
+    const int nbk = k.n_z, nb = k.n_band, tid = threadIdx.x;
+    float *recs = (float *)gsh;
+    int *dest = gsh + GATHER_TILE * RSTRIDE, *src = dest + GATHER_TILE;
+    int *cnt = src + GATHER_TILE, *pos = cnt + nbk, *start = pos + nbk;
+    for (int b = tid; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * GATHER_TILE;
+    int bk[GATHER_PER_THREAD], lr[GATHER_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GATHER_PER_THREAD; ++u) {
+        const int i = base + u * SORT_BLOCK + tid;
+        bk[u] = -1;
+        lr[u] = 0;
+        if (i < n) {
+            float f;
+            const int kk = z_bucket(k, z[i], &f);
+            bk[u] = kk < 0 ? nbk - 1 : kk;
+            lr[u] = atomicAdd(&cnt[bk[u]], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < nbk; b += SORT_BLOCK) pos[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
+    block_exclusive_scan(cnt, start, nbk, part);
+#pragma unroll
+    for (int u = 0; u < GATHER_PER_THREAD; ++u) {
+        if (bk[u] < 0) continue;
+        const int i = base + u * SORT_BLOCK + tid;
+        const int sl = start[bk[u]] + lr[u], at = pos[bk[u]] + lr[u];
+        dest[sl] = at;
+        src[sl] = i;
         float r[REC];
 #pragma unroll
         for (int p = 0; p < NP; ++p) r[p] = ga.params[(size_t)p * n + i];
@@ -106,10 +176,17 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
         r[REC_TOBS + 1] = __int_as_float(__double2hiint(t_obs));
         r[REC_M0] = __int_as_float(__double2loint(m0));
         r[REC_M0 + 1] = __int_as_float(__double2hiint(m0));
-        v4f *dst = (v4f *)(ga.rec + (size_t)at * REC);
+        v4f *row = (v4f *)(recs + (size_t)sl * RSTRIDE);
 #pragma unroll
-        for (int q = 0; q < REC / 4; ++q) dst[q] = v4f{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
+        for (int q = 0; q < REC / 4; ++q) row[q] = v4f{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
         ga.inv[i] = at;
+    }
+    __syncthreads();
+    const int nv = min(GATHER_TILE, n - base);
+    for (int c = tid; c < nv * (REC / 4); c += SORT_BLOCK) {
+        const int r = c / (REC / 4), q = c % (REC / 4);
+        ((v4f *)(ga.rec + (size_t)dest[r] * REC))[q] = ((const v4f *)(recs + (size_t)r * RSTRIDE))[q];
+        if (q == 0) perm[dest[r]] = src[r];
     }
 }
 
@@ -266,9 +343,13 @@ int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const G
     const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
     hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, c->k, n, z, hist);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
-    const GatherArgs none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, c->k, n, z, cursor,
-                       c->d_perm, ga ? *ga : none);
+    if (ga && ga->rec) {
+        hipLaunchKernelGGL(k_bucket_gather, dim3((n + GATHER_TILE - 1) / GATHER_TILE), dim3(SORT_BLOCK),
+                           gather_lds_bytes(nbk), s, c->k, n, z, cursor, c->d_perm, *ga);
+    } else {
+        hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, c->k, n, z, cursor,
+                           c->d_perm);
+    }
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }
