@@ -239,3 +239,34 @@ def test_weights_at_parameter_box_corners(ctx, orc):
     for g in range(len(th)):
         np.testing.assert_allclose(w[g].sum(), 10 ** th[g, 0], rtol=2e-5)
         np.testing.assert_allclose(w[g], ref[g], rtol=1e-4, atol=1e-7 * 10 ** th[g, 0])
+
+
+@pytest.mark.parametrize("n_band", [3, 8])
+def test_other_band_counts_match_oracle(oracle_mod, ssp2000, n_band):
+    """The per-wave LDS block is sized by the band count (the FP32 table row sums outgrow the
+    24-bit columns from 7 bands on): magnitudes, log L and gradient at 3 and 8 bands."""
+    import paper_2506_19919_amd as sps
+    filt = synth.filters(n_band)
+    o = oracle_mod.Oracle(ssp2000, filt)
+    o.build_ztable(64, 0.1, 3.0)
+    c = sps.Context(ssp2000, filt, precisions=(sps.SPS_F64, sps.SPS_F32), max_gal=4096)
+    try:
+        c.build_ztable(64, 0.1, 3.0)
+        n = 300
+        sfh, th, z = gal_inputs("dpl", n, 900 + n_band)
+        m = c.phot_approx(sfh, soa(th), dev(z)).cpu().numpy().astype(np.float64)
+        m_ref = o.phot_approx(sfh, th, z)
+        assert m.shape == (n, n_band)
+        assert np.abs(m - m_ref).max() <= MAG_TOL, np.abs(m - m_ref).max()
+        noise, sig = synth.photometric_noise(n, n_band, 31)
+        obs, sig = f32(m_ref + noise), f32(sig)
+        masks = synth.band_masks(n, n_band, 7, lo=min(3, n_band), hi=n_band)
+        ll, g = c.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8))
+        ll, g = ll.cpu().numpy().astype(np.float64), g.cpu().numpy().T.astype(np.float64)
+        rl, rg = o.loglike_grad(sfh, th, z, obs, sig, masks)
+        prop, _ = grad_tol(o, sfh, th, z, sig, masks, m)
+        assert np.all(np.abs(ll - rl) <= 1e-3 * np.abs(rl) + 1e-4)
+        ok = grad_ok(g, rg, prop)
+        assert ok.all(), (np.argwhere(~ok)[:10], g[~ok][:10], rg[~ok][:10])
+    finally:
+        c.close()
