@@ -1,7 +1,7 @@
-// Batched HMC on the unbounded parameters (Sec. 4; App. C, D.2).  One chain per
-// lane; the n_chain chains of a galaxy sit in adjacent lanes and galaxies are in
-// z-bucket order, so a wave shares its z-table slices.  Each launch advances all
-// chains by a block of iterations; chain state lives in HBM between launches.
+// Batched HMC on the unbounded parameters (Sec. 4; App. C, D.2).  Two adjacent lanes per
+// chain (HG); the n_chain chains of a galaxy sit in adjacent lane pairs and galaxies are in
+// z-bucket order, so a wave shares its z-table slices.  Each launch advances all chains by a
+// block of iterations; chain state lives in HBM between launches.
 //
 // Per iteration: momentum p ~ N(0, M) from Philox4x32-10 (Box-Muller, scaled by
 // M^1/2), n_leapfrog leapfrog steps (half kick, drift by M^-1 p, half kick; one
@@ -13,7 +13,7 @@
 // parameters over slow warm-up windows; at a window's end M^-1 = n/(n+5) var +
 // 1e-3 * 5/(n+5) and dual averaging restarts at mu = log(10 eps).
 // Sampling: Welford mean / M2 of the physical parameters per chain (FP64); the same
-// registers hold the window statistics during warm-up.
+// state arrays hold the window statistics during warm-up.
 #include "sps_eval.h"
 
 namespace sps {
