@@ -39,14 +39,19 @@ def log(msg):
 
 
 def kernel_source_digest():
-    """sha256 over the HIP sources and headers the kernels are built from."""
+    """sha256 over the code of the HIP sources and headers the kernels are built from (comments
+    and whitespace removed, so that an edit of a comment does not void the counters)."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2506_19919_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+            with open(os.path.join(d, name), encoding="utf-8") as f:
+                code = re.sub(r"/\*.*?\*/", " ", f.read(), flags=re.S)
+            code = re.sub(r"//[^\n]*", " ", code)
+            code = " ".join(code.split())
+            h.update(name.encode() + b"\0" + code.encode())
     return h.hexdigest()
 
 
