@@ -60,40 +60,45 @@ __device__ inline float unpack24(uint16_t h, uint8_t l) {
 }
 
 // Per-wave LDS of the approximate path, sized at launch.  Each half of the wave (lanes
-// 32h .. 32h + 31) owns a region of half_bytes: its lanes' columns of SLOT_W 24-bit values
-// (slot s of lane l at hi[s * HALF + l % HALF] and lo[s * HALF + l % HALF]), overlaid by
-// the FP32 table row sums T of the same lanes (row r at t[r * HALF + l % HALF]) once the
-// half's forward contraction has read its columns.  T stays in FP32: the metallicity
+// 32h .. 32h + 31) owns a region: its lanes' columns of SLOT_W 24-bit values (slot s of lane
+// l in row prow(s) of a 16-bit array hi[row * HALF + l % HALF] and of an 8-bit array lo[...]),
+// overlaid by the FP32 table row sums T of the same lanes (row r at t[r * HALF + l % HALF])
+// once the half's forward contraction has read its columns.  T stays in FP32: the metallicity
 // gradient is a difference of these sums (the weights' derivatives sum to zero over Z).
-// Then the two z-slice weights of every lane in FP32.  Up to 6 bands 18,944 bytes, so that
-// eight single-wave workgroups fit in a CU's 160 KiB.
+// Then the two z-slice weights of every lane in FP32.  Bank spreading: the regions are
+// RSKEW bytes further apart than their size (the two halves' same-lane accesses fall 32 banks
+// apart), and prow flips the low two bits of the slot by its bits 3..4, so that the four
+// slots a fragment read takes at once (8 apart) lie in different bank groups.  Up to 6
+// bands 19,200 bytes, so that eight single-wave workgroups fit in a CU's 160 KiB.
 constexpr int HALF = WAVE / 2;
 constexpr int PK_BYTES = SLOT_W * HALF * 3;
-// PK = false: the columns in FP32 as well (SLOT_W x HALF floats per half), for kernels whose
-// occupancy the LDS does not limit
+constexpr int RSKEW = 128;
+__host__ __device__ inline int prow(int s) { return s ^ ((s >> 3) & 3); }
+// PK = false: the columns in FP32 as well (SLOT_W x HALF floats per half, natural row order),
+// for kernels whose occupancy the LDS does not limit
 __host__ __device__ inline int approx_half_bytes(int n_band, bool pk) {
     const int t = n_band * NZ * HALF * 4;
     return pk ? (t > PK_BYTES ? t : PK_BYTES) : SLOT_W * HALF * 4;
 }
 // G lanes per galaxy: 64 / G galaxies per wave, 2 / G half regions
 __host__ __device__ inline int approx_lds_bytes(int n_band, bool pk, int G = 1) {
-    return (2 / G) * approx_half_bytes(n_band, pk) + 2 * WAVE * 4;
+    return (2 / G) * (approx_half_bytes(n_band, pk) + RSKEW) + 2 * WAVE * 4;
 }
 
 struct ApproxLds {
     char *base;
-    int half_bytes;
-    int w_off;   // the slice weights: after the 2 / G half regions
-    __device__ uint16_t *hi(int h) const { return (uint16_t *)(base + h * half_bytes); }
-    __device__ uint8_t *lo(int h) const { return (uint8_t *)(base + h * half_bytes + SLOT_W * HALF * 2); }
-    __device__ float *t(int h) const { return (float *)(base + h * half_bytes); }
+    int rstride;   // bytes from one half's region to the next
+    int w_off;     // the slice weights: after the 2 / G half regions
+    __device__ uint16_t *hi(int h) const { return (uint16_t *)(base + h * rstride); }
+    __device__ uint8_t *lo(int h) const { return (uint8_t *)(base + h * rstride + SLOT_W * HALF * 2); }
+    __device__ float *t(int h) const { return (float *)(base + h * rstride); }
     __device__ float *w() const { return (float *)(base + w_off); }
 };
 
 // the layout of a wave's block of approx_lds_bytes(n_band, pk, G) bytes at base
 __device__ inline ApproxLds approx_lds(char *base, int n_band, bool pk, int G) {
-    const int hb = approx_half_bytes(n_band, pk);
-    return ApproxLds{base, hb, (2 / G) * hb};
+    const int rs = approx_half_bytes(n_band, pk) + RSKEW;
+    return ApproxLds{base, rs, (2 / G) * rs};
 }
 
 // one lane's 24-bit column
@@ -112,7 +117,7 @@ struct Col24 {
         }
         __device__ Ref &operator=(const Ref &o) { return *this = (float)o; }
     };
-    __device__ Ref operator[](int s) const { return Ref{hi + s * HALF, lo + s * HALF}; }
+    __device__ Ref operator[](int s) const { return Ref{hi + prow(s) * HALF, lo + prow(s) * HALF}; }
 };
 
 // sum over the G adjacent lanes that share one galaxy (G = 1, 2, 4, ...)
@@ -340,8 +345,9 @@ __device__ inline void a_frags(const ApproxLds &L, int lane, int h, int ks, cons
     for (int m = 0; m < 2; ++m) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int o = (32 * ks + 8 * lk + e) * HALF + 16 * m + li;
-            const float v = PK ? unpack24(hi[o], lo[o]) : L.t(h)[o];
+            const int slot = 32 * ks + 8 * lk + e, c = 16 * m + li;
+            const float v = PK ? unpack24(hi[prow(slot) * HALF + c], lo[prow(slot) * HALF + c])
+                               : L.t(h)[slot * HALF + c];
             // rows outside the pass get weight 0; a row only ever feeds its own galaxy's results
             const float x0 = v * w0[m], x1 = v * w1[m];
             const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
@@ -417,9 +423,9 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
             if (nb < nbk && 16 * nb + li < n_out) {
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
-                    const int o = (16 * nb + li) * HALF + 16 * m + 4 * lk;
-                    if (MODE_ADJ && PK) store4_24(L.hi(h), L.lo(h), o, acc[nb][m]);
-                    else *(v4f *)(L.t(h) + o) = acc[nb][m];
+                    const int r = 16 * nb + li, c = 16 * m + 4 * lk;
+                    if (MODE_ADJ && PK) store4_24(L.hi(h), L.lo(h), prow(r) * HALF + c, acc[nb][m]);
+                    else *(v4f *)(L.t(h) + r * HALF + c) = acc[nb][m];
                 }
             }
         __syncthreads();
@@ -458,7 +464,7 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *led
     static_assert(G == 1 || MODE == MODE_LOGL_GRAD, "shared galaxies: value and gradient only");
     const int nb = k.n_band;
     const int lane = opaque((int)threadIdx.x & (WAVE - 1));
-    const ApproxLds L{L0.base, opaque(L0.half_bytes), opaque(L0.w_off)};
+    const ApproxLds L{L0.base, opaque(L0.rstride), opaque(L0.w_off)};
     const int row = lane / G, q = lane % G;   // the galaxy's row in the wave, the lane's part
     const int hl = row / HALF, ll = row % HALF;
     using Col = typename std::conditional<PK, Col24, LdsColT<HALF>>::type;
