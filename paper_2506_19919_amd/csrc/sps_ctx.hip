@@ -208,10 +208,8 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_lum64);
     (void)hipFree(c->d_ls32);
     (void)hipFree(c->d_lt32);
-    (void)hipFree(c->d_ls_hi);
-    (void)hipFree(c->d_ls_lo);
-    (void)hipFree(c->d_lt_hi);
-    (void)hipFree(c->d_lt_lo);
+    (void)hipFree(c->d_ls_bx);
+    (void)hipFree(c->d_lt_bx);
     (void)hipFree(c->d_wc);
     (void)hipFree(c->d_wave);
     (void)hipFree(c->d_trap);
@@ -417,20 +415,19 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
         if ((rc = upload((void **)&c->d_lt32, lt.data(), np * sizeof(float)))) return fail(rc);
     }
     if (prec_mask & (1u << SPS_BF16X)) {
-        std::vector<uint16_t> ls_h(np, 0), ls_l(np, 0), lt_h(np, 0), lt_l(np, 0);
+        std::vector<uint16_t> ls_x(2 * np, 0), lt_x(2 * np, 0);
         for (size_t s = 0; s < S; ++s)
             for (int l = 0; l < nw; ++l) {
                 const float f = (float)ssp->lum[s * nw + l];
                 const uint16_t h = bf16_rne(f), lo = bf16_rne(f - bf16_to_f(h));
-                ls_h[s * lw + l] = h;
-                ls_l[s * lw + l] = lo;
-                lt_h[(size_t)l * S_PAD + s] = h;
-                lt_l[(size_t)l * S_PAD + s] = lo;
+                const size_t a = bfx_at(s, lw, l), b = bfx_at(l, S_PAD, (int)s);
+                ls_x[a] = h;
+                ls_x[a + 32] = lo;
+                lt_x[b] = h;
+                lt_x[b + 32] = lo;
             }
-        if ((rc = upload((void **)&c->d_ls_hi, ls_h.data(), np * 2))) return fail(rc);
-        if ((rc = upload((void **)&c->d_ls_lo, ls_l.data(), np * 2))) return fail(rc);
-        if ((rc = upload((void **)&c->d_lt_hi, lt_h.data(), np * 2))) return fail(rc);
-        if ((rc = upload((void **)&c->d_lt_lo, lt_l.data(), np * 2))) return fail(rc);
+        if ((rc = upload((void **)&c->d_ls_bx, ls_x.data(), np * 4))) return fail(rc);
+        if ((rc = upload((void **)&c->d_lt_bx, lt_x.data(), np * 4))) return fail(rc);
     }
     {
         std::vector<float> wc((size_t)lw * 4, 0.0f);

@@ -271,9 +271,9 @@ constexpr int XSPLIT = 4;                                    // K ranges of the 
 
 struct XArgs {
     int M, N, K;
-    const void *A_hi, *A_lo;
+    const void *A;             // FP32 [M][lda], or BF16 hi + lo interleaved [M][2 lda] (bfx_at)
     int lda;
-    const void *B_hi, *B_lo;
+    const void *B;             // likewise [N][ldb]
     int ldb;
     int n_mt, n_nt;
     int k_splits;              // EPI_STORE: K is split into this many ranges, one partial C each
@@ -301,12 +301,13 @@ __device__ inline void x_load(const XArgs &a, int tile_m, int tile_n, int k0, in
         const int ld = isA ? a.lda : a.ldb;
         const size_t grow = (size_t)(isA ? tile_m : tile_n) + row;
         if constexpr (P == SPS_F32) {
-            const float *base = (const float *)(isA ? a.A_hi : a.B_hi);
+            const float *base = (const float *)(isA ? a.A : a.B);
             r[c] = *(const v4f *)(base + grow * ld + k0 + 4 * q);
         } else {
-            // q < 4: hi, 8 bf16 each; q >= 4: lo
-            const uint16_t *base = (const uint16_t *)(q < 4 ? (isA ? a.A_hi : a.B_hi) : (isA ? a.A_lo : a.B_lo));
-            r[c] = *(const v4f *)(base + grow * ld + k0 + 8 * (q & 3));
+            // interleaved hi / lo rows: the k-tile's 32 hi then 32 lo are one 128-byte line,
+            // chunks q < 4 hi and q >= 4 lo, in the LDS row order
+            const uint16_t *base = (const uint16_t *)(isA ? a.A : a.B);
+            r[c] = *(const v4f *)(base + grow * 2 * ld + 2 * k0 + 8 * q);
         }
     }
 }
@@ -563,7 +564,7 @@ __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, co
 
 // weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP (coalesced rows)
 template <int P>
-__global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w_hi, void *w_lo) {
+__global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w) {
     const int sidx = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
     if (sidx >= S_PAD) return;
     float v = 0.0f;
@@ -572,11 +573,12 @@ __global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w_
         v = pw[(size_t)(PW_PZ + j) * n + g] * pw[(size_t)i * n + g];
     }
     if constexpr (P == SPS_F32) {
-        ((float *)w_hi)[(size_t)g * S_PAD + sidx] = v;
+        ((float *)w)[(size_t)g * S_PAD + sidx] = v;
     } else {
         const uint16_t h = f2bf(v);
-        ((uint16_t *)w_hi)[(size_t)g * S_PAD + sidx] = h;
-        ((uint16_t *)w_lo)[(size_t)g * S_PAD + sidx] = f2bf(v - bf2f(h));
+        const size_t o = bfx_at(g, S_PAD, sidx);   // interleaved hi / lo rows
+        ((uint16_t *)w)[o] = h;
+        ((uint16_t *)w)[o + 32] = f2bf(v - bf2f(h));
     }
 }
 
@@ -647,7 +649,7 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
 // bands more than 8 sigma from the redshifted wavelength contribute below FP32 resolution
 template <int P>
 __global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, const float *params, const float *z,
-                             const double *wave, const float *wc, const float *cnum, void *r_hi, void *r_lo) {
+                             const double *wave, const float *wc, const float *cnum, void *rb) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
     if (l >= ld) return;
     float v = 0.0f;
@@ -666,11 +668,12 @@ __global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, co
         }
     }
     if (P == SPS_F32) {
-        ((float *)r_hi)[(size_t)g * ld + l] = v;
+        ((float *)rb)[(size_t)g * ld + l] = v;
     } else {
         const uint16_t h = f2bf(v);
-        ((uint16_t *)r_hi)[(size_t)g * ld + l] = h;
-        ((uint16_t *)r_lo)[(size_t)g * ld + l] = f2bf(v - bf2f(h));
+        const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
+        ((uint16_t *)rb)[o] = h;
+        ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
     }
 }
 
@@ -783,7 +786,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         c->work_bytes = off;
     }
     char *W = (char *)c->d_work;
-    void *w_hi = W + o_w, *w_lo = W + o_w + (size_t)mp * S_PAD * tsz;
+    void *w_hi = W + o_w;   // weights rows: FP32 [mp][S_PAD], or BF16 hi + lo interleaved [mp][2 S_PAD]
 
     float *pw = f64 ? nullptr : (float *)(W + o_pw);
     if (f64) {
@@ -793,8 +796,8 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         hipLaunchKernelGGL(k_exact_pw, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
                            (const float *)params, (const float *)z, pw);
         const dim3 ge((S_PAD + 255) / 256, n), be(256);
-        if (prec == SPS_F32) hipLaunchKernelGGL(k_expand<SPS_F32>, ge, be, 0, s, n, (const float *)pw, w_hi, w_lo);
-        else hipLaunchKernelGGL(k_expand<SPS_BF16X>, ge, be, 0, s, n, (const float *)pw, w_hi, w_lo);
+        if (prec == SPS_F32) hipLaunchKernelGGL(k_expand<SPS_F32>, ge, be, 0, s, n, (const float *)pw, w_hi);
+        else hipLaunchKernelGGL(k_expand<SPS_BF16X>, ge, be, 0, s, n, (const float *)pw, w_hi);
     }
     float *part = (float *)(W + o_part);
     if (f64) {
@@ -805,7 +808,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         a.K_valid = NSSP;
         a.K_pad = S_PAD;
         a.A_hi = w_hi;
-        a.A_lo = w_lo;
+        a.A_lo = nullptr;
         a.lda = S_PAD;
         a.B_hi = c->d_lum64;
         a.B_lo = nullptr;
@@ -826,11 +829,9 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         a.M = n;
         a.N = lw;
         a.K = S_PAD;
-        a.A_hi = w_hi;
-        a.A_lo = w_lo;
+        a.A = w_hi;
         a.lda = S_PAD;
-        a.B_hi = (prec == SPS_F32) ? (const void *)c->d_lt32 : (const void *)c->d_lt_hi;
-        a.B_lo = (prec == SPS_F32) ? nullptr : (const void *)c->d_lt_lo;
+        a.B = (prec == SPS_F32) ? (const void *)c->d_lt32 : (const void *)c->d_lt_bx;
         a.ldb = S_PAD;
         a.n_mt = mp / XBM;
         a.n_nt = lw / XBN;
@@ -875,25 +876,23 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
             break;
     }
     if (want_grad) {
-        void *r_hi = W + o_rb, *r_lo = W + o_rb + (size_t)mp * lw * tsz;
+        void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
         dim3 gr((lw + 255) / 256, n), br(256);
         FiltConst fl;
         for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)c->h_fc[b]; fl.fs[b] = (float)c->h_fs[b]; }
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi, r_lo);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi);
         else
             hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi, r_lo);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi);
         XArgs b{};
         b.M = n;
         b.N = S_PAD;
         b.K = lw;
-        b.A_hi = r_hi;
-        b.A_lo = r_lo;
+        b.A = r_hi;
         b.lda = lw;
-        b.B_hi = (prec == SPS_F32) ? (const void *)c->d_ls32 : (const void *)c->d_ls_hi;
-        b.B_lo = (prec == SPS_F32) ? nullptr : (const void *)c->d_ls_lo;
+        b.B = (prec == SPS_F32) ? (const void *)c->d_ls32 : (const void *)c->d_ls_bx;
         b.ldb = lw;
         b.n_mt = mp / XBM;
         b.n_nt = S_PAD / XBN;

@@ -29,6 +29,14 @@ constexpr int QB_NODE = 6 * KSTEPS * 64 * 8;
 __host__ __device__ inline int row_blocks(int n_band) { return (n_band * NZ + 15) / 16; }
 constexpr int S_PAD = 1152;       // SSP rows padded to a multiple of 128
 
+// BF16 hi + lo pairs of a row-major matrix-core operand, interleaved per 32-element chunk of
+// its contiguous (k) dimension: element k of row r (row length ld, a multiple of 32) has its
+// hi at 2 ld r + 64 (k / 32) + k % 32 and its lo 32 further on, so that the hi and lo of a
+// k-tile of 32 are one 128-byte line
+__host__ __device__ inline size_t bfx_at(size_t r, int ld, int k) {
+    return r * 2 * (size_t)ld + 64 * (size_t)(k >> 5) + (size_t)(k & 31);
+}
+
 // Kernel-facing constants, passed by value (kernarg segment).
 struct DevConsts {
     int n_band, n_wave;
@@ -72,7 +80,7 @@ struct sps_ctx {
     //   lt: [LW][S_PAD]  (B of the forward GEMM, k = SSP)
     int lw = 0;
     float *d_ls32 = nullptr, *d_lt32 = nullptr;
-    uint16_t *d_ls_hi = nullptr, *d_ls_lo = nullptr, *d_lt_hi = nullptr, *d_lt_lo = nullptr;
+    uint16_t *d_ls_bx = nullptr, *d_lt_bx = nullptr;   // BF16 hi + lo, interleaved (bfx_at)
     float *d_wc = nullptr;         // per wavelength [LW][4]: ln(l / 5500 A), l q_l, q_l / l, 0
     double *d_wave = nullptr, *d_trap = nullptr;
     double *d_edges = nullptr;     // FP64 bin edges: age_lo, age_hi [Gyr], lage_lo, lage_hi [NA each], met_lo, met_hi [NZ]
