@@ -57,7 +57,7 @@ class _Model(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_double), ("init_step", C.c_double),
-                ("seed", C.c_uint64), ("adapt_metric", C.c_int)]
+                ("seed", C.c_uint64), ("adapt_metric", C.c_int), ("path", C.c_int)]
 
 
 _lib = None
@@ -252,15 +252,15 @@ class Oracle:
         p = _f64(pri3)
         return lib().orc_log_prior(_p(p), float(x))
 
-    def logpost_grad(self, sfh, theta_u, z, obs, sigma, mask, bounds, prior):
+    def logpost_grad(self, sfh, theta_u, z, obs, sigma, mask, bounds, prior, path=0):
         x = _f64(theta_u)
         o, s = _f64(obs), _f64(sigma)
         b, pr = _f64(bounds), _f64(prior)
         lp = np.zeros(1)
         g = np.zeros(N_PARAM)
-        n_z, lo, hi, qp = self._zt()
+        n_z, lo, hi, qp = self._zt() if path == 0 else (0, C.c_double(0), C.c_double(0), None)
         rc = self.L.orc_logpost_grad(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo),
-                                     C.byref(self.model), n_z, lo, hi, qp, sfh, _p(x), C.c_double(z),
+                                     C.byref(self.model), int(path), n_z, lo, hi, qp, sfh, _p(x), C.c_double(z),
                                      _p(o), _p(s), C.c_uint8(int(mask)), _p(b), _p(pr), _p(lp), _p(g))
         assert rc == 0
         return lp[0], g
@@ -291,12 +291,12 @@ class Oracle:
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
                 keep_samples=False, keep_trace=False, gauss_prec=None, gal_id=None, n_gal_total=0,
-                adapt_metric=False):
+                adapt_metric=False, path=0):
         th0 = _f64(theta0)
         n_gal = th0.shape[1]
         assert th0.shape == (n_chain, n_gal, N_PARAM)
         cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
-                      {False: 0, True: 1, "diag": 1, "dense": 2}[adapt_metric])
+                      {False: 0, True: 1, "diag": 1, "dense": 2}[adapt_metric], int(path))
         minv = np.zeros((n_chain, n_gal, N_PARAM))
         pm, ps, rh = (np.zeros((n_gal, N_PARAM)) for _ in range(3))
         acc = np.zeros(n_gal)
@@ -305,7 +305,7 @@ class Oracle:
         tr = np.zeros((n_warmup + n_sample, n_chain, n_gal)) if keep_trace else None
         gp = _f64(gauss_prec) if gauss_prec is not None else None
         if gp is None:
-            n_z, lo, hi, qp = self._zt()
+            n_z, lo, hi, qp = self._zt() if path == 0 else (0, C.c_double(0), C.c_double(0), None)
             zz, o, s = _f64(z), _f64(obs), _f64(sigma)
             mk = np.ascontiguousarray(mask, dtype=np.uint8)
             b, pr = _f64(bounds), _f64(prior)

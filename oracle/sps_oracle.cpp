@@ -479,13 +479,17 @@ bool check_common(const orc_ssp *s, const orc_filters *f) {
 }
 
 // log posterior on unbounded parameters, value and gradient (dual numbers)
-void logpost(const Model &X, int n_z, double z_lo, double z_hi, const double *q, int sfh,
+void logpost(const Model &X, int path, int n_z, double z_lo, double z_hi, const double *q, int sfh,
              const double *xu, double z, const double *obs, const double *sig, uint8_t mask,
              const double *bounds, const double *prior, double *lp, double *grad) {
     Dual x[NP], th[NP], mags[8];
     for (int p = 0; p < NP; ++p) { x[p] = Dual(xu[p]); x[p].d[p] = 1.0; }
     for (int p = 0; p < NP; ++p) th[p] = bound<Dual>(bounds + 4 * p, x[p]);
-    mags_approx<Dual>(X.G, X.f, X.c, X.m, n_z, z_lo, z_hi, q, sfh, th, z, mags);
+    // the magnitudes of either photometry path (Sec. 3): the z table or the full spectrum
+    if (path == 0)
+        mags_approx<Dual>(X.G, X.f, X.c, X.m, n_z, z_lo, z_hi, q, sfh, th, z, mags);
+    else
+        mags_exact<Dual>(X.G, X.f, X.c, X.m, sfh, th, z, mags);
     Dual v = loglike<Dual>(mags, obs, sig, mask, X.f.n_band);
     for (int p = 0; p < NP; ++p) v += log_prior<Dual>(prior + 3 * p, x[p]);
     *lp = v.v;
@@ -696,13 +700,13 @@ double orc_unbound(const double *bnd, double th) {
 }
 double orc_log_prior(const double *pri, double x) { return log_prior<double>(pri, x); }
 
-int orc_logpost_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+int orc_logpost_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m, int path,
                      int n_z, double z_lo, double z_hi, const double *q, int sfh, const double *theta_u,
                      double z, const double *obs, const double *sigma, uint8_t mask,
                      const double *bounds, const double *prior, double *logp, double *grad) {
-    if (!check_common(s, f) || !q || !theta_u || !bounds || !prior || !logp || !grad) return 1;
+    if (!check_common(s, f) || (path == 0 && !q) || !theta_u || !bounds || !prior || !logp || !grad) return 1;
     Model X(s, f, c, m);
-    logpost(X, n_z, z_lo, z_hi, q, sfh, theta_u, z, obs, sigma, mask, bounds, prior, logp, grad);
+    logpost(X, path, n_z, z_lo, z_hi, q, sfh, theta_u, z, obs, sigma, mask, bounds, prior, logp, grad);
     return 0;
 }
 
@@ -724,7 +728,7 @@ int orc_leapfrog(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
             }
             *lp = v;
         } else {
-            logpost(*X, n_z, z_lo, z_hi, q, sfh, xx, z, obs, sigma, mask, bounds, prior, lp, gr);
+            logpost(*X, 0, n_z, z_lo, z_hi, q, sfh, xx, z, obs, sigma, mask, bounds, prior, lp, gr);
         }
     };
     double gr[NP], lp;
@@ -774,7 +778,9 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 double *inv_metric) {
     if (!cfg || cfg->n_chain < 1 || cfg->n_leapfrog < 1 || cfg->n_warmup < 0 || cfg->n_sample < 2) return 1;
     if (!theta0 || n_gal < 0) return 1;
-    if (!gauss_prec && (!check_common(s, f) || !q || !z || !obs || !sigma || !mask || !bounds || !prior))
+    if (cfg->path != 0 && cfg->path != 1) return 1;
+    if (!gauss_prec && (!check_common(s, f) || (cfg->path == 0 && !q) || !z || !obs || !sigma || !mask || !bounds ||
+                        !prior))
         return 1;
     const int C = cfg->n_chain, L = cfg->n_leapfrog, NW = cfg->n_warmup, NS = cfg->n_sample;
     const int NIT = NW + NS;
@@ -806,7 +812,7 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 }
                 *lp = v;
             } else {
-                logpost(*X, n_z, z_lo, z_hi, q, sfh, x, z[g], obs + (size_t)g * nb, sigma + (size_t)g * nb,
+                logpost(*X, cfg->path, n_z, z_lo, z_hi, q, sfh, x, z[g], obs + (size_t)g * nb, sigma + (size_t)g * nb,
                         mask[g], bounds, prior, lp, gr);
             }
         };

@@ -96,8 +96,9 @@ int orc_mags_jacobian(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c
 double orc_bound(const double *bnd, double x_unbounded);
 double orc_unbound(const double *bnd, double theta);
 double orc_log_prior(const double *pri, double x_unbounded);
-/* log posterior on the unbounded parameters and its gradient [10] */
-int orc_logpost_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+/* log posterior on the unbounded parameters and its gradient [10]; path 0: approximate
+ * photometry (needs the z table q), 1: exact photometry */
+int orc_logpost_grad(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m, int path,
                      int n_z, double z_lo, double z_hi, const double *q, int sfh,
                      const double *theta_u, double z, const double *obs, const double *sigma,
                      uint8_t mask, const double *bounds, const double *prior,
@@ -119,6 +120,7 @@ typedef struct {
     double target_accept, init_step;
     uint64_t seed;
     int adapt_metric;   /* 0: identity mass matrix; 1: diagonal, 2: dense, adapted in slow windows */
+    int path;           /* photometry of the likelihood: 0 approximate (z table), 1 exact */
 } orc_hmc_cfg;
 
 /* Slow adaptation windows of a warm-up of n_warmup iterations: window w covers
