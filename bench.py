@@ -198,6 +198,56 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False):
             "mean_accept": float(out["accept"].mean().item())}
 
 
+def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=None):
+    """HMC with exact photometry on the HMC workload's shape: every leapfrog step is one MFMA
+    value+gradient over all n x C chains.  A short run (n_iter iterations, timed) gives the
+    time per iteration; the full run's length (full_iter iterations) is extrapolated
+    linearly, since every iteration does the same work."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] exact-path HMC: {n} galaxies x {C} chains, {n_iter} iterations x {L} leapfrog steps")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C)
+    th, z = synth.galaxies_dpl(n, 104)
+    params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    noise, sig = synth.photometric_noise(n, 6, 204)
+    mags = ctx.phot_exact(synth.SFH_DPL, params, zt, prec=sps.SPS_F32)
+    obs = (mags + torch.as_tensor(noise, dtype=torch.float32, device=dev)).contiguous()
+    sigma = torch.as_tensor(sig, dtype=torch.float32, device=dev)
+    mask = torch.as_tensor(synth.band_masks(n, 6, 204)).to(dev)
+    bounds = torch.as_tensor(synth.bounds_k_x0(), dtype=torch.float32, device=dev)
+    prior = torch.as_tensor(synth.PRIOR, dtype=torch.float32, device=dev)
+    theta0 = torch.as_tensor(synth.prior_draws(C, n, 304), dtype=torch.float32, device=dev).contiguous()
+    res = {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, exact photometry (1128 SSPs x 2000 "
+                       f"wavelengths) in every step; {n_iter} iterations timed, {full_iter} extrapolated",
+           "unit": "posteriors/min (extrapolated from the timed iterations)"}
+    n_warm = n_iter // 2
+    for name, prec in (("f32", sps.SPS_F32), ("bf16x", sps.SPS_BF16X)):
+        kw = dict(n_chain=C, n_leapfrog=L, path=sps.SPS_PATH_EXACT, prec=prec, seed=404)
+        ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, n_warmup=1, n_sample=2, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, n_warmup=n_warm,
+                          n_sample=n_iter - n_warm, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_it = wall / n_iter
+        full = per_it * full_iter
+        evals = float(n) * C * (n_iter * L + 1)
+        r = {"ms_per_iteration": per_it * 1e3, "value_grad_evals_per_s": evals / wall,
+             "projected_wall_s": full, "posteriors_per_min": n / full * 60.0,
+             "mean_accept": float(out["accept"].mean().item())}
+        if approx_wall:
+            r["exact_over_approx_wall"] = full / approx_wall
+        res[name] = r
+        log(f"[bench]   {name}: {per_it * 1e3:.1f} ms per iteration, {full_iter} iterations ~ {full:.1f} s")
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +257,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
+    ap.add_argument("--no-hmc-exact", action="store_true")
     ap.add_argument("--hmc-gal", type=int, default=16_384)
     ap.add_argument("--hmc-warmup", type=int, default=200)
     ap.add_argument("--hmc-sample", type=int, default=1000)
@@ -318,6 +369,10 @@ def main():
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
                                               adapt_metric=True)
+    if not args.no_hmc_exact:
+        aw = out["hmc"]["wall_s"] if "hmc" in out else None
+        out["hmc_exact"] = bench_hmc_exact(dev, args.hmc_gal, full_iter=args.hmc_warmup + args.hmc_sample,
+                                           approx_wall=aw)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ssp, filt, th32, z32, noise, sig)

@@ -178,13 +178,21 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
  *   accept [n_gal] acceptance fraction in the sampling phase,
  *   step [n_chain][n_gal] step size after warm-up,
  *   inv_metric [n_chain][10][n_gal] diagonal M^-1 after warm-up, or NULL.
+ * path selects the photometry inside the likelihood (Sec. 3): SPS_PATH_APPROX (the z
+ * table; needs sps_build_ztable; one fused kernel runs whole blocks of iterations) or
+ * SPS_PATH_EXACT (the spectrum-level MFMA contraction and its adjoint in precision prec,
+ * SPS_F32 or SPS_BF16X, whose table must have been uploaded; every leapfrog step is one
+ * exact value+gradient call over all n_gal * n_chain chains).  prec is ignored on the
+ * approximate path.  Both paths draw the same Philox streams.
  * Needs n_gal * n_chain <= the reserved galaxy count; grows the context's chain-state
- * workspace (device memory, ~260 B per chain) on first use. */
+ * workspace (device memory, ~260 B per chain; ~460 B plus the exact path's own
+ * workspace for SPS_PATH_EXACT) on first use. */
 typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     float target_accept, init_step;
     unsigned long long seed;
     int adapt_metric;
+    int path, prec;
 } sps_hmc_cfg;
 
 int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh,

@@ -55,7 +55,7 @@ class _ModelDesc(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_float), ("init_step", C.c_float),
-                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int)]
+                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int), ("path", C.c_int), ("prec", C.c_int)]
 
 
 def _load():
@@ -253,7 +253,7 @@ class Context:
 
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
-                keep_samples=False, adapt_metric=False, stream=None):
+                keep_samples=False, adapt_metric=False, path=SPS_PATH_APPROX, prec=SPS_F32, stream=None):
         n = z.shape[0]
         _dev(z, torch.float32, (n,), "z", self.device)
         _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
@@ -269,7 +269,7 @@ class Context:
                    inv_metric=torch.empty((n_chain, NPARAM, n), **f32))
         samples = torch.empty((n_sample, n_chain, NPARAM, n), **f32) if keep_samples else None
         cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
-                      int(bool(adapt_metric)))
+                      int(bool(adapt_metric)), int(path), int(prec))
         _check(_lib.sps_hmc_run(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs),
                                 _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0),
                                 _ptr(samples), _ptr(out["post_mean"]), _ptr(out["post_sd"]),

@@ -224,6 +224,7 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hist);
     (void)hipFree(c->d_work);
+    (void)hipFree(c->d_hwork);
     delete c;
 }
 
@@ -606,7 +607,15 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
     if (cfg->adapt_metric != 0 && cfg->adapt_metric != 1) return set_error(SPS_E_INVAL, "adapt_metric must be 0 or 1");
     if ((long long)n_gal * cfg->n_chain > (long long)c->max_gal)
         return set_error(SPS_E_INVAL, "n_gal * n_chain exceeds the reserved workspace (call sps_reserve)");
-    if (c->k.n_z == 0) return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
+    if (cfg->path != SPS_PATH_APPROX && cfg->path != SPS_PATH_EXACT) return set_error(SPS_E_INVAL, "bad path");
+    if (cfg->path == SPS_PATH_APPROX && c->k.n_z == 0)
+        return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
+    if (cfg->path == SPS_PATH_EXACT) {
+        if (cfg->prec != SPS_F32 && cfg->prec != SPS_BF16X)
+            return set_error(SPS_E_INVAL, "exact-path HMC runs in SPS_F32 or SPS_BF16X");
+        if (!(c->prec_mask & (1u << cfg->prec)))
+            return set_error(SPS_E_STATE, "this precision's SSP table was not uploaded");
+    }
     if (n_gal == 0) return SPS_OK;
     if (!z || !obs || !sigma || !band_mask || !bounds || !prior || !theta0 || !post_mean || !post_sd || !rhat ||
         !accept || !step)

@@ -565,7 +565,8 @@ __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, co
 // weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP (coalesced rows)
 template <int P>
 __global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w) {
-    const int sidx = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+    // galaxies on the grid's x axis (no 65,535-block limit there), SSP columns on y
+    const int sidx = blockIdx.y * 256 + threadIdx.x, g = blockIdx.x;
     if (sidx >= S_PAD) return;
     float v = 0.0f;
     if (sidx < NSSP) {
@@ -650,7 +651,7 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
 template <int P>
 __global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, const float *params, const float *z,
                              const double *wave, const float *wc, const float *cnum, void *rb) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+    const int l = blockIdx.y * blockDim.x + threadIdx.x, g = blockIdx.x;   // galaxies on x
     if (l >= ld) return;
     float v = 0.0f;
     if (l < n_wave) {
@@ -795,7 +796,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     } else {
         hipLaunchKernelGGL(k_exact_pw, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
                            (const float *)params, (const float *)z, pw);
-        const dim3 ge((S_PAD + 255) / 256, n), be(256);
+        const dim3 ge(n, (S_PAD + 255) / 256), be(256);
         if (prec == SPS_F32) hipLaunchKernelGGL(k_expand<SPS_F32>, ge, be, 0, s, n, (const float *)pw, w_hi);
         else hipLaunchKernelGGL(k_expand<SPS_BF16X>, ge, be, 0, s, n, (const float *)pw, w_hi);
     }
@@ -877,7 +878,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     }
     if (want_grad) {
         void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
-        dim3 gr((lw + 255) / 256, n), br(256);
+        dim3 gr(n, (lw + 255) / 256), br(256);
         FiltConst fl;
         for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)c->h_fc[b]; fl.fs[b] = (float)c->h_fs[b]; }
         if (prec == SPS_F32)

@@ -362,7 +362,8 @@ __global__ void __launch_bounds__(64, 2) k_hmc(DevConsts k, HmcArgs a) {
 }
 #undef ST
 
-// pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy
+// pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy; slot
+// r * C + c holds chain c of galaxy perm[r] (of galaxy r if perm is null)
 __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ perm,
                               const double *__restrict__ wmean, const double *__restrict__ wm2,
                               const int *__restrict__ nacc, const float *__restrict__ eps,
@@ -370,7 +371,7 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
                               float *accept, float *step, float *inv_metric) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_gal) return;
-    const int g = perm[r], nslot = n_gal * C;
+    const int g = perm ? perm[r] : r, nslot = n_gal * C;
     int acc = 0;
     for (int c = 0; c < C; ++c) {
         acc += nacc[r * C + c];
@@ -403,6 +404,237 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ exact-path HMC
+// With exact photometry the model is a GEMM over all chains at once (Sec. 3), so the
+// leapfrog runs as a host loop: each step is one exact value+gradient call over every chain
+// (the likelihood entry point's own kernels), with small per-chain kernels around it for
+// the kicks, the drift and the end of the iteration.  Slot = galaxy * C + chain (the exact
+// path needs no z order).  Chain ids, Philox counters, the FP32 trajectory arithmetic, the
+// FP64 Hamiltonian and the adaptation are those of the fused approximate-path kernel.
+struct HmcxArgs {
+    int n_gal, C, nslot, nb, NW, NS;
+    int n_win;
+    int win_s[MAX_WIN], win_e[MAX_WIN];
+    float target, init_step;
+    uint32_t key0, key1;
+    const float *z, *obs, *sigma;
+    const uint8_t *mask;
+    const float *bounds, *prior, *theta0;
+    float *samples;
+    // chain state, [quantity][slot]
+    float *x, *gr, *minv, *eps, *mu, *hbar, *lebar;
+    int *nacc, *da0;
+    double *lp, *h0, *wmean, *wm2;
+    // trajectory (momentum, position), the physical parameters of the model call and its
+    // outputs (log L, gradient w.r.t. the physical parameters)
+    float *pm, *xt, *th, *logl, *grad;
+    // per-slot copies of the galaxy's inputs, the layout the exact path reads
+    float *zs, *obs_s, *sig_s;
+    uint8_t *mask_s;
+};
+
+#define XS(arr, p) (arr)[(size_t)(p) * a.nslot + s]
+
+// per-slot inputs and the starting point
+__global__ void __launch_bounds__(256) k_hmcx_setup(HmcxArgs a) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.nslot) return;
+    const int g = s / a.C, ch = s % a.C;
+    a.zs[s] = a.z[g];
+    for (int b = 0; b < a.nb; ++b) {
+        a.obs_s[(size_t)s * a.nb + b] = a.obs[(size_t)g * a.nb + b];
+        a.sig_s[(size_t)s * a.nb + b] = a.sigma[(size_t)g * a.nb + b];
+    }
+    a.mask_s[s] = a.mask[g];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const float x = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
+        float th, dth;
+        bound_param(a.bounds + 4 * p, x, th, dth);
+        XS(a.xt, p) = x;
+        XS(a.th, p) = th;
+    }
+}
+
+// log posterior on the unbounded parameters at the trajectory position from the model
+// call's log L and physical-parameter gradient: prior added, chain rule through F_B
+__device__ inline double hmcx_logpost(const HmcxArgs &a, int s, float (&x)[NP], float (&g)[NP]) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) x[p] = XS(a.xt, p);
+    float dlp[NP];
+    const double lp = (double)a.logl[s] + log_prior_all(a.prior, x, dlp);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        float th, dth;
+        bound_param(a.bounds + 4 * p, x[p], th, dth);
+        g[p] = fmaf(XS(a.grad, p), dth, dlp[p]);
+    }
+    return lp;
+}
+
+__global__ void __launch_bounds__(256) k_hmcx_init(HmcxArgs a) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.nslot) return;
+    float x[NP], g[NP];
+    const double lp = hmcx_logpost(a, s, x, g);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        XS(a.x, p) = x[p];
+        XS(a.gr, p) = g[p];
+        XS(a.minv, p) = 1.0f;
+        XS(a.wmean, p) = 0.0;
+        XS(a.wm2, p) = 0.0;
+    }
+    a.lp[s] = lp;
+    a.eps[s] = a.init_step;
+    a.mu[s] = logf(10.0f * a.init_step);
+    a.hbar[s] = 0.0f;
+    a.lebar[s] = 0.0f;
+    a.nacc[s] = 0;
+    a.da0[s] = 0;
+}
+
+// iteration it begins: momentum draw, H0, the first half kick and drift
+__global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.nslot) return;
+    const int g = s / a.C, ch = s % a.C;
+    const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
+    uint32_t w[NP];
+#pragma unroll
+    for (int blk = 0; blk < 3; ++blk) {
+        uint32_t c4[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
+        philox4x32_10(c4, a.key0, a.key1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (4 * blk + t < NP) w[4 * blk + t] = c4[t];
+    }
+    float p[NP];
+#pragma unroll
+    for (int t = 0; t < NP / 2; ++t) {
+        const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
+        float sn, cs;
+        sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
+        p[2 * t] = r * cs / sqrtf(XS(a.minv, 2 * t));
+        p[2 * t + 1] = r * sn / sqrtf(XS(a.minv, 2 * t + 1));
+    }
+    double H0 = -a.lp[s];
+    const float eps = a.eps[s];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+        const float mi = XS(a.minv, t);
+        H0 += 0.5 * (double)mi * (double)p[t] * (double)p[t];
+        p[t] = fmaf(0.5f * eps, XS(a.gr, t), p[t]);
+        XS(a.pm, t) = p[t];
+        const float xt = fmaf(eps * mi, p[t], XS(a.x, t));
+        float th, dth;
+        bound_param(a.bounds + 4 * t, xt, th, dth);
+        XS(a.xt, t) = xt;
+        XS(a.th, t) = th;
+    }
+    a.h0[s] = H0;
+}
+
+// after the model call of a leapfrog step: the closing half kick; then either the next
+// step's half kick and drift, or (last step) the Metropolis test, the step-size and metric
+// adaptation and the sample statistics
+__global__ void __launch_bounds__(256) k_hmcx_step(HmcxArgs a, int it, int last) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.nslot) return;
+    const int g = s / a.C, ch = s % a.C;
+    float x[NP], gn[NP], p[NP];
+    const double lpn = hmcx_logpost(a, s, x, gn);
+    const float eps = a.eps[s];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], XS(a.pm, t));
+    if (!last) {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            p[t] = fmaf(0.5f * eps, gn[t], p[t]);
+            XS(a.pm, t) = p[t];
+            const float xt = fmaf(eps * XS(a.minv, t), p[t], x[t]);
+            float th, dth;
+            bound_param(a.bounds + 4 * t, xt, th, dth);
+            XS(a.xt, t) = xt;
+            XS(a.th, t) = th;
+        }
+        return;
+    }
+    double H1 = -lpn;
+#pragma unroll
+    for (int t = 0; t < NP; ++t) H1 += 0.5 * (double)XS(a.minv, t) * (double)p[t] * (double)p[t];
+    const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
+    uint32_t c4[4] = {2u, (uint32_t)it, chain_id, 0u};   // the accept draw: word 2 of block 2
+    philox4x32_10(c4, a.key0, a.key1);
+    float alpha;
+    const bool acc = metropolis(H1, H1 - a.h0[s], c4[2], alpha);
+    float xn[NP];
+    if (acc) {
+        a.lp[s] = lpn;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            xn[t] = x[t];
+            XS(a.x, t) = x[t];
+            XS(a.gr, t) = gn[t];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) xn[t] = XS(a.x, t);
+    }
+    if (it < a.NW) {
+        const int da0 = a.da0[s];
+        const float m = (float)(it - da0 + 1), eta = 1.0f / (m + 10.0f);
+        float hbar = (1.0f - eta) * a.hbar[s] + eta * (a.target - alpha);
+        const float leps = a.mu[s] - sqrtf(m) / 0.05f * hbar, wk = powf(m, -0.75f);
+        float lebar = wk * leps + (1.0f - wk) * a.lebar[s];
+        float e = expf(it == a.NW - 1 ? lebar : leps);
+        int wi = -1;
+        for (int q = 0; q < a.n_win; ++q)
+            if (it >= a.win_s[q] && it < a.win_e[q]) wi = q;
+        if (wi >= 0) {
+            const double nn = (double)(it - a.win_s[wi] + 1);
+            const bool wlast = (it == a.win_e[wi] - 1);
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                double wmean = XS(a.wmean, t), wm2 = XS(a.wm2, t);
+                const double d = (double)xn[t] - wmean;
+                wmean += d / nn;
+                wm2 += d * ((double)xn[t] - wmean);
+                if (wlast) {
+                    XS(a.minv, t) = (float)(nn / (nn + 5.0) * (wm2 / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0));
+                    wmean = wm2 = 0.0;
+                }
+                XS(a.wmean, t) = wmean;
+                XS(a.wm2, t) = wm2;
+            }
+            if (wlast) {
+                a.mu[s] = logf(10.0f * e);
+                hbar = lebar = 0.0f;
+                a.da0[s] = it + 1;
+            }
+        }
+        a.hbar[s] = hbar;
+        a.lebar[s] = lebar;
+        a.eps[s] = e;
+    } else {
+        a.nacc[s] += acc ? 1 : 0;
+        const double nrec = (double)(it - a.NW + 1);
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            float th, dth;
+            bound_param(a.bounds + 4 * t, xn[t], th, dth);
+            double wmean = XS(a.wmean, t), wm2 = XS(a.wm2, t);
+            const double d = (double)th - wmean;
+            wmean += d / nrec;
+            wm2 += d * ((double)th - wmean);
+            XS(a.wmean, t) = wmean;
+            XS(a.wm2, t) = wm2;
+            if (a.samples) a.samples[(((size_t)(it - a.NW) * a.C + ch) * NP + t) * a.n_gal + g] = th;
+        }
+    }
+}
+#undef XS
+
 // Slow windows of the metric adaptation over nw warm-up iterations.  Defaults: fast
 // buffers of 75 (first) and 50 (last) iterations around windows of 25, 50, 100, ...;
 // if 75 + 25 + 50 exceeds nw, the buffers are 15 % and 10 % of nw and the first window
@@ -430,6 +662,103 @@ static int metric_windows(int nw, int *ws, int *we) {
     return n;
 }
 
+static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
+                            const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+                            const float *prior, const float *theta0, float *samples, float *post_mean,
+                            float *post_sd, float *rhat, float *accept, float *step, float *inv_metric,
+                            int n_win, const int *win_s, const int *win_e) {
+    const int C = cfg->n_chain, nslot = n_gal * C, nb = c->n_band;
+    HmcxArgs a{};
+    a.n_win = n_win;
+    for (int w = 0; w < n_win; ++w) {
+        a.win_s[w] = win_s[w];
+        a.win_e[w] = win_e[w];
+    }
+    // chain state and trajectory: floats x, gr, minv, pm, xt, th, grad [NP] + eps, mu, hbar,
+    // lebar, logl, zs + obs_s, sig_s [nb]; ints nacc, da0; doubles lp, h0 + wmean, wm2 [NP];
+    // bytes mask_s
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t o_f = carve((size_t)nslot * (7 * NP + 6 + 2 * nb) * sizeof(float));
+    const size_t o_i = carve((size_t)nslot * 2 * sizeof(int));
+    const size_t o_d = carve((size_t)nslot * (2 + 2 * NP) * sizeof(double));
+    const size_t o_m = carve((size_t)nslot);
+    if (c->hwork_bytes < off) {
+        SPS_HIP(hipDeviceSynchronize());
+        (void)hipFree(c->d_hwork);
+        c->d_hwork = nullptr;
+        c->hwork_bytes = 0;
+        SPS_HIP(hipMalloc(&c->d_hwork, off));
+        c->hwork_bytes = off;
+    }
+    char *W = (char *)c->d_hwork;
+    float *fp = (float *)(W + o_f);
+    auto fq = [&](int count) { float *r = fp; fp += (size_t)count * nslot; return r; };
+    a.x = fq(NP);
+    a.gr = fq(NP);
+    a.minv = fq(NP);
+    a.pm = fq(NP);
+    a.xt = fq(NP);
+    a.th = fq(NP);
+    a.grad = fq(NP);
+    a.eps = fq(1);
+    a.mu = fq(1);
+    a.hbar = fq(1);
+    a.lebar = fq(1);
+    a.logl = fq(1);
+    a.zs = fq(1);
+    a.obs_s = fq(nb);
+    a.sig_s = fq(nb);
+    a.nacc = (int *)(W + o_i);
+    a.da0 = a.nacc + nslot;
+    a.lp = (double *)(W + o_d);
+    a.h0 = a.lp + nslot;
+    a.wmean = a.h0 + nslot;
+    a.wm2 = a.wmean + (size_t)NP * nslot;
+    a.mask_s = (uint8_t *)(W + o_m);
+    a.n_gal = n_gal;
+    a.C = C;
+    a.nslot = nslot;
+    a.nb = nb;
+    a.NW = cfg->n_warmup;
+    a.NS = cfg->n_sample;
+    a.target = cfg->target_accept;
+    a.init_step = cfg->init_step;
+    a.key0 = (uint32_t)(cfg->seed & 0xffffffffull);
+    a.key1 = (uint32_t)(cfg->seed >> 32);
+    a.z = z;
+    a.obs = obs;
+    a.sigma = sigma;
+    a.mask = mask;
+    a.bounds = bounds;
+    a.prior = prior;
+    a.theta0 = theta0;
+    a.samples = samples;
+    const dim3 grid((nslot + 255) / 256), block(256);
+    // one exact value+gradient over every chain at the positions in a.th
+    auto model = [&]() {
+        return launch_exact(c, s, nslot, sfh, cfg->prec, a.th, a.zs, nullptr, a.obs_s, a.sig_s, a.mask_s, a.logl,
+                            a.grad);
+    };
+    hipLaunchKernelGGL(k_hmcx_setup, grid, block, 0, s, a);
+    int rc = model();
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_hmcx_init, grid, block, 0, s, a);
+    const int nit = cfg->n_warmup + cfg->n_sample;
+    for (int it = 0; it < nit; ++it) {
+        hipLaunchKernelGGL(k_hmcx_start, grid, block, 0, s, a, it);
+        for (int l = 0; l < cfg->n_leapfrog; ++l) {
+            if ((rc = model())) return rc;
+            hipLaunchKernelGGL(k_hmcx_step, grid, block, 0, s, a, it, (int)(l == cfg->n_leapfrog - 1));
+        }
+    }
+    hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
+                       nullptr, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                       inv_metric);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
                const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
@@ -441,6 +770,9 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
         a.n_win = metric_windows(cfg->n_warmup, a.win_s, a.win_e);
         if (a.n_win < 0) return set_error(SPS_E_INVAL, "n_warmup too long for the metric-window table");
     }
+    if (cfg->path == SPS_PATH_EXACT)
+        return launch_hmc_exact(c, s, cfg, n_gal, sfh, z, obs, sigma, mask, bounds, prior, theta0, samples,
+                                post_mean, post_sd, rhat, accept, step, inv_metric, a.n_win, a.win_s, a.win_e);
     // chain state: 10 x + 10 grad + 10 M^-1 + eps, mu, hbar, lebar (float), nacc, da0 (int);
     // lp + 20 Welford (double)
     const size_t fbytes = (size_t)nslot * (3 * NP + 4) * sizeof(float) + (size_t)nslot * 2 * sizeof(int);

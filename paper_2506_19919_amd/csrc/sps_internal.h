@@ -97,6 +97,8 @@ struct sps_ctx {
     int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
     void *d_work = nullptr;        // exact-path weights / partial fluxes
     size_t work_bytes = 0;
+    void *d_hwork = nullptr;       // chain state of the exact-path HMC (d_work serves its model calls)
+    size_t hwork_bytes = 0;
     // kernel timing (sps_set_kernel_timing): 2 events per pair, pairs used cyclically
     std::vector<hipEvent_t> tev;
     long long tev_calls = 0;

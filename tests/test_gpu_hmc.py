@@ -151,3 +151,64 @@ def test_posterior_moments_with_adapted_metric_agree_with_oracle(ctx, orc):
     # adapted step sizes follow the same distribution as the oracle's
     st, st_ref = out["step"].cpu().numpy(), ref["step"]
     assert 0.5 < np.median(st) / np.median(st_ref) < 2.0
+
+
+# ---------------------------------------------------------------- exact-photometry HMC
+@pytest.fixture(scope="module")
+def ctx_exact(ssp2000, filt6):
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16)
+    c.build_ztable(64, 0.1, 3.0)
+    yield c
+    c.close()
+
+
+def test_exact_path_first_iterations_match_oracle(ctx_exact, orc):
+    # same Philox streams and start: the FP32 exact-photometry chains follow the FP64 oracle's
+    # exact-photometry chains draw by draw (the bar of the approximate path's test)
+    import paper_2506_19919_amd as sps
+    n, C = 4, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 41, C)
+    kw = dict(n_chain=C, n_leapfrog=5, n_warmup=2, n_sample=3, init_step=0.01, seed=404)
+    out = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=sps.SPS_PATH_EXACT,
+                   prec=sps.SPS_F32, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=1, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
+    s_ref = ref["samples"]
+    close = np.all(np.abs(s_gpu - s_ref) <= 1e-3 * np.maximum(np.abs(s_ref), 1.0), axis=-1)
+    assert close.mean() >= 0.9, close
+    np.testing.assert_allclose(out["step"].cpu().numpy(), ref["step"], rtol=1e-3)
+
+
+@pytest.mark.parametrize("prec_name", ["SPS_F32", "SPS_BF16X"])
+def test_exact_path_posterior_moments_agree_with_approximate_path(ctx_exact, orc, prec_name):
+    # the approximate and exact magnitudes differ by ~1e-3 mag, 2 % of the 0.05 mag errors, so
+    # both photometry paths sample practically the same posterior: independent chains agree
+    # within a few posterior sds / sqrt(ESS) (the approximate-path sampler is itself checked
+    # against the oracle's)
+    import paper_2506_19919_amd as sps
+    n, C = 6, 4
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 21, C)
+    kw = dict(n_chain=C, n_leapfrog=10, n_warmup=150, n_sample=300, seed=7)
+    ex = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, path=sps.SPS_PATH_EXACT,
+                  prec=getattr(sps, prec_name), **kw)
+    ap = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, **dict(kw, seed=8))
+    pm, ps = ex["post_mean"].cpu().numpy(), ex["post_sd"].cpu().numpy()
+    pa, sa = ap["post_mean"].cpu().numpy(), ap["post_sd"].cpu().numpy()
+    dev_ = np.abs(pm - pa) / (np.maximum(ps, sa) + 1e-6)
+    assert np.median(dev_) < 0.5 and dev_.max() < 3.0, dev_
+    acc = ex["accept"].cpu().numpy()
+    assert np.all((acc > 0.3) & (acc <= 1.0))
+
+
+def test_exact_path_needs_an_uploaded_precision(ssp2000, filt6, orc):
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
+    try:
+        n, C = 2, 2
+        sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 5, C)
+        with pytest.raises(sps.SpsError):
+            _run_gpu(c, z, obs, sig, masks, bnd, pri, x0, n_chain=C, n_warmup=2, n_sample=2,
+                     path=sps.SPS_PATH_EXACT, prec=sps.SPS_BF16X)
+    finally:
+        c.close()
