@@ -248,6 +248,36 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
     return res
 
 
+def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0)):
+    """Approximate-minus-exact magnitudes (App. B) against the Gaussian band width, on the GPU:
+    FP32 exact path vs the z-table path for n galaxies of the likelihood workload's generator."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] approximation accuracy: {n} galaxies, band sigma {sigmas} A")
+    ssp = synth.ssp_grid(2000)
+    th, z = synth.galaxies_dpl(n, 107)
+    params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    res = {"workload": f"{n} galaxies (DPL SFH, burst, dust), 6 Gaussian bands 3600-9700 A, "
+                       "|m_approx - m_exact| per galaxy and band, FP32 exact path", "unit": "mag"}
+    for sig in sigmas:
+        filt = synth.filters(sigma=sig)
+        ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32,), max_gal=n)
+        ctx.build_ztable(64, 0.1, 3.0)
+        d = (ctx.phot_approx(synth.SFH_DPL, params, zt)
+             - ctx.phot_exact(synth.SFH_DPL, params, zt, prec=sps.SPS_F32)).abs().cpu().numpy()
+        ctx.close()
+        ratio = filt["center_A"] / (2.0 * np.sqrt(2.0 * np.log(2.0)) * sig)
+        res[f"sigma_{int(sig)}A"] = {"lambda_over_fwhm": [float(ratio.min()), float(ratio.max())],
+                                     "median": float(np.median(d)), "p95": float(np.percentile(d, 95)),
+                                     "max": float(d.max())}
+        log(f"[bench]   sigma {sig:.0f} A: median {np.median(d):.2e}, p95 {np.percentile(d, 95):.2e}, "
+            f"max {d.max():.2e} mag")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +288,7 @@ def main():
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-hmc-exact", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--hmc-gal", type=int, default=16_384)
     ap.add_argument("--hmc-warmup", type=int, default=200)
     ap.add_argument("--hmc-sample", type=int, default=1000)
@@ -365,6 +396,8 @@ def main():
     ctx.close()
     if not args.no_exact:
         out["exact"] = bench_exact(dev)
+    if not args.no_accuracy:
+        out["approx_accuracy"] = bench_approx_accuracy(dev)
     if not args.no_hmc:
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,

@@ -87,6 +87,35 @@ def test_exact_loglike_grad(ctx5000, orc5000, prec_name, tol):
     assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[~ok][:8], prop[~ok][:8])
 
 
+
+@pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
+def test_exact_loglike_grad_large_batch(ctx2000, orc, prec_name, tol):
+    # 16,384 galaxies: the gradient GEMM has enough output tiles to run without the K split
+    # (the batch size of the exact-photometry HMC); sampled galaxies against the oracle
+    import paper_2506_19919_amd as sps
+    n = 16_384
+    sfh, th, z = gal_inputs("dpl", n, 305)
+    rng = np.random.default_rng(1)
+    pick = np.sort(rng.choice(n, 8, replace=False))
+    noise, sig = synth.photometric_noise(n, 6, 306)
+    obs = f32(np.full((n, 6), 22.0))
+    obs[pick] = f32(orc.phot_exact(sfh, th[pick], z[pick]) + noise[pick])
+    sig = f32(sig)
+    masks = synth.band_masks(n, 6, 307)
+    prec = getattr(sps, prec_name)
+    ll, g = ctx2000.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8),
+                                 path=sps.SPS_PATH_EXACT, prec=prec)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().T.astype(np.float64)
+    assert np.isfinite(ll).all() and np.isfinite(g).all()
+    rl, rg = orc.loglike_grad(sfh, th[pick], z[pick], obs[pick], sig[pick], masks[pick], path=1)
+    m = orc.phot_exact(sfh, th[pick], z[pick])
+    r = np.abs((m - obs[pick]) / sig[pick]) * ((masks[pick][:, None] >> np.arange(6)) & 1)
+    assert np.all(np.abs(ll[pick] - rl) <= (r.sum(1) / 0.05) * tol + 1e-3)
+    m_gpu = ctx2000.phot_exact(sfh, soa(th[pick]), dev(z[pick]), prec=prec).cpu().numpy()
+    prop, _ = grad_tol(orc, sfh, th[pick], z[pick], sig[pick], masks[pick], m_gpu, path=1)
+    ok = grad_ok(g[pick], rg, prop)
+    assert ok.all(), (np.argwhere(~ok)[:8], g[pick][~ok][:8], rg[~ok][:8], prop[~ok][:8])
+
 def test_exact_matches_approx_at_z_nodes_without_dust(ctx2000, orc):
     # both GPU paths reduce to the same sum when the attenuation is flat (tau_V = 0)
     import paper_2506_19919_amd as sps
@@ -107,3 +136,23 @@ def test_exact_precision_not_uploaded_is_an_error(ssp2000, filt6):
         c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_BF16X)
     assert e.value.code == sps.SPS_E_STATE
     c.close()
+
+
+@pytest.mark.parametrize("sigma_A", [200.0, 800.0])
+def test_approximation_gap_matches_oracle(ssp2000, oracle_mod, sigma_A):
+    # the approximate-minus-exact magnitude gap (App. B) measured on the GPU equals the
+    # oracle's per galaxy and band: each FP32 path is within 1e-4 mag of the oracle
+    import paper_2506_19919_amd as sps
+    filt = synth.filters(sigma=sigma_A)
+    c = sps.Context(ssp2000, filt, precisions=(sps.SPS_F32,), max_gal=4096)
+    try:
+        c.build_ztable(64, 0.1, 3.0)
+        o = oracle_mod.Oracle(ssp2000, filt)
+        o.build_ztable(64, 0.1, 3.0)
+        sfh, th, z = gal_inputs("dpl", 96, 72)
+        ma = c.phot_approx(sfh, soa(th), dev(z)).cpu().numpy().astype(np.float64)
+        me = c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_F32).cpu().numpy().astype(np.float64)
+        ref = o.phot_approx(sfh, th, z) - o.phot_exact(sfh, th, z)
+        assert np.abs((ma - me) - ref).max() <= 2e-4
+    finally:
+        c.close()

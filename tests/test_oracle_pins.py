@@ -647,3 +647,22 @@ def test_exact_path_hmc_samples_a_consistent_posterior(orc_small):
     assert np.all(s.std(axis=0)[..., 0] > 0)
     assert 0.2 < out["accept"][0] <= 1.0
     assert abs(out["post_mean"][0, 0] - th[0, 0]) < 4 * out["post_sd"][0, 0] + 0.05
+
+
+def test_approximation_gap_grows_with_band_width(oracle_mod, ssp_small):
+    # App. B: the table approximation (attenuation taken at the effective wavelength) degrades
+    # as the band widens, and for bands with lambda/FWHM between ~3.4 and ~25 it stays within
+    # 0.06 mag.  The sigma = 400 A bands here have lambda/FWHM 3.8-10.3.
+    th, z = synth.galaxies_dpl(24, 71)
+    med = []
+    for sig in (200.0, 400.0, 800.0, 1200.0):
+        o = oracle_mod.Oracle(ssp_small, synth.filters(sigma=sig))
+        o.build_ztable(64, 0.1, 3.0)
+        d = np.abs(o.phot_approx(1, th, z) - o.phot_exact(1, th, z))
+        med.append(np.median(d))
+        if sig == 400.0:
+            fwhm = 2.0 * math.sqrt(2.0 * math.log(2.0)) * sig
+            ratio = synth.filters(sigma=sig)["center_A"] / fwhm
+            assert 3.4 <= ratio.min() and ratio.max() <= 25.5
+            assert d.max() < 0.06
+    assert all(a < b for a, b in zip(med, med[1:])), med
