@@ -56,7 +56,7 @@ __device__ inline float e_exp(float x) { return expf(x); }
 __device__ inline double e_exp(double x) { return exp(x); }
 
 struct FiltConst {
-    float fc[NB_MAX], fs[NB_MAX];
+    double fc[NB_MAX], inv_fs[NB_MAX];   // band centres and 1 / widths (FP64, as in the forward epilogue)
 };
 
 constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -562,24 +562,35 @@ __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, co
     }
 }
 
-// weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP (coalesced rows)
+// weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP.  A block takes
+// XG galaxies: their P_age and P_Z columns (galaxy-contiguous in pw) are staged in LDS, then
+// the rows are written with consecutive threads on consecutive s (whole lines).
+constexpr int XG = 16;
 template <int P>
 __global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w) {
-    // galaxies on the grid's x axis (no 65,535-block limit there), SSP columns on y
-    const int sidx = blockIdx.y * 256 + threadIdx.x, g = blockIdx.x;
-    if (sidx >= S_PAD) return;
-    float v = 0.0f;
-    if (sidx < NSSP) {
-        const int j = sidx / NA, i = sidx - j * NA;
-        v = pw[(size_t)(PW_PZ + j) * n + g] * pw[(size_t)i * n + g];
+    __shared__ float sp[NA + NZ][XG];
+    const int g0 = blockIdx.x * XG, tid = threadIdx.x;
+    for (int e = tid; e < (NA + NZ) * XG; e += 256) {
+        const int r = e / XG, t = e - r * XG, g = min(g0 + t, n - 1);
+        sp[r][t] = pw[(size_t)(r < NA ? r : PW_PZ + (r - NA)) * n + g];
     }
-    if constexpr (P == SPS_F32) {
-        ((float *)w)[(size_t)g * S_PAD + sidx] = v;
-    } else {
-        const uint16_t h = f2bf(v);
-        const size_t o = bfx_at(g, S_PAD, sidx);   // interleaved hi / lo rows
-        ((uint16_t *)w)[o] = h;
-        ((uint16_t *)w)[o + 32] = f2bf(v - bf2f(h));
+    __syncthreads();
+    const int ng = min(XG, n - g0);
+    for (int e = tid; e < ng * S_PAD; e += 256) {
+        const int t = e / S_PAD, sidx = e - t * S_PAD, g = g0 + t;
+        float v = 0.0f;
+        if (sidx < NSSP) {
+            const int j = sidx / NA, i = sidx - j * NA;
+            v = sp[NA + j][t] * sp[i][t];
+        }
+        if constexpr (P == SPS_F32) {
+            ((float *)w)[(size_t)g * S_PAD + sidx] = v;
+        } else {
+            const uint16_t h = f2bf(v);
+            const size_t o = bfx_at(g, S_PAD, sidx);   // interleaved hi / lo rows
+            ((uint16_t *)w)[o] = h;
+            ((uint16_t *)w)[o + 32] = f2bf(v - bf2f(h));
+        }
     }
 }
 
@@ -660,7 +671,7 @@ __global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, co
         const v4f w = *(const v4f *)(wc + 4 * (size_t)l);   // ln x, l q, q / l
         float s = 0.0f;
         for (int b = 0; b < nb; ++b) {
-            const float x = (float)((lo - (double)fl.fc[b]) / (double)fl.fs[b]);
+            const float x = (float)((lo - fl.fc[b]) * fl.inv_fs[b]);
             if (fabsf(x) < 8.0f) s = fmaf(cnum[(size_t)g * NB_MAX + b], __expf(-0.5f * x * x), s);
         }
         if (s != 0.0f) {
@@ -796,7 +807,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     } else {
         hipLaunchKernelGGL(k_exact_pw, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
                            (const float *)params, (const float *)z, pw);
-        const dim3 ge(n, (S_PAD + 255) / 256), be(256);
+        const dim3 ge((n + XG - 1) / XG), be(256);
         if (prec == SPS_F32) hipLaunchKernelGGL(k_expand<SPS_F32>, ge, be, 0, s, n, (const float *)pw, w_hi);
         else hipLaunchKernelGGL(k_expand<SPS_BF16X>, ge, be, 0, s, n, (const float *)pw, w_hi);
     }
@@ -880,7 +891,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
         dim3 gr(n, (lw + 255) / 256), br(256);
         FiltConst fl;
-        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = (float)c->h_fc[b]; fl.fs[b] = (float)c->h_fs[b]; }
+        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = c->h_fc[b]; fl.inv_fs[b] = 1.0 / c->h_fs[b]; }
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
                                (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi);
@@ -900,9 +911,11 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         b.C = (float *)(W + o_wb);
         b.ldc = mp;
         b.n_store = S_PAD;
-        // the gradient GEMM has few output tiles (n_mt x 9): split K into XSPLIT ranges whose
-        // partial products are summed by the reduction that reads them anyway
-        b.k_splits = (lw % (XSPLIT * XBK) == 0) ? XSPLIT : 1;
+        // at a few thousand galaxies the gradient GEMM has few output tiles (n_mt x 9): K is then
+        // split into XSPLIT ranges whose partial products k_sum_splits adds; from 1024 tiles
+        // (four blocks per CU) on the chip is full without the split and its extra traffic
+        const int tiles2 = b.n_mt * b.n_nt;
+        b.k_splits = (tiles2 < 1024 && lw % (XSPLIT * XBK) == 0) ? XSPLIT : 1;
         b.c_split = (size_t)S_PAD * mp;
         const dim3 g2(b.n_mt * b.n_nt * b.k_splits), b2(256);
         if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
