@@ -210,6 +210,7 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
     log(f"[bench] exact-path HMC: {n} galaxies x {C} chains, {n_iter} iterations x {L} leapfrog steps")
     ssp, filt = synth.ssp_grid(2000), synth.filters()
     ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C)
+    ctx.build_ztable(64, 0.1, 3.0)   # with a z table the chains are ranked by z (narrow GEMM tiles)
     th, z = synth.galaxies_dpl(n, 104)
     params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
     zt = torch.as_tensor(z.astype(np.float32)).to(dev)

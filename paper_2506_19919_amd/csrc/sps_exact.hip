@@ -264,7 +264,8 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
 //         lo.hi + hi.lo + hi.hi per tile pair, FP32 accumulation.
 // Blocks are mapped XCD-aware: consecutive dispatch slots go round-robin over the 8 XCDs, so
 // slot b is remapped to tile (b % 8) * T / 8 + b / 8 and each XCD works through one
-// contiguous run of tiles, M fastest (its A rows stay in that XCD's L2).
+// contiguous run of tiles, M fastest (its A rows stay in that XCD's L2), or N fastest where
+// whole wavelength tiles are skipped (see XArgs::win), so the skipped ones spread evenly.
 constexpr int XBM = 128, XBN = 128, XBK = 32, XROW = 144;   // XROW in bytes
 constexpr int XSTAGE = (XBM + XBN) * XROW;                   // 36,864 bytes per stage
 constexpr int XSPLIT = 4;                                    // K ranges of the gradient GEMM
@@ -287,6 +288,9 @@ struct XArgs {
     double fc[NB_MAX], inv_fs[NB_MAX];
     float *part;               // [n_nt][npart][M] (quantity-major: the finish reads it coalesced)
     int npart;
+    // per 128-galaxy row tile: the wavelength tiles (x, y: 128-wide, [x, y)) and k-tiles (z, w:
+    // 32-wide) inside some band's 8-sigma filter support for some galaxy of the tile; null: all
+    const int4 *win;
 };
 
 template <int P>
@@ -334,8 +338,30 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     if (total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
     const int sp = t / T;
     t -= sp * T;
-    const int tile_m = (t % a.n_mt) * XBM, tile_n = (t / a.n_mt) * XBN;
-    const int klen = a.K / nsp, kbeg = sp * klen;
+    // M fastest, except in a windowed forward GEMM: its skipped tiles are whole wavelength
+    // ranges, so there each XCD's run of tiles takes every wavelength tile of a few row tiles
+    const bool nfast = EPI != EPI_STORE && a.win != nullptr;
+    const int tile_m = (nfast ? t / a.n_nt : t % a.n_mt) * XBM, tile_n = (nfast ? t % a.n_nt : t / a.n_mt) * XBN;
+    int klen = a.K / nsp, kbeg = sp * klen;
+    if (a.win) {
+        // wavelengths outside every band's support for all of this tile's galaxies: the
+        // forward tile's band sums are below exp(-32) of the band's and are written as zeros;
+        // the gradient GEMM's Rbar is exactly zero there, so its K range is clipped
+        const int4 w = a.win[tile_m / XBM];
+        if constexpr (EPI == EPI_STORE) {
+            const int k0 = max(kbeg, w.z * XBK), k1 = min(kbeg + klen, w.w * XBK);
+            kbeg = k0;
+            klen = max(k1 - k0, 0);
+        } else if (tile_n / XBN < w.x || tile_n / XBN >= w.y) {
+            constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;
+            const int g = tile_m + (tid >> 1);
+            if ((tid & 1) == 0 && g < a.M) {
+                float *out = a.part + (size_t)(tile_n / XBN) * a.npart * a.M + g;
+                for (int q = 0; q < NPB * a.n_band; ++q) out[(size_t)q * a.M] = 0.0f;
+            }
+            return;
+        }
+    }
 
     v4f acc[4][4];
 #pragma unroll
@@ -658,34 +684,61 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
 }
 
 // Rbar[g][l] = sum_b (d logL / d num_b) F_att(l) T_b((1+z) l) l q_l  (zero beyond n_wave);
-// bands more than 8 sigma from the redshifted wavelength contribute below FP32 resolution
+// bands more than 8 sigma from the redshifted wavelength contribute below FP32 resolution.
+// One block per galaxy walks the row in chunks of 256 wavelengths, so the galaxy's constants
+// are loaded once (a block per chunk spent most of its short life waiting on those loads).
 template <int P>
-__global__ void k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl, const float *params, const float *z,
-                             const double *wave, const float *wc, const float *cnum, void *rb) {
-    const int l = blockIdx.y * blockDim.x + threadIdx.x, g = blockIdx.x;   // galaxies on x
-    if (l >= ld) return;
-    float v = 0.0f;
-    if (l < n_wave) {
-        const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
-        const double lo = (1.0 + (double)z[g]) * wave[l];
-        const v4f w = *(const v4f *)(wc + 4 * (size_t)l);   // ln x, l q, q / l
-        float s = 0.0f;
-        for (int b = 0; b < nb; ++b) {
-            const float x = (float)((lo - fl.fc[b]) * fl.inv_fs[b]);
-            if (fabsf(x) < 8.0f) s = fmaf(cnum[(size_t)g * NB_MAX + b], __expf(-0.5f * x * x), s);
-        }
-        if (s != 0.0f) {
-            const float F = ffl + (1.0f - ffl) * __expf(-tauv * __expf(delta * w[0]));
-            v = s * F * w[1];
-        }
+__global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
+                                                    const float *params, const float *z, const double *wave,
+                                                    const float *wc, const float *cnum, const int4 *win, void *rb) {
+    const int g = blockIdx.x, tid = threadIdx.x;
+    // the gradient GEMM reads only the k-tiles inside its row tile's filter-support window:
+    // chunks wholly outside it are never read and are not written
+    int c_lo = 0, c_hi = (ld + 255) / 256;
+    if (win) {
+        const int4 w = win[g / XBM];
+        c_lo = (w.z * XBK) / 256;
+        c_hi = min(c_hi, (w.w * XBK + 255) / 256);
     }
-    if (P == SPS_F32) {
-        ((float *)rb)[(size_t)g * ld + l] = v;
-    } else {
-        const uint16_t h = f2bf(v);
-        const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
-        ((uint16_t *)rb)[o] = h;
-        ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
+    const double opz = 1.0 + (double)z[g];
+    const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
+    float cb[NB_MAX];
+#pragma unroll
+    for (int b = 0; b < NB_MAX; ++b) cb[b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
+    for (int ch = c_lo; ch < c_hi; ++ch) {
+        const int lb0 = ch * 256, l = lb0 + tid;
+        // bands within 8 sigma of some redshifted wavelength of this chunk (uniform)
+        unsigned act = 0;
+        if (lb0 < n_wave) {
+            const double u0 = opz * wave[lb0], u1 = opz * wave[min(lb0 + 255, n_wave - 1)];
+            for (int b = 0; b < nb; ++b)
+                if (u0 < fl.fc[b] + 8.0 / fl.inv_fs[b] && u1 > fl.fc[b] - 8.0 / fl.inv_fs[b]) act |= 1u << b;
+        }
+        if (l >= ld) continue;
+        float v = 0.0f;
+        if (l < n_wave && act) {
+            const double lo = opz * wave[l];
+            const v4f w = *(const v4f *)(wc + 4 * (size_t)l);   // ln x, l q, q / l
+            float sum = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB_MAX; ++b) {
+                if (b >= nb || !((act >> b) & 1u)) continue;
+                const float x = (float)((lo - fl.fc[b]) * fl.inv_fs[b]);
+                if (fabsf(x) < 8.0f) sum = fmaf(cb[b], __expf(-0.5f * x * x), sum);
+            }
+            if (sum != 0.0f) {
+                const float F = ffl + (1.0f - ffl) * __expf(-tauv * __expf(delta * w[0]));
+                v = sum * F * w[1];
+            }
+        }
+        if (P == SPS_F32) {
+            ((float *)rb)[(size_t)g * ld + l] = v;
+        } else {
+            const uint16_t h = f2bf(v);
+            const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
+            ((uint16_t *)rb)[o] = h;
+            ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
+        }
     }
 }
 
@@ -757,6 +810,50 @@ __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sf
     for (int p = 1; p <= 6; ++p) grad[(size_t)p * n + g] = gr[p];
 }
 
+// ------------------------------------------------------------------ filter-support windows
+// Per 128-galaxy row tile: the rest-frame wavelengths any band reaches within 8 sigma for any
+// of the tile's galaxies, [min_b (c_b - 8 s_b) / (1 + z_max), max_b (c_b + 8 s_b) / (1 + z_min)],
+// as 128-wide wavelength tiles and 32-wide k-tiles of the padded grid, one index of margin on
+// each side.  One block per row tile.
+__global__ void __launch_bounds__(128) k_xwindows(int n, int n_wave, FiltConst fl, int nb, const float *z,
+                                                  const double *wave, int4 *win) {
+    __shared__ float zlo[2], zhi[2];
+    const int tid = threadIdx.x, g = min((int)blockIdx.x * XBM + tid, n - 1);
+    float mn = z[g], mx = mn;
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((tid & 63) == 0) {
+        zlo[tid >> 6] = mn;
+        zhi[tid >> 6] = mx;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double z0 = fmin(zlo[0], zlo[1]), z1 = fmax(zhi[0], zhi[1]);
+    double lo = 1e300, hi = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double s8 = 8.0 / fl.inv_fs[b];
+        lo = fmin(lo, (fl.fc[b] - s8) / (1.0 + z1));
+        hi = fmax(hi, (fl.fc[b] + s8) / (1.0 + z0));
+    }
+    // first index with wave >= lo, last with wave <= hi (binary searches on the ascending grid)
+    int a = 0, c = n_wave;
+    while (a < c) {
+        const int m = (a + c) >> 1;
+        if (wave[m] < lo) a = m + 1; else c = m;
+    }
+    const int l0 = max(a - 1, 0);
+    a = 0;
+    c = n_wave;
+    while (a < c) {
+        const int m = (a + c) >> 1;
+        if (wave[m] <= hi) a = m + 1; else c = m;
+    }
+    const int l1 = min(a, n_wave - 1);   // one past the last index <= hi, as margin
+    win[blockIdx.x] = make_int4(l0 / XBN, l1 / XBN + 1, l0 / XBK, l1 / XBK + 1);
+}
+
 // ------------------------------------------------------------------ launcher
 int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                  void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
@@ -780,6 +877,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     const size_t o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
     const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
     const size_t o_psum = f64 ? 0 : carve((size_t)n * npart * 4);
+    const size_t o_win = f64 ? 0 : carve((size_t)(mp / XBM) * sizeof(int4));
     size_t o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
     if (logl) {
         o_cn = carve((size_t)n * NB_MAX * 4);
@@ -798,6 +896,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         c->work_bytes = off;
     }
     char *W = (char *)c->d_work;
+    int4 *win = nullptr;   // filter-support windows of the row tiles (FP32 / BF16X paths)
     void *w_hi = W + o_w;   // weights rows: FP32 [mp][S_PAD], or BF16 hi + lo interleaved [mp][2 S_PAD]
 
     float *pw = f64 ? nullptr : (float *)(W + o_pw);
@@ -837,7 +936,13 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
         hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
     } else {
+        FiltConst fl;
+        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = c->h_fc[b]; fl.inv_fs[b] = 1.0 / c->h_fs[b]; }
+        win = (int4 *)(W + o_win);
+        hipLaunchKernelGGL(k_xwindows, dim3(mp / XBM), dim3(128), 0, s, n, nw, fl, nb, (const float *)z, c->d_wave,
+                           win);
         XArgs a{};
+        a.win = win;
         a.M = n;
         a.N = lw;
         a.K = S_PAD;
@@ -889,16 +994,17 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     }
     if (want_grad) {
         void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
-        dim3 gr(n, (lw + 255) / 256), br(256);
+        dim3 gr(n), br(256);
         FiltConst fl;
         for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = c->h_fc[b]; fl.inv_fs[b] = 1.0 / c->h_fs[b]; }
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, win, r_hi);
         else
             hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, r_hi);
+                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, win, r_hi);
         XArgs b{};
+        b.win = win;
         b.M = n;
         b.N = S_PAD;
         b.K = lw;

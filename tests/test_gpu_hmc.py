@@ -201,6 +201,25 @@ def test_exact_path_posterior_moments_agree_with_approximate_path(ctx_exact, orc
     assert np.all((acc > 0.3) & (acc <= 1.0))
 
 
+def test_exact_path_chain_order_does_not_change_the_draws(ctx_exact, ssp2000, filt6, orc):
+    # with a z table the chains are ranked by z inside the library, without one they keep the
+    # input order: the GEMM rows are independent, so the draws agree to FP32 rounding and every
+    # output lands on its own galaxy
+    import paper_2506_19919_amd as sps
+    n, C = 5, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 51, C)
+    kw = dict(n_chain=C, n_leapfrog=5, n_warmup=2, n_sample=3, init_step=0.01, seed=404, keep_samples=True,
+              path=sps.SPS_PATH_EXACT, prec=sps.SPS_F32)
+    a = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, **kw)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
+    try:
+        b = _run_gpu(c, z, obs, sig, masks, bnd, pri, x0, **kw)
+    finally:
+        c.close()
+    sa, sb = a["samples"].cpu().numpy(), b["samples"].cpu().numpy()
+    np.testing.assert_allclose(sa, sb, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(a["step"].cpu().numpy(), b["step"].cpu().numpy(), rtol=1e-5)
+
 def test_exact_path_needs_an_uploaded_precision(ssp2000, filt6, orc):
     import paper_2506_19919_amd as sps
     c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
