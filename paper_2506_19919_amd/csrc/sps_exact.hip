@@ -336,8 +336,16 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     const int T = a.n_mt * a.n_nt, nsp = (EPI == EPI_STORE) ? a.k_splits : 1, total = T * nsp, b = blockIdx.x;
     int t = b;
     if (total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
-    const int sp = t / T;
-    t -= sp * T;
+    // the K range: slowest, or fastest where windows clip it (then every XCD's run of tiles
+    // holds all ranges, and the mostly skipped last ones do not gather on a few XCDs)
+    int sp;
+    if (EPI == EPI_STORE && a.win != nullptr) {
+        sp = t % nsp;
+        t /= nsp;
+    } else {
+        sp = t / T;
+        t -= sp * T;
+    }
     // M fastest, except in a windowed forward GEMM: its skipped tiles are whole wavelength
     // ranges, so there each XCD's run of tiles takes every wavelength tile of a few row tiles
     const bool nfast = EPI != EPI_STORE && a.win != nullptr;
