@@ -57,7 +57,18 @@ __device__ inline double e_exp(double x) { return exp(x); }
 
 struct FiltConst {
     double fc[NB_MAX], inv_fs[NB_MAX];   // band centres and 1 / widths (FP64, as in the forward epilogue)
+    double lo8[NB_MAX], hi8[NB_MAX];     // c - 8 sigma, c + 8 sigma: the support the kernels keep
 };
+inline FiltConst filt_const(const double *fc, const double *fs) {
+    FiltConst f;
+    for (int b = 0; b < NB_MAX; ++b) {
+        f.fc[b] = fc[b];
+        f.inv_fs[b] = fs[b] > 0.0 ? 1.0 / fs[b] : 0.0;
+        f.lo8[b] = fc[b] - 8.0 * fs[b];
+        f.hi8[b] = fc[b] + 8.0 * fs[b];
+    }
+    return f;
+}
 
 constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 static_assert(S_PAD % 128 == 0 && S_PAD >= NSSP, "SSP padding");
@@ -720,7 +731,7 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
         if (lb0 < n_wave) {
             const double u0 = opz * wave[lb0], u1 = opz * wave[min(lb0 + 255, n_wave - 1)];
             for (int b = 0; b < nb; ++b)
-                if (u0 < fl.fc[b] + 8.0 / fl.inv_fs[b] && u1 > fl.fc[b] - 8.0 / fl.inv_fs[b]) act |= 1u << b;
+                if (u0 < fl.hi8[b] && u1 > fl.lo8[b]) act |= 1u << b;
         }
         if (l >= ld) continue;
         float v = 0.0f;
@@ -841,9 +852,8 @@ __global__ void __launch_bounds__(128) k_xwindows(int n, int n_wave, FiltConst f
     const double z0 = fmin(zlo[0], zlo[1]), z1 = fmax(zhi[0], zhi[1]);
     double lo = 1e300, hi = 0.0;
     for (int b = 0; b < nb; ++b) {
-        const double s8 = 8.0 / fl.inv_fs[b];
-        lo = fmin(lo, (fl.fc[b] - s8) / (1.0 + z1));
-        hi = fmax(hi, (fl.fc[b] + s8) / (1.0 + z0));
+        lo = fmin(lo, fl.lo8[b] / (1.0 + z1));
+        hi = fmax(hi, fl.hi8[b] / (1.0 + z0));
     }
     // first index with wave >= lo, last with wave <= hi (binary searches on the ascending grid)
     int a = 0, c = n_wave;
@@ -944,8 +954,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
         hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
     } else {
-        FiltConst fl;
-        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = c->h_fc[b]; fl.inv_fs[b] = 1.0 / c->h_fs[b]; }
+        const FiltConst fl = filt_const(c->h_fc, c->h_fs);
         win = (int4 *)(W + o_win);
         hipLaunchKernelGGL(k_xwindows, dim3(mp / XBM), dim3(128), 0, s, n, nw, fl, nb, (const float *)z, c->d_wave,
                            win);
@@ -1003,8 +1012,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     if (want_grad) {
         void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
         dim3 gr(n), br(256);
-        FiltConst fl;
-        for (int b = 0; b < NB_MAX; ++b) { fl.fc[b] = c->h_fc[b]; fl.inv_fs[b] = 1.0 / c->h_fs[b]; }
+        const FiltConst fl = filt_const(c->h_fc, c->h_fs);
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
                                (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, win, r_hi);
