@@ -336,18 +336,20 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga) {
-    const int nbk = c->k.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga,
+                       const DevConsts *grid) {
+    const DevConsts &kb = grid ? *grid : c->k;   // bucket grid
+    const int nbk = kb.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
     int *hist = c->d_hist, *cursor = c->d_hist + 1025;
     hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
     const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
-    hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, c->k, n, z, hist);
+    hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, kb, n, z, hist);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
     if (ga && ga->rec) {
         hipLaunchKernelGGL(k_bucket_gather, dim3((n + GATHER_TILE - 1) / GATHER_TILE), dim3(SORT_BLOCK),
                            gather_lds_bytes(nbk), s, c->k, n, z, cursor, c->d_perm, *ga);
     } else {
-        hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, c->k, n, z, cursor,
+        hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, kb, n, z, cursor,
                            c->d_perm);
     }
     SPS_HIP(hipGetLastError());

@@ -225,6 +225,7 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_hist);
     (void)hipFree(c->d_work);
     (void)hipFree(c->d_hwork);
+    (void)hipFree(c->d_xsort);
     delete c;
 }
 

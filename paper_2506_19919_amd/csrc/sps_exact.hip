@@ -873,9 +873,9 @@ __global__ void __launch_bounds__(128) k_xwindows(int n, int n_wave, FiltConst f
 }
 
 // ------------------------------------------------------------------ launcher
-int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
-                 void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
-                 float *grad) {
+static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
+                      void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
+                      float *grad) {
     const int nw = c->n_wave, nb = c->n_band;
     const bool f64 = (prec == SPS_F64);
     const int TN = f64 ? BN : XBN;                // wavelengths per tile of the forward GEMM
@@ -1053,6 +1053,92 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
         hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
                            (const float *)params, (const float *)z, (const float *)pw, (const float *)pb, grad);
     }
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
+
+// ------------------------------------------------------------------ z order
+// Inputs of the galaxy of each rank (perm: rank -> galaxy) into rank order, and the outputs
+// back to the caller's order; one thread per rank.
+__global__ void __launch_bounds__(256) k_exact_order_in(int n, int nb, const int *perm, const float *params,
+                                                        const float *z, const float *obs, const float *sigma,
+                                                        const uint8_t *mask, float *params_s, float *z_s,
+                                                        float *obs_s, float *sig_s, uint8_t *mask_s) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int g = perm[r];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) params_s[(size_t)p * n + r] = params[(size_t)p * n + g];
+    z_s[r] = z[g];
+    if (obs)
+        for (int b = 0; b < nb; ++b) {
+            obs_s[(size_t)r * nb + b] = obs[(size_t)g * nb + b];
+            sig_s[(size_t)r * nb + b] = sigma[(size_t)g * nb + b];
+        }
+    if (mask) mask_s[r] = mask[g];
+}
+
+__global__ void __launch_bounds__(256) k_exact_order_out(int n, int nb, const int *perm, const float *mag_s,
+                                                         const float *logl_s, const float *grad_s, float *mag,
+                                                         float *logl, float *grad) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int g = perm[r];
+    if (mag)
+        for (int b = 0; b < nb; ++b) mag[(size_t)g * nb + b] = mag_s[(size_t)r * nb + b];
+    if (logl) logl[g] = logl_s[r];
+    if (grad)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) grad[(size_t)p * n + g] = grad_s[(size_t)p * n + r];
+}
+
+// From XSORT_MIN galaxies on, the FP32 / BF16X paths rank the galaxies by z first (a bucket
+// sort on the z table's grid, or on 64 buckets over 0 <= z < 8 without a table): a 128-galaxy
+// row tile then spans a narrow z range, and its filter-support window (k_xwindows) covers
+// about half of the wavelength grid instead of two thirds.  Smaller batches keep their order:
+// at 4096 galaxies x 5000 wavelengths the active tiles take two rounds of blocks either way,
+// and the sort costs more than the GEMMs gain.
+constexpr int XSORT_MIN = 16384;
+int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
+                 void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
+                 float *grad, bool ordered) {
+    if (prec == SPS_F64 || ordered || n < XSORT_MIN)
+        return exact_core(c, s, n, sfh, prec, params, z, mag_out, obs, sigma, mask, logl, grad);
+    DevConsts grid = c->k;
+    if (grid.n_z == 0) {
+        grid.n_z = 65;
+        grid.z_lo = 0.0;
+        grid.dz = 0.125;
+    }
+    const int nb = c->n_band;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    const size_t o_par = carve((size_t)NP * n * 4), o_z = carve((size_t)n * 4);
+    const size_t o_obs = carve((size_t)n * nb * 4), o_sig = carve((size_t)n * nb * 4), o_msk = carve((size_t)n);
+    const size_t o_mag = carve((size_t)n * nb * 4), o_ll = carve((size_t)n * 4), o_gr = carve((size_t)NP * n * 4);
+    if (c->xsort_bytes < off) {
+        SPS_HIP(hipDeviceSynchronize());
+        (void)hipFree(c->d_xsort);
+        c->d_xsort = nullptr;
+        c->xsort_bytes = 0;
+        SPS_HIP(hipMalloc(&c->d_xsort, off));
+        c->xsort_bytes = off;
+    }
+    char *X = (char *)c->d_xsort;
+    float *par_s = (float *)(X + o_par), *z_s = (float *)(X + o_z), *obs_s = (float *)(X + o_obs);
+    float *sig_s = (float *)(X + o_sig), *mag_s = (float *)(X + o_mag), *ll_s = (float *)(X + o_ll);
+    float *gr_s = (float *)(X + o_gr);
+    uint8_t *msk_s = (uint8_t *)(X + o_msk);
+    int rc = launch_bucket_sort(c, s, n, (const float *)z, nullptr, &grid);
+    if (rc) return rc;
+    const dim3 g1((n + 255) / 256), b1(256);
+    hipLaunchKernelGGL(k_exact_order_in, g1, b1, 0, s, n, nb, (const int *)c->d_perm, (const float *)params,
+                       (const float *)z, obs, sigma, mask, par_s, z_s, obs_s, sig_s, msk_s);
+    rc = exact_core(c, s, n, sfh, prec, par_s, z_s, mag_out ? mag_s : nullptr, obs ? obs_s : nullptr,
+                    obs ? sig_s : nullptr, mask ? msk_s : nullptr, logl ? ll_s : nullptr, grad ? gr_s : nullptr);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_exact_order_out, g1, b1, 0, s, n, nb, (const int *)c->d_perm, mag_s, ll_s, gr_s,
+                       (float *)mag_out, logl, grad);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }

@@ -746,7 +746,7 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
     // one exact value+gradient over every chain at the positions in a.th
     auto model = [&]() {
         return launch_exact(c, s, nslot, sfh, cfg->prec, a.th, a.zs, nullptr, a.obs_s, a.sig_s, a.mask_s, a.logl,
-                            a.grad);
+                            a.grad, true);
     };
     hipLaunchKernelGGL(k_hmcx_setup, grid, block, 0, s, a);
     int rc = model();

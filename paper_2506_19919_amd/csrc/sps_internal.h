@@ -99,6 +99,8 @@ struct sps_ctx {
     size_t work_bytes = 0;
     void *d_hwork = nullptr;       // chain state of the exact-path HMC (d_work serves its model calls)
     size_t hwork_bytes = 0;
+    void *d_xsort = nullptr;       // exact path: inputs and outputs in z order
+    size_t xsort_bytes = 0;
     // kernel timing (sps_set_kernel_timing): 2 events per pair, pairs used cyclically
     std::vector<hipEvent_t> tev;
     long long tev_calls = 0;
@@ -131,15 +133,19 @@ struct GatherArgs {
     float *rec;                         // null: sort only
     int *inv;
 };
-int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z, const GatherArgs *ga = nullptr);
+// grid: the z buckets (n_z, z_lo, dz of a DevConsts; n_z <= 1025); null: the z table's
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z, const GatherArgs *ga = nullptr,
+                       const DevConsts *grid = nullptr);
 int launch_weights(sps_ctx *c, hipStream_t s, int n_gal, int sfh, const float *params, const float *z,
                    float *w);
 int launch_approx(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int mode, const float *params,
                   const float *z, const float *obs, const float *sigma, const uint8_t *mask,
                   const float *bounds, const float *prior, float *out_mag, float *out_val, float *out_grad);
+// ordered: the galaxies already come in z order (the exact-path HMC ranks its chains); else the
+// FP32 / BF16X paths rank them by z internally and return the outputs in the caller's order
 int launch_exact(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int prec, const void *params,
                  const void *z, void *mag_out, const float *obs, const float *sigma,
-                 const uint8_t *mask, float *logl, float *grad);
+                 const uint8_t *mask, float *logl, float *grad, bool ordered = false);
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                const float *prior, const float *theta0, float *samples, float *post_mean,

@@ -111,10 +111,14 @@ def test_exact_loglike_grad_large_batch(ctx2000, orc, prec_name, tol):
     m = orc.phot_exact(sfh, th[pick], z[pick])
     r = np.abs((m - obs[pick]) / sig[pick]) * ((masks[pick][:, None] >> np.arange(6)) & 1)
     assert np.all(np.abs(ll[pick] - rl) <= (r.sum(1) / 0.05) * tol + 1e-3)
-    m_gpu = ctx2000.phot_exact(sfh, soa(th[pick]), dev(z[pick]), prec=prec).cpu().numpy()
-    prop, _ = grad_tol(orc, sfh, th[pick], z[pick], sig[pick], masks[pick], m_gpu, path=1)
+    # the whole batch's magnitudes (ranked by z inside the library, returned in input order)
+    m_all = ctx2000.phot_exact(sfh, soa(th), dev(z), prec=prec).cpu().numpy()
+    assert np.isfinite(m_all).all()
+    assert np.abs(m_all[pick] - m).max() <= tol
+    prop, _ = grad_tol(orc, sfh, th[pick], z[pick], sig[pick], masks[pick], m_all[pick], path=1)
     ok = grad_ok(g[pick], rg, prop)
     assert ok.all(), (np.argwhere(~ok)[:8], g[pick][~ok][:8], rg[~ok][:8], prop[~ok][:8])
+
 
 def test_exact_matches_approx_at_z_nodes_without_dust(ctx2000, orc):
     # both GPU paths reduce to the same sum when the attenuation is flat (tau_V = 0)
