@@ -137,7 +137,11 @@ int sps_phot_approx(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float 
  * filter x quadrature weight applied in the epilogue.  prec = SPS_F64:
  * params/z/mag_out are double; SPS_F32 and SPS_BF16X (split hi+lo BF16 with
  * FP32 accumulation): float.  The requested precision's table must have been
- * uploaded at create. */
+ * uploaded at create.  The FP32 / BF16X paths skip wavelengths farther than 8 filter
+ * sigmas from every band for all galaxies of a 128-galaxy tile (their contribution is below
+ * exp(-32) of the band's), and from 16,384 galaxies on they process the galaxies in z order
+ * internally (outputs are still in the caller's order); both grow the context's workspace
+ * (device memory) on first use at a size. */
 int sps_phot_exact(sps_ctx *ctx, void *stream, int n_gal, int sfh, int prec, const void *params,
                    const void *z, void *mag_out);
 
