@@ -220,6 +220,26 @@ def test_exact_path_chain_order_does_not_change_the_draws(ctx_exact, ssp2000, fi
     np.testing.assert_allclose(sa, sb, rtol=1e-5, atol=1e-5)
     np.testing.assert_allclose(a["step"].cpu().numpy(), b["step"].cpu().numpy(), rtol=1e-5)
 
+def test_exact_path_metric_adaptation_matches_oracle(ctx_exact, orc):
+    # the exact path's end-of-iteration kernel carries its own copy of the window adaptation:
+    # same bar as the approximate path's test, against the oracle's exact-photometry chains
+    import paper_2506_19919_amd as sps
+    n, C = 4, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 41, C)
+    kw = dict(n_chain=C, n_leapfrog=1, n_warmup=20, n_sample=3, init_step=0.01, target_accept=0.95, seed=405,
+              adapt_metric=True)
+    out = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=sps.SPS_PATH_EXACT,
+                   prec=sps.SPS_F32, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=1, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
+    same = np.all(np.abs(s_gpu - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0),
+                  axis=(0, -1))
+    assert same.mean() >= 0.6, same
+    mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)
+    assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
+    np.testing.assert_allclose(mi_gpu[same], ref["inv_metric"][same], rtol=2e-3, atol=1e-7)
+    np.testing.assert_allclose(out["step"].cpu().numpy()[same], ref["step"][same], rtol=2e-3)
+
 def test_exact_path_needs_an_uploaded_precision(ssp2000, filt6, orc):
     import paper_2506_19919_amd as sps
     c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
