@@ -87,7 +87,6 @@ def test_exact_loglike_grad(ctx5000, orc5000, prec_name, tol):
     assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[~ok][:8], prop[~ok][:8])
 
 
-
 @pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
 def test_exact_loglike_grad_large_batch(ctx2000, orc, prec_name, tol):
     # 16,384 galaxies: the gradient GEMM has enough output tiles to run without the K split
@@ -116,6 +115,38 @@ def test_exact_loglike_grad_large_batch(ctx2000, orc, prec_name, tol):
     assert np.isfinite(m_all).all()
     assert np.abs(m_all[pick] - m).max() <= tol
     prop, _ = grad_tol(orc, sfh, th[pick], z[pick], sig[pick], masks[pick], m_all[pick], path=1)
+    ok = grad_ok(g[pick], rg, prop)
+    assert ok.all(), (np.argwhere(~ok)[:8], g[pick][~ok][:8], rg[~ok][:8], prop[~ok][:8])
+
+
+@pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
+def test_exact_full_size_sampled(ctx5000, orc5000, prec_name, tol):
+    # the benchmarked configuration: 4096 galaxies x 1128 SSPs x 5000 wavelengths (32 row
+    # tiles, K split of the gradient GEMM, filter-support windows over random z); magnitudes,
+    # log L and gradients of sampled galaxies against the oracle
+    import paper_2506_19919_amd as sps
+    n = 4096
+    sfh, th, z = gal_inputs("dpl", n, 105)
+    rng = np.random.default_rng(2)
+    pick = np.sort(rng.choice(n, 6, replace=False))
+    noise, sig = synth.photometric_noise(n, 6, 205)
+    m_ref = orc5000.phot_exact(sfh, th[pick], z[pick])
+    obs = f32(np.full((n, 6), 22.0))
+    obs[pick] = f32(m_ref + noise[pick])
+    sig = f32(sig)
+    masks = synth.band_masks(n, 6, 5)
+    prec = getattr(sps, prec_name)
+    m_all = ctx5000.phot_exact(sfh, soa(th), dev(z), prec=prec).cpu().numpy()
+    assert np.isfinite(m_all).all()
+    assert np.abs(m_all[pick] - m_ref).max() <= tol
+    ll, g = ctx5000.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8),
+                                 path=sps.SPS_PATH_EXACT, prec=prec)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().T.astype(np.float64)
+    assert np.isfinite(ll).all() and np.isfinite(g).all()
+    rl, rg = orc5000.loglike_grad(sfh, th[pick], z[pick], obs[pick], sig[pick], masks[pick], path=1)
+    r = np.abs((m_ref - obs[pick]) / sig[pick]) * ((masks[pick][:, None] >> np.arange(6)) & 1)
+    assert np.all(np.abs(ll[pick] - rl) <= (r.sum(1) / 0.05) * tol + 1e-3)
+    prop, _ = grad_tol(orc5000, sfh, th[pick], z[pick], sig[pick], masks[pick], m_all[pick], path=1)
     ok = grad_ok(g[pick], rg, prop)
     assert ok.all(), (np.argwhere(~ok)[:8], g[pick][~ok][:8], rg[~ok][:8], prop[~ok][:8])
 
