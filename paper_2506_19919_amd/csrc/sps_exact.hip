@@ -337,9 +337,16 @@ __device__ inline void x_store(char *stage, int tid, const v4f (&r)[8]) {
     }
 }
 
+// LDS stages: FP32 double-buffers (two blocks per CU); BF16X, whose MFMA phase per k-tile is
+// a quarter as long, runs one stage with three blocks per CU, trading the second stage for
+// more waves to cover the operand loads (one stage: forward 0.220 -> 0.210 ms, exact HMC
+// iteration -10 %; FP32 value+gradient +13 %)
+template <int P> constexpr int x_nstage() { return P == SPS_BF16X ? 1 : 2; }
+
 template <int P, int EPI>
-__global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
-    __shared__ __attribute__((aligned(16))) char smem[2 * XSTAGE];
+__global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) {
+    constexpr int NST = x_nstage<P>();
+    __shared__ __attribute__((aligned(16))) char smem[NST * XSTAGE];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
@@ -394,7 +401,7 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
     x_store(smem, tid, r);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        char *cur = smem + (kt & 1) * XSTAGE;
+        char *cur = smem + (NST == 2 ? (kt & 1) * XSTAGE : 0);
         if (kt + 1 < nk) x_load<P>(a, tile_m, tile_n, kbeg + (kt + 1) * XBK, tid, r);
         const char *As = cur, *Bs = cur + XBM * XROW;
         if constexpr (P == SPS_F32) {
@@ -434,7 +441,12 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                 }
         }
-        if (kt + 1 < nk) x_store(smem + ((kt + 1) & 1) * XSTAGE, tid, r);
+        if constexpr (NST == 2) {
+            if (kt + 1 < nk) x_store(smem + ((kt + 1) & 1) * XSTAGE, tid, r);
+        } else {
+            __syncthreads();   // every wave is done with the stage before it is refilled
+            if (kt + 1 < nk) x_store(smem, tid, r);
+        }
         __syncthreads();
     }
 
@@ -451,17 +463,12 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
             }
         return;
     } else {
-        // SED tile [128 galaxies][128 wavelengths] -> LDS (stride 129), then two threads per
-        // galaxy reduce 64 wavelengths each into the band sums
-        float(*sed)[XBN + 1] = reinterpret_cast<float(*)[XBN + 1]>(smem);
-        static_assert(XBM * (XBN + 1) * 4 <= 2 * XSTAGE, "SED tile fits the staging buffers");
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) sed[wm * 64 + i * 16 + 4 * lk + q][wn * 64 + j * 16 + li] = acc[i][j][q];
-        __syncthreads();
+        // SED tile [128 galaxies][128 wavelengths] -> LDS in NPASS passes of PW columns (row
+        // stride PW + 1; one stage holds half the tile), two threads per galaxy reducing PW / 2
+        // wavelengths each per pass into the band sums
+        constexpr int NPASS = (NST == 2) ? 1 : 2, PW = XBN / NPASS;
+        float(*sed)[PW + 1] = reinterpret_cast<float(*)[PW + 1]>(smem);
+        static_assert(XBM * (PW + 1) * 4 <= NST * XSTAGE, "SED columns fit the staging buffers");
         const int row = tid >> 1, half = tid & 1, g = tile_m + row;
         constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;   // num, N [, dnum/dtauV, dnum/ddelta, dnum/dFfloor]
         float accp[NB_MAX][NPB];
@@ -473,13 +480,26 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
         const float tauv = a.params[(size_t)7 * a.M + gg], delta = a.params[(size_t)8 * a.M + gg];
         const float ffl = a.params[(size_t)9 * a.M + gg];
         const double opz = 1.0 + (double)a.z[gg];
-        for (int cc = 0; cc < 64; ++cc) {
-            const int c = half * 64 + cc, l = tile_n + c;
+#pragma unroll
+        for (int pp = 0; pp < NPASS; ++pp) {
+        if (pp > 0) __syncthreads();   // the previous pass's reads are done
+        if (NPASS == 1 || wn == pp) {
+            const int c0 = (NPASS == 1) ? wn * 64 : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sed[wm * 64 + i * 16 + 4 * lk + q][c0 + j * 16 + li] = acc[i][j][q];
+        }
+        __syncthreads();
+        for (int cc = 0; cc < PW / 2; ++cc) {
+            const int c = pp * PW + half * (PW / 2) + cc, l = tile_n + c;
             if (l >= a.n_wave) break;
             const v4f w = *(const v4f *)(a.wc + 4 * (size_t)l);   // ln x, l q, q / l
             const float xd = __expf(delta * w[0]), ee = __expf(-tauv * xd);
             const float F = ffl + (1.0f - ffl) * ee;
-            const float sw = sed[row][c] * w[1];
+            const float sw = sed[row][half * (PW / 2) + cc] * w[1];
             const double lo = opz * a.wave[l];
 #pragma unroll
             for (int bb = 0; bb < NB_MAX; ++bb) {
@@ -496,6 +516,7 @@ __global__ void __launch_bounds__(256, 2) k_xgemm(XArgs a) {
                     accp[bb][4] = fmaf(stw, 1.0f - ee, accp[bb][4]);
                 }
             }
+        }
         }
 #pragma unroll
         for (int bb = 0; bb < NB_MAX; ++bb)
