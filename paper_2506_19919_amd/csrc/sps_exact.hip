@@ -746,19 +746,22 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
 #pragma unroll
     for (int b = 0; b < NB_MAX; ++b) cb[b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
     for (int ch = c_lo; ch < c_hi; ++ch) {
-        const int lb0 = ch * 256, l = lb0 + tid;
-        // bands within 8 sigma of some redshifted wavelength of this chunk (uniform)
+        const int lb0 = ch * 256, l = lb0 + tid, lc = min(l, n_wave - 1);
+        // every load of the chunk first (the element's own wavelength data does not wait for
+        // the band mask), then the bands within 8 sigma of some redshifted wavelength of the
+        // chunk (uniform)
+        const double wl = wave[lc], w0 = wave[min(lb0, n_wave - 1)], w1 = wave[min(lb0 + 255, n_wave - 1)];
+        const v4f w = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l
         unsigned act = 0;
         if (lb0 < n_wave) {
-            const double u0 = opz * wave[lb0], u1 = opz * wave[min(lb0 + 255, n_wave - 1)];
+            const double u0 = opz * w0, u1 = opz * w1;
             for (int b = 0; b < nb; ++b)
                 if (u0 < fl.hi8[b] && u1 > fl.lo8[b]) act |= 1u << b;
         }
         if (l >= ld) continue;
         float v = 0.0f;
         if (l < n_wave && act) {
-            const double lo = opz * wave[l];
-            const v4f w = *(const v4f *)(wc + 4 * (size_t)l);   // ln x, l q, q / l
+            const double lo = opz * wl;
             float sum = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB_MAX; ++b) {
