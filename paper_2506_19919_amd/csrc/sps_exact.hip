@@ -302,6 +302,9 @@ struct XArgs {
     // per 128-galaxy row tile: the wavelength tiles (x, y: 128-wide, [x, y)) and k-tiles (z, w:
     // 32-wide) inside some band's 8-sigma filter support for some galaxy of the tile; null: all
     const int4 *win;
+    // rows in z order: the forward epilogue skips, per wave, the bands farther than 8 sigma
+    // from all of its wavelengths (a wave's galaxies then share nearly one redshift)
+    int band_skip;
 };
 
 template <int P>
@@ -493,6 +496,21 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
                     for (int q = 0; q < 4; ++q) sed[wm * 64 + i * 16 + 4 * lk + q][c0 + j * 16 + li] = acc[i][j][q];
         }
         __syncthreads();
+        // bands within 8 sigma of some redshifted wavelength of some thread of the wave: a
+        // wave-uniform mask, so a skipped band is a scalar branch (all bands when the rows are
+        // in arbitrary z order, where the test would rarely skip and only cost time)
+        unsigned act = (1u << a.n_band) - 1u;
+        if (a.band_skip) {
+            const int l0 = tile_n + pp * PW + half * (PW / 2), l1 = min(l0 + PW / 2 - 1, a.n_wave - 1);
+            const double u0 = opz * a.wave[min(l0, a.n_wave - 1)], u1 = opz * a.wave[l1];
+            act = 0;
+#pragma unroll
+            for (int bb = 0; bb < NB_MAX; ++bb) {
+                if (bb >= a.n_band) break;
+                const double x0 = (u0 - a.fc[bb]) * a.inv_fs[bb], x1 = (u1 - a.fc[bb]) * a.inv_fs[bb];
+                if (__ballot(l0 < a.n_wave && x0 < 8.0 && x1 > -8.0) != 0) act |= 1u << bb;
+            }
+        }
         for (int cc = 0; cc < PW / 2; ++cc) {
             const int c = pp * PW + half * (PW / 2) + cc, l = tile_n + c;
             if (l >= a.n_wave) break;
@@ -504,6 +522,7 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
 #pragma unroll
             for (int bb = 0; bb < NB_MAX; ++bb) {
                 if (bb >= a.n_band) break;
+                if (!((act >> bb) & 1u)) continue;
                 const float x = (float)((lo - a.fc[bb]) * a.inv_fs[bb]);
                 const float tb = __expf(-0.5f * x * x);
                 const float stw = sw * tb;
@@ -899,7 +918,7 @@ __global__ void __launch_bounds__(128) k_xwindows(int n, int n_wave, FiltConst f
 // ------------------------------------------------------------------ launcher
 static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                       void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
-                      float *grad) {
+                      float *grad, bool zordered) {
     const int nw = c->n_wave, nb = c->n_band;
     const bool f64 = (prec == SPS_F64);
     const int TN = f64 ? BN : XBN;                // wavelengths per tile of the forward GEMM
@@ -984,6 +1003,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
                            win);
         XArgs a{};
         a.win = win;
+        a.band_skip = zordered ? 1 : 0;
         a.M = n;
         a.N = lw;
         a.K = S_PAD;
@@ -1127,13 +1147,9 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
                  void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
                  float *grad, bool ordered) {
     if (prec == SPS_F64 || ordered || n < XSORT_MIN)
-        return exact_core(c, s, n, sfh, prec, params, z, mag_out, obs, sigma, mask, logl, grad);
-    DevConsts grid = c->k;
-    if (grid.n_z == 0) {
-        grid.n_z = 65;
-        grid.z_lo = 0.0;
-        grid.dz = 0.125;
-    }
+        return exact_core(c, s, n, sfh, prec, params, z, mag_out, obs, sigma, mask, logl, grad,
+                          ordered && prec != SPS_F64);
+    const DevConsts grid = z_sort_grid(c);
     const int nb = c->n_band;
     size_t off = 0;
     auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
@@ -1159,7 +1175,8 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     hipLaunchKernelGGL(k_exact_order_in, g1, b1, 0, s, n, nb, (const int *)c->d_perm, (const float *)params,
                        (const float *)z, obs, sigma, mask, par_s, z_s, obs_s, sig_s, msk_s);
     rc = exact_core(c, s, n, sfh, prec, par_s, z_s, mag_out ? mag_s : nullptr, obs ? obs_s : nullptr,
-                    obs ? sig_s : nullptr, mask ? msk_s : nullptr, logl ? ll_s : nullptr, grad ? gr_s : nullptr);
+                    obs ? sig_s : nullptr, mask ? msk_s : nullptr, logl ? ll_s : nullptr, grad ? gr_s : nullptr,
+                    true);
     if (rc) return rc;
     hipLaunchKernelGGL(k_exact_order_out, g1, b1, 0, s, n, nb, (const int *)c->d_perm, mag_s, ll_s, gr_s,
                        (float *)mag_out, logl, grad);

@@ -409,10 +409,10 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
 // leapfrog runs as a host loop: each step is one exact value+gradient call over every chain
 // (the likelihood entry point's own kernels), with small per-chain kernels around it for
 // the kicks, the drift and the end of the iteration.  Slot = rank * C + chain with the
-// galaxies ranked by z when a z table exists (then a 128-row tile of the GEMMs spans a
-// narrow z range and skips the wavelengths outside its filters' support), else in input
-// order.  Chain ids, Philox counters, the FP32 trajectory arithmetic, the FP64 Hamiltonian
-// and the adaptation are those of the fused approximate-path kernel.
+// galaxies ranked by z (the z table's buckets, or z_sort_grid's without a table), so a
+// 128-row tile of the GEMMs spans a narrow z range and skips the wavelengths outside its
+// filters' support.  Chain ids, Philox counters, the FP32 trajectory arithmetic, the FP64
+// Hamiltonian and the adaptation are those of the fused approximate-path kernel.
 struct HmcxArgs {
     int n_gal, C, nslot, nb, NW, NS;
     int n_win;
@@ -422,7 +422,7 @@ struct HmcxArgs {
     const float *z, *obs, *sigma;
     const uint8_t *mask;
     const float *bounds, *prior, *theta0;
-    const int *perm;           // galaxy of each rank (z order), or null: rank = galaxy
+    const int *perm;           // galaxy of each rank (z order)
     float *samples;
     // chain state, [quantity][slot]
     float *x, *gr, *minv, *eps, *mu, *hbar, *lebar;
@@ -442,7 +442,7 @@ struct HmcxArgs {
 __global__ void __launch_bounds__(256) k_hmcx_setup(HmcxArgs a) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
-    const int g = a.perm ? a.perm[s / a.C] : s / a.C, ch = s % a.C;
+    const int g = a.perm[s / a.C], ch = s % a.C;
     a.zs[s] = a.z[g];
     for (int b = 0; b < a.nb; ++b) {
         a.obs_s[(size_t)s * a.nb + b] = a.obs[(size_t)g * a.nb + b];
@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(256) k_hmcx_init(HmcxArgs a) {
 __global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
-    const int g = a.perm ? a.perm[s / a.C] : s / a.C, ch = s % a.C;
+    const int g = a.perm[s / a.C], ch = s % a.C;
     const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
     uint32_t w[NP];
 #pragma unroll
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it) {
 __global__ void __launch_bounds__(256) k_hmcx_step(HmcxArgs a, int it, int last) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
-    const int g = a.perm ? a.perm[s / a.C] : s / a.C, ch = s % a.C;
+    const int g = a.perm[s / a.C], ch = s % a.C;
     float x[NP], gn[NP], p[NP];
     const double lpn = hmcx_logpost(a, s, x, gn);
     const float eps = a.eps[s];
@@ -737,8 +737,9 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
     a.prior = prior;
     a.theta0 = theta0;
     a.samples = samples;
-    if (c->k.n_z > 0) {   // rank the galaxies by z (the table's buckets)
-        int rc0 = launch_bucket_sort(c, s, n_gal, z);
+    {   // rank the galaxies by z
+        const DevConsts grid = z_sort_grid(c);
+        int rc0 = launch_bucket_sort(c, s, n_gal, z, nullptr, &grid);
         if (rc0) return rc0;
         a.perm = c->d_perm;
     }

@@ -133,6 +133,17 @@ struct GatherArgs {
     float *rec;                         // null: sort only
     int *inv;
 };
+// z buckets for ranking galaxies by redshift: the z table's nodes, or 64 buckets over
+// 0 <= z < 8 when no table was built (z beyond goes to one overflow bucket)
+inline DevConsts z_sort_grid(const sps_ctx *c) {
+    DevConsts g = c->k;
+    if (g.n_z == 0) {
+        g.n_z = 65;
+        g.z_lo = 0.0;
+        g.dz = 0.125;
+    }
+    return g;
+}
 // grid: the z buckets (n_z, z_lo, dz of a DevConsts; n_z <= 1025); null: the z table's
 int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z, const GatherArgs *ga = nullptr,
                        const DevConsts *grid = nullptr);

@@ -202,9 +202,9 @@ def test_exact_path_posterior_moments_agree_with_approximate_path(ctx_exact, orc
 
 
 def test_exact_path_chain_order_does_not_change_the_draws(ctx_exact, ssp2000, filt6, orc):
-    # with a z table the chains are ranked by z inside the library, without one they keep the
-    # input order: the GEMM rows are independent, so the draws agree to FP32 rounding and every
-    # output lands on its own galaxy
+    # the chains are ranked by z inside the library, on the z table's buckets or, without a
+    # table, on a fixed grid: the two orders differ, the GEMM rows are independent, so the draws
+    # agree to FP32 rounding and every output lands on its own galaxy
     import paper_2506_19919_amd as sps
     n, C = 5, 2
     sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 51, C)
