@@ -806,20 +806,36 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
 
 // dP_age and dP_Z from Wbar = dlogL/dP_SSP (stored [s][ld], galaxies contiguous):
 //   dP_age(i) = sum_j P_Z(j) Wbar[j NA + i],  dP_Z(j) = sum_i P_age(i) Wbar[j NA + i]
-// one thread per (galaxy, output), written SoA pb[r][n] (r < NA: dP_age, then dP_Z)
+// Thread per (galaxy, group of WB_AGES ages): each Wbar element is read once; the group's
+// dP_age are complete, its dP_Z are partial sums written SoA pb[NA + grp NZ + j][n] and added
+// by the weights adjoint.  Written SoA pb[r][n] (r < NA: dP_age).
+constexpr int WB_GROUPS = 4, WB_AGES = (NA + WB_GROUPS - 1) / WB_GROUPS;
 __global__ void __launch_bounds__(256) k_wbar_reduce(int n, const float *pw, const float *wbar, int ld,
                                                      float *pb) {
-    const int g = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    const int g = blockIdx.x * 256 + threadIdx.x, grp = blockIdx.y;
     if (g >= n) return;
-    float s = 0.0f;
-    if (r < NA) {
+    float pz[NZ], dz[NZ];
 #pragma unroll
-        for (int j = 0; j < NZ; ++j) s = fmaf(pw[(size_t)(PW_PZ + j) * n + g], wbar[(size_t)(j * NA + r) * ld + g], s);
-    } else {
-        const int j = r - NA;
-        for (int i = 0; i < NA; ++i) s = fmaf(pw[(size_t)i * n + g], wbar[(size_t)(j * NA + i) * ld + g], s);
+    for (int j = 0; j < NZ; ++j) {
+        pz[j] = pw[(size_t)(PW_PZ + j) * n + g];
+        dz[j] = 0.0f;
     }
-    pb[(size_t)r * n + g] = s;
+    const int i1 = min(NA, (grp + 1) * WB_AGES);
+    for (int i = grp * WB_AGES; i < i1; ++i) {
+        float w[NZ];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) w[j] = wbar[(size_t)(j * NA + i) * ld + g];
+        const float pa = pw[(size_t)i * n + g];
+        float da = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+            da = fmaf(pz[j], w[j], da);
+            dz[j] = fmaf(pa, w[j], dz[j]);
+        }
+        pb[(size_t)i * n + g] = da;
+    }
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) pb[(size_t)(NA + grp * NZ + j) * n + g] = dz[j];
 }
 
 // sum of the K-range partial products into the first one (float4 per thread)
@@ -862,7 +878,11 @@ __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sf
     for (int i = q; i < NA; i += GPL) col[i] = pb[(size_t)i * n + gg];
     float pzbar[NZ];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) pzbar[j] = pb[(size_t)(NA + j) * n + gg];
+    for (int j = 0; j < NZ; ++j) {
+        float v = 0.0f;
+        for (int q = 0; q < WB_GROUPS; ++q) v += pb[(size_t)(NA + q * NZ + j) * n + gg];
+        pzbar[j] = v;
+    }
     float gr[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) gr[p] = 0.0f;
@@ -945,7 +965,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         if (want_grad) {
             o_rb = carve((size_t)nsplit * mp * lw * tsz);
             o_wb = carve((size_t)XSPLIT * S_PAD * mp * 4);
-            o_pb = carve((size_t)(NA + NZ) * n * 4);
+            o_pb = carve((size_t)(NA + WB_GROUPS * NZ) * n * 4);
         }
     }
     if (c->work_bytes < off) {
@@ -1092,7 +1112,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
             hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, n4, b.k_splits, n4,
                                (v4f *)b.C);
         }
-        hipLaunchKernelGGL(k_wbar_reduce, dim3((n + 255) / 256, NA + NZ), dim3(256), 0, s, n, (const float *)pw,
+        hipLaunchKernelGGL(k_wbar_reduce, dim3((n + 255) / 256, WB_GROUPS), dim3(256), 0, s, n, (const float *)pw,
                            (const float *)b.C, mp, pb);
         hipLaunchKernelGGL(k_exact_adjoint, dim3((n + 64 / GPL - 1) / (64 / GPL)), dim3(64), 0, s, c->k, n, sfh,
                            (const float *)params, (const float *)z, (const float *)pw, (const float *)pb, grad);
