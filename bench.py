@@ -282,6 +282,58 @@ def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0)):
     return res
 
 
+def bench_posterior_agreement(dev, n=1024, C=4, L=10, n_warm=200, n_samp=1000):
+    """App. B's second test: the same sampler, same starts and draws, with approximate and with
+    exact (BF16 hi+lo) photometry on n galaxies of the HMC workload; the posterior means are
+    compared in units of the posterior sd."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] approximate vs exact posteriors: {n} galaxies x {C} chains, {n_warm} + {n_samp} iterations")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C)
+    ctx.build_ztable(64, 0.1, 3.0)
+    th, z = synth.galaxies_dpl(16_384, 104)
+    th, z = th[:n], z[:n]
+    params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    noise, sig = synth.photometric_noise(16_384, 6, 204)
+    mags = ctx.phot_exact(synth.SFH_DPL, params, zt, prec=sps.SPS_F32)
+    obs = (mags + torch.as_tensor(noise[:n], dtype=torch.float32, device=dev)).contiguous()
+    sigma = torch.as_tensor(sig[:n], dtype=torch.float32, device=dev).contiguous()
+    mask = torch.as_tensor(np.ascontiguousarray(synth.band_masks(16_384, 6, 204)[:n])).to(dev)
+    bounds = torch.as_tensor(synth.bounds_k_x0(), dtype=torch.float32, device=dev)
+    prior = torch.as_tensor(synth.PRIOR, dtype=torch.float32, device=dev)
+    theta0 = torch.as_tensor(np.ascontiguousarray(synth.prior_draws(C, 16_384, 304)[:, :, :n]),
+                             dtype=torch.float32, device=dev)
+    kw = dict(n_chain=C, n_leapfrog=L, n_warmup=n_warm, n_sample=n_samp, seed=404)
+    t0 = time.perf_counter()
+    ap = ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ex = ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, path=sps.SPS_PATH_EXACT,
+                     prec=sps.SPS_BF16X, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.close()
+    pa, sa = ap["post_mean"].cpu().numpy(), ap["post_sd"].cpu().numpy()
+    pe, se = ex["post_mean"].cpu().numpy(), ex["post_sd"].cpu().numpy()
+    d = np.abs(pe - pa) / np.maximum(np.maximum(sa, se), 1e-12)
+    conv = np.all(ap["rhat"].cpu().numpy() < 1.2, axis=0) & np.all(ex["rhat"].cpu().numpy() < 1.2, axis=0)
+    res = {"workload": f"{n} galaxies of the HMC workload x {C} chains, {L} leapfrog steps, {n_warm} + {n_samp} "
+                       "iterations, same starts and Philox draws; exact path in BF16 hi+lo",
+           "median_abs_mean_diff_over_sd": float(np.median(d)),
+           "p90_abs_mean_diff_over_sd": float(np.percentile(d, 90)),
+           "median_sd_ratio_exact_over_approx": float(np.median(se / np.maximum(sa, 1e-12))),
+           "both_converged_fraction": float(conv.mean()),
+           "median_abs_mean_diff_over_sd_converged": float(np.median(d[:, conv])) if conv.any() else None,
+           "wall_s_approx": t1 - t0, "wall_s_exact": t2 - t1}
+    log(f"[bench]   |mean diff| / sd: median {res['median_abs_mean_diff_over_sd']:.3f}, 90th pct "
+        f"{res['p90_abs_mean_diff_over_sd']:.3f}; wall {t1 - t0:.2f} s approx, {t2 - t1:.2f} s exact")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +345,7 @@ def main():
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-hmc-exact", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-posterior-agreement", action="store_true")
     ap.add_argument("--hmc-gal", type=int, default=16_384)
     ap.add_argument("--hmc-warmup", type=int, default=200)
     ap.add_argument("--hmc-sample", type=int, default=1000)
@@ -406,6 +459,8 @@ def main():
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
                                               adapt_metric=True)
+    if not args.no_posterior_agreement:
+        out["posterior_agreement"] = bench_posterior_agreement(dev)
     if not args.no_hmc_exact:
         aw = out["hmc"]["wall_s"] if "hmc" in out else None
         out["hmc_exact"] = bench_hmc_exact(dev, args.hmc_gal, full_iter=args.hmc_warmup + args.hmc_sample,
