@@ -189,8 +189,9 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
  * exact value+gradient call over all n_gal * n_chain chains).  prec is ignored on the
  * approximate path.  Both paths draw the same Philox streams.
  * Needs n_gal * n_chain <= the reserved galaxy count; grows the context's chain-state
- * workspace (device memory, ~260 B per chain; ~460 B plus the exact path's own
- * workspace for SPS_PATH_EXACT) on first use. */
+ * workspace (device memory, ~470 B per chain with its trajectory scratch; for SPS_PATH_EXACT
+ * ~540 B plus the exact path's own workspace) on first use.  The exact path ranks the chains
+ * by z internally (on the z table's buckets if one was built, else on a fixed grid). */
 typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     float target_accept, init_step;
