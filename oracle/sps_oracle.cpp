@@ -18,8 +18,8 @@
  *                            and, optionally, a diagonal mass matrix adapted in a
  *                            warm-up phase)
  *
- * Readings where the paper is silent or garbled are listed in the design doc and
- * restated next to the code they govern.  No blocking, fusion or reordering:
+ * Readings where the paper is silent or garbled are restated next to the code
+ * they govern.  No blocking, fusion or reordering:
  * each quantity is computed from its definition.  Derivatives come from
  * forward-mode dual numbers carried through the same code.
  */

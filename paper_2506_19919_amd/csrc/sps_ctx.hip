@@ -288,7 +288,7 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
     if (!ssp->log10_met || !ssp->log10_age_yr || !ssp->wave_A || !ssp->lum)
         return set_error(SPS_E_INVAL, "null SSP array");
     if (ssp->n_age != NA || ssp->n_met != NZ)
-        return set_error(SPS_E_INVAL, "unsupported SSP grid: this build tiles n_age = 94, n_met = 12");
+        return set_error(SPS_E_INVAL, "unsupported SSP grid: the kernels tile n_age = 94, n_met = 12");
     if (ssp->n_wave < 2) return set_error(SPS_E_INVAL, "n_wave < 2");
     if (!increasing(ssp->log10_met, NZ) || !increasing(ssp->log10_age_yr, NA) ||
         !increasing(ssp->wave_A, ssp->n_wave) || !(ssp->wave_A[0] > 0.0))
