@@ -151,6 +151,31 @@ def test_exact_full_size_sampled(ctx5000, orc5000, prec_name, tol):
     assert ok.all(), (np.argwhere(~ok)[:8], g[pick][~ok][:8], rg[~ok][:8], prop[~ok][:8])
 
 
+@pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
+def test_exact_lognormal_burst_forward_and_grad(ctx2000, orc, prec_name, tol):
+    # the log-normal star-formation history with a burst through the FP32 / BF16X exact path
+    import paper_2506_19919_amd as sps
+    n = 150
+    sfh, th, z = gal_inputs("lognormal_burst", n, 131)
+    prec = getattr(sps, prec_name)
+    m_ref = orc.phot_exact(sfh, th, z)
+    m = ctx2000.phot_exact(sfh, soa(th), dev(z), prec=prec).cpu().numpy()
+    assert np.abs(m - m_ref).max() <= tol
+    k = 24
+    noise, sig = synth.photometric_noise(k, 6, 132)
+    obs, sig = f32(m_ref[:k] + noise), f32(sig)
+    masks = synth.band_masks(k, 6, 133)
+    ll, g = ctx2000.loglike_grad(sfh, soa(th[:k]), dev(z[:k]), dev(obs), dev(sig), dev(masks, torch.uint8),
+                                 path=sps.SPS_PATH_EXACT, prec=prec)
+    rl, rg = orc.loglike_grad(sfh, th[:k], z[:k], obs, sig, masks, path=1)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().T.astype(np.float64)
+    r = np.abs((m_ref[:k] - obs) / sig) * ((masks[:, None] >> np.arange(6)) & 1)
+    assert np.all(np.abs(ll - rl) <= (r.sum(1) / 0.05) * tol + 1e-3)
+    prop, _ = grad_tol(orc, sfh, th[:k], z[:k], sig, masks, m[:k], path=1)
+    ok = grad_ok(g, rg, prop)
+    assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[~ok][:8], prop[~ok][:8])
+
+
 def test_exact_matches_approx_at_z_nodes_without_dust(ctx2000, orc):
     # both GPU paths reduce to the same sum when the attenuation is flat (tau_V = 0)
     import paper_2506_19919_amd as sps
