@@ -176,6 +176,31 @@ def test_exact_lognormal_burst_forward_and_grad(ctx2000, orc, prec_name, tol):
     assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[~ok][:8], prop[~ok][:8])
 
 
+@pytest.mark.parametrize("n", [1, 129])
+@pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
+def test_exact_ragged_batches(ctx2000, orc, n, prec_name, tol):
+    # one galaxy, and a second 128-galaxy row tile holding one galaxy: padded rows must not
+    # leak into the real ones (forward and gradient)
+    import paper_2506_19919_amd as sps
+    sfh, th, z = gal_inputs("dpl", n, 400 + n)
+    prec = getattr(sps, prec_name)
+    m_ref = orc.phot_exact(sfh, th, z)
+    m = ctx2000.phot_exact(sfh, soa(th), dev(z), prec=prec).cpu().numpy()
+    assert np.abs(m - m_ref).max() <= tol
+    noise, sig = synth.photometric_noise(n, 6, 500 + n)
+    obs, sig = f32(m_ref + noise), f32(sig)
+    masks = synth.band_masks(n, 6, 600 + n)
+    ll, g = ctx2000.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8),
+                                 path=sps.SPS_PATH_EXACT, prec=prec)
+    rl, rg = orc.loglike_grad(sfh, th, z, obs, sig, masks, path=1)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().T.astype(np.float64)
+    r = np.abs((m_ref - obs) / sig) * ((masks[:, None] >> np.arange(6)) & 1)
+    assert np.all(np.abs(ll - rl) <= (r.sum(1) / 0.05) * tol + 1e-3)
+    prop, _ = grad_tol(orc, sfh, th, z, sig, masks, m, path=1)
+    ok = grad_ok(g, rg, prop)
+    assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[~ok][:8], prop[~ok][:8])
+
+
 def test_exact_matches_approx_at_z_nodes_without_dust(ctx2000, orc):
     # both GPU paths reduce to the same sum when the attenuation is flat (tau_V = 0)
     import paper_2506_19919_amd as sps
