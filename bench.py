@@ -38,12 +38,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest():
+def kernel_source_digest(d=None):
     """sha256 over the code of the HIP sources and headers the kernels are built from (comments
-    and whitespace removed, so that an edit of a comment does not void the counters)."""
+    and whitespace removed, so that an edit of a comment does not void the counters); d: the
+    source folder (default: the package's csrc)."""
     import hashlib
     import re
-    d = os.path.join(ROOT, "paper_2506_19919_amd", "csrc")
+    d = d or os.path.join(ROOT, "paper_2506_19919_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h")):
@@ -55,14 +56,14 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or None when the
     summary is missing or the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("traffic_") and ":" in line:
                 k, v = line.split(":", 1)
