@@ -8,8 +8,10 @@
 // The GEMM runs on MFMA (FP64 16x16x4, FP32 16x16x4, or BF16 16x16x32 with the
 // split W = W_hi + W_lo, L = L_hi + L_lo and three products hi.hi + hi.lo + lo.hi
 // accumulated in FP32).  The attenuation, filter and quadrature weights are
-// generated in the epilogue and reduced over each 64-wavelength tile into
-// per-tile partial sums; a small kernel finishes the sums per galaxy.
+// generated in the epilogue and reduced over each wavelength tile (64 wide on the
+// FP64 path, 128 on the FP32 / BF16X paths) into per-tile partial sums; small
+// kernels finish the sums per galaxy.  The FP32 / BF16X paths skip the wavelength
+// tiles outside every band's 8-sigma support for a 128-galaxy row tile.
 // Gradient (FP32 / BF16X): dlogL/dnum -> Rbar[g][l] -> second GEMM
 // Wbar = Rbar . L^T -> dP_age, dP_Z -> the weights adjoint shared with the
 // approximate path; dust derivatives come from extra epilogue partials.
