@@ -359,12 +359,14 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
     const int T = a.n_mt * a.n_nt, nsp = (EPI == EPI_STORE) ? a.k_splits : 1, total = T * nsp, b = blockIdx.x;
     int t = b;
     if (total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
-    // the K range: slowest, or fastest where windows clip it (then every XCD's run of tiles
-    // holds all ranges, and the mostly skipped last ones do not gather on a few XCDs)
+    // the K range: slowest, or between M and N where windows clip it (every XCD's run of tiles
+    // then holds all ranges, so the mostly skipped last ones do not gather on a few XCDs, and
+    // consecutive tiles still share their B rows and K range in L2)
     int sp;
     if (EPI == EPI_STORE && a.win != nullptr) {
-        sp = t % nsp;
-        t /= nsp;
+        const int m_ = t % a.n_mt, rest = t / a.n_mt;
+        sp = rest % nsp;
+        t = (rest / nsp) * a.n_mt + m_;
     } else {
         sp = t / T;
         t -= sp * T;
