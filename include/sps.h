@@ -96,7 +96,7 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
 int sps_reserve(sps_ctx *ctx, int max_gal);
 
 /* Build the SSP x band flux table c_SSP(z) on n_z uniform nodes in [z_lo, z_hi]
- * (Sec. 3: "calculated in advance ... on a lookup table").  Stored distance-free
+ * (Sec. 3, the precomputed c_SSP lookup table after Eq. photo_integral_approx).  Stored distance-free
  * and divided by the band normalisation: Q[k][b][j][i] =
  *   sum_l L[j][i][l] T_b((1+z_k) l) l q_l / sum_l T_b((1+z_k) l) q_l / l
  * with trapezoid weights q_l on the SSP wavelength grid; FP64 arithmetic,

@@ -57,7 +57,11 @@ class _Model(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_double), ("init_step", C.c_double),
-                ("seed", C.c_uint64), ("adapt_metric", C.c_int), ("path", C.c_int)]
+                ("seed", C.c_uint64), ("adapt_metric", C.c_int), ("path", C.c_int),
+                ("it_begin", C.c_int), ("it_end", C.c_int)]
+
+
+HMC_STATE = 400   # doubles of per-chain state carried between the calls of a split run
 
 
 _lib = None
@@ -86,6 +90,7 @@ def lib():
         _lib.orc_log_prior.argtypes = [C.c_void_p, d]
         _lib.orc_rhat.restype = d
         _lib.orc_rhat.argtypes = [C.c_int, C.c_int, C.c_void_p]
+        _lib.orc_hmc_prior_draw.restype = None
         _lib.orc_philox4x32_10.restype = None
         _lib.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     return _lib
@@ -291,18 +296,35 @@ class Oracle:
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
                 keep_samples=False, keep_trace=False, gauss_prec=None, gal_id=None, n_gal_total=0,
-                adapt_metric=False, path=0):
-        th0 = _f64(theta0)
-        n_gal = th0.shape[1]
-        assert th0.shape == (n_chain, n_gal, N_PARAM)
+                adapt_metric=False, path=0, it_begin=0, it_end=0, state=None, samples=None, n_gal=None):
+        """theta0 [chain][galaxy][10] unbounded start, or None to draw it from the prior.
+        A run split over calls passes it_begin / it_end and the same `state` array
+        ([chain][galaxy][HMC_STATE] float64, updated in place) to every call, and `samples`
+        (kept across the calls) to collect the draws."""
+        if theta0 is not None:
+            th0 = _f64(theta0)
+            n_gal = th0.shape[1]
+            assert th0.shape == (n_chain, n_gal, N_PARAM)
+        else:
+            th0 = None
+            n_gal = len(z) if n_gal is None else n_gal
+        if state is not None:
+            assert state.dtype == np.float64 and state.flags.c_contiguous
+            assert state.shape == (n_chain, n_gal, HMC_STATE)
         cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
-                      {False: 0, True: 1, "diag": 1, "dense": 2}[adapt_metric], int(path))
+                      {False: 0, True: 1, "diag": 1, "dense": 2}[adapt_metric], int(path), int(it_begin),
+                      int(it_end))
         minv = np.zeros((n_chain, n_gal, N_PARAM))
         pm, ps, rh = (np.zeros((n_gal, N_PARAM)) for _ in range(3))
         acc = np.zeros(n_gal)
         step = np.zeros((n_chain, n_gal))
-        smp = np.zeros((n_sample, n_chain, n_gal, N_PARAM)) if keep_samples else None
+        if samples is not None:
+            assert samples.shape == (n_sample, n_chain, n_gal, N_PARAM) and samples.dtype == np.float64
+            smp = samples
+        else:
+            smp = np.zeros((n_sample, n_chain, n_gal, N_PARAM)) if keep_samples else None
         tr = np.zeros((n_warmup + n_sample, n_chain, n_gal)) if keep_trace else None
+        tra = np.zeros((n_warmup + n_sample, n_chain, n_gal, 3)) if keep_trace else None
         gp = _f64(gauss_prec) if gauss_prec is not None else None
         if gp is None:
             n_z, lo, hi, qp = self._zt() if path == 0 else (0, C.c_double(0), C.c_double(0), None)
@@ -312,19 +334,29 @@ class Oracle:
             args = (_p(zz), _p(o), _p(s), _p(mk), _p(b), _p(pr))
         else:
             n_z, lo, hi, qp = 0, C.c_double(0), C.c_double(0), None
-            args = (None,) * 6
+            pr = _f64(prior) if prior is not None else None   # prior draws of the start only
+            args = (None,) * 5 + (_p(pr),)
         gid = np.ascontiguousarray(gal_id, dtype=np.uint32) if gal_id is not None else None
         rc = self.L.orc_hmc_run(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo),
                                 C.byref(self.model), n_z, lo, hi, qp, sfh, C.byref(cfg), n_gal,
                                 *args, _p(th0), _p(gp), _p(pm), _p(ps), _p(rh), _p(acc), _p(step),
-                                _p(smp), _p(tr), int(n_gal_total), _p(gid), _p(minv))
+                                _p(smp), _p(tr), int(n_gal_total), _p(gid), _p(minv), _p(tra), _p(state))
         assert rc == 0, rc
         out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step, inv_metric=minv)
-        if keep_samples:
+        if smp is not None:
             out["samples"] = smp
         if keep_trace:
             out["trace_logp"] = tr
+            out["trace_alpha"], out["trace_margin"], out["trace_eps"] = tra[..., 0], tra[..., 1], tra[..., 2]
         return out
+
+
+def hmc_prior_draw(prior, seed, chain_id):
+    """Unbounded starting point drawn from the skew-normal priors [10][3] for one chain id."""
+    pr = _f64(prior)
+    x = np.zeros(N_PARAM)
+    lib().orc_hmc_prior_draw(_p(pr), C.c_uint64(seed), C.c_uint32(chain_id), _p(x))
+    return x
 
 
 def philox4x32_10(ctr, key):
@@ -333,6 +365,13 @@ def philox4x32_10(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def gauss_legendre(n):
+    """Nodes and weights of the oracle's n-point Gauss-Legendre rule on [-1, 1]."""
+    x, w = np.zeros(n), np.zeros(n)
+    assert lib().orc_gauss_legendre(int(n), _p(x), _p(w)) == 0
+    return x, w
 
 
 def hmc_windows(n_warmup):

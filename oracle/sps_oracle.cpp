@@ -98,29 +98,69 @@ using std::pow;
 using std::sqrt;
 
 // ------------------------------------------------------------------------
-// Gauss-Legendre nodes (Newton iteration on P_n) and adaptive bisection
+// Gauss-Legendre nodes by the Golub-Welsch method, and adaptive bisection
 // ------------------------------------------------------------------------
+// The n-point rule's nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix of
+// the Legendre three-term recurrence (zero diagonal, off-diagonal k / sqrt(4k^2 - 1)), and each
+// weight is 2 (the integral of the weight function) times the squared first component of the
+// node's unit eigenvector (Golub & Welsch 1969).  The eigenproblem is solved by cyclic Jacobi
+// rotations, which for n <= 16 converge to rounding in a handful of sweeps.
 struct GaussLegendre {
     int n;
     double x[16], w[16];
     explicit GaussLegendre(int n_) : n(n_) {
-        for (int i = 0; i < (n + 1) / 2; ++i) {
-            double zz = std::cos(PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
-            for (int it = 0; it < 100; ++it) {
-                double p1 = 1.0, p2 = 0.0;
-                for (int j = 1; j <= n; ++j) {
-                    double p3 = p2;
-                    p2 = p1;
-                    p1 = ((2.0 * j - 1.0) * zz * p2 - (j - 1.0) * p3) / j;
+        long double a[16][16] = {{0.0L}}, v[16][16] = {{0.0L}};   // extended precision, rounded at the end
+        for (int i = 0; i < n; ++i) v[i][i] = 1.0;
+        for (int k = 1; k < n; ++k) a[k - 1][k] = a[k][k - 1] = k / std::sqrt(4.0L * k * k - 1.0L);
+        for (int sweep = 0; sweep < 50; ++sweep) {
+            long double off = 0.0L;
+            for (int i = 0; i < n; ++i)
+                for (int j = i + 1; j < n; ++j) off += a[i][j] * a[i][j];
+            if (off < 1e-4000L) break;
+            for (int pi = 0; pi < n; ++pi)
+                for (int qi = pi + 1; qi < n; ++qi) {
+                    if (a[pi][qi] == 0.0L) continue;
+                    // rotation in the (pi, qi) plane that zeroes a[pi][qi]
+                    const long double th = (a[qi][qi] - a[pi][pi]) / (2.0L * a[pi][qi]);
+                    const long double t = (th >= 0.0L ? 1.0L : -1.0L) / (std::fabs(th) + std::sqrt(th * th + 1.0L));
+                    const long double c = 1.0L / std::sqrt(t * t + 1.0L), sn = t * c;
+                    for (int r = 0; r < n; ++r) {   // A <- A G (columns pi, qi)
+                        const long double ap = a[r][pi], aq = a[r][qi];
+                        a[r][pi] = c * ap - sn * aq;
+                        a[r][qi] = sn * ap + c * aq;
+                    }
+                    for (int r = 0; r < n; ++r) {   // A <- G^T A (rows pi, qi)
+                        const long double ap = a[pi][r], aq = a[qi][r];
+                        a[pi][r] = c * ap - sn * aq;
+                        a[qi][r] = sn * ap + c * aq;
+                    }
+                    for (int r = 0; r < n; ++r) {   // eigenvectors: V <- V G
+                        const long double vp = v[r][pi], vq = v[r][qi];
+                        v[r][pi] = c * vp - sn * vq;
+                        v[r][qi] = sn * vp + c * vq;
+                    }
                 }
-                pp = n * (zz * p1 - p2) / (zz * zz - 1.0);
-                double z1 = zz;
-                zz = z1 - p1 / pp;
-                if (std::fabs(zz - z1) < 1e-16) break;
-            }
-            x[i] = -zz;
-            x[n - 1 - i] = zz;
-            w[i] = w[n - 1 - i] = 2.0 / ((1.0 - zz * zz) * pp * pp);
+        }
+        // nodes in increasing order with their weights
+        int idx[16];
+        for (int i = 0; i < n; ++i) idx[i] = i;
+        std::sort(idx, idx + n, [&](int i, int j) { return a[i][i] < a[j][j]; });
+        long double xl[16], wl[16];
+        for (int i = 0; i < n; ++i) {
+            xl[i] = a[idx[i]][idx[i]];
+            wl[i] = 2.0L * v[0][idx[i]] * v[0][idx[i]];
+        }
+        // the rule is symmetric: average the mirrored pairs (and put the middle node of an odd
+        // rule exactly at 0)
+        for (int i = 0; i < n / 2; ++i) {
+            const long double xs = 0.5L * (xl[n - 1 - i] - xl[i]), ws = 0.5L * (wl[i] + wl[n - 1 - i]);
+            x[i] = (double)-xs;
+            x[n - 1 - i] = (double)xs;
+            w[i] = w[n - 1 - i] = (double)ws;
+        }
+        if (n % 2) {
+            x[n / 2] = 0.0;
+            w[n / 2] = (double)wl[n / 2];
         }
     }
 };
@@ -746,6 +786,13 @@ int orc_leapfrog(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox(ctr, key, out); }
 
+int orc_gauss_legendre(int n, double *x, double *w) {
+    if (n < 1 || n > 16 || !x || !w) return 1;
+    GaussLegendre g(n);
+    for (int i = 0; i < n; ++i) { x[i] = g.x[i]; w[i] = g.w[i]; }
+    return 0;
+}
+
 int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end) {
     return hmc_windows(n_warmup, max_win, start, end);
 }
@@ -769,26 +816,53 @@ double orc_rhat(int n_chain, int n, const double *x) {
     return std::sqrt(V / W);
 }
 
+void orc_hmc_prior_draw(const double *prior, uint64_t seed, uint32_t chain_id, double *x) {
+    // A skew-normal variate (App. C, Eq. SkewNormPrior) from two independent standard normals
+    // U0, U1 by the half-normal representation: Z = delta |U0| + sqrt(1 - delta^2) U1 with
+    // delta = s / sqrt(1 + s^2) is SN(0, 1, s), and x = xi + omega Z.  (U0, U1) of parameter p
+    // is the Box-Muller pair of uniforms 2p, 2p + 1 of the Philox blocks (blk, 0, chain id, 1),
+    // blk = 0..4.
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t w[20];
+    for (int blk = 0; blk < 5; ++blk) {
+        const uint32_t ctr[4] = {(uint32_t)blk, 0u, chain_id, 1u};
+        philox(ctr, key, w + 4 * blk);
+    }
+    for (int p = 0; p < NP; ++p) {
+        const double r = std::sqrt(-2.0 * std::log(u01(w[2 * p]))), a = 2.0 * PI * u01(w[2 * p + 1]);
+        const double u0 = r * std::cos(a), u1 = r * std::sin(a);
+        const double sk = prior[3 * p + 2], delta = sk / std::sqrt(1.0 + sk * sk);
+        x[p] = prior[3 * p] + prior[3 * p + 1] * (delta * std::fabs(u0) + std::sqrt(1.0 - delta * delta) * u1);
+    }
+}
+
 int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                 int n_z, double z_lo, double z_hi, const double *q, int sfh, const orc_hmc_cfg *cfg,
                 int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
                 const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
                 double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id,
-                double *inv_metric) {
+                double *inv_metric, double *trace_acc, double *state) {
     if (!cfg || cfg->n_chain < 1 || cfg->n_leapfrog < 1 || cfg->n_warmup < 0 || cfg->n_sample < 2) return 1;
-    if (!theta0 || n_gal < 0) return 1;
+    if (n_gal < 0) return 1;
     if (cfg->path != 0 && cfg->path != 1) return 1;
     if (!gauss_prec && (!check_common(s, f) || (cfg->path == 0 && !q) || !z || !obs || !sigma || !mask || !bounds ||
                         !prior))
         return 1;
     const int C = cfg->n_chain, L = cfg->n_leapfrog, NW = cfg->n_warmup, NS = cfg->n_sample;
     const int NIT = NW + NS;
+    // iterations [it0, it1) of this call; a run split over calls carries every chain's state in
+    // `state` ([chain][galaxy][ORC_HMC_STATE]) from one call to the next
+    const int it0 = cfg->it_begin, it1 = cfg->it_end > 0 ? cfg->it_end : NIT;
+    if (it0 < 0 || it1 > NIT || it0 >= it1 || ((it0 > 0 || it1 < NIT) && !state)) return 1;
+    if (it0 == 0 && !theta0 && !prior) return 1;
     const int nb = f ? f->n_band : 0;
     Model *X = gauss_prec ? nullptr : new Model(s, f, c, m);
-    // per (chain, galaxy) Welford statistics of the physical parameters
-    std::vector<double> cmean((size_t)C * n_gal * NP, 0.0), cm2((size_t)C * n_gal * NP, 0.0);
-    std::vector<int> cacc((size_t)C * n_gal, 0);
+    std::vector<double> local;
+    if (!state) {
+        local.assign((size_t)C * n_gal * ORC_HMC_STATE, 0.0);
+        state = local.data();
+    }
     const uint32_t key[2] = {(uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32)};
     // dual-averaging constants (Hoffman & Gelman 2014, step-size adaptation)
     const double gamma = 0.05, t0 = 10.0, kappa = 0.75, delta = cfg->target_accept;
@@ -817,23 +891,29 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             }
         };
         auto physical = [&](int p, double x) { return gauss_prec ? x : bound<double>(bounds + 4 * p, x); };
-        double x[NP], gr[NP], lp;
-        for (int p = 0; p < NP; ++p) x[p] = theta0[(size_t)cg * NP + p];
-        eval(x, &lp, gr);
-        double eps = cfg->init_step, mu = std::log(10.0 * cfg->init_step), hbar = 0.0, leps_bar = 0.0;
-        int da_start = 0;  // iteration at which dual averaging last (re)started
-        // diagonal inverse mass matrix M^-1 (identity unless adapted) and the
-        // Welford statistics of x inside the current slow window
-        double minv[NP], wmu[NP] = {0.0}, wm2[NP] = {0.0};
-        for (int k = 0; k < NP; ++k) minv[k] = 1.0;
-        // dense metric (adapt_metric = 2): M^-1 = Mi, Mi = Lc Lc^T, co-moments of the window
+        // the chain's state, unpacked from / packed into its ORC_HMC_STATE doubles (layout in the header)
+        double *S = state + (size_t)cg * ORC_HMC_STATE;
+        double *x = S + 0, *gr = S + 10, *minv = S + 30, *wmu = S + 40, *wm2 = S + 50, *mean = S + 60, *m2 = S + 70;
+        double(*Mi)[NP] = (double(*)[NP])(S + 100), (*Lc)[NP] = (double(*)[NP])(S + 200);
+        double(*wcm)[NP] = (double(*)[NP])(S + 300);
+        if (it0 == 0) {
+            std::fill(S, S + ORC_HMC_STATE, 0.0);
+            if (theta0) {
+                for (int p = 0; p < NP; ++p) x[p] = theta0[(size_t)cg * NP + p];
+            } else {
+                orc_hmc_prior_draw(prior, cfg->seed, chain_id, x);
+            }
+            eval(x, &S[20], gr);
+            S[21] = cfg->init_step;                       // eps
+            S[22] = std::log(10.0 * cfg->init_step);      // mu
+            // diagonal inverse mass matrix M^-1 (identity unless adapted); dense M^-1 = Lc Lc^T
+            for (int k = 0; k < NP; ++k) minv[k] = Mi[k][k] = Lc[k][k] = 1.0;
+        }
+        double lp = S[20], eps = S[21], mu = S[22], hbar = S[23], leps_bar = S[24];
+        int da_start = (int)S[25];   // iteration at which dual averaging last (re)started
+        int win = (int)S[26], n_rec = (int)S[27], n_acc = (int)S[28];
         const bool dense = cfg->adapt_metric == 2;
-        double Mi[NP][NP] = {{0.0}}, Lc[NP][NP] = {{0.0}}, wcm[NP][NP] = {{0.0}};
-        for (int k = 0; k < NP; ++k) Mi[k][k] = Lc[k][k] = 1.0;
-        int win = 0;
-        double *mean = &cmean[(size_t)cg * NP], *m2 = &cm2[(size_t)cg * NP];
-        int n_rec = 0, n_acc = 0;
-        for (int it = 0; it < NIT; ++it) {
+        for (int it = it0; it < it1; ++it) {
             uint32_t w[12];
             for (int blk = 0; blk < 3; ++blk) {
                 uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
@@ -855,13 +935,13 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                     p[k] = v / Lc[k][k];
                 }
             }
-            auto kinetic = [&](const double *q) {
+            auto kinetic = [&](const double *qv) {
                 double e = 0.0;
                 if (dense) {
                     for (int i = 0; i < NP; ++i)
-                        for (int j = 0; j < NP; ++j) e += 0.5 * q[i] * Mi[i][j] * q[j];
+                        for (int j = 0; j < NP; ++j) e += 0.5 * qv[i] * Mi[i][j] * qv[j];
                 } else {
-                    for (int k = 0; k < NP; ++k) e += 0.5 * minv[k] * q[k] * q[k];
+                    for (int k = 0; k < NP; ++k) e += 0.5 * minv[k] * qv[k] * qv[k];
                 }
                 return e;
             };
@@ -887,7 +967,14 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             double dH = H1 - H0;
             bool divergent = !std::isfinite(H1) || dH > 1000.0;
             double alpha = divergent ? 0.0 : std::min(1.0, std::exp(-dH));
-            bool acc = !divergent && std::log(u01(w[10])) < -dH;
+            const double log_u = std::log(u01(w[10]));
+            bool acc = !divergent && log_u < -dH;
+            if (trace_acc) {
+                double *t = trace_acc + (((size_t)it * C + ch) * n_gal + g) * 3;
+                t[0] = alpha;
+                t[1] = log_u + dH;   // accepted iff negative (and not divergent)
+                t[2] = eps;
+            }
             if (acc) {
                 for (int k = 0; k < NP; ++k) { x[k] = xn[k]; gr[k] = grn[k]; }
                 lp = lpn;
@@ -955,28 +1042,38 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             }
             if (trace_logp) trace_logp[((size_t)it * C + ch) * n_gal + g] = lp;
         }
+        S[20] = lp;
+        S[21] = eps;
+        S[22] = mu;
+        S[23] = hbar;
+        S[24] = leps_bar;
+        S[25] = da_start;
+        S[26] = win;
+        S[27] = n_rec;
+        S[28] = n_acc;
         if (inv_metric)
             for (int k = 0; k < NP; ++k) inv_metric[(size_t)cg * NP + k] = dense ? Mi[k][k] : minv[k];
-        cacc[cg] = n_acc;
         if (step) step[cg] = eps;
     }
+    delete X;
+    if (it1 < NIT) return 0;   // summaries once the run is complete
     for (int g = 0; g < n_gal; ++g) {
         int acc = 0;
-        for (int ch = 0; ch < C; ++ch) acc += cacc[(size_t)ch * n_gal + g];
+        for (int ch = 0; ch < C; ++ch) acc += (int)state[((size_t)ch * n_gal + g) * ORC_HMC_STATE + 28];
         if (accept) accept[g] = (double)acc / ((double)C * NS);
         for (int k = 0; k < NP; ++k) {
             double gm = 0.0, W = 0.0, B = 0.0, ss = 0.0;
+            auto cmean = [&](int ch) { return state[((size_t)ch * n_gal + g) * ORC_HMC_STATE + 60 + k]; };
+            auto cm2 = [&](int ch) { return state[((size_t)ch * n_gal + g) * ORC_HMC_STATE + 70 + k]; };
             for (int ch = 0; ch < C; ++ch) {
-                size_t o = ((size_t)ch * n_gal + g) * NP + k;
-                gm += cmean[o];
-                W += cm2[o] / (NS - 1);
+                gm += cmean(ch);
+                W += cm2(ch) / (NS - 1);
             }
             gm /= C;
             W /= C;
             for (int ch = 0; ch < C; ++ch) {
-                size_t o = ((size_t)ch * n_gal + g) * NP + k;
-                B += (cmean[o] - gm) * (cmean[o] - gm);
-                ss += cm2[o] + NS * (cmean[o] - gm) * (cmean[o] - gm);
+                B += (cmean(ch) - gm) * (cmean(ch) - gm);
+                ss += cm2(ch) + NS * (cmean(ch) - gm) * (cmean(ch) - gm);
             }
             double Bn = (C > 1) ? B / (C - 1) : 0.0;  // = B/n in the usual notation
             double V = (NS - 1.0) / NS * W + Bn;
@@ -985,7 +1082,6 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
             if (rhat) rhat[(size_t)g * NP + k] = (C > 1) ? std::sqrt(V / W) : NaN;
         }
     }
-    delete X;
     return 0;
 }
 

@@ -111,6 +111,9 @@ int orc_leapfrog(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
                  const double *sigma, uint8_t mask, const double *bounds, const double *prior,
                  const double *gauss_prec, int n_step, double eps, double *x, double *p, double *logp);
 
+/* ---- the n-point Gauss-Legendre rule on [-1, 1] (1 <= n <= 16), nodes increasing ---- */
+int orc_gauss_legendre(int n, double *x, double *w);
+
 /* ---- counter-based RNG (Philox4x32-10) ---- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -121,14 +124,27 @@ typedef struct {
     uint64_t seed;
     int adapt_metric;   /* 0: identity mass matrix; 1: diagonal, 2: dense, adapted in slow windows */
     int path;           /* photometry of the likelihood: 0 approximate (z table), 1 exact */
+    int it_begin, it_end;  /* iterations [it_begin, it_end) of this call (it_end 0 = to the end) */
 } orc_hmc_cfg;
+
+/* Per-chain state carried between the calls of a run split over several calls, ORC_HMC_STATE
+ * doubles per chain: [0,10) x, [10,20) grad log p, 20 log p, 21 step size, 22 mu, 23 Hbar,
+ * 24 log eps bar, 25 iteration at which dual averaging last restarted, 26 metric window index,
+ * 27 samples recorded, 28 samples accepted, [30,40) diagonal M^-1, [40,60) Welford mean and
+ * M2 of the current metric window, [60,80) Welford mean and M2 of the physical draws,
+ * [100,200) dense M^-1, [200,300) its Cholesky factor, [300,400) window co-moments. */
+#define ORC_HMC_STATE 400
+
+/* Starting point drawn from the skew-normal prior of every parameter (App. C): x[10]. */
+void orc_hmc_prior_draw(const double *prior, uint64_t seed, uint32_t chain_id, double *x);
 
 /* Slow adaptation windows of a warm-up of n_warmup iterations: window w covers
  * iterations [start[w], end[w]).  Returns the number of windows (0 if n_warmup < 20);
  * at most max_win are written. */
 int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end);
 
-/* theta0[c][g][10] unbounded start; outputs:
+/* theta0[c][g][10] unbounded start, or NULL: drawn from the prior (orc_hmc_prior_draw with the
+ * chain's Philox chain id); outputs:
  *   post_mean, post_sd, rhat [g][10] (physical parameters),
  *   accept [g] (fraction accepted in the sampling phase, all chains),
  *   step [c][g] (step size after warm-up),
@@ -139,7 +155,13 @@ int orc_hmc_windows(int n_warmup, int max_win, int *start, int *end);
  * then the physical map is the identity).
  * gal_id (may be NULL): global galaxy indices when these galaxies are a subset of a batch of
  * n_gal_total galaxies; the Philox chain id is then chain * n_gal_total + gal_id[g].
- * inv_metric [c][g][10] (may be NULL): diagonal of the inverse mass matrix after warm-up. */
+ * inv_metric [c][g][10] (may be NULL): diagonal of the inverse mass matrix after warm-up.
+ * trace_acc [n_warmup+n_sample][c][g][3] (may be NULL): per iteration the acceptance
+ * probability, log u + (H1 - H0) (the proposal is accepted iff this is negative and it did not
+ * diverge) and the step size the iteration used.
+ * state [c][g][ORC_HMC_STATE] (may be NULL unless the call covers part of the run): read at
+ * it_begin > 0, written at the end of every call.  Summaries are written by the call that ends
+ * the run. */
 int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                 int n_z, double z_lo, double z_hi, const double *q, int sfh,
                 const orc_hmc_cfg *cfg, int n_gal, const double *z, const double *obs,
@@ -147,7 +169,7 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 const double *theta0, const double *gauss_prec,
                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
                 double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id,
-                double *inv_metric);
+                double *inv_metric, double *trace_acc, double *state);
 
 /* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
 double orc_rhat(int n_chain, int n, const double *x);

@@ -63,3 +63,25 @@ def grad_tol(orc, sfh, th, z, sig, masks, m_gpu, path=0, rtol=1e-3):
 
 def grad_ok(g, ref, prop, rtol=1e-3):
     return np.abs(g - ref) <= rtol * np.abs(ref) + prop + 1e-6 * np.abs(ref).max(axis=1, keepdims=True)
+
+
+def general_bounds_prior(x_mid):
+    """Bounds with k != 1 and x0 != 0 and skew-normal priors with s != 0 (App. C).
+
+    x_mid [10]: typical unbounded values of the galaxies (for k = 1, x0 = 0); the prior of
+    parameter 9 is centred two widths below them with s = -4, so that s y < -5 and the
+    far-tail branch of log Phi is taken for most galaxies."""
+    k = np.array([0.5, 2.3, 1.0, 0.5, 2.3, 0.8, 1.7, 0.5, 2.3, 1.2])
+    x0 = np.array([-1.0, 0.7, 0.0, 0.7, -1.0, 0.3, -0.5, 0.7, -1.0, 0.2])
+    bnd = np.column_stack([synth.BOUNDS, k, x0])
+    s = np.array([2.5, -4.0, 0.0, 1.5, -2.0, 3.0, -1.0, 2.5, -4.0, -4.0])
+    om = np.array([1.5, 1.0, 2.0, 1.5, 1.0, 1.2, 1.5, 2.0, 1.0, 0.5])
+    xi = np.array([0.3, -0.2, 0.0, 0.5, -0.4, 0.1, 0.0, -0.3, 0.2, 0.0])
+    xi[9] = x_mid[9] - 2 * om[9]
+    pri = np.column_stack([xi, om, s])
+    return f32(bnd), f32(pri)
+
+
+def bound_jacobian(bnd, th):
+    """d theta / d x of the bounding map at theta: k (theta - lo)(hi - theta) / (hi - lo)."""
+    return bnd[:, 2] * (th - bnd[:, 0]) * (bnd[:, 1] - th) / (bnd[:, 1] - bnd[:, 0])

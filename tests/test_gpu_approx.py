@@ -5,7 +5,8 @@ import pytest
 import torch
 
 import synth
-from gpu_common import bounds_prior, dev, f32, gal_inputs, grad_close, grad_ok, grad_tol, grad_vec_ok, soa
+from gpu_common import (bound_jacobian, bounds_prior, dev, f32, gal_inputs, general_bounds_prior, grad_close, grad_ok,
+                        grad_tol, grad_vec_ok, soa)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +130,31 @@ def test_logpost_grad_matches_oracle(ctx, orc):
         assert abs(lp[g] - rl) < 1e-3 * max(1.0, abs(rl))
         ok = grad_ok(gr[g:g + 1], rg[None, :], prop[g:g + 1] * dth[g] * 1.01)
         assert ok.all(), (g, gr[g], rg, prop[g] * dth[g])
+
+
+@pytest.mark.parametrize("n", [40, 130])
+def test_logpost_grad_skewed_prior_general_bounds(ctx, orc, n):
+    # App. C with k != 1, x0 != 0 and s != 0: both branches of the skew-normal log prior
+    # (Phi directly, and the scaled complementary error function where s y < -5)
+    sfh, th, z = gal_inputs("dpl", n, 37 + n)
+    obs, sig, masks = _obs(orc, sfh, th, z, 8, synth.band_masks(n, 6, 3))
+    bnd1, _ = bounds_prior()
+    x_mid = np.median([[orc.unbound(bnd1[p], th[g, p]) for p in range(10)] for g in range(n)], axis=0)
+    bnd, pri = general_bounds_prior(x_mid)
+    x = f32(np.array([[orc.unbound(bnd[p], th[g, p]) for p in range(10)] for g in range(n)]))
+    assert np.all(np.isfinite(x))
+    y9 = (x[:, 9] - pri[9, 0]) / pri[9, 1]
+    assert np.sum(pri[9, 2] * y9 < -5) >= n // 4 and np.sum(pri[9, 2] * y9 > -5) >= 1
+    lp, gr = ctx.logpost_grad(sfh, soa(x), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri))
+    lp, gr = lp.cpu().numpy(), gr.cpu().numpy().T.astype(np.float64)
+    thx = np.array([[orc.bound(bnd[p], x[g, p]) for p in range(10)] for g in range(n)])
+    m_gpu = ctx.phot_approx(sfh, soa(f32(thx)), dev(z)).cpu().numpy()
+    prop, _ = grad_tol(orc, sfh, thx, z, sig, masks, m_gpu)
+    for g in range(n):
+        rl, rg = orc.logpost_grad(sfh, x[g], z[g], obs[g], sig[g], masks[g], bnd, pri)
+        assert abs(lp[g] - rl) < 1e-3 * max(1.0, abs(rl)), (g, lp[g], rl)
+        ok = grad_ok(gr[g:g + 1], rg[None, :], prop[g:g + 1] * bound_jacobian(bnd, thx[g]) * 1.01)
+        assert ok.all(), (g, gr[g], rg)
 
 
 def test_deterministic_across_runs(ctx, orc):

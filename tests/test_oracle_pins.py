@@ -111,10 +111,11 @@ def test_dpl_bin_mass_hypergeometric_closed_form(orc, ssp2000, tau, alpha, beta,
     ref = _dpl_cumulative(t_obs - lo, tau, alpha, beta) - _dpl_cumulative(t_obs - hi, tau, alpha, beta)
     m = orc.smooth_bin_mass(synth.SFH_DPL, th, z)
     live = hi > lo
-    # the closed-form reference is a difference of two cumulatives: its own rounding is
-    # a few ulp of the total mass formed, which bounds the absolute tolerance
+    # the closed-form reference is a difference of two cumulatives, each a scipy hyp2f1 value
+    # good to about 1e-15 relative: its error is a few 1e-15 of the total mass formed, which
+    # bounds the absolute tolerance
     scale = _dpl_cumulative(t_obs, tau, alpha, beta)
-    np.testing.assert_allclose(m[live], ref[live], rtol=1e-10, atol=8e-16 * scale)
+    np.testing.assert_allclose(m[live], ref[live], rtol=1e-10, atol=4e-15 * scale)
     assert np.all(m[~live] == 0)
 
 
@@ -442,6 +443,67 @@ def test_bounding_roundtrip_and_jacobian(oracle_mod):
             assert d == pytest.approx((th - lo) * (hi - th) / (hi - lo), rel=1e-6)
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 10, 16])
+def test_gauss_legendre_rule_matches_numpy(oracle_mod, n):
+    # the quadrature rule behind the oracle's adaptive integrals: numpy's leggauss, and exact
+    # integrals of x^k, k < 2n, on [-1, 1]
+    x, w = oracle_mod.gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(x, xr, atol=2e-16)
+    np.testing.assert_allclose(w, wr, rtol=1e-14)   # numpy's own weights are good to ~1e-15
+    for k in range(2 * n):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert np.sum(w * x ** k) == pytest.approx(exact, abs=2e-15)
+
+
+@pytest.mark.parametrize("k,x0", [(0.5, -1.0), (2.3, 0.7), (0.5, 0.7), (2.3, -1.0)])
+def test_bounding_function_general_slope_and_centre(oracle_mod, k, x0):
+    # App. C, Eq. BoundingFunction with k != 1 and x0 != 0.  Properties of a logistic map
+    # from (-inf, inf) onto (y_lo, y_hi), none of them the formula itself:
+    #   the midpoint of the range sits at x0; the map is point-symmetric about it;
+    #   its slope there is k (y_hi - y_lo) / 4; it is monotone and tends to the bounds;
+    #   its derivative is k (theta - y_lo)(y_hi - theta) / (y_hi - y_lo) (logistic ODE);
+    #   unbound inverts it
+    O = oracle_mod.Oracle
+    for lo, hi in synth.BOUNDS:
+        b = np.array([lo, hi, k, x0])
+        assert O.bound(b, x0) == pytest.approx(0.5 * (lo + hi), abs=1e-12 * max(1.0, abs(hi)))
+        for d in (0.1, 1.3, 4.0):
+            assert O.bound(b, x0 + d) + O.bound(b, x0 - d) == pytest.approx(lo + hi, abs=1e-12 * max(1.0, abs(hi)))
+        h = 1e-5
+        slope = (O.bound(b, x0 + h) - O.bound(b, x0 - h)) / (2 * h)
+        assert slope == pytest.approx(k * (hi - lo) / 4, rel=1e-8)
+        xs = np.linspace(x0 - 30 / k, x0 + 30 / k, 61)
+        th = np.array([O.bound(b, x) for x in xs])
+        assert np.all(np.diff(th) >= 0) and th[0] - lo < 1e-9 * (hi - lo) and hi - th[-1] < 1e-9 * (hi - lo)
+        for x in (x0 - 3.0 / k, x0 - 0.4, x0 + 0.9, x0 + 5.0 / k):
+            t = O.bound(b, x)
+            d = (O.bound(b, x + 1e-6) - O.bound(b, x - 1e-6)) / 2e-6
+            assert d == pytest.approx(k * (t - lo) * (hi - t) / (hi - lo), rel=1e-6)
+            assert O.unbound(b, t) == pytest.approx(x, abs=1e-8)
+
+
+def test_prior_draws_follow_the_skew_normal(oracle_mod):
+    # starting points drawn from the prior (App. C, Eq. SkewNormPrior) for 20,000 chain ids:
+    # the skew-normal's closed-form mean xi + omega delta sqrt(2/pi) and variance
+    # omega^2 (1 - 2 delta^2 / pi), delta = s / sqrt(1 + s^2), and a Kolmogorov-Smirnov test
+    # against scipy's skew-normal CDF
+    pri = np.array([[0.0, 1.5, 0.0], [0.3, 0.7, 2.5], [-1.2, 2.0, -4.0], [2.0, 0.5, 8.0], [0.0, 1.0, -0.5],
+                    [1.0, 0.2, 0.0], [0.0, 3.0, 1.0], [-2.0, 1.0, 3.0], [0.5, 0.5, -2.0], [0.0, 1.0, 0.0]])
+    n = 20000
+    x = np.array([oracle_mod.hmc_prior_draw(pri, 404, c) for c in range(n)])
+    for p in range(10):
+        xi, om, sk = pri[p]
+        de = sk / math.sqrt(1 + sk * sk)
+        mean, var = xi + om * de * math.sqrt(2 / math.pi), om * om * (1 - 2 * de * de / math.pi)
+        assert abs(x[:, p].mean() - mean) < 4.5 * math.sqrt(var / n)
+        assert abs(x[:, p].var() / var - 1) < 0.05
+        assert stats.kstest(x[:, p], lambda v: stats.skewnorm.cdf(v, sk, loc=xi, scale=om)).pvalue > 1e-3
+    # different seeds give different draws; the same seed and chain id the same draw
+    assert not np.array_equal(oracle_mod.hmc_prior_draw(pri, 405, 7), x[7])
+    assert np.array_equal(oracle_mod.hmc_prior_draw(pri, 404, 7), x[7])
+
+
 def test_skew_normal_prior_matches_library(oracle_mod):
     O = oracle_mod.Oracle
     for xi, om, s in ((0.0, 1.0, 0.0), (0.3, 0.7, 2.5), (-1.2, 2.0, -4.0)):
@@ -540,6 +602,64 @@ def test_hmc_tiny_step_accepts_everything_and_is_deterministic(orc):
     a = orc.hmc_run(1, None, None, None, None, None, None, th0, **kw)
     b = orc.hmc_run(1, None, None, None, None, None, None, th0, **kw)
     assert np.all(a["accept"] == 1.0)
+    assert np.array_equal(a["samples"], b["samples"])
+
+
+@pytest.mark.parametrize("adapt", [False, "diag", "dense"])
+def test_hmc_split_run_reproduces_the_uninterrupted_run(orc, adapt):
+    # a run split over three calls (the state carried in between) draws exactly what one call
+    # draws: every sample, step size, metric and summary bit for bit; the cuts fall inside the
+    # warm-up, on a metric-window boundary and inside the sampling phase
+    rng = np.random.default_rng(17)
+    a = rng.normal(size=(10, 10))
+    prec = a @ a.T / 10 + np.eye(10)
+    th0 = rng.normal(size=(2, 3, 10))
+    kw = dict(n_chain=2, n_leapfrog=3, n_warmup=100, n_sample=60, seed=21, gauss_prec=prec, adapt_metric=adapt)
+    whole = orc.hmc_run(1, None, None, None, None, None, None, th0, keep_samples=True, **kw)
+    import oracle
+    state = np.zeros((2, 3, oracle.HMC_STATE))
+    smp = np.zeros((60, 2, 3, 10))
+    for b, e in ((0, 37), (37, 90), (90, 130), (130, 160)):
+        part = orc.hmc_run(1, None, None, None, None, None, None, th0, it_begin=b, it_end=e, state=state,
+                           samples=smp, **kw)
+    assert oracle.hmc_windows(100) == [(15, 90)]
+    assert np.array_equal(smp, whole["samples"])
+    for key in ("post_mean", "post_sd", "rhat", "accept", "step", "inv_metric"):
+        assert np.array_equal(part[key], whole[key]), key
+
+
+def test_hmc_split_run_on_the_sps_posterior(orc_small):
+    sfh, th, z = 1, *synth.galaxies_dpl(2, 61)
+    obs = orc_small.phot_approx(sfh, th, z) + 0.02
+    sig = np.full_like(obs, 0.05)
+    masks = np.array([63, 45], np.uint8)
+    bnd = np.column_stack([synth.BOUNDS, np.full(10, 1.3), np.full(10, -0.2)])
+    pri = np.column_stack([np.zeros(10), np.full(10, 1.5), np.linspace(-3, 3, 10)])
+    kw = dict(n_chain=2, n_leapfrog=4, n_warmup=6, n_sample=4, init_step=0.02, seed=8)
+    whole = orc_small.hmc_run(sfh, z, obs, sig, masks, bnd, pri, None, keep_samples=True, **kw)
+    import oracle
+    state = np.zeros((2, 2, oracle.HMC_STATE))
+    smp = np.zeros((4, 2, 2, 10))
+    orc_small.hmc_run(sfh, z, obs, sig, masks, bnd, pri, None, it_begin=0, it_end=5, state=state, samples=smp, **kw)
+    last = orc_small.hmc_run(sfh, z, obs, sig, masks, bnd, pri, None, it_begin=5, it_end=10, state=state,
+                             samples=smp, **kw)
+    assert np.array_equal(smp, whole["samples"])
+    assert np.array_equal(last["post_mean"], whole["post_mean"])
+    assert np.all(np.isfinite(smp))
+
+
+def test_hmc_start_from_the_prior(orc):
+    # theta0 = None draws every chain's start from the prior with its Philox chain id
+    # (chain * n_gal + galaxy): the same run as one given those draws explicitly
+    import oracle
+    rng = np.random.default_rng(2)
+    prec = np.diag(rng.uniform(0.5, 2.0, 10))
+    pri = np.column_stack([rng.normal(size=10), rng.uniform(0.5, 2, 10), rng.uniform(-3, 3, 10)])
+    n_gal, C = 3, 2
+    x0 = np.array([[oracle.hmc_prior_draw(pri, 77, c * n_gal + g) for g in range(n_gal)] for c in range(C)])
+    kw = dict(n_chain=C, n_leapfrog=2, n_warmup=5, n_sample=5, seed=77, gauss_prec=prec, keep_samples=True)
+    a = orc.hmc_run(1, np.zeros(n_gal), None, None, None, None, pri, None, **kw)
+    b = orc.hmc_run(1, np.zeros(n_gal), None, None, None, None, pri, x0, **kw)
     assert np.array_equal(a["samples"], b["samples"])
 
 
