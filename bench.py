@@ -120,7 +120,7 @@ def bench_exact(dev, n=4096, steps=5, warmup=2):
     import synth
     log(f"[bench] exact path: {n} galaxies x 5000 wavelengths")
     ssp, filt = synth.ssp_grid(5000), synth.filters()
-    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=n)
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=n, max_exact=n)
     th, z = synth.galaxies_dpl(n, 105)
     params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
     zt = torch.as_tensor(z.astype(np.float32)).to(dev)
@@ -213,7 +213,7 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
     import synth
     log(f"[bench] exact-path HMC: {n} galaxies x {C} chains, {n_iter} iterations x {L} leapfrog steps")
     ssp, filt = synth.ssp_grid(2000), synth.filters()
-    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C)
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C, max_exact=n * C)
     ctx.build_ztable(64, 0.1, 3.0)   # with a z table the chains are ranked by z (narrow GEMM tiles)
     th, z = synth.galaxies_dpl(n, 104)
     params = torch.as_tensor(np.ascontiguousarray(th.T.astype(np.float32))).to(dev)
@@ -269,7 +269,7 @@ def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0)):
                        "|m_approx - m_exact| per galaxy and band, FP32 exact path", "unit": "mag"}
     for sig in sigmas:
         filt = synth.filters(sigma=sig)
-        ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32,), max_gal=n)
+        ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32,), max_gal=n, max_exact=n)
         ctx.build_ztable(64, 0.1, 3.0)
         d = (ctx.phot_approx(synth.SFH_DPL, params, zt)
              - ctx.phot_exact(synth.SFH_DPL, params, zt, prec=sps.SPS_F32)).abs().cpu().numpy()
@@ -293,7 +293,7 @@ def bench_posterior_agreement(dev, n=1024, C=4, L=10, n_warm=200, n_samp=1000):
     import synth
     log(f"[bench] approximate vs exact posteriors: {n} galaxies x {C} chains, {n_warm} + {n_samp} iterations")
     ssp, filt = synth.ssp_grid(2000), synth.filters()
-    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C)
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n * C, max_exact=n * C)
     ctx.build_ztable(64, 0.1, 3.0)
     th, z = synth.galaxies_dpl(16_384, 104)
     th, z = th[:n], z[:n]

@@ -31,7 +31,13 @@
  *    thread-local message.  Invalid sizes, enums or NULL required pointers are
  *    errors.  NaN parameters propagate to NaN outputs and are not errors.  A
  *    redshift outside the context's z table gives NaN outputs for that galaxy
- *    on the approximate path (no host synchronisation is made to report it).
+ *    on the approximate path and sets a device-side flag that the next
+ *    sps_status call reports as SPS_E_RANGE (the compute call itself does not
+ *    synchronise to find out).
+ *  - Compute calls never allocate device memory: the context's workspaces are
+ *    sized by sps_create / sps_reserve (approximate path, HMC chain state) and
+ *    sps_reserve_exact (exact path); a call larger than they allow returns
+ *    SPS_E_STATE (or SPS_E_INVAL for n_gal above the reserved galaxy count).
  *  - Calls on one context from several host threads must be serialised by the
  *    caller; work enqueued on different streams must not overlap in time when
  *    it uses the context's internal workspace (all compute calls do).
@@ -92,8 +98,25 @@ typedef struct sps_ctx sps_ctx;
 int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_filter_desc *filters,
                const sps_model_desc *model, unsigned prec_mask, int max_gal);
 
-/* Grow the per-galaxy workspace to max_gal galaxies (synchronises the device). */
+/* Grow the per-galaxy workspace to max_gal galaxies: the approximate path's records
+ * (196 B per galaxy) and the approximate-path HMC's chain state for max_gal chain slots
+ * (n_gal * n_chain; about 470 B per slot with its trajectory scratch).  Synchronises the
+ * device; never shrinks. */
 int sps_reserve(sps_ctx *ctx, int max_gal);
+
+/* Size the exact path's workspace for calls of up to max_rows galaxies (or exact-path HMC
+ * chains, n_gal * n_chain), for every precision uploaded at create, with the gradient:
+ * the weights rows, partial band sums, Rbar and Wbar of the two GEMMs (about 34 KB per
+ * row at 2000 wavelengths and 50 KB at 5000), the z-order buffer from 16,384 rows on, and
+ * the exact-path HMC's chain state (~0.6 KB per chain).  Also grows
+ * sps_reserve's galaxy count to max_rows.  Synchronises the device; never shrinks. */
+int sps_reserve_exact(sps_ctx *ctx, int max_rows);
+
+/* Synchronises the device, then reports and clears the device-side error flags raised by
+ * compute calls since the last sps_status: SPS_E_STATE if an HMC resume blob did not match
+ * its run, else SPS_E_RANGE if a redshift outside the z table reached the approximate
+ * path, else SPS_OK. */
+int sps_status(sps_ctx *ctx);
 
 /* Build the SSP x band flux table c_SSP(z) on n_z uniform nodes in [z_lo, z_hi]
  * (Sec. 3, the precomputed c_SSP lookup table after Eq. photo_integral_approx).  Stored distance-free
@@ -140,8 +163,8 @@ int sps_phot_approx(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float 
  * uploaded at create.  The FP32 / BF16X paths skip wavelengths farther than 8 filter
  * sigmas from every band for all galaxies of a 128-galaxy tile (their contribution is below
  * exp(-32) of the band's), and from 16,384 galaxies on they process the galaxies in z order
- * internally (outputs are still in the caller's order); both grow the context's workspace
- * (device memory) on first use at a size. */
+ * internally (outputs are still in the caller's order).  n_gal <= the rows reserved by
+ * sps_reserve_exact, else SPS_E_STATE. */
 int sps_phot_exact(sps_ctx *ctx, void *stream, int n_gal, int sfh, int prec, const void *params,
                    const void *z, void *mag_out);
 
@@ -166,7 +189,9 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
  * steps per iteration, per-chain step size adapted by dual averaging over n_warmup
  * iterations, then n_sample recorded iterations; momentum and accept draws from
  * Philox4x32-10 keyed by seed with counter (draw block, iteration, chain id =
- * c * n_gal + g, 0).  Hamiltonian and accept test in FP64.
+ * c * n_gal + g, 0).  Hamiltonian and accept test in FP64.  Starting points: theta0, or
+ * if theta0 is NULL a draw from the skew-normal prior of each parameter (App. C, Eq.
+ * SkewNormPrior; half-normal representation, Philox counter (block 0..4, 0, chain id, 1)).
  * Mass matrix: identity if adapt_metric = 0.  If adapt_metric = 1 (and n_warmup >= 20),
  * a per-chain diagonal M is adapted in slow warm-up windows (fast buffer of 75
  * iterations, windows of 25, 50, 100, ... with the last stretched to the end of the
@@ -176,7 +201,7 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
  * the current step size.  The paper's warm-up tunes its sampler's parameters without
  * stating the scheme; this is the windowed scheme of the Stan manual.
  * All device pointers:
- *   theta0 [n_chain][10][n_gal] unbounded starting points (required),
+ *   theta0 [n_chain][10][n_gal] unbounded starting points, or NULL (prior draws),
  *   samples [n_sample][n_chain][10][n_gal] physical draws or NULL,
  *   post_mean, post_sd, rhat [10][n_gal] (physical parameters, pooled chains),
  *   accept [n_gal] acceptance fraction in the sampling phase,
@@ -188,23 +213,40 @@ int sps_logpost_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float
  * SPS_F32 or SPS_BF16X, whose table must have been uploaded; every leapfrog step is one
  * exact value+gradient call over all n_gal * n_chain chains).  prec is ignored on the
  * approximate path.  Both paths draw the same Philox streams.
- * Needs n_gal * n_chain <= the reserved galaxy count; grows the context's chain-state
- * workspace (device memory, ~470 B per chain with its trajectory scratch; for SPS_PATH_EXACT
- * ~540 B plus the exact path's own workspace) on first use.  The exact path ranks the chains
- * by z internally (on the z table's buckets if one was built, else on a fixed grid). */
+ * Needs n_gal * n_chain <= the galaxy count reserved by sps_reserve (and, for
+ * SPS_PATH_EXACT, <= the rows reserved by sps_reserve_exact).  The exact path ranks the
+ * chains by z internally (on the z table's buckets if one was built, else on a fixed grid).
+ *
+ * Splitting a run over calls (checkpoint / resume, Sec. 4's long runs): cfg.it_begin and
+ * cfg.it_end select the iterations [it_begin, it_end) of the n_warmup + n_sample that this
+ * call runs (it_end = 0: to the end).  state_inout (device memory of
+ * sps_hmc_state_bytes(n_gal, n_chain) bytes, owned by the caller) then carries every
+ * chain's state between the calls: a call with it_begin = 0 starts the chains (theta0 or
+ * prior draws) and one with it_begin > 0 continues from the state the previous call wrote
+ * (its header must name the same n_gal, n_chain, n_warmup, n_sample, adapt_metric, seed,
+ * n_leapfrog and it_begin iterations done, else sps_status reports SPS_E_STATE); every call
+ * writes the state back.  The draws are those of the uninterrupted run, to the bit, for
+ * either photometry path (the blob is the same for both).  samples are written for the
+ * sampling iterations this call runs; the summaries (post_mean .. inv_metric, required
+ * then) by the call that ends the run.  state_inout may be NULL for a whole run. */
 typedef struct {
     int n_chain, n_leapfrog, n_warmup, n_sample;
     float target_accept, init_step;
     unsigned long long seed;
     int adapt_metric;
     int path, prec;
+    int it_begin, it_end;
 } sps_hmc_cfg;
 
 int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh,
                 const float *z, const float *obs, const float *sigma, const uint8_t *band_mask,
                 const float *bounds, const float *prior, const float *theta0, float *samples,
                 float *post_mean, float *post_sd, float *rhat, float *accept, float *step,
-                float *inv_metric);
+                float *inv_metric, void *state_inout);
+
+/* Bytes of an sps_hmc_run resume blob for n_gal galaxies x n_chain chains (0 if invalid):
+ * a 256-byte header and 312 bytes per chain. */
+size_t sps_hmc_state_bytes(int n_gal, int n_chain);
 
 #ifdef __cplusplus
 }

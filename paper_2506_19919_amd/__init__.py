@@ -24,10 +24,10 @@ SPS_PATH_APPROX, SPS_PATH_EXACT = 0, 1
 NPARAM = 10
 MAX_BAND = 8
 
-ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_build_ztable", "sps_get_ztable", "sps_destroy",
-                 "sps_last_error", "sps_weights", "sps_phot_approx", "sps_phot_exact",
-                 "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_set_kernel_timing",
-                 "sps_kernel_times")
+ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_reserve_exact", "sps_status", "sps_build_ztable",
+                 "sps_get_ztable", "sps_destroy", "sps_last_error", "sps_weights", "sps_phot_approx",
+                 "sps_phot_exact", "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_hmc_state_bytes",
+                 "sps_set_kernel_timing", "sps_kernel_times")
 
 
 class SpsError(RuntimeError):
@@ -55,7 +55,8 @@ class _ModelDesc(C.Structure):
 class _HmcCfg(C.Structure):
     _fields_ = [("n_chain", C.c_int), ("n_leapfrog", C.c_int), ("n_warmup", C.c_int),
                 ("n_sample", C.c_int), ("target_accept", C.c_float), ("init_step", C.c_float),
-                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int), ("path", C.c_int), ("prec", C.c_int)]
+                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int), ("path", C.c_int), ("prec", C.c_int),
+                ("it_begin", C.c_int), ("it_end", C.c_int)]
 
 
 def _load():
@@ -68,6 +69,10 @@ def _load():
     lib.sps_create.argtypes = [C.POINTER(vp), i, C.POINTER(_SspDesc), C.POINTER(_FilterDesc),
                                C.POINTER(_ModelDesc), C.c_uint, i]
     lib.sps_reserve.argtypes = [vp, i]
+    lib.sps_reserve_exact.argtypes = [vp, i]
+    lib.sps_status.argtypes = [vp]
+    lib.sps_hmc_state_bytes.argtypes = [i, i]
+    lib.sps_hmc_state_bytes.restype = C.c_size_t
     lib.sps_build_ztable.argtypes = [vp, i, C.c_double, C.c_double]
     lib.sps_get_ztable.argtypes = [vp, vp]
     lib.sps_destroy.argtypes = [vp]
@@ -78,11 +83,11 @@ def _load():
     lib.sps_loglike_grad.argtypes = [vp, vp, i, i, i, i, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_logpost_grad.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_hmc_run.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp, vp]
+                                vp, vp, vp, vp, vp, vp, vp]
     lib.sps_set_kernel_timing.argtypes = [vp, i]
     lib.sps_kernel_times.argtypes = [vp, vp, i, C.POINTER(i)]
     for name in ABI_FUNCTIONS:
-        if name not in ("sps_destroy", "sps_last_error"):
+        if name not in ("sps_destroy", "sps_last_error", "sps_hmc_state_bytes"):
             getattr(lib, name).restype = C.c_int
     return lib
 
@@ -127,7 +132,7 @@ class Context:
     """One library context: SSP grid, filters and model constants on one GPU."""
 
     def __init__(self, ssp: dict, filters: dict, model: dict | None = None, device: int = 0,
-                 precisions=(SPS_F64, SPS_F32), max_gal: int = 1 << 20):
+                 precisions=(SPS_F64, SPS_F32), max_gal: int = 1 << 20, max_exact: int = 0):
         m = dict(H0=70.0, Om=0.3, sigma_logz=0.2, burst_dlogt=0.3)
         m.update(model or {})
         self._keep = [np.ascontiguousarray(ssp[k], dtype=np.float64)
@@ -147,7 +152,10 @@ class Context:
         self.device = torch.device("cuda", device)
         self.n_met, self.n_age, self.n_wave, self.n_band = len(met), len(age), len(wave), len(cen)
         self.max_gal = max_gal
+        self.max_exact = 0
         self.ztable_spec = None
+        if max_exact:
+            self.reserve_exact(max_exact)
 
     def close(self):
         if getattr(self, "h", None):
@@ -164,6 +172,17 @@ class Context:
     def reserve(self, max_gal: int):
         _check(_lib.sps_reserve(self.h, max_gal))
         self.max_gal = max(self.max_gal, max_gal)
+
+    def reserve_exact(self, max_rows: int):
+        """Size the exact path's workspace for calls of up to max_rows galaxies (or HMC chains)."""
+        _check(_lib.sps_reserve_exact(self.h, max_rows))
+        self.max_exact = max(self.max_exact, max_rows)
+        self.max_gal = max(self.max_gal, max_rows)
+
+    def status(self):
+        """Synchronise and raise SpsError for device-side errors flagged since the last check
+        (SPS_E_RANGE: a redshift outside the z table; SPS_E_STATE: a mismatched resume blob)."""
+        _check(_lib.sps_status(self.h))
 
     def build_ztable(self, n_z: int = 64, z_lo: float = 0.1, z_hi: float = 3.0):
         _check(_lib.sps_build_ztable(self.h, n_z, C.c_double(z_lo), C.c_double(z_hi)))
@@ -251,9 +270,18 @@ class Context:
                                      _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(lp), _ptr(g)))
         return lp, g
 
+    def hmc_state(self, n_gal, n_chain):
+        """A device buffer for hmc_run's resume state (zero-filled)."""
+        nbytes = _lib.sps_hmc_state_bytes(n_gal, n_chain)
+        return torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
+
     def hmc_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
-                keep_samples=False, adapt_metric=False, path=SPS_PATH_APPROX, prec=SPS_F32, stream=None):
+                keep_samples=False, adapt_metric=False, path=SPS_PATH_APPROX, prec=SPS_F32, stream=None,
+                it_begin=0, it_end=0, state=None, samples=None):
+        """theta0 [chain][10][galaxy] or None (prior draws).  A run split over calls passes
+        it_begin / it_end, the same `state` (hmc_state) and, to collect every draw, the same
+        `samples` tensor to each call; the summaries come from the call that ends the run."""
         n = z.shape[0]
         _dev(z, torch.float32, (n,), "z", self.device)
         _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
@@ -261,21 +289,27 @@ class Context:
         _dev(mask, torch.uint8, (n,), "band_mask", self.device)
         _dev(bounds, torch.float32, (NPARAM, 4), "bounds", self.device)
         _dev(prior, torch.float32, (NPARAM, 3), "prior", self.device)
-        _dev(theta0, torch.float32, (n_chain, NPARAM, n), "theta0", self.device)
+        if theta0 is not None:
+            _dev(theta0, torch.float32, (n_chain, NPARAM, n), "theta0", self.device)
+        if state is not None:
+            _dev(state, torch.uint8, (_lib.sps_hmc_state_bytes(n, n_chain),), "state", self.device)
         f32 = dict(dtype=torch.float32, device=self.device)
         out = dict(post_mean=torch.empty((NPARAM, n), **f32), post_sd=torch.empty((NPARAM, n), **f32),
                    rhat=torch.empty((NPARAM, n), **f32), accept=torch.empty(n, **f32),
                    step=torch.empty((n_chain, n), **f32),
                    inv_metric=torch.empty((n_chain, NPARAM, n), **f32))
-        samples = torch.empty((n_sample, n_chain, NPARAM, n), **f32) if keep_samples else None
+        if samples is not None:
+            _dev(samples, torch.float32, (n_sample, n_chain, NPARAM, n), "samples", self.device)
+        elif keep_samples:
+            samples = torch.empty((n_sample, n_chain, NPARAM, n), **f32)
         cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
-                      int(bool(adapt_metric)), int(path), int(prec))
+                      int(bool(adapt_metric)), int(path), int(prec), int(it_begin), int(it_end))
         _check(_lib.sps_hmc_run(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs),
                                 _ptr(sigma), _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0),
                                 _ptr(samples), _ptr(out["post_mean"]), _ptr(out["post_sd"]),
                                 _ptr(out["rhat"]), _ptr(out["accept"]), _ptr(out["step"]),
-                                _ptr(out["inv_metric"])))
-        if keep_samples:
+                                _ptr(out["inv_metric"]), _ptr(state)))
+        if samples is not None:
             out["samples"] = samples
         return out
 

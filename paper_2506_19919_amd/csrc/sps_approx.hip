@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restr
 // each block reserves a range per bucket in the global cursor, then places its galaxies
 // (the order only: k_bucket_gather places them with their input records)
 __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
-                                                              int *__restrict__ cursor, int *__restrict__ perm) {
+                                                              int *__restrict__ cursor, int *__restrict__ perm,
+                                                              int *__restrict__ status) {
     extern __shared__ int sh[];
     const int nbk = k.n_z;
     int *cnt = sh, *pos = sh + nbk;
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int 
             const int kk = z_bucket(k, z[i], &f);
             kk_t[t] = kk < 0 ? nbk - 1 : kk;
             atomicAdd(&cnt[kk_t[t]], 1);
+            if (kk < 0 && status) atomicOr(status, STATUS_Z_RANGE);
         }
     }
     __syncthreads();
@@ -147,6 +149,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_gather(DevConsts k, int n
             const int kk = z_bucket(k, z[i], &f);
             bk[u] = kk < 0 ? nbk - 1 : kk;
             lr[u] = atomicAdd(&cnt[bk[u]], 1);
+            if (kk < 0 && ga.status) atomicOr(ga.status, STATUS_Z_RANGE);
         }
     }
     __syncthreads();
@@ -336,34 +339,41 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga,
-                       const DevConsts *grid) {
+int launch_bucket_sort_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, const float *z, const GatherArgs *ga,
+                          const DevConsts *grid) {
     const DevConsts &kb = grid ? *grid : c->k;   // bucket grid
     const int nbk = kb.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
-    int *hist = c->d_hist, *cursor = c->d_hist + 1025;
+    int *hist = ws.hist, *cursor = ws.hist + 1025;
     hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
     const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
     hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, kb, n, z, hist);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
     if (ga && ga->rec) {
         hipLaunchKernelGGL(k_bucket_gather, dim3((n + GATHER_TILE - 1) / GATHER_TILE), dim3(SORT_BLOCK),
-                           gather_lds_bytes(nbk), s, c->k, n, z, cursor, c->d_perm, *ga);
+                           gather_lds_bytes(nbk), s, c->k, n, z, cursor, ws.perm, *ga);
     } else {
         hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, kb, n, z, cursor,
-                           c->d_perm);
+                           ws.perm, grid ? nullptr : c->d_status);
     }
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }
 
-int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const float *params, const float *z,
-                  const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
-                  const float *prior, float *out_mag, float *out_val, float *out_grad) {
+ApproxWs ctx_ws(sps_ctx *c) { return ApproxWs{c->d_perm, c->d_inv, c->d_hist, c->d_rec, c->d_orec}; }
+
+int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga,
+                       const DevConsts *grid) {
+    return launch_bucket_sort_ws(c, s, ctx_ws(c), n, z, ga, grid);
+}
+
+int launch_approx_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, int sfh, int mode, const float *params,
+                     const float *z, const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+                     const float *prior, float *out_mag, float *out_val, float *out_grad) {
     const GatherArgs ga{params, mode == MODE_MAGS ? nullptr : obs, mode == MODE_MAGS ? nullptr : sigma,
-                        mode == MODE_MAGS ? nullptr : mask, c->d_rec, c->d_inv};
-    int rc = launch_bucket_sort(c, s, n, z, &ga);
+                        mode == MODE_MAGS ? nullptr : mask, ws.rec, ws.inv, c->d_status};
+    int rc = launch_bucket_sort_ws(c, s, ws, n, z, &ga, nullptr);
     if (rc) return rc;
-    ApproxArgs a{n, sfh, mode, c->d_rec, bounds, prior, c->d_qf, c->d_qa, c->d_orec};
+    ApproxArgs a{n, sfh, mode, ws.rec, bounds, prior, c->d_qf, c->d_qa, ws.orec};
     const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE), ug((n + 255) / 256), ub(256);
     const int nb = c->n_band;
     const size_t lds_bytes = approx_lds_bytes(nb, true);
@@ -373,34 +383,41 @@ int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const flo
             if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, lds_bytes, s, c->k, a);
             if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
+            hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL:
             if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, lds_bytes, s, c->k, a);
             if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag, out_val,
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag, out_val,
                                out_grad);
             break;
         case MODE_LOGL_GRAD:
             if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, lds_bytes, s, c->k, a);
             if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
                                out_val, out_grad);
             break;
         case MODE_LOGPOST_GRAD:
             if (tev) (void)hipEventRecord(tev[0], s);
             hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, lds_bytes, s, c->k, a);
             if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, c->d_inv, c->d_orec, out_mag,
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
                                out_val, out_grad);
             break;
         default: return set_error(SPS_E_INVAL, "bad approx mode");
     }
     SPS_HIP(hipGetLastError());
     return SPS_OK;
+}
+
+int launch_approx(sps_ctx *c, hipStream_t s, int n, int sfh, int mode, const float *params, const float *z,
+                  const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+                  const float *prior, float *out_mag, float *out_val, float *out_grad) {
+    return launch_approx_ws(c, s, ctx_ws(c), n, sfh, mode, params, z, obs, sigma, mask, bounds, prior, out_mag,
+                            out_val, out_grad);
 }
 
 int launch_weights(sps_ctx *c, hipStream_t s, int n, int sfh, const float *params, const float *z, float *w) {

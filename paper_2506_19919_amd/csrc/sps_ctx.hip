@@ -223,6 +223,8 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_rec);
     (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hist);
+    (void)hipFree(c->d_status);
+    (void)hipFree(c->d_hstate);
     (void)hipFree(c->d_work);
     (void)hipFree(c->d_hwork);
     (void)hipFree(c->d_xsort);
@@ -269,15 +271,70 @@ int sps_reserve(sps_ctx *c, int max_gal) {
     (void)hipFree(c->d_inv);
     (void)hipFree(c->d_rec);
     (void)hipFree(c->d_orec);
+    (void)hipFree(c->d_hstate);
     c->d_perm = c->d_inv = nullptr;
     c->d_rec = c->d_orec = nullptr;
+    c->d_hstate = nullptr;
+    c->hstate_bytes = 0;
     c->max_gal = 0;
     SPS_HIP(hipMalloc(&c->d_perm, (size_t)max_gal * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_inv, (size_t)max_gal * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_rec, (size_t)max_gal * REC * sizeof(float)));
     SPS_HIP(hipMalloc(&c->d_orec, (size_t)max_gal * OREC * sizeof(float)));
+    const size_t hb = hmc_state_bytes(max_gal);
+    SPS_HIP(hipMalloc(&c->d_hstate, hb));
+    c->hstate_bytes = hb;
     c->max_gal = max_gal;
     return SPS_OK;
+}
+
+int sps_reserve_exact(sps_ctx *c, int max_rows) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if (max_rows < 1) return set_error(SPS_E_INVAL, "max_rows < 1");
+    if (max_rows > c->max_gal && (rc = sps_reserve(c, max_rows))) return rc;
+    if (max_rows <= c->max_exact) return SPS_OK;
+    size_t wb = 0;
+    for (int p = SPS_F64; p <= SPS_BF16X; ++p)
+        if (c->prec_mask & (1u << p)) {
+            const bool lik = (p != SPS_F64);   // the FP64 path computes magnitudes only
+            wb = std::max(wb, exact_ws_bytes(c, max_rows, p, lik, lik));
+        }
+    const size_t xb = exact_xsort_bytes(c, max_rows), hb = hmcx_state_bytes(c, max_rows);
+    SPS_HIP(hipDeviceSynchronize());
+    (void)hipFree(c->d_work);
+    (void)hipFree(c->d_xsort);
+    (void)hipFree(c->d_hwork);
+    c->d_work = c->d_xsort = c->d_hwork = nullptr;
+    c->work_bytes = c->xsort_bytes = c->hwork_bytes = 0;
+    c->max_exact = 0;
+    SPS_HIP(hipMalloc(&c->d_work, wb));
+    if (xb) SPS_HIP(hipMalloc(&c->d_xsort, xb));
+    SPS_HIP(hipMalloc(&c->d_hwork, hb));
+    c->work_bytes = wb;
+    c->xsort_bytes = xb;
+    c->hwork_bytes = hb;
+    c->max_exact = max_rows;
+    return SPS_OK;
+}
+
+int sps_status(sps_ctx *c) {
+    int rc = enter(c);
+    if (rc) return rc;
+    SPS_HIP(hipDeviceSynchronize());
+    int bits = 0;
+    SPS_HIP(hipMemcpy(&bits, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+    SPS_HIP(hipMemset(c->d_status, 0, sizeof(int)));
+    if (bits & STATUS_HMC_STATE)
+        return set_error(SPS_E_STATE, "an HMC resume blob did not match its run (configuration or iteration)");
+    if (bits & STATUS_Z_RANGE)
+        return set_error(SPS_E_RANGE, "a redshift outside the z table was given to the approximate path (NaN outputs)");
+    return SPS_OK;
+}
+
+size_t sps_hmc_state_bytes(int n_gal, int n_chain) {
+    if (n_gal < 0 || n_chain < 1) return 0;
+    return 256 + sps::chain_state_bytes_public(n_gal * n_chain);
 }
 
 int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_filter_desc *flt,
@@ -441,7 +498,8 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
         }
         if ((rc = upload((void **)&c->d_wc, wc.data(), wc.size() * sizeof(float)))) return fail(rc);
     }
-    if (hipMalloc(&c->d_hist, 2 * 1025 * sizeof(int)) != hipSuccess)
+    if (hipMalloc(&c->d_hist, 2 * 1025 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->d_status, sizeof(int)) != hipSuccess || hipMemset(c->d_status, 0, sizeof(int)) != hipSuccess)
         return fail(set_error(SPS_E_NOMEM, "workspace allocation failed"));
     if ((rc = sps_reserve(c, max_gal))) return fail(rc);
     *out = c;
@@ -596,7 +654,7 @@ int sps_logpost_grad(sps_ctx *c, void *stream, int n_gal, int sfh, const float *
 int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                 const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
                 const float *prior, const float *theta0, float *samples, float *post_mean, float *post_sd,
-                float *rhat, float *accept, float *step, float *inv_metric) {
+                float *rhat, float *accept, float *step, float *inv_metric, void *state_inout) {
     int rc = enter(c);
     if (rc) return rc;
     if (!cfg) return set_error(SPS_E_INVAL, "null config");
@@ -608,6 +666,14 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
     if (cfg->adapt_metric != 0 && cfg->adapt_metric != 1) return set_error(SPS_E_INVAL, "adapt_metric must be 0 or 1");
     if ((long long)n_gal * cfg->n_chain > (long long)c->max_gal)
         return set_error(SPS_E_INVAL, "n_gal * n_chain exceeds the reserved workspace (call sps_reserve)");
+    const int nit = cfg->n_warmup + cfg->n_sample;
+    const int it1 = cfg->it_end > 0 ? cfg->it_end : nit;
+    if (cfg->it_begin < 0 || cfg->it_end < 0 || it1 > nit || cfg->it_begin >= it1)
+        return set_error(SPS_E_INVAL, "need 0 <= it_begin < it_end <= n_warmup + n_sample (it_end 0 = to the end)");
+    if ((cfg->it_begin > 0 || it1 < nit) && !state_inout)
+        return set_error(SPS_E_INVAL, "a run split over calls needs state_inout");
+    if (cfg->path == SPS_PATH_EXACT && (long long)n_gal * cfg->n_chain > (long long)c->max_exact)
+        return set_error(SPS_E_STATE, "n_gal * n_chain exceeds the reserved exact rows (call sps_reserve_exact)");
     if (cfg->path != SPS_PATH_APPROX && cfg->path != SPS_PATH_EXACT) return set_error(SPS_E_INVAL, "bad path");
     if (cfg->path == SPS_PATH_APPROX && c->k.n_z == 0)
         return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
@@ -618,11 +684,12 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
             return set_error(SPS_E_STATE, "this precision's SSP table was not uploaded");
     }
     if (n_gal == 0) return SPS_OK;
-    if (!z || !obs || !sigma || !band_mask || !bounds || !prior || !theta0 || !post_mean || !post_sd || !rhat ||
-        !accept || !step)
+    if (!z || !obs || !sigma || !band_mask || !bounds || !prior)
         return set_error(SPS_E_INVAL, "null array");
+    if (it1 == nit && (!post_mean || !post_sd || !rhat || !accept || !step))
+        return set_error(SPS_E_INVAL, "null summary array (required from the call that ends the run)");
     return launch_hmc(c, (hipStream_t)stream, cfg, n_gal, sfh, z, obs, sigma, band_mask, bounds, prior, theta0,
-                      samples, post_mean, post_sd, rhat, accept, step, inv_metric);
+                      samples, post_mean, post_sd, rhat, accept, step, inv_metric, state_inout);
 }
 
 }  // extern "C"

@@ -944,46 +944,64 @@ __global__ void __launch_bounds__(128) k_xwindows(int n, int n_wave, FiltConst f
 }
 
 // ------------------------------------------------------------------ launcher
+// Byte offsets of the exact path's workspace for n rows: weights rows | per-galaxy weights |
+// partial sums | their tile sums | filter windows | dlogL/dnum | Rbar | Wbar | dP.  logl: the
+// likelihood outputs are wanted; grad: also the gradient.
+struct ExactLayout {
+    size_t o_w = 0, o_pw = 0, o_part = 0, o_psum = 0, o_win = 0, o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
+    size_t bytes = 0;
+};
+static ExactLayout exact_layout(const sps_ctx *c, int n, int prec, bool logl, bool grad) {
+    const int nw = c->n_wave, nb = c->n_band;
+    const bool f64 = (prec == SPS_F64);
+    const int n_tiles = f64 ? (nw + BN - 1) / BN : c->lw / XBN;
+    const int mp = round_up(n, XBM);              // A operands are read in whole 128-row tiles
+    const bool want_grad = logl && grad;
+    const int npart = (want_grad ? 5 : 2) * nb;
+    const int esz = f64 ? 8 : 4;
+    const int tsz = f64 ? 8 : (prec == SPS_F32 ? 4 : 2);
+    const int nsplit = (prec == SPS_BF16X) ? 2 : 1;
+    ExactLayout L;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    L.o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
+    L.o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
+    L.o_part = carve((size_t)n_tiles * n * npart * esz);
+    L.o_psum = f64 ? 0 : carve((size_t)n * npart * 4);
+    L.o_win = f64 ? 0 : carve((size_t)(mp / XBM) * sizeof(int4));
+    if (logl) {
+        L.o_cn = carve((size_t)n * NB_MAX * 4);
+        if (want_grad) {
+            L.o_rb = carve((size_t)nsplit * mp * c->lw * tsz);
+            L.o_wb = carve((size_t)XSPLIT * S_PAD * mp * 4);
+            L.o_pb = carve((size_t)(NA + WB_GROUPS * NZ) * n * 4);
+        }
+    }
+    L.bytes = off;
+    return L;
+}
+
+size_t exact_ws_bytes(const sps_ctx *c, int n, int prec, bool logl, bool grad) {
+    return exact_layout(c, n, prec, logl, grad).bytes;
+}
+
 static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                       void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
                       float *grad, bool zordered) {
     const int nw = c->n_wave, nb = c->n_band;
     const bool f64 = (prec == SPS_F64);
-    const int TN = f64 ? BN : XBN;                // wavelengths per tile of the forward GEMM
     const int n_tiles = f64 ? (nw + BN - 1) / BN : c->lw / XBN;
     const int mp = round_up(n, XBM);              // A operands are read in whole 128-row tiles
     const bool want_grad = grad != nullptr;
     const int npart = (want_grad ? 5 : 2) * nb;
-    const int esz = f64 ? 8 : 4;
-    const int tsz = f64 ? 8 : (prec == SPS_F32 ? 4 : 2);
-    const int nsplit = (prec == SPS_BF16X) ? 2 : 1;
     const int lw = c->lw;                         // padded wavelength stride of Rbar
-    (void)TN;
-    // workspace: weights rows | per-galaxy weights | partial sums | dlogL/dnum | Rbar | Wbar | dP
-    size_t off = 0;
-    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    const size_t o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
-    const size_t o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
-    const size_t o_part = carve((size_t)n_tiles * n * npart * esz);
-    const size_t o_psum = f64 ? 0 : carve((size_t)n * npart * 4);
-    const size_t o_win = f64 ? 0 : carve((size_t)(mp / XBM) * sizeof(int4));
-    size_t o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
-    if (logl) {
-        o_cn = carve((size_t)n * NB_MAX * 4);
-        if (want_grad) {
-            o_rb = carve((size_t)nsplit * mp * lw * tsz);
-            o_wb = carve((size_t)XSPLIT * S_PAD * mp * 4);
-            o_pb = carve((size_t)(NA + WB_GROUPS * NZ) * n * 4);
-        }
-    }
-    if (c->work_bytes < off) {
-        SPS_HIP(hipDeviceSynchronize());
-        (void)hipFree(c->d_work);
-        c->d_work = nullptr;
-        c->work_bytes = 0;
-        SPS_HIP(hipMalloc(&c->d_work, off));
-        c->work_bytes = off;
-    }
+    const ExactLayout Lo = exact_layout(c, n, prec, logl != nullptr, want_grad);
+    const size_t o_w = Lo.o_w, o_pw = Lo.o_pw, o_part = Lo.o_part, o_psum = Lo.o_psum, o_win = Lo.o_win;
+    const size_t o_cn = Lo.o_cn, o_rb = Lo.o_rb, o_wb = Lo.o_wb, o_pb = Lo.o_pb;
+    if (c->work_bytes < Lo.bytes || n > c->max_exact)
+        return set_error(SPS_E_STATE, "the exact path's workspace holds " + std::to_string(c->max_exact) +
+                                          " rows, this call needs " + std::to_string(n) +
+                                          " (call sps_reserve_exact)");
     char *W = (char *)c->d_work;
     int4 *win = nullptr;   // filter-support windows of the row tiles (FP32 / BF16X paths)
     void *w_hi = W + o_w;   // weights rows: FP32 [mp][S_PAD], or BF16 hi + lo interleaved [mp][2 S_PAD]
@@ -1179,6 +1197,28 @@ __global__ void __launch_bounds__(256) k_exact_order_out(int n, int nb, const in
 // at 4096 galaxies x 5000 wavelengths the active tiles take two rounds of blocks either way,
 // and the sort costs more than the GEMMs gain.
 constexpr int XSORT_MIN = 16384;
+struct XsortLayout {
+    size_t o_par, o_z, o_obs, o_sig, o_msk, o_mag, o_ll, o_gr, bytes;
+};
+static XsortLayout xsort_layout(const sps_ctx *c, int n) {
+    const int nb = c->n_band;
+    XsortLayout x{};
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
+    x.o_par = carve((size_t)NP * n * 4);
+    x.o_z = carve((size_t)n * 4);
+    x.o_obs = carve((size_t)n * nb * 4);
+    x.o_sig = carve((size_t)n * nb * 4);
+    x.o_msk = carve((size_t)n);
+    x.o_mag = carve((size_t)n * nb * 4);
+    x.o_ll = carve((size_t)n * 4);
+    x.o_gr = carve((size_t)NP * n * 4);
+    x.bytes = off;
+    return x;
+}
+
+size_t exact_xsort_bytes(const sps_ctx *c, int n) { return n >= XSORT_MIN ? xsort_layout(c, n).bytes : 0; }
+
 int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                  void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
                  float *grad, bool ordered) {
@@ -1187,19 +1227,12 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
                           ordered && prec != SPS_F64);
     const DevConsts grid = z_sort_grid(c);
     const int nb = c->n_band;
-    size_t off = 0;
-    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    const size_t o_par = carve((size_t)NP * n * 4), o_z = carve((size_t)n * 4);
-    const size_t o_obs = carve((size_t)n * nb * 4), o_sig = carve((size_t)n * nb * 4), o_msk = carve((size_t)n);
-    const size_t o_mag = carve((size_t)n * nb * 4), o_ll = carve((size_t)n * 4), o_gr = carve((size_t)NP * n * 4);
-    if (c->xsort_bytes < off) {
-        SPS_HIP(hipDeviceSynchronize());
-        (void)hipFree(c->d_xsort);
-        c->d_xsort = nullptr;
-        c->xsort_bytes = 0;
-        SPS_HIP(hipMalloc(&c->d_xsort, off));
-        c->xsort_bytes = off;
-    }
+    const XsortLayout xl = xsort_layout(c, n);
+    const size_t o_par = xl.o_par, o_z = xl.o_z, o_obs = xl.o_obs, o_sig = xl.o_sig, o_msk = xl.o_msk;
+    const size_t o_mag = xl.o_mag, o_ll = xl.o_ll, o_gr = xl.o_gr;
+    if (c->xsort_bytes < xl.bytes || n > c->max_gal)
+        return set_error(SPS_E_STATE, "the exact path's z-order buffer is too small for " + std::to_string(n) +
+                                          " galaxies (call sps_reserve_exact)");
     char *X = (char *)c->d_xsort;
     float *par_s = (float *)(X + o_par), *z_s = (float *)(X + o_z), *obs_s = (float *)(X + o_obs);
     float *sig_s = (float *)(X + o_sig), *mag_s = (float *)(X + o_mag), *ll_s = (float *)(X + o_ll);

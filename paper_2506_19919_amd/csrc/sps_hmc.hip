@@ -37,7 +37,138 @@ __device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1)
 __device__ inline float u01f(uint32_t w) { return fmaf((float)w, 2.3283064365386963e-10f, 1.1641532182693481e-10f); }
 __device__ inline double u01d(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
 
+// Unbounded starting point drawn from the skew-normal prior of every parameter (App. C, Eq.
+// SkewNormPrior) by the half-normal representation: with U0, U1 standard normals and
+// delta = s / sqrt(1 + s^2), xi + omega (delta |U0| + sqrt(1 - delta^2) U1) is skew-normal.
+// (U0, U1) of parameter p is the Box-Muller pair of words 2p, 2p + 1 of the Philox blocks
+// (blk, 0, chain id, 1), blk = 0..4 (the momentum draws use counter word 3 = 0).
+__device__ __noinline__ void prior_draw(const float *prior, uint32_t key0, uint32_t key1, uint32_t chain_id,
+                                        float (&x)[SPS_NPARAM]) {
+    uint32_t w[20];
+#pragma unroll
+    for (int blk = 0; blk < 5; ++blk) {
+        uint32_t c4[4] = {(uint32_t)blk, 0u, chain_id, 1u};
+        philox4x32_10(c4, key0, key1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[4 * blk + t] = c4[t];
+    }
+#pragma unroll
+    for (int p = 0; p < SPS_NPARAM; ++p) {
+        const float r = sqrtf(-2.0f * logf(u01f(w[2 * p])));
+        float sn, cs;
+        sincosf(6.283185307179586f * u01f(w[2 * p + 1]), &sn, &cs);
+        const float sk = prior[3 * p + 2], inv = 1.0f / sqrtf(1.0f + sk * sk);   // sqrt(1 - delta^2)
+        x[p] = prior[3 * p] + prior[3 * p + 1] * (sk * inv * fabsf(r * cs) + inv * (r * sn));
+    }
+}
+
 constexpr int MAX_WIN = 24;
+
+// Chain state carried from one iteration to the next, SoA [quantity][slot]: the state of a run
+// that a resume blob (sps_hmc_run's state_inout) holds between calls.
+struct ChainState {
+    float *x, *gr, *minv;               // [NP][slot]
+    float *eps, *mu, *hbar, *lebar;     // [slot]
+    int *nacc, *da0;                    // [slot]
+    double *lp, *wmean, *wm2;           // [slot], [NP][slot], [NP][slot]
+};
+// floats, ints and doubles per chain slot
+constexpr int CS_F = 3 * SPS_NPARAM + 4, CS_I = 2, CS_D = 1 + 2 * SPS_NPARAM;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t chain_state_bytes(int nslot) {
+    return align256((size_t)nslot * CS_F * 4) + align256((size_t)nslot * CS_I * 4) + align256((size_t)nslot * CS_D * 8);
+}
+// the quantities laid out from base for nslot slots
+static ChainState chain_state_at(void *base, int nslot) {
+    ChainState cs;
+    char *b = (char *)base;
+    float *f = (float *)b;
+    cs.x = f;
+    cs.gr = f + (size_t)SPS_NPARAM * nslot;
+    cs.minv = f + (size_t)2 * SPS_NPARAM * nslot;
+    cs.eps = f + (size_t)3 * SPS_NPARAM * nslot;
+    cs.mu = cs.eps + nslot;
+    cs.hbar = cs.mu + nslot;
+    cs.lebar = cs.hbar + nslot;
+    int *ip = (int *)(b + align256((size_t)nslot * CS_F * 4));
+    cs.nacc = ip;
+    cs.da0 = ip + nslot;
+    double *d = (double *)(b + align256((size_t)nslot * CS_F * 4) + align256((size_t)nslot * CS_I * 4));
+    cs.lp = d;
+    cs.wmean = d + nslot;
+    cs.wm2 = d + (size_t)(1 + SPS_NPARAM) * nslot;
+    return cs;
+}
+
+// Resume blob: a 256-byte header (HMC_HDR_WORDS ints) and then the chain state of every chain
+// in the canonical order q = chain * n_gal + galaxy (the Philox chain id).
+constexpr int HMC_MAGIC = 0x48535053, HMC_VERSION = 1, HMC_HDR_WORDS = 12;
+struct HmcHeader {
+    int w[HMC_HDR_WORDS];   // magic, version, n_gal, n_chain, n_warmup, n_sample, iterations done,
+                            // adapt_metric, seed low, seed high, n_leapfrog, 0
+};
+
+// Copies the chain state between the working layout (slot = rank * C + chain, galaxies ranked
+// by perm) and the blob's canonical layout.  to_blob = 0: blob -> workspace (the header must
+// describe this run with it_done = the iterations already run, else STATUS_HMC_STATE); 1:
+// workspace -> blob, header written with it_done.
+__global__ void __launch_bounds__(256) k_state_move(ChainState ws, ChainState bl, int n_gal, int C,
+                                                    const int *__restrict__ perm, int to_blob, HmcHeader hdr,
+                                                    int *__restrict__ hdr_dev, int *__restrict__ status) {
+    const int nslot = n_gal * C, s = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < HMC_HDR_WORDS) {
+        const int t = threadIdx.x;
+        if (to_blob) hdr_dev[t] = hdr.w[t];
+        else if (hdr_dev[t] != hdr.w[t]) atomicOr(status, STATUS_HMC_STATE);
+    }
+    if (s >= nslot) return;
+    const int ch = s % C, g = perm ? perm[s / C] : s / C, q = ch * n_gal + g;
+    const int src = to_blob ? s : q, dst = to_blob ? q : s;
+    const ChainState &from = to_blob ? ws : bl, &to = to_blob ? bl : ws;
+#pragma unroll
+    for (int p = 0; p < SPS_NPARAM; ++p) {
+        const size_t a = (size_t)p * nslot;
+        to.x[a + dst] = from.x[a + src];
+        to.gr[a + dst] = from.gr[a + src];
+        to.minv[a + dst] = from.minv[a + src];
+        to.wmean[a + dst] = from.wmean[a + src];
+        to.wm2[a + dst] = from.wm2[a + src];
+    }
+    to.eps[dst] = from.eps[src];
+    to.mu[dst] = from.mu[src];
+    to.hbar[dst] = from.hbar[src];
+    to.lebar[dst] = from.lebar[src];
+    to.nacc[dst] = from.nacc[src];
+    to.da0[dst] = from.da0[src];
+    to.lp[dst] = from.lp[src];
+}
+
+static HmcHeader hmc_header(const sps_hmc_cfg *cfg, int n_gal, int it_done) {
+    HmcHeader h{};
+    h.w[0] = HMC_MAGIC;
+    h.w[1] = HMC_VERSION;
+    h.w[2] = n_gal;
+    h.w[3] = cfg->n_chain;
+    h.w[4] = cfg->n_warmup;
+    h.w[5] = cfg->n_sample;
+    h.w[6] = it_done;
+    h.w[7] = cfg->adapt_metric;
+    h.w[8] = (int)(uint32_t)(cfg->seed & 0xffffffffull);
+    h.w[9] = (int)(uint32_t)(cfg->seed >> 32);
+    h.w[10] = cfg->n_leapfrog;
+    return h;
+}
+
+// blob -> workspace (to_blob = 0, header checked against it_done) or workspace -> blob
+static int move_state(sps_ctx *c, hipStream_t s, const ChainState &ws, void *blob, const sps_hmc_cfg *cfg,
+                      int n_gal, const int *perm, int to_blob, int it_done) {
+    const int nslot = n_gal * cfg->n_chain;
+    const ChainState bl = chain_state_at((char *)blob + 256, nslot);
+    hipLaunchKernelGGL(k_state_move, dim3((nslot + 255) / 256), dim3(256), 0, s, ws, bl, n_gal, cfg->n_chain,
+                       perm, to_blob, hmc_header(cfg, n_gal, it_done), (int *)blob, c->d_status);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
+}
 
 // lanes per chain: two adjacent lanes share a chain's model evaluations (each takes half of
 // the age bins and bands), so the 65,536 chains of a 16,384-galaxy batch make 2,048 waves,
@@ -187,11 +318,14 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     float x[NP], gr[NP];
+    if (a.theta0) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
-        TMP(a.xt, p) = x[p];
+        for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)si.ch * NP + p) * a.n_gal + si.g];
+    } else {
+        prior_draw(a.prior, a.key0, a.key1, si.chain_id, x);
     }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) TMP(a.xt, p) = x[p];
     const double lp = logpost<SFH>(k, ledge, a, lc, lds, gr);
     if (!si.valid) return;
 #pragma unroll
@@ -438,8 +572,8 @@ struct HmcxArgs {
 
 #define XS(arr, p) (arr)[(size_t)(p) * a.nslot + s]
 
-// per-slot inputs and the starting point
-__global__ void __launch_bounds__(256) k_hmcx_setup(HmcxArgs a) {
+// per-slot inputs and (start = 1) the starting point
+__global__ void __launch_bounds__(256) k_hmcx_setup(HmcxArgs a, int start) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
     const int g = a.perm[s / a.C], ch = s % a.C;
@@ -449,12 +583,19 @@ __global__ void __launch_bounds__(256) k_hmcx_setup(HmcxArgs a) {
         a.sig_s[(size_t)s * a.nb + b] = a.sigma[(size_t)g * a.nb + b];
     }
     a.mask_s[s] = a.mask[g];
+    if (!start) return;   // a resumed run: the chain state comes from the blob
+    float x[NP];
+    if (a.theta0) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) x[p] = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
+    } else {
+        prior_draw(a.prior, a.key0, a.key1, (uint32_t)(ch * a.n_gal + g), x);
+    }
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const float x = a.theta0[((size_t)ch * NP + p) * a.n_gal + g];
         float th, dth;
-        bound_param(a.bounds + 4 * p, x, th, dth);
-        XS(a.xt, p) = x;
+        bound_param(a.bounds + 4 * p, x[p], th, dth);
+        XS(a.xt, p) = x[p];
         XS(a.th, p) = th;
     }
 }
@@ -665,60 +806,76 @@ static int metric_windows(int nw, int *ws, int *we) {
     return n;
 }
 
+size_t chain_state_bytes_public(int nslot) { return chain_state_bytes(nslot); }
+
+size_t hmc_state_bytes(int nslot) {
+    const size_t ntmp = ((size_t)nslot * HG + 63) / 64 * 64;   // trajectory scratch: every lane of the grid
+    return chain_state_bytes(nslot) + align256((size_t)2 * NP * ntmp * sizeof(float));
+}
+
+// the exact-path HMC's per-slot arrays besides the chain state: floats pm, xt, th, grad [NP] +
+// logl, zs + obs_s, sig_s [nb]; double h0; bytes mask_s
+struct HmcxLayout {
+    size_t o_f, o_d, o_m, bytes;
+};
+static HmcxLayout hmcx_layout(int nslot, int nb) {
+    HmcxLayout L{};
+    size_t off = chain_state_bytes(nslot);
+    L.o_f = off;
+    off += align256((size_t)nslot * (4 * NP + 2 + 2 * nb) * sizeof(float));
+    L.o_d = off;
+    off += align256((size_t)nslot * sizeof(double));
+    L.o_m = off;
+    off += align256((size_t)nslot);
+    L.bytes = off;
+    return L;
+}
+size_t hmcx_state_bytes(const sps_ctx *c, int nslot) { return hmcx_layout(nslot, c->n_band).bytes; }
+
 static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                             const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                             const float *prior, const float *theta0, float *samples, float *post_mean,
                             float *post_sd, float *rhat, float *accept, float *step, float *inv_metric,
-                            int n_win, const int *win_s, const int *win_e) {
+                            int n_win, const int *win_s, const int *win_e, void *state) {
     const int C = cfg->n_chain, nslot = n_gal * C, nb = c->n_band;
+    const int nit = cfg->n_warmup + cfg->n_sample;
+    const int it0 = cfg->it_begin, it1 = cfg->it_end > 0 ? cfg->it_end : nit;
     HmcxArgs a{};
     a.n_win = n_win;
     for (int w = 0; w < n_win; ++w) {
         a.win_s[w] = win_s[w];
         a.win_e[w] = win_e[w];
     }
-    // chain state and trajectory: floats x, gr, minv, pm, xt, th, grad [NP] + eps, mu, hbar,
-    // lebar, logl, zs + obs_s, sig_s [nb]; ints nacc, da0; doubles lp, h0 + wmean, wm2 [NP];
-    // bytes mask_s
-    size_t off = 0;
-    auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
-    const size_t o_f = carve((size_t)nslot * (7 * NP + 6 + 2 * nb) * sizeof(float));
-    const size_t o_i = carve((size_t)nslot * 2 * sizeof(int));
-    const size_t o_d = carve((size_t)nslot * (2 + 2 * NP) * sizeof(double));
-    const size_t o_m = carve((size_t)nslot);
-    if (c->hwork_bytes < off) {
-        SPS_HIP(hipDeviceSynchronize());
-        (void)hipFree(c->d_hwork);
-        c->d_hwork = nullptr;
-        c->hwork_bytes = 0;
-        SPS_HIP(hipMalloc(&c->d_hwork, off));
-        c->hwork_bytes = off;
-    }
+    const HmcxLayout L = hmcx_layout(nslot, nb);
+    if (c->hwork_bytes < L.bytes || nslot > c->max_exact)
+        return set_error(SPS_E_STATE, "the exact-path HMC needs " + std::to_string(nslot) +
+                                          " reserved exact rows (call sps_reserve_exact)");
     char *W = (char *)c->d_hwork;
-    float *fp = (float *)(W + o_f);
+    const ChainState cs = chain_state_at(W, nslot);
+    a.x = cs.x;
+    a.gr = cs.gr;
+    a.minv = cs.minv;
+    a.eps = cs.eps;
+    a.mu = cs.mu;
+    a.hbar = cs.hbar;
+    a.lebar = cs.lebar;
+    a.nacc = cs.nacc;
+    a.da0 = cs.da0;
+    a.lp = cs.lp;
+    a.wmean = cs.wmean;
+    a.wm2 = cs.wm2;
+    float *fp = (float *)(W + L.o_f);
     auto fq = [&](int count) { float *r = fp; fp += (size_t)count * nslot; return r; };
-    a.x = fq(NP);
-    a.gr = fq(NP);
-    a.minv = fq(NP);
     a.pm = fq(NP);
     a.xt = fq(NP);
     a.th = fq(NP);
     a.grad = fq(NP);
-    a.eps = fq(1);
-    a.mu = fq(1);
-    a.hbar = fq(1);
-    a.lebar = fq(1);
     a.logl = fq(1);
     a.zs = fq(1);
     a.obs_s = fq(nb);
     a.sig_s = fq(nb);
-    a.nacc = (int *)(W + o_i);
-    a.da0 = a.nacc + nslot;
-    a.lp = (double *)(W + o_d);
-    a.h0 = a.lp + nslot;
-    a.wmean = a.h0 + nslot;
-    a.wm2 = a.wmean + (size_t)NP * nslot;
-    a.mask_s = (uint8_t *)(W + o_m);
+    a.h0 = (double *)(W + L.o_d);
+    a.mask_s = (uint8_t *)(W + L.o_m);
     a.n_gal = n_gal;
     a.C = C;
     a.nslot = nslot;
@@ -749,21 +906,26 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
         return launch_exact(c, s, nslot, sfh, cfg->prec, a.th, a.zs, nullptr, a.obs_s, a.sig_s, a.mask_s, a.logl,
                             a.grad, true);
     };
-    hipLaunchKernelGGL(k_hmcx_setup, grid, block, 0, s, a);
-    int rc = model();
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_hmcx_init, grid, block, 0, s, a);
-    const int nit = cfg->n_warmup + cfg->n_sample;
-    for (int it = 0; it < nit; ++it) {
+    int rc;
+    hipLaunchKernelGGL(k_hmcx_setup, grid, block, 0, s, a, (int)(it0 == 0));
+    if (it0 == 0) {
+        if ((rc = model())) return rc;
+        hipLaunchKernelGGL(k_hmcx_init, grid, block, 0, s, a);
+    } else if ((rc = move_state(c, s, cs, state, cfg, n_gal, a.perm, 0, it0))) {
+        return rc;
+    }
+    for (int it = it0; it < it1; ++it) {
         hipLaunchKernelGGL(k_hmcx_start, grid, block, 0, s, a, it);
         for (int l = 0; l < cfg->n_leapfrog; ++l) {
             if ((rc = model())) return rc;
             hipLaunchKernelGGL(k_hmcx_step, grid, block, 0, s, a, it, (int)(l == cfg->n_leapfrog - 1));
         }
     }
-    hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
-                       a.perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
-                       inv_metric);
+    if (state && (rc = move_state(c, s, cs, state, cfg, n_gal, a.perm, 1, it1))) return rc;
+    if (it1 == nit)
+        hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
+                           a.perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                           inv_metric);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }
@@ -771,7 +933,7 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
                const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
-               float *step, float *inv_metric) {
+               float *step, float *inv_metric, void *state) {
     const int C = cfg->n_chain, nslot = n_gal * C;
     HmcArgs a{};
     a.n_win = 0;
@@ -781,25 +943,14 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     }
     if (cfg->path == SPS_PATH_EXACT)
         return launch_hmc_exact(c, s, cfg, n_gal, sfh, z, obs, sigma, mask, bounds, prior, theta0, samples,
-                                post_mean, post_sd, rhat, accept, step, inv_metric, a.n_win, a.win_s, a.win_e);
-    // chain state: 10 x + 10 grad + 10 M^-1 + eps, mu, hbar, lebar (float), nacc, da0 (int);
-    // lp + 20 Welford (double)
-    const size_t fbytes = (size_t)nslot * (3 * NP + 4) * sizeof(float) + (size_t)nslot * 2 * sizeof(int);
-    const size_t dofs = (fbytes + 255) & ~(size_t)255;
-    const int ntmp = (nslot * HG + 63) / 64 * 64;   // every lane of the grid
-    const size_t tofs = (dofs + (size_t)nslot * (2 * NP + 1) * sizeof(double) + 255) & ~(size_t)255;
-    const size_t need = tofs + (size_t)2 * NP * ntmp * sizeof(float);
-    if (c->work_bytes < need) {
-        SPS_HIP(hipDeviceSynchronize());
-        (void)hipFree(c->d_work);
-        c->d_work = nullptr;
-        c->work_bytes = 0;
-        SPS_HIP(hipMalloc(&c->d_work, need));
-        c->work_bytes = need;
-    }
+                                post_mean, post_sd, rhat, accept, step, inv_metric, a.n_win, a.win_s, a.win_e, state);
+    const int nit = cfg->n_warmup + cfg->n_sample;
+    const int it0 = cfg->it_begin, it1 = cfg->it_end > 0 ? cfg->it_end : nit;
+    if (c->hstate_bytes < hmc_state_bytes(nslot))
+        return set_error(SPS_E_STATE, "the HMC chain state needs n_gal * n_chain reserved galaxies (call sps_reserve)");
     int rc = launch_bucket_sort(c, s, n_gal, z);
     if (rc) return rc;
-    float *fp = (float *)c->d_work;
+    const ChainState cs = chain_state_at(c->d_hstate, nslot);
     a.n_gal = n_gal;
     a.C = C;
     a.L = cfg->n_leapfrog;
@@ -821,37 +972,43 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.qf = c->d_qf;
     a.qa = c->d_qa;
     a.samples = samples;
-    a.x = fp;
-    a.gr = fp + (size_t)NP * nslot;
-    a.minv = fp + (size_t)2 * NP * nslot;
-    a.eps = fp + (size_t)3 * NP * nslot;
-    a.mu = a.eps + nslot;
-    a.hbar = a.mu + nslot;
-    a.lebar = a.hbar + nslot;
-    a.nacc = (int *)(a.lebar + nslot);
-    a.da0 = a.nacc + nslot;
-    a.lp = (double *)((char *)c->d_work + dofs);
-    a.pm = (float *)((char *)c->d_work + tofs);
+    a.x = cs.x;
+    a.gr = cs.gr;
+    a.minv = cs.minv;
+    a.eps = cs.eps;
+    a.mu = cs.mu;
+    a.hbar = cs.hbar;
+    a.lebar = cs.lebar;
+    a.nacc = cs.nacc;
+    a.da0 = cs.da0;
+    a.lp = cs.lp;
+    a.wmean = cs.wmean;
+    a.wm2 = cs.wm2;
+    const int ntmp = (nslot * HG + 63) / 64 * 64;   // every lane of the grid
+    a.pm = (float *)((char *)c->d_hstate + chain_state_bytes(nslot));
     a.xt = a.pm + (size_t)NP * ntmp;
     a.ntmp = ntmp;
-    a.wmean = a.lp + nslot;
-    a.wm2 = a.wmean + (size_t)NP * nslot;
-    const int nit = cfg->n_warmup + cfg->n_sample;
     const int blk_it = 25;
     dim3 grid((nslot * HG + 63) / 64), block(64);
     const bool dpl = (sfh == SPS_SFH_DPL);
     const size_t lds_bytes = approx_lds_bytes(c->n_band, false, HG);
-    if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
-    else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
-    for (int it0 = 0; it0 < nit; it0 += blk_it) {
-        a.it0 = it0;
-        a.it1 = it0 + blk_it < nit ? it0 + blk_it : nit;
+    if (it0 == 0) {
+        if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
+        else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
+    } else if ((rc = move_state(c, s, cs, state, cfg, n_gal, c->d_perm, 0, it0))) {
+        return rc;
+    }
+    for (int b0 = it0; b0 < it1; b0 += blk_it) {
+        a.it0 = b0;
+        a.it1 = b0 + blk_it < it1 ? b0 + blk_it : it1;
         if (dpl) hipLaunchKernelGGL(k_hmc<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
         else hipLaunchKernelGGL(k_hmc<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
     }
-    hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
-                       c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
-                       inv_metric);
+    if (state && (rc = move_state(c, s, cs, state, cfg, n_gal, c->d_perm, 1, it1))) return rc;
+    if (it1 == nit)
+        hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
+                           c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                           inv_metric);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }

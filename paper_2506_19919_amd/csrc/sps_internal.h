@@ -95,6 +95,11 @@ struct sps_ctx {
     float *d_rec = nullptr;        // inputs in z-bucket order, one 128-byte record per galaxy
     float *d_orec = nullptr;       // outputs in z-bucket order, 64 bytes per galaxy
     int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
+    int *d_status = nullptr;       // device-side error bits (STATUS_*), read and cleared by sps_status
+    void *d_hstate = nullptr;      // chain state of the approximate-path HMC, max_gal chain slots
+    size_t hstate_bytes = 0;
+    // exact path, sized by sps_reserve_exact for max_exact rows (galaxies or HMC chains)
+    int max_exact = 0;
     void *d_work = nullptr;        // exact-path weights / partial fluxes
     size_t work_bytes = 0;
     void *d_hwork = nullptr;       // chain state of the exact-path HMC (d_work serves its model calls)
@@ -109,6 +114,9 @@ struct sps_ctx {
 namespace sps {
 
 int set_error(int code, const std::string &msg);
+
+// device-side error bits in sps_ctx::d_status (set by kernels, reported by sps_status)
+enum { STATUS_Z_RANGE = 1, STATUS_HMC_STATE = 2 };
 // the next timing event pair (start, stop) if kernel timing is on, else nullptr
 hipEvent_t *timing_pair(sps_ctx *c);
 int hip_check(hipError_t e, const char *what);
@@ -132,6 +140,7 @@ struct GatherArgs {
     const uint8_t *mask;                // may be null (all bands)
     float *rec;                         // null: sort only
     int *inv;
+    int *status;                        // STATUS_Z_RANGE is set here for a z outside the table (or null)
 };
 // z buckets for ranking galaxies by redshift: the z table's nodes, or 64 buckets over
 // 0 <= z < 8 when no table was built (z beyond goes to one overflow bucket)
@@ -144,11 +153,30 @@ inline DevConsts z_sort_grid(const sps_ctx *c) {
     }
     return g;
 }
-// grid: the z buckets (n_z, z_lo, dz of a DevConsts; n_z <= 1025); null: the z table's
+// grid: the z buckets (n_z, z_lo, dz of a DevConsts; n_z <= 1025); null: the z table's, and a z
+// outside the table then sets STATUS_Z_RANGE
 int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n_gal, const float *z, const GatherArgs *ga = nullptr,
                        const DevConsts *grid = nullptr);
+// device bytes of the workspaces, for the reservation calls
+size_t exact_ws_bytes(const sps_ctx *c, int n, int prec, bool logl, bool grad);
+size_t exact_xsort_bytes(const sps_ctx *c, int n);
+size_t hmc_state_bytes(int nslot);
+size_t chain_state_bytes_public(int nslot);   // chain state of nslot chains in a resume blob
+size_t hmcx_state_bytes(const sps_ctx *c, int nslot);
 int launch_weights(sps_ctx *c, hipStream_t s, int n_gal, int sfh, const float *params, const float *z,
                    float *w);
+// the approximate path's per-call buffers: z-bucket order, its inverse, the sort's histogram and
+// cursors (2 x 1025 ints), input and output records; the context's, or another owner's
+struct ApproxWs {
+    int *perm, *inv, *hist;
+    float *rec, *orec;
+};
+ApproxWs ctx_ws(sps_ctx *c);
+int launch_bucket_sort_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, const float *z, const GatherArgs *ga,
+                          const DevConsts *grid);
+int launch_approx_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, int sfh, int mode, const float *params,
+                     const float *z, const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
+                     const float *prior, float *out_mag, float *out_val, float *out_grad);
 int launch_approx(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int mode, const float *params,
                   const float *z, const float *obs, const float *sigma, const uint8_t *mask,
                   const float *bounds, const float *prior, float *out_mag, float *out_val, float *out_grad);
@@ -160,7 +188,7 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int prec, const 
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                const float *prior, const float *theta0, float *samples, float *post_mean,
-               float *post_sd, float *rhat, float *accept, float *step, float *inv_metric);
+               float *post_sd, float *rhat, float *accept, float *step, float *inv_metric, void *state);
 
 // modes of the approximate-path kernel
 enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3 };

@@ -57,6 +57,14 @@ def test_approx_edge_cases(ctx, orc):
     assert np.all(np.isnan(m[[1, 3]])) and np.all(np.isfinite(m[[0, 2, 4]]))
     ref = orc.phot_approx(sfh, th, z)
     np.testing.assert_allclose(m[[0, 2, 4]], ref[[0, 2, 4]], atol=MAG_TOL)
+    # the out-of-table redshifts are reported by the next status check, which clears the flag
+    import paper_2506_19919_amd as sps
+    with pytest.raises(sps.SpsError) as e:
+        ctx.status()
+    assert e.value.code == sps.SPS_E_RANGE
+    ctx.status()
+    ctx.phot_approx(sfh, soa(th[[0, 2, 4]]), dev(z[[0, 2, 4]]))
+    ctx.status()
     # empty batch is a no-op
     empty = torch.empty((10, 0), device="cuda")
     out = ctx.phot_approx(sfh, empty, torch.empty(0, device="cuda"))

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def ctx2000(ssp2000, filt6):
     import paper_2506_19919_amd as sps
-    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16,
+                    max_exact=1 << 14)
     yield c
     c.close()
 
@@ -27,7 +28,8 @@ def ssp5000():
 @pytest.fixture(scope="module")
 def ctx5000(ssp5000, filt6):
     import paper_2506_19919_amd as sps
-    c = sps.Context(ssp5000, filt6, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16)
+    c = sps.Context(ssp5000, filt6, precisions=(sps.SPS_F64, sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16,
+                    max_exact=4096)
     yield c
     c.close()
 
@@ -215,7 +217,7 @@ def test_exact_matches_approx_at_z_nodes_without_dust(ctx2000, orc):
 
 def test_exact_precision_not_uploaded_is_an_error(ssp2000, filt6):
     import paper_2506_19919_amd as sps
-    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64,), max_gal=16)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64,), max_gal=16, max_exact=16)
     sfh, th, z = gal_inputs("dpl", 4, 1)
     with pytest.raises(sps.SpsError) as e:
         c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_BF16X)
@@ -229,7 +231,7 @@ def test_approximation_gap_matches_oracle(ssp2000, oracle_mod, sigma_A):
     # oracle's per galaxy and band: each FP32 path is within 1e-4 mag of the oracle
     import paper_2506_19919_amd as sps
     filt = synth.filters(sigma=sigma_A)
-    c = sps.Context(ssp2000, filt, precisions=(sps.SPS_F32,), max_gal=4096)
+    c = sps.Context(ssp2000, filt, precisions=(sps.SPS_F32,), max_gal=4096, max_exact=4096)
     try:
         c.build_ztable(64, 0.1, 3.0)
         o = oracle_mod.Oracle(ssp2000, filt)
@@ -239,5 +241,22 @@ def test_approximation_gap_matches_oracle(ssp2000, oracle_mod, sigma_A):
         me = c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_F32).cpu().numpy().astype(np.float64)
         ref = o.phot_approx(sfh, th, z) - o.phot_exact(sfh, th, z)
         assert np.abs((ma - me) - ref).max() <= 2e-4
+    finally:
+        c.close()
+
+
+def test_exact_call_beyond_the_reservation_is_refused(ssp2000, filt6):
+    # compute calls never allocate: a batch larger than sps_reserve_exact sized the workspace
+    # for is an error, and reserving more makes the same call work
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=256, max_exact=64)
+    try:
+        sfh, th, z = gal_inputs("dpl", 65, 3)
+        with pytest.raises(sps.SpsError) as e:
+            c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_F32)
+        assert e.value.code == sps.SPS_E_STATE
+        c.reserve_exact(65)
+        m = c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_F32)
+        assert torch.isfinite(m).all()
     finally:
         c.close()

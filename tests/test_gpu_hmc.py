@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import synth
-from gpu_common import bounds_prior, dev, f32, gal_inputs
+from gpu_common import bounds_prior, dev, draws_follow_oracle, f32, gal_inputs, general_bounds_prior
 
 pytestmark = pytest.mark.gpu
 
@@ -41,12 +41,42 @@ def test_first_iterations_match_oracle(ctx, orc):
     sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 11, C)
     kw = dict(n_chain=C, n_leapfrog=10, n_warmup=2, n_sample=3, init_step=0.01, seed=404)
     out = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
-    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)        # [s][c][g][10]
-    s_ref = ref["samples"]
-    close = np.all(np.abs(s_gpu - s_ref) <= 1e-3 * np.maximum(np.abs(s_ref), 1.0), axis=-1)
-    assert close.mean() >= 0.9, close
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
     np.testing.assert_allclose(out["step"].cpu().numpy(), ref["step"], rtol=1e-3)
+
+
+@pytest.mark.parametrize("kind", ["dpl", "lognormal_burst"])
+def test_fixed_step_iterations_match_oracle_every_chain(ctx, orc, kind):
+    # no warm-up (the step size stays at init_step), 8 iterations of 10 leapfrog steps with
+    # moving chains: every chain of every galaxy follows the oracle draw by draw, up to a
+    # Metropolis decision that was a near tie in FP64
+    n, C = 8, 3
+    if kind == "dpl":
+        sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 91, C)
+    else:
+        sfh, th, z = gal_inputs(kind, n, 92)
+        th[:, 3] = 1.0
+        th[:, synth.P_FFLOOR] = 0.05
+        noise, sig = synth.photometric_noise(n, 6, 93)
+        obs, sig = f32(orc.phot_approx(sfh, th, z) + noise), f32(sig)
+        masks = synth.band_masks(n, 6, 94)
+        bnd, pri = bounds_prior()
+        xt = np.array([[orc.unbound(bnd[p], th[g, p]) for p in range(10)] for g in range(n)])
+        x0 = f32(xt[None] + 0.05 * np.random.default_rng(95).normal(size=(C, n, 10)))
+    kw = dict(n_chain=C, n_leapfrog=10, n_warmup=0, n_sample=8, init_step=0.01, seed=406)
+    th0 = dev(np.ascontiguousarray(np.transpose(x0, (0, 2, 1))))
+    out = ctx.hmc_run(sfh, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), th0,
+                      keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 2, (ok, excused)
+    # the chains move: most iterations are accepted, and the draws are not all the start
+    assert np.mean(ref["trace_margin"] < 0) > 0.5
+    assert np.all(np.abs(s_gpu[-1] - s_gpu[0]).max(axis=-1) > 0)
 
 
 def test_first_iterations_match_oracle_lognormal(ctx, orc):
@@ -68,10 +98,10 @@ def test_first_iterations_match_oracle_lognormal(ctx, orc):
     th0 = dev(np.ascontiguousarray(np.transpose(x0, (0, 2, 1))))
     out = ctx.hmc_run(sfh, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), th0,
                       keep_samples=True, **kw)
-    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
-    close = np.all(np.abs(s_gpu - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0), axis=-1)
-    assert close.mean() >= 0.9, close
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
     # step sizes after two warm-up iterations: dual averaging moves log eps by
     # sqrt(m) / gamma * eta * d(alpha) ~ 2.4 d(alpha); where a chain's acceptance is below 1 the
     # FP32 magnitudes (~1.6e-5 mag) move Delta H, and so alpha, by ~2e-3 here, hence 1e-2
@@ -130,10 +160,10 @@ def test_full_size_batch_short_run(ctx, orc):
     s = out["samples"].cpu().numpy()
     assert np.isfinite(s).all()
     ref = orc.hmc_run(1, z[pick], obs[pick], sig[pick], masks[pick], bnd, pri, x0[:, pick], keep_samples=True,
-                      gal_id=pick, n_gal_total=n, **kw)
+                      keep_trace=True, gal_id=pick, n_gal_total=n, **kw)
     s_pick = s[:, :, :, pick].transpose(0, 1, 3, 2)
-    close = np.all(np.abs(s_pick - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0), axis=-1)
-    assert close.mean() >= 0.9
+    ok, excused = draws_follow_oracle(s_pick, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
 
 
 def test_metric_adaptation_matches_oracle(ctx, orc):
@@ -146,11 +176,11 @@ def test_metric_adaptation_matches_oracle(ctx, orc):
     kw = dict(n_chain=C, n_leapfrog=1, n_warmup=20, n_sample=3, init_step=0.01, target_accept=0.95, seed=405,
               adapt_metric=True)
     out = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
-    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)        # [s][c][g][10]
-    same = np.all(np.abs(s_gpu - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0),
-                  axis=(0, -1))                                       # [c][g]
-    assert same.mean() >= 0.6, same
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    same = ~excused                                                   # [c][g]
     mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)       # [c][g][10]
     assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
     np.testing.assert_allclose(mi_gpu[same], ref["inv_metric"][same], rtol=2e-3, atol=1e-7)
@@ -186,7 +216,7 @@ def test_posterior_moments_with_adapted_metric_agree_with_oracle(ctx, orc):
 @pytest.fixture(scope="module")
 def ctx_exact(ssp2000, filt6):
     import paper_2506_19919_amd as sps
-    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=1 << 16, max_exact=1024)
     c.build_ztable(64, 0.1, 3.0)
     yield c
     c.close()
@@ -201,12 +231,26 @@ def test_exact_path_first_iterations_match_oracle(ctx_exact, orc):
     kw = dict(n_chain=C, n_leapfrog=5, n_warmup=2, n_sample=3, init_step=0.01, seed=404)
     out = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=sps.SPS_PATH_EXACT,
                    prec=sps.SPS_F32, **kw)
-    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=1, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
-    s_ref = ref["samples"]
-    close = np.all(np.abs(s_gpu - s_ref) <= 1e-3 * np.maximum(np.abs(s_ref), 1.0), axis=-1)
-    assert close.mean() >= 0.9, close
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
     np.testing.assert_allclose(out["step"].cpu().numpy(), ref["step"], rtol=1e-3)
+
+
+def test_exact_path_fixed_step_iterations_match_oracle_every_chain(ctx_exact, orc):
+    # the exact-photometry chains with moving trajectories (no warm-up), every chain checked
+    import paper_2506_19919_amd as sps
+    n, C = 5, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 97, C)
+    kw = dict(n_chain=C, n_leapfrog=5, n_warmup=0, n_sample=6, init_step=0.01, seed=407)
+    out = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=sps.SPS_PATH_EXACT,
+                   prec=sps.SPS_F32, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert np.mean(ref["trace_margin"] < 0) > 0.5
 
 
 @pytest.mark.parametrize("prec_name", ["SPS_F32", "SPS_BF16X"])
@@ -240,7 +284,7 @@ def test_exact_path_chain_order_does_not_change_the_draws(ctx_exact, ssp2000, fi
     kw = dict(n_chain=C, n_leapfrog=5, n_warmup=2, n_sample=3, init_step=0.01, seed=404, keep_samples=True,
               path=sps.SPS_PATH_EXACT, prec=sps.SPS_F32)
     a = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, **kw)
-    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64, max_exact=64)
     try:
         b = _run_gpu(c, z, obs, sig, masks, bnd, pri, x0, **kw)
     finally:
@@ -259,11 +303,11 @@ def test_exact_path_metric_adaptation_matches_oracle(ctx_exact, orc):
               adapt_metric=True)
     out = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=sps.SPS_PATH_EXACT,
                    prec=sps.SPS_F32, **kw)
-    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, path=1, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
-    same = np.all(np.abs(s_gpu - ref["samples"]) <= 1e-3 * np.maximum(np.abs(ref["samples"]), 1.0),
-                  axis=(0, -1))
-    assert same.mean() >= 0.6, same
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    same = ~excused
     mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)
     assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
     np.testing.assert_allclose(mi_gpu[same], ref["inv_metric"][same], rtol=2e-3, atol=1e-7)
@@ -271,7 +315,7 @@ def test_exact_path_metric_adaptation_matches_oracle(ctx_exact, orc):
 
 def test_exact_path_needs_an_uploaded_precision(ssp2000, filt6, orc):
     import paper_2506_19919_amd as sps
-    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=64, max_exact=64)
     try:
         n, C = 2, 2
         sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 5, C)
@@ -280,3 +324,92 @@ def test_exact_path_needs_an_uploaded_precision(ssp2000, filt6, orc):
                      path=sps.SPS_PATH_EXACT, prec=sps.SPS_BF16X)
     finally:
         c.close()
+
+
+# ---------------------------------------------------------------- resume, prior starts
+def _split_run(ctx, z, obs, sig, masks, bnd, pri, x0, cuts, **kw):
+    """The same run split at the iterations in `cuts`, the state carried between the calls."""
+    n, C = len(z), kw["n_chain"]
+    state = ctx.hmc_state(n, C)
+    smp = torch.zeros((kw["n_sample"], C, 10, n), device="cuda")
+    th0 = None if x0 is None else dev(np.ascontiguousarray(np.transpose(x0, (0, 2, 1))))
+    edges = [0, *cuts, kw["n_warmup"] + kw["n_sample"]]
+    for b, e in zip(edges[:-1], edges[1:]):
+        out = ctx.hmc_run(1, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), th0,
+                          it_begin=b, it_end=e, state=state, samples=smp, **kw)
+    ctx.status()
+    return out
+
+
+@pytest.mark.parametrize("adapt", [False, True])
+def test_split_run_reproduces_the_uninterrupted_run(ctx, orc, adapt):
+    # three calls with the chain state carried in a resume blob draw exactly what one call
+    # draws (the cuts fall inside a 25-iteration launch block, in the warm-up and in the
+    # sampling phase)
+    n, C = 7, 3
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 71, C)
+    kw = dict(n_chain=C, n_leapfrog=4, n_warmup=40, n_sample=30, seed=77, adapt_metric=adapt)
+    whole = _run_gpu(ctx, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    part = _split_run(ctx, z, obs, sig, masks, bnd, pri, x0, (13, 52), **kw)
+    assert torch.equal(part["samples"], whole["samples"])
+    for key in ("post_mean", "post_sd", "rhat", "accept", "step", "inv_metric"):
+        assert torch.equal(part[key], whole[key]), key
+
+
+def test_split_run_exact_path(ctx_exact, orc):
+    import paper_2506_19919_amd as sps
+    n, C = 4, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 73, C)
+    kw = dict(n_chain=C, n_leapfrog=3, n_warmup=6, n_sample=5, init_step=0.02, seed=78, path=sps.SPS_PATH_EXACT,
+              prec=sps.SPS_BF16X)
+    whole = _run_gpu(ctx_exact, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    part = _split_run(ctx_exact, z, obs, sig, masks, bnd, pri, x0, (4, 8), **kw)
+    assert torch.equal(part["samples"], whole["samples"])
+    assert torch.equal(part["post_mean"], whole["post_mean"])
+
+
+def test_resume_blob_of_another_run_is_reported(ctx, orc):
+    import paper_2506_19919_amd as sps
+    n, C = 3, 2
+    sfh, th, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, n, 75, C)
+    kw = dict(n_chain=C, n_leapfrog=2, n_warmup=4, n_sample=4)
+    state = ctx.hmc_state(n, C)
+    args = (1, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), None)
+    ctx.hmc_run(*args, it_begin=0, it_end=3, state=state, seed=1, **kw)
+    ctx.status()
+    # continuing at the wrong iteration, or with another seed, is flagged
+    ctx.hmc_run(*args, it_begin=4, it_end=8, state=state, seed=1, **kw)
+    with pytest.raises(sps.SpsError) as e:
+        ctx.status()
+    assert e.value.code == sps.SPS_E_STATE
+    ctx.hmc_run(*args, it_begin=3, it_end=8, state=state, seed=2, **kw)
+    with pytest.raises(sps.SpsError):
+        ctx.status()
+    ctx.status()   # the flags were cleared
+    # a split run without a blob is refused on the host
+    with pytest.raises(sps.SpsError):
+        ctx.hmc_run(*args, it_begin=0, it_end=3, seed=1, **kw)
+
+
+def test_prior_start_matches_oracle(ctx, orc):
+    # theta0 = None: every chain starts from its own prior draw (App. C, skew-normal priors
+    # with s != 0); the GPU's FP32 draw and the oracle's FP64 draw agree to rounding, and the
+    # first iterations then follow each other draw by draw
+    n, C = 5, 2
+    sfh, th, z, obs, sig, masks, _, _, _ = _problem(orc, n, 81, C)
+    bnd1, _ = bounds_prior()
+    x_mid = np.median([[orc.unbound(bnd1[p], th[g, p]) for p in range(10)] for g in range(n)], axis=0)
+    bnd, pri = general_bounds_prior(x_mid)
+    # narrow priors centred on the galaxies' own unbounded values under these bounds: the
+    # starts lie near the data, where no parameter saturates its bounding map in FP32
+    xg = np.median([[orc.unbound(bnd[p], th[g, p]) for p in range(10)] for g in range(n)], axis=0)
+    pri[:, 0] = f32(xg)
+    pri[:, 1] = 0.3
+    kw = dict(n_chain=C, n_leapfrog=10, n_warmup=0, n_sample=4, init_step=0.005, seed=404)
+    out = ctx.hmc_run(1, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), None,
+                      keep_samples=True, **kw)
+    ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, None, keep_samples=True, keep_trace=True, **kw)
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
+    ok, excused = draws_follow_oracle(s_gpu, ref)
+    dev_ = (np.abs(s_gpu - ref["samples"]) / np.maximum(np.abs(ref["samples"]), 1.0)).max(axis=(0, 3))
+    assert ok.all() and excused.sum() <= 1, (ok, excused, dev_, ref["trace_margin"].transpose(1, 2, 0))
