@@ -64,6 +64,12 @@ class _HmcCfg(C.Structure):
 HMC_STATE = 400   # doubles of per-chain state carried between the calls of a split run
 
 
+class _NutsCfg(C.Structure):
+    _fields_ = [("n_chain", C.c_int), ("max_depth", C.c_int), ("n_warmup", C.c_int),
+                ("n_sample", C.c_int), ("target_accept", C.c_double), ("init_step", C.c_double),
+                ("seed", C.c_uint64), ("adapt_metric", C.c_int), ("path", C.c_int)]
+
+
 _lib = None
 
 
@@ -349,6 +355,53 @@ class Oracle:
             out["trace_logp"] = tr
             out["trace_alpha"], out["trace_margin"], out["trace_eps"] = tra[..., 0], tra[..., 1], tra[..., 2]
         return out
+
+
+def _nuts_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, max_depth=10, n_warmup=200,
+              n_sample=1000, target_accept=0.8, init_step=0.1, seed=404, keep_samples=False, gauss_prec=None,
+              gal_id=None, n_gal_total=0, adapt_metric=False, path=0, n_gal=None):
+    """NUTS (Hoffman & Gelman 2014, Algorithm 3 + dual averaging); arguments as hmc_run.
+    Returns the summaries, and per iteration the tree depth and leapfrog steps."""
+    if theta0 is not None:
+        th0 = _f64(theta0)
+        n_gal = th0.shape[1]
+        assert th0.shape == (n_chain, n_gal, N_PARAM)
+    else:
+        th0 = None
+        n_gal = len(z) if n_gal is None else n_gal
+    cfg = _NutsCfg(n_chain, max_depth, n_warmup, n_sample, target_accept, init_step, seed, int(bool(adapt_metric)),
+                   int(path))
+    minv = np.zeros((n_chain, n_gal, N_PARAM))
+    pm, ps, rh = (np.zeros((n_gal, N_PARAM)) for _ in range(3))
+    acc = np.zeros(n_gal)
+    step = np.zeros((n_chain, n_gal))
+    smp = np.zeros((n_sample, n_chain, n_gal, N_PARAM)) if keep_samples else None
+    depth = np.zeros((n_warmup + n_sample, n_chain, n_gal), np.int32)
+    steps = np.zeros((n_warmup + n_sample, n_chain, n_gal), np.int32)
+    gp = _f64(gauss_prec) if gauss_prec is not None else None
+    if gp is None:
+        n_z, lo, hi, qp = self._zt() if path == 0 else (0, C.c_double(0), C.c_double(0), None)
+        zz, o, s = _f64(z), _f64(obs), _f64(sigma)
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        b, pr = _f64(bounds), _f64(prior)
+        args = (_p(zz), _p(o), _p(s), _p(mk), _p(b), _p(pr))
+    else:
+        n_z, lo, hi, qp = 0, C.c_double(0), C.c_double(0), None
+        pr = _f64(prior) if prior is not None else None
+        args = (None,) * 5 + (_p(pr),)
+    gid = np.ascontiguousarray(gal_id, dtype=np.uint32) if gal_id is not None else None
+    rc = self.L.orc_nuts_run(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo), C.byref(self.model), n_z,
+                             lo, hi, qp, sfh, C.byref(cfg), n_gal, *args, _p(th0), _p(gp), _p(pm), _p(ps), _p(rh),
+                             _p(acc), _p(step), _p(smp), _p(depth), _p(steps), _p(minv), int(n_gal_total), _p(gid))
+    assert rc == 0, rc
+    out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step, inv_metric=minv, depth=depth,
+               steps=steps)
+    if smp is not None:
+        out["samples"] = smp
+    return out
+
+
+Oracle.nuts_run = _nuts_run
 
 
 def hmc_prior_draw(prior, seed, chain_id):

@@ -1085,4 +1085,248 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
     return 0;
 }
 
+// ---- No-U-Turn Sampler (the paper's second gradient-based sampler, App. D.2; Sec. 4 runs it
+// beside HMC).  Hoffman & Gelman (2014), Algorithm 3 (the "efficient" NUTS: slice variable,
+// doubling in a random direction, a subtree's proposal taken with probability
+// min(1, n'/n)) with the dual averaging of their Algorithm 6 (acceptance statistic = mean of
+// min(1, exp(H0 - H)) over the leaves of the final tree).  The recursion of BuildTree is
+// unrolled leaf by leaf, which builds the same leaves and makes the same U-turn checks in the
+// same order: after the last leaf of every dyadic block of a subtree (innermost first), the
+// block's ends are tested, and a divergent leaf ends the subtree at once.  Inside a subtree
+// the proposal is a uniform choice among its valid leaves (reservoir sampling), the
+// distribution the recursion's pairwise choices give.  Diagonal metric: the U-turn test uses
+// the velocities M^-1 p.  Philox draws: momentum and slice (blk 0..2, it, chain, 0: words 0..9
+// momentum as in HMC, word 10 the slice uniform), per doubling j (j, it, chain, 2: word 0 the
+// direction, word 1 the subtree's acceptance), per leaf (leaf index in the iteration, it,
+// chain, 3: word 0 the reservoir uniform).
+int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                 int n_z, double z_lo, double z_hi, const double *q, int sfh, const orc_nuts_cfg *cfg,
+                 int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
+                 const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
+                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
+                 double *samples, int *trace_depth, int *trace_steps, double *inv_metric, int n_gal_total,
+                 const uint32_t *gal_id) {
+    if (!cfg || cfg->n_chain < 1 || cfg->max_depth < 1 || cfg->max_depth > 12 || cfg->n_warmup < 0 ||
+        cfg->n_sample < 2 || n_gal < 0)
+        return 1;
+    if (cfg->path != 0 && cfg->path != 1) return 1;
+    if (cfg->adapt_metric != 0 && cfg->adapt_metric != 1) return 1;
+    if (!gauss_prec && (!check_common(s, f) || (cfg->path == 0 && !q) || !z || !obs || !sigma || !mask || !bounds ||
+                        !prior))
+        return 1;
+    if (!theta0 && !prior) return 1;
+    const int C = cfg->n_chain, NW = cfg->n_warmup, NS = cfg->n_sample, NIT = NW + NS, D = cfg->max_depth;
+    const int nb = f ? f->n_band : 0;
+    const double DELTA_MAX = 1000.0;
+    Model *X = gauss_prec ? nullptr : new Model(s, f, c, m);
+    std::vector<double> cmean((size_t)C * n_gal * NP, 0.0), cm2((size_t)C * n_gal * NP, 0.0), cacc((size_t)C * n_gal);
+    const uint32_t key[2] = {(uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32)};
+    const double gamma = 0.05, t0 = 10.0, kappa = 0.75, delta = cfg->target_accept;
+    int w_start[64], w_end[64];
+    const int n_win = cfg->adapt_metric ? std::min(hmc_windows(NW, 64, w_start, w_end), 64) : 0;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long cg = 0; cg < (long)C * n_gal; ++cg) {
+        const int ch = (int)(cg / n_gal), g = (int)(cg % n_gal);
+        const uint32_t chain_id = gal_id ? (uint32_t)ch * (uint32_t)n_gal_total + gal_id[g] : (uint32_t)cg;
+        auto eval = [&](const double *x, double *lp, double *gr) {
+            if (gauss_prec) {
+                double v = 0.0;
+                for (int a = 0; a < NP; ++a) {
+                    double ax = 0.0;
+                    for (int b = 0; b < NP; ++b) ax += gauss_prec[a * NP + b] * x[b];
+                    gr[a] = -ax;
+                    v += -0.5 * x[a] * ax;
+                }
+                *lp = v;
+            } else {
+                logpost(*X, cfg->path, n_z, z_lo, z_hi, q, sfh, x, z[g], obs + (size_t)g * nb, sigma + (size_t)g * nb,
+                        mask[g], bounds, prior, lp, gr);
+            }
+        };
+        auto physical = [&](int p, double x) { return gauss_prec ? x : bound<double>(bounds + 4 * p, x); };
+        double x[NP], gr[NP], lp, minv[NP], wmu[NP] = {0.0}, wm2[NP] = {0.0};
+        if (theta0) {
+            for (int p = 0; p < NP; ++p) x[p] = theta0[(size_t)cg * NP + p];
+        } else {
+            orc_hmc_prior_draw(prior, cfg->seed, chain_id, x);
+        }
+        eval(x, &lp, gr);
+        for (int k = 0; k < NP; ++k) minv[k] = 1.0;
+        double eps = cfg->init_step, mu = std::log(10.0 * cfg->init_step), hbar = 0.0, leps_bar = 0.0, acc_sum = 0.0;
+        int da_start = 0, win = 0, n_rec = 0;
+        double *mean = &cmean[(size_t)cg * NP], *m2 = &cm2[(size_t)cg * NP];
+        auto kinetic = [&](const double *pv) {
+            double e = 0.0;
+            for (int k = 0; k < NP; ++k) e += 0.5 * minv[k] * pv[k] * pv[k];
+            return e;
+        };
+        // no U-turn between the forward-time ends of a stretch: (x+ - x-) . M^-1 p >= 0 at both
+        auto no_uturn = [&](const double *xa, const double *pa, const double *xb, const double *pb, int dirn) {
+            double da = 0.0, db = 0.0;
+            for (int k = 0; k < NP; ++k) {
+                const double dx = dirn * (xb[k] - xa[k]);
+                da += dx * minv[k] * pa[k];
+                db += dx * minv[k] * pb[k];
+            }
+            return da >= 0.0 && db >= 0.0;
+        };
+        for (int it = 0; it < NIT; ++it) {
+            uint32_t w[12];
+            for (int blk = 0; blk < 3; ++blk) {
+                const uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
+                philox(ctr, key, w + 4 * blk);
+            }
+            double p0[NP];
+            for (int k = 0; k < NP / 2; ++k) {
+                const double r = std::sqrt(-2.0 * std::log(u01(w[2 * k]))), a = 2.0 * PI * u01(w[2 * k + 1]);
+                p0[2 * k] = r * std::cos(a) / std::sqrt(minv[2 * k]);
+                p0[2 * k + 1] = r * std::sin(a) / std::sqrt(minv[2 * k + 1]);
+            }
+            const double H0 = -lp + kinetic(p0);
+            const double log_u = std::log(u01(w[10])) - H0;   // slice variable u ~ U(0, exp(-H0))
+            // the tree's two ends, the proposal
+            double xl[NP], pl[NP], gl[NP], xr[NP], pr[NP], grr[NP], xm[NP], gm[NP], lpl = lp, lpr = lp, lpm = lp;
+            for (int k = 0; k < NP; ++k) {
+                xl[k] = xr[k] = xm[k] = x[k];
+                pl[k] = pr[k] = p0[k];
+                gl[k] = grr[k] = gm[k] = gr[k];
+            }
+            long n = 1;
+            bool s_tree = true;
+            int j = 0, leaf = 0;
+            double alpha_sum = 0.0;
+            while (s_tree && j < D) {
+                uint32_t wj[4];
+                const uint32_t cj[4] = {(uint32_t)j, (uint32_t)it, chain_id, 2u};
+                philox(cj, key, wj);
+                const int dirn = u01(wj[0]) < 0.5 ? -1 : 1;
+                // the subtree of 2^j leaves grows from the end in direction dirn
+                double xe[NP], pe[NP], ge[NP], lpe;
+                for (int k = 0; k < NP; ++k) {
+                    xe[k] = dirn < 0 ? xl[k] : xr[k];
+                    pe[k] = dirn < 0 ? pl[k] : pr[k];
+                    ge[k] = dirn < 0 ? gl[k] : grr[k];
+                }
+                lpe = dirn < 0 ? lpl : lpr;
+                double xs[NP] = {0.0}, gs[NP] = {0.0}, lps = 0.0, ckx[13][NP], ckp[13][NP];
+                long n_sub = 0;
+                bool s_sub = true;
+                const long n_leaf = 1L << j;
+                for (long k = 0; k < n_leaf && s_sub; ++k) {
+                    // one leapfrog step of size dirn * eps
+                    const double e = dirn * eps;
+                    for (int t = 0; t < NP; ++t) pe[t] += 0.5 * e * ge[t];
+                    for (int t = 0; t < NP; ++t) xe[t] += e * minv[t] * pe[t];
+                    eval(xe, &lpe, ge);
+                    for (int t = 0; t < NP; ++t) pe[t] += 0.5 * e * ge[t];
+                    const double H = -lpe + kinetic(pe);
+                    alpha_sum += std::isfinite(H) ? std::min(1.0, std::exp(H0 - H)) : 0.0;
+                    ++leaf;
+                    if (log_u <= -H) {   // the leaf lies in the slice: a valid proposal
+                        ++n_sub;
+                        uint32_t wl[4];
+                        const uint32_t cl[4] = {(uint32_t)(leaf - 1), (uint32_t)it, chain_id, 3u};
+                        philox(cl, key, wl);
+                        if (u01(wl[0]) * n_sub < 1.0) {   // probability 1 / n_sub
+                            for (int t = 0; t < NP; ++t) { xs[t] = xe[t]; gs[t] = ge[t]; }
+                            lps = lpe;
+                        }
+                    }
+                    if (!(log_u < DELTA_MAX - H)) s_sub = false;   // divergence (or a non-finite H)
+                    // the first leaf of every dyadic block that starts here
+                    for (int l = 1; l <= j; ++l)
+                        if (k % (1L << l) == 0)
+                            for (int t = 0; t < NP; ++t) { ckx[l][t] = xe[t]; ckp[l][t] = pe[t]; }
+                    // every block that ends here (innermost first): its ends must not have turned
+                    for (int l = 1; l <= j && s_sub; ++l)
+                        if ((k + 1) % (1L << l) == 0 && !no_uturn(ckx[l], ckp[l], xe, pe, dirn)) s_sub = false;
+                }
+                for (int k = 0; k < NP; ++k) {
+                    if (dirn < 0) { xl[k] = xe[k]; pl[k] = pe[k]; gl[k] = ge[k]; }
+                    else { xr[k] = xe[k]; pr[k] = pe[k]; grr[k] = ge[k]; }
+                }
+                if (dirn < 0) lpl = lpe; else lpr = lpe;
+                if (s_sub && n_sub > 0 && u01(wj[1]) * n < n_sub) {   // probability min(1, n_sub / n)
+                    for (int k = 0; k < NP; ++k) { xm[k] = xs[k]; gm[k] = gs[k]; }
+                    lpm = lps;
+                }
+                n += n_sub;
+                s_tree = s_sub && no_uturn(xl, pl, xr, pr, 1);
+                ++j;
+            }
+            for (int k = 0; k < NP; ++k) { x[k] = xm[k]; gr[k] = gm[k]; }
+            lp = lpm;
+            const double alpha = alpha_sum / leaf;
+            if (trace_depth) trace_depth[((size_t)it * C + ch) * n_gal + g] = j;
+            if (trace_steps) trace_steps[((size_t)it * C + ch) * n_gal + g] = leaf;
+            if (it < NW) {
+                const double mm = it - da_start + 1.0, eta = 1.0 / (mm + t0);
+                hbar = (1.0 - eta) * hbar + eta * (delta - alpha);
+                const double leps = mu - std::sqrt(mm) / gamma * hbar, wk = std::pow(mm, -kappa);
+                leps_bar = wk * leps + (1.0 - wk) * leps_bar;
+                eps = std::exp(it == NW - 1 ? leps_bar : leps);
+                if (win < n_win && it >= w_start[win]) {
+                    const double nn = it - w_start[win] + 1.0;
+                    for (int k = 0; k < NP; ++k) {
+                        const double d = x[k] - wmu[k];
+                        wmu[k] += d / nn;
+                        wm2[k] += d * (x[k] - wmu[k]);
+                    }
+                    if (it == w_end[win] - 1) {
+                        for (int k = 0; k < NP; ++k) {
+                            minv[k] = nn / (nn + 5.0) * (wm2[k] / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0);
+                            wmu[k] = wm2[k] = 0.0;
+                        }
+                        mu = std::log(10.0 * eps);
+                        hbar = leps_bar = 0.0;
+                        da_start = it + 1;
+                        ++win;
+                    }
+                }
+            } else {
+                acc_sum += alpha;
+                ++n_rec;
+                for (int k = 0; k < NP; ++k) {
+                    const double th = physical(k, x[k]), d = th - mean[k];
+                    mean[k] += d / n_rec;
+                    m2[k] += d * (th - mean[k]);
+                    if (samples) samples[(((size_t)(it - NW) * C + ch) * n_gal + g) * NP + k] = th;
+                }
+            }
+        }
+        if (inv_metric)
+            for (int k = 0; k < NP; ++k) inv_metric[(size_t)cg * NP + k] = minv[k];
+        cacc[cg] = acc_sum;
+        if (step) step[cg] = eps;
+    }
+    delete X;
+    for (int g = 0; g < n_gal; ++g) {
+        double acc = 0.0;
+        for (int ch = 0; ch < C; ++ch) acc += cacc[(size_t)ch * n_gal + g];
+        if (accept) accept[g] = acc / ((double)C * NS);
+        for (int k = 0; k < NP; ++k) {
+            double gm = 0.0, W = 0.0, B = 0.0, ss = 0.0;
+            for (int ch = 0; ch < C; ++ch) {
+                const size_t o = ((size_t)ch * n_gal + g) * NP + k;
+                gm += cmean[o];
+                W += cm2[o] / (NS - 1);
+            }
+            gm /= C;
+            W /= C;
+            for (int ch = 0; ch < C; ++ch) {
+                const size_t o = ((size_t)ch * n_gal + g) * NP + k;
+                B += (cmean[o] - gm) * (cmean[o] - gm);
+                ss += cm2[o] + NS * (cmean[o] - gm) * (cmean[o] - gm);
+            }
+            const double Bn = (C > 1) ? B / (C - 1) : 0.0;
+            const double V = (NS - 1.0) / NS * W + Bn;
+            if (post_mean) post_mean[(size_t)g * NP + k] = gm;
+            if (post_sd) post_sd[(size_t)g * NP + k] = std::sqrt(ss / ((double)C * NS - 1.0));
+            if (rhat) rhat[(size_t)g * NP + k] = (C > 1) ? std::sqrt(V / W) : NaN;
+        }
+    }
+    return 0;
+}
+
 }  // extern "C"

@@ -171,6 +171,27 @@ int orc_hmc_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, cons
                 double *samples, double *trace_logp, int n_gal_total, const uint32_t *gal_id,
                 double *inv_metric, double *trace_acc, double *state);
 
+/* ---- NUTS (Hoffman & Gelman 2014, Algorithm 3 with the dual averaging of Algorithm 6) ---- */
+typedef struct {
+    int n_chain, max_depth, n_warmup, n_sample;   /* max_depth: at most 2^max_depth - 1 leaves (<= 12) */
+    double target_accept, init_step;
+    uint64_t seed;
+    int adapt_metric;   /* 0: identity; 1: diagonal, adapted in the HMC's slow windows */
+    int path;           /* 0 approximate photometry, 1 exact */
+} orc_nuts_cfg;
+
+/* Arguments as orc_hmc_run; accept [g] is the mean acceptance statistic (mean over the leaves
+ * of min(1, exp(H0 - H))) of the sampling phase; trace_depth / trace_steps
+ * [n_warmup+n_sample][c][g] (may be NULL): the tree depth (doublings) and the leapfrog steps
+ * of every iteration. */
+int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
+                 int n_z, double z_lo, double z_hi, const double *q, int sfh, const orc_nuts_cfg *cfg,
+                 int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
+                 const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
+                 double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
+                 double *samples, int *trace_depth, int *trace_steps, double *inv_metric, int n_gal_total,
+                 const uint32_t *gal_id);
+
 /* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
 double orc_rhat(int n_chain, int n, const double *x);
 

@@ -789,3 +789,103 @@ def test_approximation_gap_grows_with_band_width(oracle_mod, ssp_small):
             assert 3.4 <= ratio.min() and ratio.max() <= 25.5
             assert np.percentile(d, 99) < 0.06
     assert all(a < b for a, b in zip(med, med[1:])), med
+
+
+# --------------------------------------------------------------------------
+# NUTS (Hoffman & Gelman 2014, Algorithm 3 with dual averaging)
+# --------------------------------------------------------------------------
+def test_nuts_gaussian_target_moments(orc):
+    # a 10-dimensional Gaussian with scales over a decade: pooled means and sds within
+    # Monte-Carlo error, R-hat ~ 1, the adapted step size near the smallest scale
+    sd = np.array([0.5, 1.0, 2.0, 0.3, 1.5, 1.0, 0.8, 1.2, 2.5, 0.7])
+    th0 = np.random.default_rng(1).normal(size=(4, 3, 10))
+    for adapt in (False, True):
+        out = orc.nuts_run(1, None, None, None, None, None, None, th0, n_chain=4, max_depth=10, n_warmup=500,
+                           n_sample=3000, seed=5, gauss_prec=np.diag(1 / sd ** 2), adapt_metric=adapt)
+        assert np.all(out["rhat"] < 1.01)
+        assert np.all(np.abs(out["post_mean"]) < 4 * sd / math.sqrt(4 * 3000 / 4))
+        np.testing.assert_allclose(out["post_sd"], np.broadcast_to(sd, (3, 10)), rtol=0.05)
+        assert np.all((out["accept"] > 0.7) & (out["accept"] < 0.97))
+
+
+def test_nuts_u_turn_ends_a_harmonic_trajectory_near_half_a_period(orc):
+    # unit Gaussian, identity metric, fixed step 0.1: the phase-space orbits are circles of
+    # period 2 pi, and a trajectory turns after about half a period, pi / 0.1 ~ 31 steps, so
+    # the doubling stops at depth 5 (31 leaves) nearly always; the draws stay N(0, 1)
+    th0 = np.random.default_rng(2).normal(size=(4, 3, 10))
+    out = orc.nuts_run(1, None, None, None, None, None, None, th0, n_chain=4, max_depth=10, n_warmup=0,
+                       n_sample=2000, init_step=0.1, seed=6, gauss_prec=np.eye(10), keep_samples=True)
+    d = out["depth"].ravel()
+    assert np.mean(d == 5) > 0.9 and d.min() >= 4
+    x = out["samples"].reshape(-1, 10)
+    assert stats.kstest(x[:, 0], "norm").pvalue > 1e-3
+    assert abs(x.var() - 1.0) < 0.03
+
+
+def test_nuts_flat_target_proposal_is_uniform_over_the_last_doubling(orc):
+    # zero gradient (flat target): trajectories are straight lines, never turn and never leave
+    # the slice, so every tree reaches max_depth and, at each doubling, the new subtree holds as
+    # many valid leaves as the tree before it: the proposal is taken from it with probability
+    # min(1, n'/n) = 1.  The draw is therefore uniform over the 2^(D-1) leaves of the last
+    # doubling: its distance from the start, in steps, is uniform over that stretch
+    D, eps = 4, 0.5
+    th0 = np.zeros((1, 500, 10))
+    out = orc.nuts_run(1, None, None, None, None, None, None, th0, n_chain=1, max_depth=D, n_warmup=0,
+                       n_sample=2, init_step=eps, seed=7, gauss_prec=np.zeros((10, 10)), keep_samples=True)
+    assert np.all(out["depth"] == D) and np.all(out["steps"] == 2 ** D - 1)
+    # first iteration: x = k eps p0 for the chosen leaf k (signed); |k| in the last doubling is
+    # 2^(D-1) .. 2^D - 1 on the side it grew, minus the leaves of the earlier doublings on
+    # the other side; the leaf's index within the last doubling is uniform on 0 .. 2^(D-1) - 1
+    import oracle
+    idx = []
+    for g in range(500):
+        w = np.concatenate([oracle.philox4x32_10([b, 0, g, 0], [7, 0]) for b in range(3)])
+        u = (w.astype(np.float64) + 0.5) / 2 ** 32
+        p0 = np.empty(10)
+        r = np.sqrt(-2 * np.log(u[0:10:2]))
+        a = 2 * np.pi * u[1:10:2]
+        p0[0::2], p0[1::2] = r * np.cos(a), r * np.sin(a)
+        kk = out["samples"][0, 0, g, 0] / (eps * p0[0])        # signed leaf offset of the draw
+        dirs = [1 if (oracle.philox4x32_10([j, 0, g, 2], [7, 0])[0] + 0.5) / 2 ** 32 >= 0.5 else -1
+                for j in range(D)]
+        left = sum(2 ** j for j in range(D - 1) if dirs[j] < 0)
+        right = sum(2 ** j for j in range(D - 1) if dirs[j] > 0)
+        k = int(round(kk))
+        assert abs(kk - k) < 1e-6
+        if dirs[-1] > 0:
+            assert right < k <= right + 2 ** (D - 1)
+            idx.append(k - right - 1)
+        else:
+            assert -left - 2 ** (D - 1) <= k < -left
+            idx.append(-left - 1 - k)
+    counts = np.bincount(idx, minlength=2 ** (D - 1))
+    assert stats.chisquare(counts).pvalue > 1e-3
+
+
+def test_nuts_step_size_adaptation_reaches_its_target(orc):
+    prec = np.diag(1 / np.linspace(0.5, 2.0, 10) ** 2)
+    th0 = np.random.default_rng(9).normal(size=(4, 2, 10))
+    for target in (0.65, 0.9):
+        out = orc.nuts_run(1, None, None, None, None, None, None, th0, n_chain=4, max_depth=8, n_warmup=600,
+                           n_sample=600, target_accept=target, seed=3, gauss_prec=prec)
+        assert np.all(np.abs(out["accept"] - target) < 0.1)
+
+
+def test_nuts_on_the_sps_posterior_agrees_with_hmc(orc_small):
+    # the same posterior sampled by NUTS and by long-run HMC with an adapted metric: the
+    # posterior means agree within a few posterior sds / sqrt(ESS)
+    sfh, (th, z) = 1, synth.galaxies_dpl(1, 63)
+    obs = orc_small.phot_approx(sfh, th, z) + np.random.default_rng(5).normal(0, 0.05, (1, 6))
+    sig = np.full_like(obs, 0.05)
+    masks = np.array([63], np.uint8)
+    bnd = np.column_stack([synth.BOUNDS, np.ones(10), np.zeros(10)])
+    pri = np.column_stack([np.zeros(10), np.full(10, 1.5), np.zeros(10)])
+    x0 = np.array([[[orc_small.unbound(bnd[p], th[g, p]) for p in range(10)] for g in range(1)]] * 8)
+    nu = orc_small.nuts_run(sfh, z, obs, sig, masks, bnd, pri, x0, n_chain=8, max_depth=6, n_warmup=100,
+                            n_sample=150, seed=11, init_step=0.01, adapt_metric=True)
+    hm = orc_small.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, n_chain=8, n_leapfrog=15, n_warmup=100,
+                           n_sample=150, seed=12, init_step=0.01, adapt_metric=True)
+    assert np.all(np.isfinite(nu["post_mean"]))
+    dev = np.abs(nu["post_mean"] - hm["post_mean"]) / (np.maximum(nu["post_sd"], hm["post_sd"]) + 1e-9)
+    assert np.median(dev) < 0.5, dev
+    assert nu["depth"][100:].mean() > 2
