@@ -87,6 +87,12 @@ def bound_jacobian(bnd, th):
     return bnd[:, 2] * (th - bnd[:, 0]) * (bnd[:, 1] - th) / (bnd[:, 1] - bnd[:, 0])
 
 
+# at most this fraction of chains may be cut short by a near tie: with |log u + dH| < 1e-2 and
+# mostly accepted moves a chain meets one in about 2 % of its iterations, so 8 iterations cut
+# ~15 % of chains; a quarter keeps the comparison from going vacuous
+MAX_EXCUSED = 0.25
+
+
 def draws_follow_oracle(s_gpu, ref, rtol=1e-3, tie=1e-2):
     """Per chain, whether the GPU's draws follow the oracle's on the same Philox stream.
 

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import synth
-from gpu_common import bounds_prior, dev, draws_follow_oracle, f32, gal_inputs, general_bounds_prior
+from gpu_common import MAX_EXCUSED, bounds_prior, dev, draws_follow_oracle, f32, gal_inputs, general_bounds_prior
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,7 @@ def test_first_iterations_match_oracle(ctx, orc):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)        # [s][c][g][10]
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     np.testing.assert_allclose(out["step"].cpu().numpy(), ref["step"], rtol=1e-3)
 
 
@@ -73,7 +73,7 @@ def test_fixed_step_iterations_match_oracle_every_chain(ctx, orc, kind):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 2, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     # the chains move: most iterations are accepted, and the draws are not all the start
     assert np.mean(ref["trace_margin"] < 0) > 0.5
     assert np.all(np.abs(s_gpu[-1] - s_gpu[0]).max(axis=-1) > 0)
@@ -101,7 +101,7 @@ def test_first_iterations_match_oracle_lognormal(ctx, orc):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     # step sizes after two warm-up iterations: dual averaging moves log eps by
     # sqrt(m) / gamma * eta * d(alpha) ~ 2.4 d(alpha); where a chain's acceptance is below 1 the
     # FP32 magnitudes (~1.6e-5 mag) move Delta H, and so alpha, by ~2e-3 here, hence 1e-2
@@ -163,7 +163,7 @@ def test_full_size_batch_short_run(ctx, orc):
                       keep_trace=True, gal_id=pick, n_gal_total=n, **kw)
     s_pick = s[:, :, :, pick].transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_pick, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
 
 
 def test_metric_adaptation_matches_oracle(ctx, orc):
@@ -179,7 +179,7 @@ def test_metric_adaptation_matches_oracle(ctx, orc):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)        # [s][c][g][10]
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     same = ~excused                                                   # [c][g]
     mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)       # [c][g][10]
     assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
@@ -234,7 +234,7 @@ def test_exact_path_first_iterations_match_oracle(ctx_exact, orc):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     np.testing.assert_allclose(out["step"].cpu().numpy(), ref["step"], rtol=1e-3)
 
 
@@ -249,7 +249,7 @@ def test_exact_path_fixed_step_iterations_match_oracle_every_chain(ctx_exact, or
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     assert np.mean(ref["trace_margin"] < 0) > 0.5
 
 
@@ -306,7 +306,7 @@ def test_exact_path_metric_adaptation_matches_oracle(ctx_exact, orc):
     ref = orc.hmc_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, keep_trace=True, path=1, **kw)
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
-    assert ok.all() and excused.sum() <= 1, (ok, excused)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
     same = ~excused
     mi_gpu = out["inv_metric"].cpu().numpy().transpose(0, 2, 1)
     assert np.all(mi_gpu > 0) and not np.all(mi_gpu == 1.0)
@@ -412,4 +412,4 @@ def test_prior_start_matches_oracle(ctx, orc):
     s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)
     ok, excused = draws_follow_oracle(s_gpu, ref)
     dev_ = (np.abs(s_gpu - ref["samples"]) / np.maximum(np.abs(ref["samples"]), 1.0)).max(axis=(0, 3))
-    assert ok.all() and excused.sum() <= 1, (ok, excused, dev_, ref["trace_margin"].transpose(1, 2, 0))
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused, dev_, ref["trace_margin"].transpose(1, 2, 0))
