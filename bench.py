@@ -24,14 +24,25 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s: non-packed FP32 FMA on all SIMDs
-# algorithmic FLOP per value+gradient evaluation of one galaxy (the dense part):
+# MI355X published FP32 vector peak (256 CU x 2.4 GHz; the packed-FP32 rate)
+PEAK_FP32_VECTOR = 157.3
+# counted work of one value+gradient evaluation of one galaxy, in FLOP (lane-ops for the
+# weights, transcendentals weighted x4 as quarter-rate instructions):
 #   forward contraction over both z-table slices: 2 slices x 6 bands x 1128 SSPs x 2 = 27,072
 #   adjoint contraction (d/dP_age over both slices):                              27,072
+#   SSP weights (bin quadrature, burst window, metallicity), forward and adjoint: 2 x 10,000
 CONTRACTION_FLOP_PER_EVAL = 2 * 27_072
+WEIGHTS_OPS_PER_EVAL = 2 * 10_000
+WORK_PER_EVAL = CONTRACTION_FLOP_PER_EVAL + WEIGHTS_OPS_PER_EVAL
+# forward only (the approximate-magnitude workload): one contraction, one weights pass
+WORK_PER_FWD = 27_072 + 10_000
+# algorithmic HBM bytes per galaxy of the approximate forward call: 10 parameters + z in,
+# 6 magnitudes out (FP32)
+APPROX_FWD_BYTES = 4 * (10 + 1 + 6)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_approx_logl_grad_1M_traffic.md")
+FWD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_approx_mags_100k_counters.md")
 
 
 def log(msg):
@@ -56,19 +67,29 @@ def kernel_source_digest(d=None):
     return h.hexdigest()
 
 
-def measured_traffic(path=TRAFFIC_FILE):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or None when the
-    summary is missing or the kernel sources changed since the counters were taken."""
+def profile_values(path, prefix="traffic_"):
+    """The `key: value` lines starting with prefix of a committed rocprofv3 summary, as
+    {key: str}, or None when the summary is missing or the kernel sources changed since its
+    counters were taken (its `<prefix>source_sha256` line no longer matches)."""
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as f:
         for line in f:
-            if line.startswith("traffic_") and ":" in line:
+            if line.startswith(prefix) and ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("traffic_source_sha256") != kernel_source_digest():
+    if vals.get(prefix + "source_sha256") != kernel_source_digest():
+        return None
+    return vals
+
+
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy calibration), or None when the
+    summary is missing or the kernel sources changed since the counters were taken."""
+    vals = profile_values(path)
+    if vals is None:
         return None
     try:
         return float(vals["traffic_fetch_bytes_per_launch"]) + float(vals["traffic_write_bytes_per_launch"])
@@ -76,10 +97,43 @@ def measured_traffic(path=TRAFFIC_FILE):
         return None
 
 
+def measured_busy(path):
+    """VALU and matrix-core busy fractions of the kernel a committed counter summary covers
+    ({"valu_busy": f, "mfma_busy": f}), or None when missing or stale."""
+    vals = profile_values(path, "busy_")
+    if vals is None:
+        return None
+    try:
+        return {"valu_busy": float(vals["busy_valu"]), "mfma_busy": float(vals["busy_mfma"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and the logical CPUs the process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": name, "logical_cpus_available": avail}
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+
+
 def cpu_baseline(ssp, filt, th, z, noise, sig, budget_s=12.0):
-    """The FP64 oracle (as it stands) on a bounded sample of the same workload."""
+    """The FP64 oracle (as it stands) on a bounded sample of the headline workload."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     orc = oracle.Oracle(ssp, filt)
     orc.build_ztable(64, 0.1, 3.0)
 
@@ -95,9 +149,16 @@ def cpu_baseline(ssp, filt, th, z, noise, sig, budget_s=12.0):
     dt = run(probe)
     n = int(min(len(z), max(probe, probe * budget_s / max(dt, 1e-6))))
     dt = run(n)
-    return dict(value=n / dt, unit="evals/s", cores=threads, kind="oracle",
+    return dict(value=n / dt, unit="evals/s", cores=oracle_threads(), kind="oracle",
                 sample=f"first {n} galaxies of the 1,000,000-galaxy workload, value+gradient "
-                       f"(forward-mode dual numbers), FP64, OpenMP over galaxies")
+                       f"(forward-mode dual numbers), FP64, OpenMP over galaxies", **cpu_model())
+
+
+def _scaled_sample(run, n_total, probe, budget_s):
+    """Times run(probe), then run(n) with n sized so that it takes about budget_s; (n, seconds)."""
+    dt = run(probe)
+    n = int(min(n_total, max(probe, probe * budget_s / max(dt, 1e-6))))
+    return n, (run(n) if n != probe else dt)
 
 
 def timed(fn, steps, warmup):
@@ -112,7 +173,96 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def bench_exact(dev, n=4096, steps=5, warmup=2):
+def bench_exact_f64(dev, n=64, steps=20, warmup=3, cpu=True):
+    """Exact photometry in FP64 on the matrix cores (the parity workload): n log-normal-SFH
+    galaxies x 1128 SSPs x 2000 wavelengths x 6 bands, forward magnitudes."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] exact FP64 forward: {n} galaxies x 2000 wavelengths")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F64,), max_gal=n, max_exact=n)
+    th, z = synth.galaxies_lognormal(n, 101, burst=False)
+    params = torch.as_tensor(np.ascontiguousarray(th.T)).to(dev)
+    zt = torch.as_tensor(z).to(dev)
+    fwd = lambda: ctx.phot_exact(synth.SFH_LOGNORMAL, params, zt, prec=sps.SPS_F64)   # noqa: E731
+    t = timed(fwd, steps, warmup)
+    mags = fwd().cpu().numpy()
+    ctx.close()
+    flop = 2.0 * n * 1128 * 2000
+    res = {"workload": f"exact photometry forward, FP64, {n} galaxies (log-normal SFH), 1128 SSPs x 2000 "
+                       "wavelengths x 6 bands", "unit": "evals/s", "evals_per_s": n / t, "ms_forward": t * 1e3,
+           "gemm_tflops": flop / t / 1e12, "fp64_mfma_peak_tflops": 78.6,
+           "frac_of_fp64_mfma_peak": flop / t / 1e12 / 78.6}
+    log(f"[bench]   FP64 forward {t * 1e3:.3f} ms")
+    if cpu:
+        import oracle
+        orc = oracle.Oracle(ssp, filt)
+        t0 = time.perf_counter()
+        ref = orc.phot_exact(synth.SFH_LOGNORMAL, th, z)
+        dt = time.perf_counter() - t0
+        res["max_abs_dmag_vs_oracle"] = float(np.abs(mags - ref).max())
+        res["cpu_baseline"] = dict(value=n / dt, unit="evals/s", cores=oracle_threads(), kind="oracle",
+                                   sample=f"all {n} galaxies, FP64 forward", **cpu_model())
+        log(f"[bench]   max |dm| vs oracle {res['max_abs_dmag_vs_oracle']:.2e}; oracle {dt:.2f} s")
+    return res
+
+
+def bench_approx_fwd(dev, n=100_000, steps=20, warmup=3, cpu=True, budget_s=8.0):
+    """Approximate magnitudes (the z-table path), forward only: n log-normal-SFH galaxies with a
+    burst, 6 bands; evals/s, algorithmic HBM rate and the model kernel's own duration."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] approximate forward: {n} galaxies")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F64,), max_gal=n)
+    ctx.build_ztable(64, 0.1, 3.0)
+    th, z = synth.galaxies_lognormal(n, 102, burst=True)
+    params = torch.as_tensor(synth.soa32(th)).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    out = torch.empty((n, 6), dtype=torch.float32, device=dev)
+    fwd = lambda: ctx.phot_approx(synth.SFH_LOGNORMAL, params, zt, out=out)   # noqa: E731
+    for _ in range(warmup):
+        fwd()
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(steps)
+    t = timed(fwd, steps, 0)
+    kernel_ms = float(np.mean(ctx.kernel_times()))
+    ctx.set_kernel_timing(0)
+    ctx.close()
+    work = WORK_PER_FWD * n / (kernel_ms * 1e-3) / 1e12
+    res = {"workload": f"approximate photometry forward, FP32, {n} galaxies (log-normal SFH with burst), "
+                       "6 bands, z table 64 nodes", "unit": "evals/s", "evals_per_s": n / t,
+           "ms_per_call": t * 1e3, "kernel": "k_approx<MODE_MAGS>", "kernel_ms": kernel_ms,
+           "hbm_gbps_algorithmic_call": APPROX_FWD_BYTES * n / t / 1e9,
+           "hbm_gbps_algorithmic_kernel": APPROX_FWD_BYTES * n / (kernel_ms * 1e-3) / 1e9,
+           "algorithmic_bytes_per_galaxy": APPROX_FWD_BYTES,
+           "work_per_galaxy": WORK_PER_FWD, "work_tflops": work,
+           "frac_of_fp32_vector_peak": work / PEAK_FP32_VECTOR}
+    busy = measured_busy(FWD_COUNTERS_FILE)
+    if busy:
+        res.update(busy)
+    log(f"[bench]   {t * 1e3:.3f} ms per call (kernel {kernel_ms:.3f} ms), "
+        f"{res['hbm_gbps_algorithmic_call']:.1f} GB/s algorithmic")
+    if cpu:
+        import oracle
+        orc = oracle.Oracle(ssp, filt)
+        orc.build_ztable(64, 0.1, 3.0)
+
+        def run(m):
+            t0 = time.perf_counter()
+            orc.phot_approx(synth.SFH_LOGNORMAL, th[:m], z[:m])
+            return time.perf_counter() - t0
+        m, dt = _scaled_sample(run, n, 512, budget_s)
+        res["cpu_baseline"] = dict(value=m / dt, unit="evals/s", cores=oracle_threads(), kind="oracle",
+                                   sample=f"first {m} of the {n} galaxies, FP64 forward", **cpu_model())
+    return res
+
+
+def bench_exact(dev, n=4096, steps=5, warmup=2, cpu=False, budget_s=10.0):
     """Exact-photometry value+gradient (MFMA) at 4096 galaxies x 1128 SSPs x 5000 wavelengths."""
     import torch
 
@@ -151,13 +301,29 @@ def bench_exact(dev, n=4096, steps=5, warmup=2):
                      "dense_equivalent_frac_of_peak_forward": mult * gemm_flop / fwd / 1e12 / peak,
                      "dense_equivalent_frac_of_peak_value_grad": mult * 2 * gemm_flop / vg / 1e12 / peak}
         log(f"[bench]   {name}: fwd {fwd * 1e3:.3f} ms, value+grad {vg * 1e3:.3f} ms")
+    obs_h = obs.cpu().numpy().astype(np.float64)
     ctx.close()
+    if cpu:
+        import oracle
+        orc = oracle.Oracle(ssp, filt)
+        m64 = np.full(n, 63, np.uint8)
+
+        def run(m):
+            t0 = time.perf_counter()
+            orc.loglike_grad(synth.SFH_DPL, th[:m], z[:m], obs_h[:m], sig[:m], m64[:m], path=1)
+            return time.perf_counter() - t0
+        m, dt = _scaled_sample(run, n, 16, budget_s)
+        res["cpu_baseline"] = dict(value=m / dt, unit="evals/s", cores=oracle_threads(), kind="oracle",
+                                   sample=f"first {m} of the {n} galaxies, exact value+gradient, FP64 "
+                                          "(forward-mode dual numbers)", **cpu_model())
     return res
 
 
-def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False):
-    """Batched HMC: n galaxies x C chains, L leapfrog steps, warm-up + sampling; posteriors/min.
-    adapt_metric: identity mass matrix (False) or the windowed diagonal adaptation (True)."""
+def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False, cpu=False, budget_s=12.0):
+    """Batched HMC: n galaxies x C chains, L leapfrog steps, warm-up + sampling; converged
+    posteriors/min (all ten R-hat < 1.2) and the raw rate over all galaxies.
+    adapt_metric: identity mass matrix (False) or the windowed diagonal adaptation (True).
+    cpu: also run the oracle's HMC for whole runs of as many chains as it has threads."""
     import torch
 
     import paper_2506_19919_amd as sps
@@ -190,16 +356,37 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False):
     conv = float(np.mean(np.all(rhat < 1.2, axis=0)))
     evals = float(n) * C * (n_warm + n_samp) * L
     ctx.close()
-    log(f"[bench]   HMC wall {wall:.2f} s, converged fraction {conv:.3f} (adapt_metric={adapt_metric})")
-    return {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, {n_warm} warm-up + {n_samp} samples, "
-                        "approximate photometry, 3-6 bands per galaxy, starts drawn from the prior",
-            "mass_matrix": "diagonal, adapted in slow warm-up windows" if adapt_metric else "identity",
-            "posteriors_per_min": n / wall * 60.0,
-            "converged_posteriors_per_min": conv * n / wall * 60.0,
-            "converged_fraction_rhat_lt_1.2": conv,
-            "value_grad_evals_per_s": evals / wall,
-            "wall_s": wall,
-            "mean_accept": float(out["accept"].mean().item())}
+    log(f"[bench]   HMC wall {wall:.2f} s, converged fraction {conv:.3f} (adapt_metric={adapt_metric}, L={L})")
+    res = {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, {n_warm} warm-up + {n_samp} samples, "
+                       "approximate photometry, 3-6 bands per galaxy, starts drawn from the prior",
+           "mass_matrix": "diagonal, adapted in slow warm-up windows" if adapt_metric else "identity",
+           "unit": "converged posteriors/min (all ten R-hat < 1.2)",
+           "converged_posteriors_per_min": conv * n / wall * 60.0,
+           "converged_fraction_rhat_lt_1.2": conv,
+           "posteriors_per_min_all_galaxies": n / wall * 60.0,
+           "value_grad_evals_per_s": evals / wall,
+           "wall_s": wall,
+           "mean_accept": float(out["accept"].mean().item())}
+    if cpu:
+        import oracle
+        m = max(1, oracle_threads() // C)
+        orc = oracle.Oracle(ssp, filt)
+        orc.build_ztable(64, 0.1, 3.0)
+        x0 = np.ascontiguousarray(synth.prior_draws(C, n, 304)[:, :, :m].transpose(0, 2, 1))
+        obs_h = obs[:m].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        ref = orc.hmc_run(synth.SFH_DPL, z[:m], obs_h, sig[:m], mask[:m].cpu().numpy(), synth.bounds_k_x0(),
+                          synth.PRIOR, x0, n_chain=C, n_leapfrog=L, n_warmup=n_warm, n_sample=n_samp, seed=404,
+                          adapt_metric=adapt_metric)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = dict(value=m / dt * 60.0, unit="posteriors/min (all galaxies)",
+                                   cores=oracle_threads(), kind="oracle",
+                                   sample=f"first {m} galaxies x {C} chains, the full {n_warm} + {n_samp} "
+                                          f"iterations ({m * C} chains, one per thread)",
+                                   converged_fraction=float(np.mean(np.all(ref["rhat"] < 1.2, axis=1))),
+                                   **cpu_model())
+        log(f"[bench]   oracle HMC: {m} galaxies in {dt:.1f} s")
+    return res
 
 
 def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=None):
@@ -253,9 +440,11 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
     return res
 
 
-def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0)):
-    """Approximate-minus-exact magnitudes (App. B) against the Gaussian band width, on the GPU:
-    FP32 exact path vs the z-table path for n galaxies of the likelihood workload's generator."""
+def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0), tau_vs=(0.0, 0.5, 1.0, 2.0, 4.0)):
+    """Approximate-minus-exact magnitudes (App. B) against the Gaussian band width and against
+    the dust optical depth, on the GPU: FP32 exact path vs the z-table path for n galaxies of the
+    likelihood workload's generator (for the tau_V axis: 400 A bands, tau_V set to each value
+    for every galaxy)."""
     import torch
 
     import paper_2506_19919_amd as sps
@@ -280,6 +469,25 @@ def bench_approx_accuracy(dev, n=4096, sigmas=(200.0, 400.0, 800.0)):
                                      "max": float(d.max())}
         log(f"[bench]   sigma {sig:.0f} A: median {np.median(d):.2e}, p95 {np.percentile(d, 95):.2e}, "
             f"max {d.max():.2e} mag")
+    filt = synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F32,), max_gal=n, max_exact=n)
+    ctx.build_ztable(64, 0.1, 3.0)
+    # the generator's attenuation floors (F_floor up to 0.3) flatten F_att at large tau_V; the
+    # second sweep sets every floor to 0
+    for floor in (None, 0.0):
+        for tv in tau_vs:
+            t2 = th.copy()
+            t2[:, synth.P_TAUV] = tv
+            if floor is not None:
+                t2[:, synth.P_FFLOOR] = floor
+            p2 = torch.as_tensor(synth.soa32(t2)).to(dev)
+            d = (ctx.phot_approx(synth.SFH_DPL, p2, zt)
+                 - ctx.phot_exact(synth.SFH_DPL, p2, zt, prec=sps.SPS_F32)).abs().cpu().numpy()
+            key = f"tau_v_{tv:g}" + ("" if floor is None else "_no_floor")
+            res[key] = {"sigma_A": 400.0, "f_floor": "generator U(0, 0.3)" if floor is None else floor,
+                        "median": float(np.median(d)), "p95": float(np.percentile(d, 95)), "max": float(d.max())}
+            log(f"[bench]   {key}: median {np.median(d):.2e}, p95 {np.percentile(d, 95):.2e}, max {d.max():.2e} mag")
+    ctx.close()
     return res
 
 
@@ -346,6 +554,7 @@ def main():
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-hmc-exact", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-approx-fwd", action="store_true")
     ap.add_argument("--no-posterior-agreement", action="store_true")
     ap.add_argument("--hmc-exact-iters", type=int, default=6,
                     help="iterations timed in the exact-path HMC leg (the full run length is extrapolated)")
@@ -417,7 +626,8 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (step events {per_launch_ms:.3f} ms, "
         f"k_approx events {kernel_ms:.3f} ms)")
 
-    achieved = CONTRACTION_FLOP_PER_EVAL * n / (kernel_ms * 1e-3) / 1e12
+    achieved = WORK_PER_EVAL * n / (kernel_ms * 1e-3) / 1e12
+    contraction_rate = CONTRACTION_FLOP_PER_EVAL * n / (kernel_ms * 1e-3) / 1e12
     out = {
         "metric": "photometry value+grad evals/s (exact vs approx); HMC posteriors/min, 1 GPU",
         "value": value,
@@ -429,7 +639,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32 (contractions: bf16 hi+lo x3 on MFMA, f32 accumulate)",
         "data": "synthetic",
         "config": {
             "workload": "log-likelihood value+gradient, approximate photometry, 1,000,000 galaxies, "
@@ -440,26 +650,38 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": PEAK_FP32_VALU,
+            "peak": PEAK_FP32_VECTOR,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU,
+            "frac": achieved / PEAK_FP32_VECTOR,
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_approx<MODE_LOGL_GRAD>, per-launch time from HIP events recorded around it on "
                       "its stream",
             "kernel_ms": kernel_ms,
             "step_ms_events": per_launch_ms,
-            "flop_per_launch": CONTRACTION_FLOP_PER_EVAL * n,
+            "work_per_eval": {"contraction_flop": CONTRACTION_FLOP_PER_EVAL,
+                              "weights_lane_ops": WEIGHTS_OPS_PER_EVAL, "total": WORK_PER_EVAL},
+            "work_per_launch": WORK_PER_EVAL * n,
+            "contraction_only_tflops": contraction_rate,
+            "contraction_only_frac": contraction_rate / PEAK_FP32_VECTOR,
         },
     }
+    busy = measured_busy(TRAFFIC_FILE)
+    if busy:
+        out["roofline"].update(busy)
     del params, zt, obs, sigma, mask, logl, grad, mags
     ctx.close()
+    cpu = not args.no_cpu_baseline
     if not args.no_exact:
-        out["exact"] = bench_exact(dev)
+        out["exact_f64"] = bench_exact_f64(dev, cpu=cpu)
+    if not args.no_approx_fwd:
+        out["approx_fwd"] = bench_approx_fwd(dev, cpu=cpu)
+    if not args.no_exact:
+        out["exact"] = bench_exact(dev, cpu=cpu)
     if not args.no_accuracy:
         out["approx_accuracy"] = bench_approx_accuracy(dev)
     if not args.no_hmc:
-        out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample)
+        out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample, cpu=cpu)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
                                               adapt_metric=True)
     if not args.no_posterior_agreement:

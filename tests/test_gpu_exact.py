@@ -245,6 +245,27 @@ def test_approximation_gap_matches_oracle(ssp2000, oracle_mod, sigma_A):
         c.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("tau_v", [0.0, 4.0])
+def test_approximation_gap_against_dust_matches_oracle(ssp2000, filt6, oracle_mod, tau_v):
+    # the tau_V axis of the approximation study (App. B): the GPU's approximate-minus-exact gap
+    # equals the oracle's per galaxy and band with every galaxy at one optical depth
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=4096, max_exact=4096)
+    try:
+        c.build_ztable(64, 0.1, 3.0)
+        o = oracle_mod.Oracle(ssp2000, filt6)
+        o.build_ztable(64, 0.1, 3.0)
+        sfh, th, z = gal_inputs("dpl", 96, 74)
+        th[:, synth.P_TAUV] = tau_v
+        ma = c.phot_approx(sfh, soa(th), dev(z)).cpu().numpy().astype(np.float64)
+        me = c.phot_exact(sfh, soa(th), dev(z), prec=sps.SPS_F32).cpu().numpy().astype(np.float64)
+        ref = o.phot_approx(sfh, th, z) - o.phot_exact(sfh, th, z)
+        assert np.abs((ma - me) - ref).max() <= 2e-4
+    finally:
+        c.close()
+
+
 def test_exact_call_beyond_the_reservation_is_refused(ssp2000, filt6):
     # compute calls never allocate: a batch larger than sps_reserve_exact sized the workspace
     # for is an error, and reserving more makes the same call work

@@ -791,6 +791,36 @@ def test_approximation_gap_grows_with_band_width(oracle_mod, ssp_small):
     assert all(a < b for a, b in zip(med, med[1:])), med
 
 
+def test_approximation_gap_grows_with_dust_optical_depth(oracle_mod, ssp_small):
+    # App. B: the table path takes the attenuation at the band's effective wavelength, so its
+    # error grows with how much the attenuation varies across the band, i.e. with tau_V.  With
+    # no attenuation (tau_V = 0, or a floor F_floor = 1) what is left is the interpolation of the
+    # table in z alone: the same gap whatever the dust slope
+    o = oracle_mod.Oracle(ssp_small, synth.filters())
+    o.build_ztable(64, 0.1, 3.0)
+    th, z = synth.galaxies_dpl(24, 73)
+    th[:, synth.P_FFLOOR] = 0.0
+
+    def gap(t):
+        return o.phot_approx(1, t, z) - o.phot_exact(1, t, z)
+    t0 = th.copy()
+    t0[:, synth.P_TAUV] = 0.0
+    g0 = gap(t0)
+    t1 = t0.copy()
+    t1[:, synth.P_DELTA] = -1.4
+    np.testing.assert_allclose(gap(t1), g0, rtol=0, atol=1e-12)
+    t2 = th.copy()
+    t2[:, synth.P_TAUV] = 3.0
+    t2[:, synth.P_FFLOOR] = 1.0
+    np.testing.assert_allclose(gap(t2), g0, rtol=0, atol=1e-12)
+    med = []
+    for tv in (0.0, 0.5, 1.0, 2.0, 4.0):
+        t = th.copy()
+        t[:, synth.P_TAUV] = tv
+        med.append(np.median(np.abs(gap(t))))
+    assert all(a < b for a, b in zip(med, med[1:])), med
+
+
 # --------------------------------------------------------------------------
 # NUTS (Hoffman & Gelman 2014, Algorithm 3 with dual averaging)
 # --------------------------------------------------------------------------
