@@ -389,6 +389,62 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False, cpu=False, 
     return res
 
 
+def bench_nuts(dev, n=16_384, n_warm=100, n_samp=200, C=4, max_depth=8):
+    """NUTS on n galaxies of the HMC workload x C chains, both lock-step schedules: the chains
+    of a wave starting every iteration together (sync, the vectorised-over-chains form) or each
+    chain moving on when its own tree is done.  Reports the wall time, converged posteriors per
+    minute, leapfrog steps per second and the lock-step efficiency (the chains' leapfrog steps
+    over the steps their waves took times the chains per wave)."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] NUTS: {n} galaxies x {C} chains, {n_warm} + {n_samp} iterations, max depth {max_depth}")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_F64,), max_gal=n * C)
+    ctx.build_ztable(64, 0.1, 3.0)
+    ctx.reserve_nuts(n * C, max_depth)
+    th, z = synth.galaxies_dpl(16_384, 104)
+    th, z = th[:n], z[:n]
+    params = torch.as_tensor(synth.soa32(th)).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    noise, sig = synth.photometric_noise(16_384, 6, 204)
+    mags = ctx.phot_approx(synth.SFH_DPL, params, zt)
+    obs = (mags + torch.as_tensor(noise[:n], dtype=torch.float32, device=dev)).contiguous()
+    sigma = torch.as_tensor(sig[:n], dtype=torch.float32, device=dev).contiguous()
+    mask = torch.as_tensor(np.ascontiguousarray(synth.band_masks(16_384, 6, 204)[:n])).to(dev)
+    bounds = torch.as_tensor(synth.bounds_k_x0(), dtype=torch.float32, device=dev)
+    prior = torch.as_tensor(synth.PRIOR, dtype=torch.float32, device=dev)
+    theta0 = torch.as_tensor(np.ascontiguousarray(synth.prior_draws(C, 16_384, 304)[:, :, :n]),
+                             dtype=torch.float32, device=dev)
+    res = {"workload": f"{n} galaxies of the HMC workload x {C} chains, NUTS max depth {max_depth}, {n_warm} warm-up "
+                       f"+ {n_samp} samples, approximate photometry", "unit": "converged posteriors/min"}
+    kw = dict(n_chain=C, max_depth=max_depth, n_warmup=n_warm, n_sample=n_samp, seed=404)
+    ctx.nuts_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, n_chain=C, max_depth=3, n_warmup=1,
+                 n_sample=2, seed=1)
+    for name, sync in (("sync", True), ("free", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.nuts_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, sync_iterations=sync,
+                           keep_depth=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lk = out["lockstep"].cpu().numpy().astype(np.float64)
+        conv = float(np.mean(np.all(out["rhat"].cpu().numpy() < 1.2, axis=0)))
+        depth = out["depth"].cpu().numpy()
+        res[name] = {"wall_s": wall, "converged_fraction_rhat_lt_1.2": conv,
+                     "converged_posteriors_per_min": conv * n / wall * 60.0,
+                     "posteriors_per_min_all_galaxies": n / wall * 60.0,
+                     "leapfrog_steps_per_s": lk[0] / wall, "lockstep_efficiency": lk[0] / max(lk[1], 1.0),
+                     "mean_tree_depth": float(depth.mean()), "max_tree_depth": int(depth.max()),
+                     "mean_leapfrog_steps_per_iteration": lk[0] / (n * C * (n_warm + n_samp)),
+                     "mean_accept": float(out["accept"].mean().item())}
+        log(f"[bench]   {name}: wall {wall:.2f} s, lock-step efficiency {res[name]['lockstep_efficiency']:.3f}, "
+            f"mean depth {depth.mean():.2f}, converged {conv:.3f}")
+    ctx.close()
+    return res
+
+
 def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=None):
     """HMC with exact photometry on the HMC workload's shape: every leapfrog step is one MFMA
     value+gradient over all n x C chains.  A short run (n_iter iterations, timed) gives the
@@ -555,6 +611,7 @@ def main():
     ap.add_argument("--no-hmc-exact", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-approx-fwd", action="store_true")
+    ap.add_argument("--no-nuts", action="store_true")
     ap.add_argument("--no-posterior-agreement", action="store_true")
     ap.add_argument("--hmc-exact-iters", type=int, default=6,
                     help="iterations timed in the exact-path HMC leg (the full run length is extrapolated)")
@@ -684,6 +741,8 @@ def main():
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample, cpu=cpu)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
                                               adapt_metric=True)
+    if not args.no_nuts:
+        out["nuts"] = bench_nuts(dev)
     if not args.no_posterior_agreement:
         out["posterior_agreement"] = bench_posterior_agreement(dev)
     if not args.no_hmc_exact:

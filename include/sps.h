@@ -248,6 +248,50 @@ int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, i
  * a 256-byte header and 312 bytes per chain. */
 size_t sps_hmc_state_bytes(int n_gal, int n_chain);
 
+/* No-U-Turn Sampler (the paper's second gradient-based sampler, Sec. 4 and App. D.2):
+ * Hoffman & Gelman (2014), Algorithm 3 (slice variable, trajectory doubling in a random
+ * direction, a new subtree's proposal taken with probability min(1, n'/n)) with the dual
+ * averaging of their Algorithm 6 (acceptance statistic: the mean of min(1, exp(H0 - H)) over
+ * the final tree's leaves, target target_accept); identity or windowed diagonal metric as in
+ * sps_hmc_run.  Approximate photometry (the z table) only.  At most 2^max_depth - 1 leapfrog
+ * steps per iteration, 1 <= max_depth <= 12.
+ * Philox4x32-10 keyed by seed (chain id = c * n_gal + g): momentum and slice (counter
+ * (blk 0..2, it, chain id, 0): words 0..9 the momentum as in HMC, word 10 the slice uniform),
+ * per doubling j (j, it, chain id, 2: word 0 the direction, word 1 the subtree's acceptance),
+ * per leaf (leaf index within the iteration, it, chain id, 3: the reservoir uniform).
+ * Chains run in lock-step per wavefront (32 chains of a wave evaluate the model together):
+ * sync_iterations = 1 makes a wave's chains start every iteration together, so that each
+ * iteration lasts as long as the wave's deepest tree; 0 lets a chain whose tree is done start
+ * its next iteration at once.  The draws are the same either way.
+ * Arguments as sps_hmc_run (whole runs only: no resume blob), plus, all optional (NULL):
+ *   depth [n_warmup + n_sample][n_chain][n_gal] int: tree depth (doublings) per iteration,
+ *   n_leaf [n_chain][n_gal] int: leapfrog steps of each chain over the run,
+ *   lockstep [2] unsigned long long: [0] the chains' leapfrog steps, [1] the steps the waves
+ *     took times the chains they hold (the evaluations the hardware spent); [0] / [1] is the
+ *     lock-step efficiency.
+ * accept [n_gal] is the mean acceptance statistic of the sampling phase.  Needs a workspace
+ * from sps_reserve_nuts for n_gal * n_chain chains at this max_depth (else SPS_E_STATE) and
+ * n_gal <= the galaxies reserved by sps_reserve. */
+typedef struct {
+    int n_chain, max_depth, n_warmup, n_sample;
+    float target_accept, init_step;
+    unsigned long long seed;
+    int adapt_metric;
+    int sync_iterations;
+} sps_nuts_cfg;
+
+int sps_nuts_run(sps_ctx *ctx, void *stream, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
+                 const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
+                 const float *prior, const float *theta0, float *samples, float *post_mean, float *post_sd,
+                 float *rhat, float *accept, float *step, float *inv_metric, int *depth, int *n_leaf,
+                 unsigned long long *lockstep);
+
+/* Size the NUTS workspace for up to max_chains chains (n_gal * n_chain) at trees of up to
+ * max_depth doublings: the chain state, the two ends of the trajectory, the proposals and
+ * one checkpoint per doubling level (about (1.6 + 0.08 max_depth) KB per chain).  Also grows
+ * sps_reserve's galaxy count to max_chains.  Synchronises the device; never shrinks. */
+int sps_reserve_nuts(sps_ctx *ctx, int max_chains, int max_depth);
+
 #ifdef __cplusplus
 }
 #endif

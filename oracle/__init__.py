@@ -361,7 +361,8 @@ def _nuts_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, 
               n_sample=1000, target_accept=0.8, init_step=0.1, seed=404, keep_samples=False, gauss_prec=None,
               gal_id=None, n_gal_total=0, adapt_metric=False, path=0, n_gal=None):
     """NUTS (Hoffman & Gelman 2014, Algorithm 3 + dual averaging); arguments as hmc_run.
-    Returns the summaries, and per iteration the tree depth and leapfrog steps."""
+    Returns the summaries, and per iteration the tree depth, the leapfrog steps and how near its
+    slice and U-turn decisions came to their thresholds (margin_slice, margin_turn)."""
     if theta0 is not None:
         th0 = _f64(theta0)
         n_gal = th0.shape[1]
@@ -378,6 +379,7 @@ def _nuts_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, 
     smp = np.zeros((n_sample, n_chain, n_gal, N_PARAM)) if keep_samples else None
     depth = np.zeros((n_warmup + n_sample, n_chain, n_gal), np.int32)
     steps = np.zeros((n_warmup + n_sample, n_chain, n_gal), np.int32)
+    margin = np.zeros((n_warmup + n_sample, n_chain, n_gal, 2))
     gp = _f64(gauss_prec) if gauss_prec is not None else None
     if gp is None:
         n_z, lo, hi, qp = self._zt() if path == 0 else (0, C.c_double(0), C.c_double(0), None)
@@ -392,10 +394,11 @@ def _nuts_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, 
     gid = np.ascontiguousarray(gal_id, dtype=np.uint32) if gal_id is not None else None
     rc = self.L.orc_nuts_run(C.byref(self.ssp), C.byref(self.filt), C.byref(self.cosmo), C.byref(self.model), n_z,
                              lo, hi, qp, sfh, C.byref(cfg), n_gal, *args, _p(th0), _p(gp), _p(pm), _p(ps), _p(rh),
-                             _p(acc), _p(step), _p(smp), _p(depth), _p(steps), _p(minv), int(n_gal_total), _p(gid))
+                             _p(acc), _p(step), _p(smp), _p(depth), _p(steps), _p(margin), _p(minv), int(n_gal_total),
+                             _p(gid))
     assert rc == 0, rc
     out = dict(post_mean=pm, post_sd=ps, rhat=rh, accept=acc, step=step, inv_metric=minv, depth=depth,
-               steps=steps)
+               steps=steps, margin_slice=margin[..., 0], margin_turn=margin[..., 1])
     if smp is not None:
         out["samples"] = smp
     return out

@@ -1104,8 +1104,8 @@ int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
                  int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
                  const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
                  double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                 double *samples, int *trace_depth, int *trace_steps, double *inv_metric, int n_gal_total,
-                 const uint32_t *gal_id) {
+                 double *samples, int *trace_depth, int *trace_steps, double *trace_margin, double *inv_metric,
+                 int n_gal_total, const uint32_t *gal_id) {
     if (!cfg || cfg->n_chain < 1 || cfg->max_depth < 1 || cfg->max_depth > 12 || cfg->n_warmup < 0 ||
         cfg->n_sample < 2 || n_gal < 0)
         return 1;
@@ -1161,14 +1161,23 @@ int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
             for (int k = 0; k < NP; ++k) e += 0.5 * minv[k] * pv[k] * pv[k];
             return e;
         };
+        // smallest distance of this iteration's decisions from their thresholds (trace only):
+        // |log u + H| over the leaves, and the cosine of the angle between the stretch and the
+        // velocity at its ends over the U-turn tests
+        double mg_slice = INFINITY, mg_turn = INFINITY;
         // no U-turn between the forward-time ends of a stretch: (x+ - x-) . M^-1 p >= 0 at both
         auto no_uturn = [&](const double *xa, const double *pa, const double *xb, const double *pb, int dirn) {
-            double da = 0.0, db = 0.0;
+            double da = 0.0, db = 0.0, dd = 0.0, va = 0.0, vb = 0.0;
             for (int k = 0; k < NP; ++k) {
                 const double dx = dirn * (xb[k] - xa[k]);
                 da += dx * minv[k] * pa[k];
                 db += dx * minv[k] * pb[k];
+                dd += dx * dx;
+                va += minv[k] * pa[k] * minv[k] * pa[k];
+                vb += minv[k] * pb[k] * minv[k] * pb[k];
             }
+            if (dd > 0.0 && va > 0.0 && vb > 0.0)
+                mg_turn = std::min(mg_turn, std::min(std::fabs(da) / std::sqrt(dd * va), std::fabs(db) / std::sqrt(dd * vb)));
             return da >= 0.0 && db >= 0.0;
         };
         for (int it = 0; it < NIT; ++it) {
@@ -1185,6 +1194,7 @@ int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
             }
             const double H0 = -lp + kinetic(p0);
             const double log_u = std::log(u01(w[10])) - H0;   // slice variable u ~ U(0, exp(-H0))
+            mg_slice = mg_turn = INFINITY;
             // the tree's two ends, the proposal
             double xl[NP], pl[NP], gl[NP], xr[NP], pr[NP], grr[NP], xm[NP], gm[NP], lpl = lp, lpr = lp, lpm = lp;
             for (int k = 0; k < NP; ++k) {
@@ -1222,6 +1232,7 @@ int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
                     for (int t = 0; t < NP; ++t) pe[t] += 0.5 * e * ge[t];
                     const double H = -lpe + kinetic(pe);
                     alpha_sum += std::isfinite(H) ? std::min(1.0, std::exp(H0 - H)) : 0.0;
+                    if (std::isfinite(H)) mg_slice = std::min(mg_slice, std::fabs(log_u + H));
                     ++leaf;
                     if (log_u <= -H) {   // the leaf lies in the slice: a valid proposal
                         ++n_sub;
@@ -1260,6 +1271,10 @@ int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, con
             const double alpha = alpha_sum / leaf;
             if (trace_depth) trace_depth[((size_t)it * C + ch) * n_gal + g] = j;
             if (trace_steps) trace_steps[((size_t)it * C + ch) * n_gal + g] = leaf;
+            if (trace_margin) {
+                trace_margin[(((size_t)it * C + ch) * n_gal + g) * 2] = mg_slice;
+                trace_margin[(((size_t)it * C + ch) * n_gal + g) * 2 + 1] = mg_turn;
+            }
             if (it < NW) {
                 const double mm = it - da_start + 1.0, eta = 1.0 / (mm + t0);
                 hbar = (1.0 - eta) * hbar + eta * (delta - alpha);

@@ -183,14 +183,17 @@ typedef struct {
 /* Arguments as orc_hmc_run; accept [g] is the mean acceptance statistic (mean over the leaves
  * of min(1, exp(H0 - H))) of the sampling phase; trace_depth / trace_steps
  * [n_warmup+n_sample][c][g] (may be NULL): the tree depth (doublings) and the leapfrog steps
- * of every iteration. */
+ * of every iteration; trace_margin [n_warmup+n_sample][c][g][2] (may be NULL): per iteration
+ * the smallest |log u + H| over the leaves (slice membership) and the smallest cosine between
+ * a tested stretch and the velocity at its ends (U-turn tests), i.e. how near the iteration's
+ * decisions came to their thresholds. */
 int orc_nuts_run(const orc_ssp *s, const orc_filters *f, const orc_cosmo *c, const orc_model *m,
                  int n_z, double z_lo, double z_hi, const double *q, int sfh, const orc_nuts_cfg *cfg,
                  int n_gal, const double *z, const double *obs, const double *sigma, const uint8_t *mask,
                  const double *bounds, const double *prior, const double *theta0, const double *gauss_prec,
                  double *post_mean, double *post_sd, double *rhat, double *accept, double *step,
-                 double *samples, int *trace_depth, int *trace_steps, double *inv_metric, int n_gal_total,
-                 const uint32_t *gal_id);
+                 double *samples, int *trace_depth, int *trace_steps, double *trace_margin, double *inv_metric,
+                 int n_gal_total, const uint32_t *gal_id);
 
 /* classic Gelman-Rubin R-hat over x[c][n] (n_chain chains of n draws) */
 double orc_rhat(int n_chain, int n, const double *x);

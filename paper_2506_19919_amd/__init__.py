@@ -27,7 +27,7 @@ MAX_BAND = 8
 ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_reserve_exact", "sps_status", "sps_build_ztable",
                  "sps_get_ztable", "sps_destroy", "sps_last_error", "sps_weights", "sps_phot_approx",
                  "sps_phot_exact", "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_hmc_state_bytes",
-                 "sps_set_kernel_timing", "sps_kernel_times")
+                 "sps_set_kernel_timing", "sps_kernel_times", "sps_nuts_run", "sps_reserve_nuts")
 
 
 class SpsError(RuntimeError):
@@ -59,6 +59,12 @@ class _HmcCfg(C.Structure):
                 ("it_begin", C.c_int), ("it_end", C.c_int)]
 
 
+class _NutsCfg(C.Structure):
+    _fields_ = [("n_chain", C.c_int), ("max_depth", C.c_int), ("n_warmup", C.c_int),
+                ("n_sample", C.c_int), ("target_accept", C.c_float), ("init_step", C.c_float),
+                ("seed", C.c_ulonglong), ("adapt_metric", C.c_int), ("sync_iterations", C.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_19919_amd/build.py")
@@ -84,6 +90,9 @@ def _load():
     lib.sps_logpost_grad.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_hmc_run.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp, vp, vp]
+    lib.sps_nuts_run.argtypes = [vp, vp, C.POINTER(_NutsCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
+                                 vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sps_reserve_nuts.argtypes = [vp, i, i]
     lib.sps_set_kernel_timing.argtypes = [vp, i]
     lib.sps_kernel_times.argtypes = [vp, vp, i, C.POINTER(i)]
     for name in ABI_FUNCTIONS:
@@ -178,6 +187,11 @@ class Context:
         _check(_lib.sps_reserve_exact(self.h, max_rows))
         self.max_exact = max(self.max_exact, max_rows)
         self.max_gal = max(self.max_gal, max_rows)
+
+    def reserve_nuts(self, max_chains: int, max_depth: int = 10):
+        """Size the NUTS workspace for up to max_chains chains (n_gal * n_chain) at max_depth."""
+        _check(_lib.sps_reserve_nuts(self.h, max_chains, max_depth))
+        self.max_gal = max(self.max_gal, max_chains)
 
     def status(self):
         """Synchronise and raise SpsError for device-side errors flagged since the last check
@@ -311,6 +325,42 @@ class Context:
                                 _ptr(out["inv_metric"]), _ptr(state)))
         if samples is not None:
             out["samples"] = samples
+        return out
+
+
+    def nuts_run(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, max_depth=10,
+                 n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
+                 keep_samples=False, adapt_metric=False, sync_iterations=False, keep_depth=False, stream=None):
+        """NUTS on the approximate path; theta0 [chain][10][galaxy] or None (prior draws).
+        Returns the summaries, n_leaf [chain][galaxy] (leapfrog steps of each chain), lockstep
+        (chain steps, wave steps x chains per wave) and optionally samples and depth."""
+        n = z.shape[0]
+        _dev(z, torch.float32, (n,), "z", self.device)
+        _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
+        _dev(sigma, torch.float32, (n, self.n_band), "sigma", self.device)
+        _dev(mask, torch.uint8, (n,), "band_mask", self.device)
+        _dev(bounds, torch.float32, (NPARAM, 4), "bounds", self.device)
+        _dev(prior, torch.float32, (NPARAM, 3), "prior", self.device)
+        if theta0 is not None:
+            _dev(theta0, torch.float32, (n_chain, NPARAM, n), "theta0", self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        out = dict(post_mean=torch.empty((NPARAM, n), **f32), post_sd=torch.empty((NPARAM, n), **f32),
+                   rhat=torch.empty((NPARAM, n), **f32), accept=torch.empty(n, **f32),
+                   step=torch.empty((n_chain, n), **f32),
+                   inv_metric=torch.empty((n_chain, NPARAM, n), **f32),
+                   n_leaf=torch.empty((n_chain, n), dtype=torch.int32, device=self.device),
+                   lockstep=torch.zeros(2, dtype=torch.int64, device=self.device))
+        if keep_samples:
+            out["samples"] = torch.empty((n_sample, n_chain, NPARAM, n), **f32)
+        if keep_depth:
+            out["depth"] = torch.empty((n_warmup + n_sample, n_chain, n), dtype=torch.int32, device=self.device)
+        cfg = _NutsCfg(n_chain, max_depth, n_warmup, n_sample, target_accept, init_step, seed,
+                       int(bool(adapt_metric)), int(bool(sync_iterations)))
+        _check(_lib.sps_nuts_run(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs), _ptr(sigma),
+                                 _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0), _ptr(out.get("samples")),
+                                 _ptr(out["post_mean"]), _ptr(out["post_sd"]), _ptr(out["rhat"]),
+                                 _ptr(out["accept"]), _ptr(out["step"]), _ptr(out["inv_metric"]),
+                                 _ptr(out.get("depth")), _ptr(out["n_leaf"]), _ptr(out["lockstep"])))
         return out
 
 

@@ -228,6 +228,7 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_work);
     (void)hipFree(c->d_hwork);
     (void)hipFree(c->d_xsort);
+    (void)hipFree(c->d_nwork);
     delete c;
 }
 
@@ -315,6 +316,23 @@ int sps_reserve_exact(sps_ctx *c, int max_rows) {
     c->xsort_bytes = xb;
     c->hwork_bytes = hb;
     c->max_exact = max_rows;
+    return SPS_OK;
+}
+
+int sps_reserve_nuts(sps_ctx *c, int max_chains, int max_depth) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if (max_chains < 1) return set_error(SPS_E_INVAL, "max_chains < 1");
+    if (max_depth < 1 || max_depth > 12) return set_error(SPS_E_INVAL, "need 1 <= max_depth <= 12");
+    if (max_chains > c->max_gal && (rc = sps_reserve(c, max_chains))) return rc;
+    const size_t nb = nuts_state_bytes(max_chains, max_depth);
+    if (nb <= c->nwork_bytes) return SPS_OK;
+    SPS_HIP(hipDeviceSynchronize());
+    (void)hipFree(c->d_nwork);
+    c->d_nwork = nullptr;
+    c->nwork_bytes = 0;
+    SPS_HIP(hipMalloc(&c->d_nwork, nb));
+    c->nwork_bytes = nb;
     return SPS_OK;
 }
 
@@ -690,6 +708,33 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
         return set_error(SPS_E_INVAL, "null summary array (required from the call that ends the run)");
     return launch_hmc(c, (hipStream_t)stream, cfg, n_gal, sfh, z, obs, sigma, band_mask, bounds, prior, theta0,
                       samples, post_mean, post_sd, rhat, accept, step, inv_metric, state_inout);
+}
+
+int sps_nuts_run(sps_ctx *c, void *stream, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
+                 const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
+                 const float *prior, const float *theta0, float *samples, float *post_mean, float *post_sd,
+                 float *rhat, float *accept, float *step, float *inv_metric, int *depth, int *n_leaf,
+                 unsigned long long *lockstep) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if (!cfg) return set_error(SPS_E_INVAL, "null config");
+    if ((rc = check_gal(c, n_gal, sfh))) return rc;
+    if (cfg->n_chain < 1 || cfg->n_chain > 64 || cfg->max_depth < 1 || cfg->max_depth > 12 || cfg->n_warmup < 0 ||
+        cfg->n_sample < 2)
+        return set_error(SPS_E_INVAL, "need 1 <= n_chain <= 64, 1 <= max_depth <= 12, n_warmup >= 0, n_sample >= 2");
+    if (!(cfg->init_step > 0.0f) || !(cfg->target_accept > 0.0f && cfg->target_accept < 1.0f))
+        return set_error(SPS_E_INVAL, "need init_step > 0 and 0 < target_accept < 1");
+    if (cfg->adapt_metric != 0 && cfg->adapt_metric != 1) return set_error(SPS_E_INVAL, "adapt_metric must be 0 or 1");
+    if (cfg->sync_iterations != 0 && cfg->sync_iterations != 1)
+        return set_error(SPS_E_INVAL, "sync_iterations must be 0 or 1");
+    if ((long long)n_gal * cfg->n_chain > (long long)c->max_gal)
+        return set_error(SPS_E_INVAL, "n_gal * n_chain exceeds the reserved workspace (call sps_reserve_nuts)");
+    if (c->k.n_z == 0) return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
+    if (n_gal == 0) return SPS_OK;
+    if (!z || !obs || !sigma || !band_mask || !bounds || !prior || !post_mean || !post_sd || !rhat || !accept || !step)
+        return set_error(SPS_E_INVAL, "null array");
+    return launch_nuts(c, (hipStream_t)stream, cfg, n_gal, sfh, z, obs, sigma, band_mask, bounds, prior, theta0,
+                       samples, post_mean, post_sd, rhat, accept, step, inv_metric, depth, n_leaf, lockstep);
 }
 
 }  // extern "C"

@@ -497,24 +497,25 @@ __global__ void __launch_bounds__(64, 2) k_hmc(DevConsts k, HmcArgs a) {
 #undef ST
 
 // pooled posterior mean / sd, classic Gelman-Rubin R-hat and acceptance per galaxy; slot
-// r * C + c holds chain c of galaxy perm[r] (of galaxy r if perm is null)
+// r * C + c holds chain c of galaxy perm[r] (of galaxy r if perm is null).  Acceptance: the
+// accepted count nacc, or (nacc null) the summed acceptance statistic accsum, over C x NS.
 __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ perm,
                               const double *__restrict__ wmean, const double *__restrict__ wm2,
-                              const int *__restrict__ nacc, const float *__restrict__ eps,
-                              const float *__restrict__ minv, float *post_mean, float *post_sd, float *rhat,
-                              float *accept, float *step, float *inv_metric) {
+                              const int *__restrict__ nacc, const double *__restrict__ accsum,
+                              const float *__restrict__ eps, const float *__restrict__ minv, float *post_mean,
+                              float *post_sd, float *rhat, float *accept, float *step, float *inv_metric) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_gal) return;
     const int g = perm ? perm[r] : r, nslot = n_gal * C;
-    int acc = 0;
+    double acc = 0.0;
     for (int c = 0; c < C; ++c) {
-        acc += nacc[r * C + c];
+        acc += nacc ? (double)nacc[r * C + c] : accsum[r * C + c];
         step[(size_t)c * n_gal + g] = eps[r * C + c];
         if (inv_metric)
             for (int p = 0; p < NP; ++p)
                 inv_metric[((size_t)c * NP + p) * n_gal + g] = minv[(size_t)p * nslot + r * C + c];
     }
-    accept[g] = (float)acc / ((float)C * NS);
+    accept[g] = (float)(acc / ((double)C * NS));
     for (int p = 0; p < NP; ++p) {
         double gm = 0.0, W = 0.0, B = 0.0, ss = 0.0;
         for (int c = 0; c < C; ++c) {
@@ -536,6 +537,448 @@ __global__ void k_hmc_summary(int n_gal, int C, int NS, const int *__restrict__ 
         post_sd[(size_t)p * n_gal + g] = (float)sqrt(ss / ((double)C * NS - 1.0));
         rhat[(size_t)p * n_gal + g] = (C > 1) ? (float)sqrt(V / W) : __int_as_float(0x7fc00000);
     }
+}
+
+// ------------------------------------------------------------------ NUTS
+// The No-U-Turn Sampler (Sec. 4 and App. D.2 run it beside HMC): Hoffman & Gelman (2014),
+// Algorithm 3 (slice variable, trajectory doubling in a random direction, a new subtree's
+// proposal taken with probability min(1, n'/n)) with the dual averaging of their Algorithm 6
+// (acceptance statistic: the mean of min(1, exp(H0 - H)) over the final tree's leaves).  The
+// recursive tree building is run leaf by leaf as a per-chain state machine: after each leaf
+// the U-turn test runs on every dyadic block of the subtree that ends there (innermost
+// first), and a divergent leaf (log u >= 1000 - H) or a turned block ends the subtree.  Inside
+// a subtree the proposal is a uniform choice among its slice-valid leaves (reservoir
+// sampling, the distribution the recursion's pairwise choices give).  Diagonal metric: the
+// U-turn test uses the velocities M^-1 p.
+//
+// Lock-step: the chains of a wave evaluate the model together (the contractions are
+// wave-wide), so every leaf step costs the whole wave and a chain whose tree is done waits
+// for the wave's slowest.  With sync = 1 the chains of a wave also start every iteration
+// together (the vectorised-over-chains form, where each iteration lasts as long as the
+// wave's deepest tree); with sync = 0 a chain whose tree is done begins its next iteration at
+// once, so the wave's cost is the slowest chain's total over the launch's iterations, not
+// the sum of per-iteration maxima.  The draws do not depend on it.
+//
+// Philox draws (chain id = c * n_gal + g): momentum and slice (blk 0..2, it, chain, 0:
+// words 0..9 the momentum as in HMC, word 10 the slice uniform), per doubling j (j, it,
+// chain, 2: word 0 the direction, word 1 the subtree's acceptance), per leaf (leaf index in
+// the iteration, it, chain, 3: word 0 the reservoir uniform).
+constexpr int NUTS_MAX_DEPTH = 12;
+
+struct NutsArgs : HmcArgs {
+    int D;                    // maximum tree depth: at most 2^D - 1 leaves per iteration
+    int sync;                 // 1: a wave's chains start each iteration together
+    // tree state per slot, [quantity][slot]: the two ends (position, momentum, gradient), the
+    // proposal, the current subtree's proposal, the dyadic-block checkpoints [D][2][NP][slot]
+    float *xl, *pl, *gl, *xr, *pr, *grr, *xm, *gm, *xs, *gs, *ck;
+    double *lpl, *lpr, *lpm, *lps, *asum_it, *accsum;   // [slot]
+    int *nleaf;               // [slot] leapfrog steps over the run
+    int *depth_out;           // [n_it][C][n_gal] tree depth per iteration, or null
+    unsigned long long *lockstep;   // [2]: chain leapfrog steps, wave leaf steps x chains per wave
+};
+
+// no U-turn between two forward-time ends of a stretch (both dot products >= 0); the first
+// end at xa/pa (SoA, slot s), the second in registers
+__device__ inline bool no_uturn_at(const float *xa, const float *pa, size_t ns, int s, const float (&xb)[NP],
+                                   const float (&pb)[NP], const float *minv_s, int dirn) {
+    float da = 0.0f, db = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+        const float mi = minv_s[(size_t)t * ns];
+        const float dx = (float)dirn * (xb[t] - xa[(size_t)t * ns + s]);
+        da = fmaf(dx * mi, pa[(size_t)t * ns + s], da);
+        db = fmaf(dx * mi, pb[t], db);
+    }
+    return da >= 0.0f && db >= 0.0f;
+}
+
+#define NS_(arr, p) (arr)[(size_t)(p) * si.nslot + opaque(si.sl)]
+#define ST(arr, p) (arr)[(size_t)(p) * si.nslot + opaque(si.sl)]
+
+enum { NU_START = 0, NU_SUB = 1, NU_LEAF = 2 };
+
+template <int SFH>
+__global__ void __launch_bounds__(64, 2) k_nuts(DevConsts k, NutsArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char lds_dyn[];   // approx_lds_bytes(n_band, false, HG)
+    const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
+    __shared__ float ledge[NA + 1];
+    stage_log_age_edges(k, ledge);
+    const SlotInfo si = slot_info(a);
+    const LaneCtx lc = lane_ctx(k, a, si);
+    const uint32_t chain_id = si.chain_id;
+    const int D = a.D;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) TMP(a.xt, p) = ST(a.x, p);
+
+    int it = a.it0, phase = NU_START, j = 0, kk = 0, dirn = 1, n = 1, nsub = 0, leaf = 0;
+    bool done = !si.valid || it >= a.it1, s_sub = true;
+    double logu = 0.0, H0 = 0.0, asum = 0.0;
+    float eps = a.eps[si.sl];
+    unsigned long long wave_steps = 0, my_leaves = 0;
+
+    while (__any(!done)) {
+        // wave-wide, so taken by every lane before any branch: are all unfinished chains
+        // between iterations?
+        const bool all_between = __all(done || phase == NU_START);
+        bool act = !done;
+        if (a.sync && phase == NU_START && !all_between) act = false;
+        if (act && phase == NU_START) {   // a new iteration: momentum, slice, the one-leaf tree
+            uint32_t w[12];
+#pragma unroll
+            for (int blk = 0; blk < 3; ++blk) {
+                uint32_t c4[4] = {(uint32_t)blk, (uint32_t)it, chain_id, 0u};
+                philox4x32_10(c4, a.key0, a.key1);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) w[4 * blk + t] = c4[t];
+            }
+            double kin = 0.0;
+#pragma unroll
+            for (int t = 0; t < NP / 2; ++t) {
+                const float r = sqrtf(-2.0f * logf(u01f(w[2 * t])));
+                float sn, cs;
+                sincosf(6.283185307179586f * u01f(w[2 * t + 1]), &sn, &cs);
+                const float m0 = ST(a.minv, 2 * t), m1 = ST(a.minv, 2 * t + 1);
+                const float p0 = r * cs / sqrtf(m0), p1 = r * sn / sqrtf(m1);
+                kin += 0.5 * (double)m0 * (double)p0 * (double)p0 + 0.5 * (double)m1 * (double)p1 * (double)p1;
+                NS_(a.pl, 2 * t) = p0;
+                NS_(a.pr, 2 * t) = p0;
+                NS_(a.pl, 2 * t + 1) = p1;
+                NS_(a.pr, 2 * t + 1) = p1;
+            }
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                const float x = ST(a.x, t), g = ST(a.gr, t);
+                NS_(a.xl, t) = x;
+                NS_(a.xr, t) = x;
+                NS_(a.xm, t) = x;
+                NS_(a.gl, t) = g;
+                NS_(a.grr, t) = g;
+                NS_(a.gm, t) = g;
+            }
+            const double lp = a.lp[si.sl];
+            a.lpl[si.sl] = lp;
+            a.lpr[si.sl] = lp;
+            a.lpm[si.sl] = lp;
+            H0 = -lp + kin;
+            logu = log(u01d(w[10])) - H0;
+            n = 1;
+            j = 0;
+            leaf = 0;
+            asum = 0.0;
+            eps = a.eps[si.sl];
+            phase = NU_SUB;
+        }
+        if (act && phase == NU_SUB) {   // a new subtree of 2^j leaves in a random direction
+            uint32_t c4[4] = {(uint32_t)j, (uint32_t)it, chain_id, 2u};
+            philox4x32_10(c4, a.key0, a.key1);
+            dirn = u01d(c4[0]) < 0.5 ? -1 : 1;
+            nsub = 0;
+            s_sub = true;
+            kk = 0;
+            phase = NU_LEAF;
+        }
+        // one leapfrog step from the growing end (every lane evaluates the model; only the
+        // active ones keep the result)
+        float *ex = dirn < 0 ? a.xl : a.xr, *ep = dirn < 0 ? a.pl : a.pr, *eg = dirn < 0 ? a.gl : a.grr;
+        const float e = (float)dirn * eps;
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                const float p = fmaf(0.5f * e, NS_(eg, t), NS_(ep, t));
+                NS_(ep, t) = p;
+                const float x = fmaf(e * ST(a.minv, t), p, NS_(ex, t));
+                NS_(ex, t) = x;
+                TMP(a.xt, t) = x;
+            }
+        }
+        asm volatile("" ::: "memory");
+        float ge[NP];
+        const double lpe = logpost<SFH>(k, ledge, a, lc, lds, ge);
+        asm volatile("" ::: "memory");
+        ++wave_steps;
+        if (!act) continue;
+        float xe[NP], pe[NP];
+        double kin = 0.0;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            xe[t] = NS_(ex, t);
+            pe[t] = fmaf(0.5f * e, ge[t], NS_(ep, t));
+            NS_(ep, t) = pe[t];
+            NS_(eg, t) = ge[t];
+            kin += 0.5 * (double)ST(a.minv, t) * (double)pe[t] * (double)pe[t];
+        }
+        (dirn < 0 ? a.lpl : a.lpr)[si.sl] = lpe;
+        const double H = -lpe + kin;
+        asum += isfinite(H) ? fmin(1.0, exp(H0 - H)) : 0.0;
+        ++leaf;
+        if (logu <= -H) {   // a slice-valid leaf: the subtree's proposal with probability 1 / nsub
+            ++nsub;
+            uint32_t c4[4] = {(uint32_t)(leaf - 1), (uint32_t)it, chain_id, 3u};
+            philox4x32_10(c4, a.key0, a.key1);
+            if (u01d(c4[0]) * (double)nsub < 1.0) {
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    NS_(a.xs, t) = xe[t];
+                    NS_(a.gs, t) = ge[t];
+                }
+                a.lps[si.sl] = lpe;
+            }
+        }
+        if (!(logu < 1000.0 - H)) s_sub = false;   // divergence (or a non-finite H)
+        const size_t cstride = (size_t)2 * NP * si.nslot;
+        for (int l = 1; l <= j; ++l)   // the first leaf of every dyadic block starting here
+            if ((kk & ((1 << l) - 1)) == 0) {
+                float *cx = a.ck + (size_t)(l - 1) * cstride, *cp = cx + (size_t)NP * si.nslot;
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    NS_(cx, t) = xe[t];
+                    NS_(cp, t) = pe[t];
+                }
+            }
+        for (int l = 1; l <= j && s_sub; ++l)   // every block ending here, innermost first
+            if (((kk + 1) & ((1 << l) - 1)) == 0) {
+                const float *cx = a.ck + (size_t)(l - 1) * cstride, *cp = cx + (size_t)NP * si.nslot;
+                if (!no_uturn_at(cx, cp, si.nslot, opaque(si.sl), xe, pe, a.minv + opaque(si.sl), dirn))
+                    s_sub = false;
+            }
+        ++kk;
+        if (kk < (1 << j) && s_sub) continue;
+        // the subtree is done: its proposal replaces the tree's with probability min(1, nsub / n)
+        {
+            uint32_t c4[4] = {(uint32_t)j, (uint32_t)it, chain_id, 2u};
+            philox4x32_10(c4, a.key0, a.key1);
+            if (s_sub && nsub > 0 && u01d(c4[1]) * (double)n < (double)nsub) {
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    NS_(a.xm, t) = NS_(a.xs, t);
+                    NS_(a.gm, t) = NS_(a.gs, t);
+                }
+                a.lpm[si.sl] = a.lps[si.sl];
+            }
+        }
+        n += nsub;
+        bool s_tree = s_sub;
+        if (s_tree) {
+            float xb[NP], pb[NP];
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                xb[t] = NS_(a.xr, t);
+                pb[t] = NS_(a.pr, t);
+            }
+            s_tree = no_uturn_at(a.xl, a.pl, si.nslot, opaque(si.sl), xb, pb, a.minv + opaque(si.sl), 1);
+        }
+        ++j;
+        if (s_tree && j < D) {
+            phase = NU_SUB;
+            continue;
+        }
+        // the iteration is done: the proposal becomes the chain's state
+        float xn[NP];
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            xn[t] = NS_(a.xm, t);
+            ST(a.x, t) = xn[t];
+            ST(a.gr, t) = NS_(a.gm, t);
+        }
+        a.lp[si.sl] = a.lpm[si.sl];
+        const float alpha = (float)(asum / (double)leaf);
+        my_leaves += (unsigned long long)leaf;
+        a.nleaf[si.sl] += leaf;
+        if (a.depth_out) a.depth_out[((size_t)it * a.C + si.ch) * a.n_gal + si.g] = j;
+        if (it < a.NW) {   // dual averaging and the metric windows, as in HMC
+            int da0 = a.da0[si.sl];
+            const float m = (float)(it - da0 + 1), eta = 1.0f / (m + 10.0f);
+            float hbar = (1.0f - eta) * a.hbar[si.sl] + eta * (a.target - alpha);
+            const float leps = a.mu[si.sl] - sqrtf(m) / 0.05f * hbar, wk = powf(m, -0.75f);
+            float lebar = wk * leps + (1.0f - wk) * a.lebar[si.sl];
+            eps = expf(it == a.NW - 1 ? lebar : leps);
+            int wi = -1;
+            for (int q = 0; q < a.n_win; ++q)
+                if (it >= a.win_s[q] && it < a.win_e[q]) wi = q;
+            if (wi >= 0) {
+                const double nn = (double)(it - a.win_s[wi] + 1);
+                const bool wlast = (it == a.win_e[wi] - 1);
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    double wmean = ST(a.wmean, t), wm2 = ST(a.wm2, t);
+                    const double d = (double)xn[t] - wmean;
+                    wmean += d / nn;
+                    wm2 += d * ((double)xn[t] - wmean);
+                    if (wlast) {
+                        ST(a.minv, t) = (float)(nn / (nn + 5.0) * (wm2 / (nn - 1.0)) + 1e-3 * 5.0 / (nn + 5.0));
+                        wmean = wm2 = 0.0;
+                    }
+                    ST(a.wmean, t) = wmean;
+                    ST(a.wm2, t) = wm2;
+                }
+                if (wlast) {
+                    a.mu[si.sl] = logf(10.0f * eps);
+                    hbar = lebar = 0.0f;
+                    a.da0[si.sl] = it + 1;
+                }
+            }
+            a.hbar[si.sl] = hbar;
+            a.lebar[si.sl] = lebar;
+            a.eps[si.sl] = eps;
+        } else {
+            a.accsum[si.sl] += (double)alpha;
+            const double nrec = (double)(it - a.NW + 1);
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                float th, dth;
+                bound_param(a.bounds + 4 * t, xn[t], th, dth);
+                double wmean = ST(a.wmean, t), wm2 = ST(a.wm2, t);
+                const double d = (double)th - wmean;
+                wmean += d / nrec;
+                wm2 += d * ((double)th - wmean);
+                ST(a.wmean, t) = wmean;
+                ST(a.wm2, t) = wm2;
+                if (a.samples) a.samples[(((size_t)(it - a.NW) * a.C + si.ch) * NP + t) * a.n_gal + si.g] = th;
+            }
+        }
+        ++it;
+        phase = NU_START;
+        if (it >= a.it1) done = true;
+    }
+    if (a.lockstep) {   // one lane per chain counts its steps; lane 0 the wave's
+        const bool own = si.valid && (threadIdx.x % HG) == 0;
+        unsigned long long chains = own ? 1ull : 0ull, mine = own ? my_leaves : 0ull;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            chains += __shfl_xor(chains, o, WAVE);
+            mine += __shfl_xor(mine, o, WAVE);
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.lockstep[0], mine);
+            atomicAdd(&a.lockstep[1], wave_steps * chains);
+        }
+    }
+}
+#undef NS_
+#undef ST
+
+// per-slot leapfrog counts to the caller's [n_chain][n_gal] order
+__global__ void k_nuts_leaves(int n_gal, int C, const int *__restrict__ perm, const int *__restrict__ nl,
+                              int *__restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_gal * C) return;
+    out[(size_t)(s % C) * n_gal + perm[s / C]] = nl[s];
+}
+
+static int metric_windows(int nw, int *ws, int *we);
+
+// the NUTS workspace: the HMC chain state and trajectory scratch, then the tree state
+struct NutsLayout {
+    size_t o_tree, o_ck, o_d, o_i, bytes;
+};
+static NutsLayout nuts_layout(int nslot, int D) {
+    NutsLayout L{};
+    size_t off = hmc_state_bytes(nslot);
+    L.o_tree = off;
+    off += align256((size_t)10 * NP * nslot * sizeof(float));
+    L.o_ck = off;
+    off += align256((size_t)D * 2 * NP * nslot * sizeof(float));
+    L.o_d = off;
+    off += align256((size_t)6 * nslot * sizeof(double));
+    L.o_i = off;
+    off += align256((size_t)nslot * sizeof(int));
+    L.bytes = off;
+    return L;
+}
+size_t nuts_state_bytes(int nslot, int max_depth) { return nuts_layout(nslot, max_depth).bytes; }
+
+int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
+                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
+                const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
+                float *step, float *inv_metric, int *depth, int *n_leaf, unsigned long long *lockstep) {
+    const int C = cfg->n_chain, nslot = n_gal * C, D = cfg->max_depth;
+    const NutsLayout L = nuts_layout(nslot, D);
+    if (c->nwork_bytes < L.bytes)
+        return set_error(SPS_E_STATE, "the NUTS workspace needs n_gal * n_chain chains at this max_depth "
+                                      "(call sps_reserve_nuts)");
+    NutsArgs a{};
+    a.n_win = 0;
+    if (cfg->adapt_metric) {
+        a.n_win = metric_windows(cfg->n_warmup, a.win_s, a.win_e);
+        if (a.n_win < 0) return set_error(SPS_E_INVAL, "n_warmup too long for the metric-window table");
+    }
+    int rc = launch_bucket_sort(c, s, n_gal, z);
+    if (rc) return rc;
+    char *W = (char *)c->d_nwork;
+    const ChainState cs = chain_state_at(W, nslot);
+    a.n_gal = n_gal;
+    a.C = C;
+    a.L = 0;
+    a.NW = cfg->n_warmup;
+    a.NS = cfg->n_sample;
+    a.sfh = sfh;
+    a.target = cfg->target_accept;
+    a.init_step = cfg->init_step;
+    a.key0 = (uint32_t)(cfg->seed & 0xffffffffull);
+    a.key1 = (uint32_t)(cfg->seed >> 32);
+    a.z = z;
+    a.obs = obs;
+    a.sigma = sigma;
+    a.mask = mask;
+    a.bounds = bounds;
+    a.prior = prior;
+    a.theta0 = theta0;
+    a.perm = c->d_perm;
+    a.qf = c->d_qf;
+    a.qa = c->d_qa;
+    a.samples = samples;
+    a.x = cs.x;
+    a.gr = cs.gr;
+    a.minv = cs.minv;
+    a.eps = cs.eps;
+    a.mu = cs.mu;
+    a.hbar = cs.hbar;
+    a.lebar = cs.lebar;
+    a.nacc = cs.nacc;
+    a.da0 = cs.da0;
+    a.lp = cs.lp;
+    a.wmean = cs.wmean;
+    a.wm2 = cs.wm2;
+    const int ntmp = (nslot * HG + 63) / 64 * 64;
+    a.pm = (float *)(W + chain_state_bytes(nslot));
+    a.xt = a.pm + (size_t)NP * ntmp;
+    a.ntmp = ntmp;
+    a.D = D;
+    a.sync = cfg->sync_iterations;
+    float *tf = (float *)(W + L.o_tree);
+    float **tq[10] = {&a.xl, &a.pl, &a.gl, &a.xr, &a.pr, &a.grr, &a.xm, &a.gm, &a.xs, &a.gs};
+    for (int q = 0; q < 10; ++q) *tq[q] = tf + (size_t)q * NP * nslot;
+    a.ck = (float *)(W + L.o_ck);
+    double *td = (double *)(W + L.o_d);
+    double **dq[6] = {&a.lpl, &a.lpr, &a.lpm, &a.lps, &a.asum_it, &a.accsum};
+    for (int q = 0; q < 6; ++q) *dq[q] = td + (size_t)q * nslot;
+    a.nleaf = (int *)(W + L.o_i);
+    a.depth_out = depth;
+    a.lockstep = lockstep;
+    SPS_HIP(hipMemsetAsync(a.accsum, 0, (size_t)nslot * sizeof(double), s));
+    SPS_HIP(hipMemsetAsync(a.nleaf, 0, (size_t)nslot * sizeof(int), s));
+    if (lockstep) SPS_HIP(hipMemsetAsync(lockstep, 0, 2 * sizeof(unsigned long long), s));
+    dim3 grid((nslot * HG + 63) / 64), block(64);
+    const bool dpl = (sfh == SPS_SFH_DPL);
+    const size_t lds_bytes = approx_lds_bytes(c->n_band, false, HG);
+    const HmcArgs &ha = a;
+    if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, ha);
+    else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, ha);
+    const int nit = cfg->n_warmup + cfg->n_sample, blk_it = 10;
+    for (int b0 = 0; b0 < nit; b0 += blk_it) {
+        a.it0 = b0;
+        a.it1 = b0 + blk_it < nit ? b0 + blk_it : nit;
+        if (dpl) hipLaunchKernelGGL(k_nuts<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, a);
+        else hipLaunchKernelGGL(k_nuts<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, a);
+    }
+    hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample, c->d_perm,
+                       a.wmean, a.wm2, (const int *)nullptr, a.accsum, a.eps, a.minv, post_mean, post_sd, rhat,
+                       accept, step, inv_metric);
+    if (n_leaf)
+        hipLaunchKernelGGL(k_nuts_leaves, dim3((nslot + 255) / 256), dim3(256), 0, s, n_gal, C, c->d_perm, a.nleaf,
+                           n_leaf);
+    SPS_HIP(hipGetLastError());
+    return SPS_OK;
 }
 
 // ------------------------------------------------------------------ exact-path HMC
@@ -924,7 +1367,7 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
     if (state && (rc = move_state(c, s, cs, state, cfg, n_gal, a.perm, 1, it1))) return rc;
     if (it1 == nit)
         hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
-                           a.perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                           a.perm, a.wmean, a.wm2, a.nacc, nullptr, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
                            inv_metric);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
@@ -1007,7 +1450,7 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     if (state && (rc = move_state(c, s, cs, state, cfg, n_gal, c->d_perm, 1, it1))) return rc;
     if (it1 == nit)
         hipLaunchKernelGGL(k_hmc_summary, dim3((n_gal + 255) / 256), dim3(256), 0, s, n_gal, C, cfg->n_sample,
-                           c->d_perm, a.wmean, a.wm2, a.nacc, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
+                           c->d_perm, a.wmean, a.wm2, a.nacc, nullptr, a.eps, a.minv, post_mean, post_sd, rhat, accept, step,
                            inv_metric);
     SPS_HIP(hipGetLastError());
     return SPS_OK;

@@ -106,6 +106,9 @@ struct sps_ctx {
     size_t hwork_bytes = 0;
     void *d_xsort = nullptr;       // exact path: inputs and outputs in z order
     size_t xsort_bytes = 0;
+    // NUTS, sized by sps_reserve_nuts: chain state, trajectory scratch and tree state
+    void *d_nwork = nullptr;
+    size_t nwork_bytes = 0;
     // kernel timing (sps_set_kernel_timing): 2 events per pair, pairs used cyclically
     std::vector<hipEvent_t> tev;
     long long tev_calls = 0;
@@ -189,6 +192,12 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                const float *prior, const float *theta0, float *samples, float *post_mean,
                float *post_sd, float *rhat, float *accept, float *step, float *inv_metric, void *state);
+
+size_t nuts_state_bytes(int nslot, int max_depth);
+int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
+                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
+                const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
+                float *step, float *inv_metric, int *depth, int *n_leaf, unsigned long long *lockstep);
 
 // modes of the approximate-path kernel
 enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3 };

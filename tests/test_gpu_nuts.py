@@ -1,0 +1,143 @@
+"""GPU NUTS against the FP64 oracle's NUTS on the same Philox streams: trees, depths and
+draws agree iteration by iteration until a decision of the oracle's came within rounding of
+its threshold; the lock-step schedule does not change the draws."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import MAX_EXCUSED, bounds_prior, dev, f32, gal_inputs
+
+pytestmark = pytest.mark.gpu
+
+# near ties: over trees of up to 31 leaves the FP32 trajectories move H by up to ~1e-2 and the
+# U-turn cosines by ~1e-5 (deeper trees drift further: at 127 leaves H moves by more than
+# 1e-2, and the dual averaging then carries the difference into the step size)
+TIE_SLICE, TIE_TURN = 2e-2, 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx(ssp2000, filt6):
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64,), max_gal=1 << 12)
+    c.build_ztable(64, 0.1, 3.0)
+    c.reserve_nuts(1 << 12, 10)
+    yield c
+    c.close()
+
+
+def _problem(orc, kind, n, seed, n_chain):
+    sfh, th, z = gal_inputs(kind, n, seed)
+    if kind != "dpl":
+        th[:, 3] = 1.0
+        th[:, synth.P_FFLOOR] = 0.05
+    noise, sig = synth.photometric_noise(n, 6, seed + 1)
+    obs = f32(orc.phot_approx(sfh, th, z) + noise)
+    sig = f32(sig)
+    masks = synth.band_masks(n, 6, seed + 2)
+    bnd, pri = bounds_prior()
+    x_true = np.array([[orc.unbound(bnd[p], th[g, p]) for p in range(10)] for g in range(n)])
+    x0 = f32(x_true[None] + 0.05 * np.random.default_rng(seed + 3).normal(size=(n_chain, n, 10)))
+    return sfh, z, obs, sig, masks, bnd, pri, x0
+
+
+def _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, **kw):
+    th0 = dev(np.ascontiguousarray(np.transpose(x0, (0, 2, 1))))   # [chain][10][gal]
+    return ctx.nuts_run(sfh, dev(z), dev(obs), dev(sig), dev(masks, torch.uint8), dev(bnd), dev(pri), th0,
+                        keep_samples=True, keep_depth=True, **kw)
+
+
+def follow(out, ref, n_warm, rtol=1e-3):
+    """Per chain [c][g]: (ok, excused).  A chain is compared iteration by iteration (tree depth
+    equal, draw within rtol) up to the first iteration in which one of the oracle's slice or
+    U-turn decisions was a near tie; a chain that differs before that fails."""
+    tie = (ref["margin_slice"] < TIE_SLICE) | (ref["margin_turn"] < TIE_TURN)      # [it][c][g]
+    before = np.cumsum(tie, axis=0) == 0
+    depth_ok = out["depth"].cpu().numpy() == ref["depth"]
+    s_gpu = out["samples"].cpu().numpy().transpose(0, 1, 3, 2)                      # [s][c][g][10]
+    s_ref = ref["samples"]
+    close = np.all(np.abs(s_gpu - s_ref) <= rtol * np.maximum(np.abs(s_ref), 1.0), axis=-1)
+    close_all = np.concatenate([np.ones_like(depth_ok[:n_warm]), close], axis=0) & depth_ok
+    ok = np.all(close_all | ~before, axis=0)
+    return ok, tie.any(axis=0)
+
+
+@pytest.mark.parametrize("kind", ["dpl", "lognormal_burst"])
+def test_first_iterations_match_oracle(ctx, orc, kind):
+    # fixed step size, no warm-up: every chain's trees (depth) and draws follow the oracle
+    n, C = 6, 3
+    sfh, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, kind, n, 501, C)
+    kw = dict(n_chain=C, max_depth=5, n_warmup=0, n_sample=6, init_step=0.02, seed=407)
+    out = _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, **kw)
+    ref = orc.nuts_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ok, excused = follow(out, ref, 0)
+    assert ok.all() and excused.mean() <= MAX_EXCUSED, (ok, excused)
+    # the trees are not trivial: one to several doublings
+    d = ref["depth"]
+    assert d.min() == 1 and d.max() >= 3
+    # leapfrog steps per chain agree for the chains never cut short
+    nl = out["n_leaf"].cpu().numpy()
+    same = ~excused
+    np.testing.assert_array_equal(nl[same], ref["steps"].sum(axis=0)[same])
+
+
+def test_warmup_adaptation_matches_oracle(ctx, orc):
+    # dual averaging of the step size on the mean acceptance statistic: the adapted step
+    # sizes and the first draws after warm-up agree per chain
+    n, C = 8, 2
+    sfh, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, "dpl", n, 511, C)
+    kw = dict(n_chain=C, max_depth=4, n_warmup=8, n_sample=3, init_step=0.02, seed=408)
+    out = _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, **kw)
+    ref = orc.nuts_run(sfh, z, obs, sig, masks, bnd, pri, x0, keep_samples=True, **kw)
+    ok, excused = follow(out, ref, 8)
+    assert ok.all() and excused.mean() <= 0.5, (ok, excused)
+    same = ~excused
+    assert same.sum() >= 5
+    np.testing.assert_allclose(out["step"].cpu().numpy()[same], ref["step"][same], rtol=1e-3)
+    assert np.all(np.abs(np.log(ref["step"] / 0.02)) > 0.05)   # the step sizes did adapt
+
+
+def test_lockstep_schedule_does_not_change_the_draws(ctx, orc):
+    # chains that start every iteration together (sync) and chains that move on as soon as
+    # their own tree is done draw the same samples bit for bit; the free schedule spends no
+    # more wave steps, and both count the same chain steps
+    n, C = 64, 4
+    sfh, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, "dpl", n, 521, C)
+    kw = dict(n_chain=C, max_depth=8, n_warmup=10, n_sample=10, init_step=0.05, seed=409)
+    a = _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, sync_iterations=True, **kw)
+    b = _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, sync_iterations=False, **kw)
+    for key in ("samples", "step", "depth", "n_leaf", "post_mean"):
+        assert torch.equal(a[key], b[key]), key
+    la, lb = a["lockstep"].cpu().numpy(), b["lockstep"].cpu().numpy()
+    assert la[0] == lb[0] == int(a["n_leaf"].sum().item())
+    assert lb[1] <= la[1] and la[0] <= lb[1]
+
+
+def test_posterior_moments_agree_with_oracle(ctx, orc):
+    # a longer run: pooled posterior means within a few Monte-Carlo errors of the oracle's
+    n, C = 4, 4
+    sfh, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, "dpl", n, 531, C)
+    kw = dict(n_chain=C, max_depth=8, n_warmup=100, n_sample=300, init_step=0.05, seed=410)
+    out = _gpu(ctx, sfh, z, obs, sig, masks, bnd, pri, x0, **kw)
+    ref = orc.nuts_run(sfh, z, obs, sig, masks, bnd, pri, x0, **kw)
+    pm, ps = out["post_mean"].cpu().numpy().T, out["post_sd"].cpu().numpy().T
+    err = np.sqrt(ps ** 2 + ref["post_sd"] ** 2) / np.sqrt(C * 300 / 20.0)
+    assert np.mean(np.abs(pm - ref["post_mean"]) <= 4 * err + 1e-6) >= 0.9
+    acc = out["accept"].cpu().numpy()
+    assert np.all((acc > 0.5) & (acc <= 1.0))
+
+
+def test_reservation_is_required(ssp2000, filt6, orc):
+    import paper_2506_19919_amd as sps
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F64,), max_gal=64)
+    try:
+        c.build_ztable(64, 0.1, 3.0)
+        sfh, z, obs, sig, masks, bnd, pri, x0 = _problem(orc, "dpl", 4, 541, 2)
+        with pytest.raises(sps.SpsError) as e:
+            _gpu(c, sfh, z, obs, sig, masks, bnd, pri, x0, n_chain=2, max_depth=5, n_warmup=0, n_sample=2)
+        assert e.value.code == sps.SPS_E_STATE
+        c.reserve_nuts(8, 5)
+        out = _gpu(c, sfh, z, obs, sig, masks, bnd, pri, x0, n_chain=2, max_depth=5, n_warmup=0, n_sample=2)
+        assert torch.isfinite(out["samples"]).all()
+    finally:
+        c.close()
