@@ -857,6 +857,11 @@ __global__ void __launch_bounds__(64, 2) k_nuts(DevConsts k, NutsArgs a) {
 #undef NS_
 #undef ST
 
+__global__ void k_zero_words(uint32_t *__restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 // per-slot leapfrog counts to the caller's [n_chain][n_gal] order
 __global__ void k_nuts_leaves(int n_gal, int C, const int *__restrict__ perm, const int *__restrict__ nl,
                               int *__restrict__ out) {
@@ -955,9 +960,12 @@ int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, i
     a.nleaf = (int *)(W + L.o_i);
     a.depth_out = depth;
     a.lockstep = lockstep;
-    SPS_HIP(hipMemsetAsync(a.accsum, 0, (size_t)nslot * sizeof(double), s));
-    SPS_HIP(hipMemsetAsync(a.nleaf, 0, (size_t)nslot * sizeof(int), s));
-    if (lockstep) SPS_HIP(hipMemsetAsync(lockstep, 0, 2 * sizeof(unsigned long long), s));
+    // counters start at zero (fill kernels rather than memset nodes, so the sequence can be
+    // captured in a graph)
+    hipLaunchKernelGGL(k_zero_words, dim3((2 * nslot + 255) / 256), dim3(256), 0, s, (uint32_t *)a.accsum,
+                       (size_t)2 * nslot);
+    hipLaunchKernelGGL(k_zero_words, dim3((nslot + 255) / 256), dim3(256), 0, s, (uint32_t *)a.nleaf, (size_t)nslot);
+    if (lockstep) hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (uint32_t *)lockstep, (size_t)4);
     dim3 grid((nslot * HG + 63) / 64), block(64);
     const bool dpl = (sfh == SPS_SFH_DPL);
     const size_t lds_bytes = approx_lds_bytes(c->n_band, false, HG);
