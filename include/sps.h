@@ -248,6 +248,21 @@ int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, i
  * a 256-byte header and 312 bytes per chain. */
 size_t sps_hmc_state_bytes(int n_gal, int n_chain);
 
+/* sps_loglike_grad (approximate path) for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, kernels and results as sps_loglike_grad with path = SPS_PATH_APPROX, but its
+ * per-call buffers (sort order, histogram, input and output records) are a static device
+ * array of the library, about 6.6 MB per device for SPS_STATIC_MAX_GAL galaxies, held until
+ * the process ends; it allocates nothing and calls no allocating routine.  n_gal above
+ * SPS_STATIC_MAX_GAL is SPS_E_INVAL.  Every call on one device shares that device's array,
+ * which keeps the last call's contents (each call clears what it needs): calls that overlap in
+ * time on one device (other streams, other contexts, other host threads) race and must be
+ * serialised by the caller.  The context still provides the tables and the z table. */
+#define SPS_STATIC_MAX_GAL 32768
+int sps_loglike_grad_static(sps_ctx *ctx, void *stream, int n_gal, int sfh, const float *params, const float *z,
+                            const float *obs, const float *sigma, const uint8_t *band_mask, float *logl_out,
+                            float *grad_out);
+
 /* No-U-Turn Sampler (the paper's second gradient-based sampler, Sec. 4 and App. D.2):
  * Hoffman & Gelman (2014), Algorithm 3 (slice variable, trajectory doubling in a random
  * direction, a new subtree's proposal taken with probability min(1, n'/n)) with the dual

@@ -24,10 +24,13 @@ SPS_PATH_APPROX, SPS_PATH_EXACT = 0, 1
 NPARAM = 10
 MAX_BAND = 8
 
+STATIC_MAX_GAL = 32768   # SPS_STATIC_MAX_GAL of include/sps.h
+
 ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_reserve_exact", "sps_status", "sps_build_ztable",
                  "sps_get_ztable", "sps_destroy", "sps_last_error", "sps_weights", "sps_phot_approx",
                  "sps_phot_exact", "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_hmc_state_bytes",
-                 "sps_set_kernel_timing", "sps_kernel_times", "sps_nuts_run", "sps_reserve_nuts")
+                 "sps_set_kernel_timing", "sps_kernel_times", "sps_nuts_run", "sps_reserve_nuts",
+                 "sps_loglike_grad_static")
 
 
 class SpsError(RuntimeError):
@@ -93,6 +96,7 @@ def _load():
     lib.sps_nuts_run.argtypes = [vp, vp, C.POINTER(_NutsCfg), i, i, vp, vp, vp, vp, vp, vp, vp, vp,
                                  vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_reserve_nuts.argtypes = [vp, i, i]
+    lib.sps_loglike_grad_static.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_set_kernel_timing.argtypes = [vp, i]
     lib.sps_kernel_times.argtypes = [vp, vp, i, C.POINTER(i)]
     for name in ABI_FUNCTIONS:
@@ -269,6 +273,23 @@ class Context:
         _check(_lib.sps_loglike_grad(self.h, _stream(stream), n, sfh, path, prec, _ptr(params), _ptr(z),
                                      _ptr(obs), _ptr(sigma), _ptr(mask), _ptr(logl_out),
                                      _ptr(grad_out) if grad else None))
+        return (logl_out, grad_out) if grad else logl_out
+
+    def loglike_grad_static(self, sfh, params, z, obs, sigma, mask, grad=True, logl_out=None, grad_out=None,
+                            stream=None):
+        """loglike_grad on the approximate path through the entry point that allocates nothing
+        (its buffers are the library's static device array; n_gal <= STATIC_MAX_GAL)."""
+        n = self._gal(params, z)
+        _dev(obs, torch.float32, (n, self.n_band), "obs", self.device)
+        _dev(sigma, torch.float32, (n, self.n_band), "sigma", self.device)
+        _dev(mask, torch.uint8, (n,), "band_mask", self.device)
+        if logl_out is None:
+            logl_out = torch.empty(n, dtype=torch.float32, device=self.device)
+        if grad and grad_out is None:
+            grad_out = torch.empty((NPARAM, n), dtype=torch.float32, device=self.device)
+        _check(_lib.sps_loglike_grad_static(self.h, _stream(stream), n, sfh, _ptr(params), _ptr(z), _ptr(obs),
+                                            _ptr(sigma), _ptr(mask), _ptr(logl_out),
+                                            _ptr(grad_out) if grad else None))
         return (logl_out, grad_out) if grad else logl_out
 
     def logpost_grad(self, sfh, x, z, obs, sigma, mask, bounds, prior, stream=None):

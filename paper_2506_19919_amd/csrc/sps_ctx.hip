@@ -2,10 +2,33 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "sps_model.h"
+
+namespace sps {
+
+// Scratch of sps_loglike_grad_static: the approximate path's per-call buffers (z-bucket order,
+// its inverse, the sort's histogram and cursors, the input and output records) for up to
+// SPS_STATIC_MAX_GAL galaxies, laid out at 256-byte boundaries.  One copy per device, held
+// until the process ends.  In host code the array's name is not a device address: kernels
+// get the address hipGetSymbolAddress returned for the current device (g_scratch).
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t ST_PERM = 0;
+constexpr size_t ST_INV = ST_PERM + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
+constexpr size_t ST_HIST = ST_INV + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
+constexpr size_t ST_REC = ST_HIST + al256((size_t)2 * 1025 * sizeof(int));
+constexpr size_t ST_OREC = ST_REC + al256((size_t)SPS_STATIC_MAX_GAL * REC * sizeof(float));
+constexpr size_t ST_BYTES = ST_OREC + al256((size_t)SPS_STATIC_MAX_GAL * OREC * sizeof(float));
+static __device__ __align__(256) unsigned char scratch[ST_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static char *g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+}  // namespace sps
 
 namespace {
 
@@ -467,6 +490,17 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
     int rc = SPS_OK;
     auto fail = [&](int code) { free_ctx(c); return code; };
     if (hipSetDevice(device) != hipSuccess) return fail(set_error(SPS_E_HIP, "hipSetDevice failed"));
+    {   // the static scratch's address on this device, looked up once per device
+        if (device < 0 || device >= MAX_DEVICES) return fail(set_error(SPS_E_INVAL, "device index out of range"));
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(set_error(SPS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)));
+            g_scratch[device] = (char *)p;
+        }
+    }
     auto upload = [&](void **dst, const void *src, size_t bytes) -> int {
         SPS_HIP(hipMalloc(dst, bytes));
         SPS_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -708,6 +742,26 @@ int sps_hmc_run(sps_ctx *c, void *stream, const sps_hmc_cfg *cfg, int n_gal, int
         return set_error(SPS_E_INVAL, "null summary array (required from the call that ends the run)");
     return launch_hmc(c, (hipStream_t)stream, cfg, n_gal, sfh, z, obs, sigma, band_mask, bounds, prior, theta0,
                       samples, post_mean, post_sd, rhat, accept, step, inv_metric, state_inout);
+}
+
+int sps_loglike_grad_static(sps_ctx *c, void *stream, int n_gal, int sfh, const float *params, const float *z,
+                            const float *obs, const float *sigma, const uint8_t *band_mask, float *logl_out,
+                            float *grad_out) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if (n_gal < 0 || n_gal > SPS_STATIC_MAX_GAL)
+        return set_error(SPS_E_INVAL, "n_gal must be 0.." + std::to_string(SPS_STATIC_MAX_GAL) +
+                                          " for sps_loglike_grad_static");
+    if (sfh != SPS_SFH_LOGNORMAL && sfh != SPS_SFH_DPL) return set_error(SPS_E_INVAL, "bad sfh kind");
+    if (c->k.n_z == 0) return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
+    if (n_gal == 0) return SPS_OK;
+    if (!params || !z || !obs || !sigma || !band_mask || !logl_out) return set_error(SPS_E_INVAL, "null array");
+    char *base = g_scratch[c->device];   // set by sps_create for this device
+    if (!base) return set_error(SPS_E_STATE, "no static scratch on this device");
+    const ApproxWs ws{(int *)(base + ST_PERM), (int *)(base + ST_INV), (int *)(base + ST_HIST),
+                      (float *)(base + ST_REC), (float *)(base + ST_OREC)};
+    return launch_approx_ws(c, (hipStream_t)stream, ws, n_gal, sfh, grad_out ? MODE_LOGL_GRAD : MODE_LOGL, params, z,
+                            obs, sigma, band_mask, nullptr, nullptr, nullptr, logl_out, grad_out);
 }
 
 int sps_nuts_run(sps_ctx *c, void *stream, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
