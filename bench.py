@@ -289,11 +289,14 @@ def bench_exact(dev, n=4096, steps=5, warmup=2, cpu=False, budget_s=10.0):
     # hi/lo split spends three products per algorithmic one
     peaks = {"f32": (157.3, 1), "bf16x": (2500.0, 3)}
     for name, prec in (("f32", sps.SPS_F32), ("bf16x", sps.SPS_BF16X)):
+        # the tile order the autotuner picks for this shape (results do not depend on it)
+        chosen, tune_ms = ctx.autotune_exact(synth.SFH_DPL, params, zt, obs, sigma, mask, prec=prec)
         fwd = timed(lambda: ctx.phot_exact(synth.SFH_DPL, params, zt, prec=prec), steps, warmup)
         vg = timed(lambda: ctx.loglike_grad(synth.SFH_DPL, params, zt, obs, sigma, mask,
                                             path=sps.SPS_PATH_EXACT, prec=prec), steps, warmup)
         peak, mult = peaks[name]
-        res[name] = {"value_grad_evals_per_s": n / vg, "forward_evals_per_s": n / fwd,
+        res[name] = {"autotuned": {"exact_order": chosen["exact_order"], "exact_xcd": chosen["exact_xcd"]},
+                     "value_grad_evals_per_s": n / vg, "forward_evals_per_s": n / fwd,
                      "ms_value_grad": vg * 1e3, "ms_forward": fwd * 1e3,
                      "dense_equivalent_gemm_tflops_forward": gemm_flop / fwd / 1e12,
                      "dense_equivalent_gemm_tflops_value_grad": 2 * gemm_flop / vg / 1e12,
@@ -492,6 +495,53 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
             r["exact_over_approx_wall"] = full / approx_wall
         res[name] = r
         log(f"[bench]   {name}: {per_it * 1e3:.1f} ms per iteration, {full_iter} iterations ~ {full:.1f} s")
+    ctx.close()
+    return res
+
+
+def bench_hmc_exact_graph(dev, n=1024, C=4, L=10, n_iter=20):
+    """The exact-path HMC at a small batch (n x C chains), where each leapfrog step's ~10
+    kernels are short: one iteration captured as a hipGraph and replayed, against the same
+    kernels launched one by one; then the autotuner's own choice for this shape."""
+    import torch
+
+    import paper_2506_19919_amd as sps
+    import synth
+    log(f"[bench] exact-path HMC graph replay: {n} galaxies x {C} chains, {n_iter} iterations")
+    ssp, filt = synth.ssp_grid(2000), synth.filters()
+    ctx = sps.Context(ssp, filt, precisions=(sps.SPS_BF16X,), max_gal=n * C, max_exact=n * C)
+    ctx.build_ztable(64, 0.1, 3.0)
+    th, z = synth.galaxies_dpl(16_384, 104)
+    th, z = th[:n], z[:n]
+    params = torch.as_tensor(synth.soa32(th)).to(dev)
+    zt = torch.as_tensor(z.astype(np.float32)).to(dev)
+    noise, sig = synth.photometric_noise(16_384, 6, 204)
+    mags = ctx.phot_exact(synth.SFH_DPL, params, zt, prec=sps.SPS_BF16X)
+    obs = (mags + torch.as_tensor(noise[:n], dtype=torch.float32, device=dev)).contiguous()
+    sigma = torch.as_tensor(sig[:n], dtype=torch.float32, device=dev).contiguous()
+    mask = torch.as_tensor(np.ascontiguousarray(synth.band_masks(16_384, 6, 204)[:n])).to(dev)
+    bounds = torch.as_tensor(synth.bounds_k_x0(), dtype=torch.float32, device=dev)
+    prior = torch.as_tensor(synth.PRIOR, dtype=torch.float32, device=dev)
+    theta0 = torch.as_tensor(np.ascontiguousarray(synth.prior_draws(C, 16_384, 304)[:, :, :n]),
+                             dtype=torch.float32, device=dev)
+    args = (synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0)
+    kw = dict(n_chain=C, n_leapfrog=L, n_warmup=n_iter // 2, n_sample=n_iter - n_iter // 2, seed=404,
+              path=sps.SPS_PATH_EXACT, prec=sps.SPS_BF16X)
+    res = {"workload": f"{n} galaxies x {C} chains ({n * C} chains), {L} leapfrog steps, exact photometry in "
+                       f"BF16 hi+lo, {n_iter} iterations", "unit": "ms per iteration"}
+    for name, g in (("kernels", 0), ("graph", 1)):
+        ctx.set_launch(hmcx_graph=g)
+        ctx.hmc_run(*args, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.hmc_run(*args, **kw)
+        torch.cuda.synchronize()
+        res[f"ms_per_iteration_{name}"] = (time.perf_counter() - t0) / n_iter * 1e3
+    res["graph_speedup"] = res["ms_per_iteration_kernels"] / res["ms_per_iteration_graph"]
+    chosen, ms = ctx.autotune_hmc(*args, **kw)
+    res["autotuned_hmcx_graph"] = chosen["hmcx_graph"]
+    log(f"[bench]   {res['ms_per_iteration_kernels']:.2f} ms per iteration launched kernel by kernel, "
+        f"{res['ms_per_iteration_graph']:.2f} ms replayed as a graph; autotuner picks graph={chosen['hmcx_graph']}")
     ctx.close()
     return res
 
@@ -749,6 +799,8 @@ def main():
         aw = out["hmc"]["wall_s"] if "hmc" in out else None
         out["hmc_exact"] = bench_hmc_exact(dev, args.hmc_gal, n_iter=args.hmc_exact_iters,
                                            full_iter=args.hmc_warmup + args.hmc_sample, approx_wall=aw)
+    if not args.no_hmc_exact:
+        out["hmc_exact_graph"] = bench_hmc_exact_graph(dev)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ssp, filt, th32, z32, noise, sig)

@@ -248,6 +248,47 @@ int sps_hmc_run(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, i
  * a 256-byte header and 312 bytes per chain. */
 size_t sps_hmc_state_bytes(int n_gal, int n_chain);
 
+/* Launch choices of a context that never change any result, only the order or grouping in
+ * which independent work is issued (every output is bitwise the same for every setting):
+ *   exact_order      exact-path GEMM tile order: 0 the built-in policy (M fastest, N fastest
+ *                    for the windowed forward GEMM), 1 M fastest, 2 N fastest
+ *   exact_xcd        1: each of the 8 XCDs takes one contiguous run of tiles; 0: tiles in
+ *                    dispatch order (round-robin over the XCDs)
+ *   hmc_block_iters  approximate-path HMC iterations per kernel launch, 1..1000 (default 25)
+ *   nuts_block_iters NUTS iterations per kernel launch, 1..1000 (default 10)
+ *   hmcx_graph       exact-path HMC: 1 captures one iteration (about 10 kernels per leapfrog
+ *                    step) as a hipGraph once per call and replays it, the iteration index read
+ *                    from device memory; 0 launches the kernels one by one (default 1) */
+typedef struct {
+    int exact_order, exact_xcd, hmc_block_iters, nuts_block_iters, hmcx_graph;
+} sps_launch_cfg;
+
+int sps_get_launch(sps_ctx *ctx, sps_launch_cfg *out);
+int sps_set_launch(sps_ctx *ctx, const sps_launch_cfg *cfg);   /* SPS_E_INVAL for a value out of range */
+
+/* Autotuner of the launch choices above (setup calls: they synchronise the device and may
+ * allocate).  Each times the candidates with HIP events on `stream`, on the caller's own
+ * inputs (a few repetitions each, the median kept), sets the fastest in the context and writes
+ * it to *chosen (may be NULL); *timed_ms (may be NULL) receives the chosen candidate's time, or
+ * 0 if the choice came from the cache.  If the environment variable SPS_AUTOTUNE_CACHE names a
+ * file, choices are looked up there first (key: the call kind, device name and CU count, and
+ * the shape of the call) and new ones are added to it (a JSON object, one entry per line).
+ *  sps_autotune_exact: exact_order x exact_xcd on sps_loglike_grad(path = SPS_PATH_EXACT) of
+ *    these inputs (obs, sigma, band_mask may be NULL: sps_phot_exact is timed instead).
+ *  sps_autotune_hmc: hmc_block_iters (approximate path) or hmcx_graph (exact path) on a short
+ *    run of cfg's sampler (cfg->n_warmup + cfg->n_sample iterations are not run: a few
+ *    iterations of each candidate are) on these inputs. */
+int sps_autotune_exact(sps_ctx *ctx, void *stream, int n_gal, int sfh, int prec, const float *params, const float *z,
+                       const float *obs, const float *sigma, const uint8_t *band_mask, sps_launch_cfg *chosen,
+                       float *timed_ms);
+/* Autotuner of sps_hmc_run's launch choice (see sps_autotune_exact above for the protocol):
+ * hmc_block_iters on the approximate path (candidates 5, 10, 25, 50; timed on 50 iterations)
+ * or hmcx_graph on the exact path (timed on 10 iterations), each a throwaway run of cfg's
+ * sampler on these inputs (at most n_warmup + n_sample iterations). */
+int sps_autotune_hmc(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
+                     const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
+                     const float *prior, const float *theta0, sps_launch_cfg *chosen, float *timed_ms);
+
 /* sps_loglike_grad (approximate path) for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same
  * arguments, kernels and results as sps_loglike_grad with path = SPS_PATH_APPROX, but its

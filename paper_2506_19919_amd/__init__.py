@@ -30,7 +30,8 @@ ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_reserve_exact", "sps_status",
                  "sps_get_ztable", "sps_destroy", "sps_last_error", "sps_weights", "sps_phot_approx",
                  "sps_phot_exact", "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_hmc_state_bytes",
                  "sps_set_kernel_timing", "sps_kernel_times", "sps_nuts_run", "sps_reserve_nuts",
-                 "sps_loglike_grad_static")
+                 "sps_loglike_grad_static", "sps_get_launch", "sps_set_launch", "sps_autotune_exact",
+                 "sps_autotune_hmc")
 
 
 class SpsError(RuntimeError):
@@ -68,6 +69,14 @@ class _NutsCfg(C.Structure):
                 ("seed", C.c_ulonglong), ("adapt_metric", C.c_int), ("sync_iterations", C.c_int)]
 
 
+class _LaunchCfg(C.Structure):
+    _fields_ = [("exact_order", C.c_int), ("exact_xcd", C.c_int), ("hmc_block_iters", C.c_int),
+                ("nuts_block_iters", C.c_int), ("hmcx_graph", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_19919_amd/build.py")
@@ -97,6 +106,12 @@ def _load():
                                  vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sps_reserve_nuts.argtypes = [vp, i, i]
     lib.sps_loglike_grad_static.argtypes = [vp, vp, i, i, vp, vp, vp, vp, vp, vp, vp]
+    lib.sps_get_launch.argtypes = [vp, C.POINTER(_LaunchCfg)]
+    lib.sps_set_launch.argtypes = [vp, C.POINTER(_LaunchCfg)]
+    lib.sps_autotune_exact.argtypes = [vp, vp, i, i, i, vp, vp, vp, vp, vp, C.POINTER(_LaunchCfg),
+                                       C.POINTER(C.c_float)]
+    lib.sps_autotune_hmc.argtypes = [vp, vp, C.POINTER(_HmcCfg), i, i, vp, vp, vp, vp, vp, vp, vp,
+                                     C.POINTER(_LaunchCfg), C.POINTER(C.c_float)]
     lib.sps_set_kernel_timing.argtypes = [vp, i]
     lib.sps_kernel_times.argtypes = [vp, vp, i, C.POINTER(i)]
     for name in ABI_FUNCTIONS:
@@ -191,6 +206,40 @@ class Context:
         _check(_lib.sps_reserve_exact(self.h, max_rows))
         self.max_exact = max(self.max_exact, max_rows)
         self.max_gal = max(self.max_gal, max_rows)
+
+    # ---- launch choices (none changes a result) and their autotuner
+    def get_launch(self) -> dict:
+        l = _LaunchCfg()
+        _check(_lib.sps_get_launch(self.h, C.byref(l)))
+        return l.as_dict()
+
+    def set_launch(self, **kw):
+        """Change some launch choices: exact_order, exact_xcd, hmc_block_iters, nuts_block_iters,
+        hmcx_graph (see sps.h)."""
+        l = _LaunchCfg(**{**self.get_launch(), **kw})
+        _check(_lib.sps_set_launch(self.h, C.byref(l)))
+
+    def autotune_exact(self, sfh, params, z, obs=None, sigma=None, mask=None, prec=SPS_BF16X, stream=None):
+        """Time the exact path's tile orders on these inputs, keep the fastest; returns
+        (choices, ms of the chosen one, 0 if it came from SPS_AUTOTUNE_CACHE)."""
+        n = self._gal(params, z)
+        l, ms = _LaunchCfg(), C.c_float(0)
+        _check(_lib.sps_autotune_exact(self.h, _stream(stream), n, sfh, prec, _ptr(params), _ptr(z), _ptr(obs),
+                                       _ptr(sigma), _ptr(mask), C.byref(l), C.byref(ms)))
+        return l.as_dict(), ms.value
+
+    def autotune_hmc(self, sfh, z, obs, sigma, mask, bounds, prior, theta0, n_chain=4, n_leapfrog=10,
+                     n_warmup=200, n_sample=1000, target_accept=0.8, init_step=0.1, seed=404,
+                     adapt_metric=False, path=SPS_PATH_APPROX, prec=SPS_F32, stream=None):
+        """Time hmc_run's launch choice (iterations per launch, or graph replay on the exact
+        path) on a short run of these inputs; returns (choices, ms or 0 if cached)."""
+        n = z.shape[0]
+        cfg = _HmcCfg(n_chain, n_leapfrog, n_warmup, n_sample, target_accept, init_step, seed,
+                      int(bool(adapt_metric)), int(path), int(prec), 0, 0)
+        l, ms = _LaunchCfg(), C.c_float(0)
+        _check(_lib.sps_autotune_hmc(self.h, _stream(stream), C.byref(cfg), n, sfh, _ptr(z), _ptr(obs), _ptr(sigma),
+                                     _ptr(mask), _ptr(bounds), _ptr(prior), _ptr(theta0), C.byref(l), C.byref(ms)))
+        return l.as_dict(), ms.value
 
     def reserve_nuts(self, max_chains: int, max_depth: int = 10):
         """Size the NUTS workspace for up to max_chains chains (n_gal * n_chain) at max_depth."""

@@ -228,6 +228,9 @@ void free_ctx(sps_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     free_timing(c);
+    (void)release_graph(c);
+    if (c->graph_done) (void)hipEventDestroy(c->graph_done);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     (void)hipFree(c->d_lum64);
     (void)hipFree(c->d_ls32);
     (void)hipFree(c->d_lt32);
@@ -550,6 +553,9 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
         }
         if ((rc = upload((void **)&c->d_wc, wc.data(), wc.size() * sizeof(float)))) return fail(rc);
     }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming) != hipSuccess)
+        return fail(set_error(SPS_E_HIP, "stream / event creation failed"));
     if (hipMalloc(&c->d_hist, 2 * 1025 * sizeof(int)) != hipSuccess ||
         hipMalloc(&c->d_status, sizeof(int)) != hipSuccess || hipMemset(c->d_status, 0, sizeof(int)) != hipSuccess)
         return fail(set_error(SPS_E_NOMEM, "workspace allocation failed"));

@@ -307,6 +307,10 @@ struct XArgs {
     // rows in z order: the forward epilogue skips, per wave, the bands farther than 8 sigma
     // from all of its wavelengths (a wave's galaxies then share nearly one redshift)
     int band_skip;
+    // tile order (sps_launch_cfg): 0 the built-in policy, 1 M fastest, 2 N fastest; xcd: one
+    // contiguous run of tiles per XCD (1) or dispatch order (0).  Every order computes the same
+    // tiles the same way.
+    int order, xcd;
 };
 
 template <int P>
@@ -358,7 +362,7 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
     // XCD-aware tile order; with a split K the slot also names the K range
     const int T = a.n_mt * a.n_nt, nsp = (EPI == EPI_STORE) ? a.k_splits : 1, total = T * nsp, b = blockIdx.x;
     int t = b;
-    if (total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
+    if (a.xcd && total % 8 == 0) t = (b % 8) * (total / 8) + b / 8;
     // the K range: slowest, or between M and N where windows clip it (every XCD's run of tiles
     // then holds all ranges, so the mostly skipped last ones do not gather on a few XCDs, and
     // consecutive tiles still share their B rows and K range in L2)
@@ -373,7 +377,7 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
     }
     // M fastest, except in a windowed forward GEMM: its skipped tiles are whole wavelength
     // ranges, so there each XCD's run of tiles takes every wavelength tile of a few row tiles
-    const bool nfast = EPI != EPI_STORE && a.win != nullptr;
+    const bool nfast = a.order == 0 ? (EPI != EPI_STORE && a.win != nullptr) : (a.order == 2);
     const int tile_m = (nfast ? t / a.n_nt : t % a.n_mt) * XBM, tile_n = (nfast ? t % a.n_nt : t / a.n_mt) * XBN;
     int klen = a.K / nsp, kbeg = sp * klen;
     if (a.win) {
@@ -1072,6 +1076,8 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.inv_fs[b] = 1.0 / c->h_fs[b]; }
         a.part = part;
         a.npart = npart;
+        a.order = c->launch.exact_order;
+        a.xcd = c->launch.exact_xcd;
         const dim3 gx(a.n_mt * a.n_nt), bx(256);
         if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT>), gx, bx, 0, s, a);
         else if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT_DUST>), gx, bx, 0, s, a);
@@ -1133,6 +1139,8 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         const int tiles2 = b.n_mt * b.n_nt;
         b.k_splits = (tiles2 < 1024 && lw % (XSPLIT * XBK) == 0) ? XSPLIT : 1;
         b.c_split = (size_t)S_PAD * mp;
+        b.order = c->launch.exact_order;
+        b.xcd = c->launch.exact_xcd;
         const dim3 g2(b.n_mt * b.n_nt * b.k_splits), b2(256);
         if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
         else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE>), g2, b2, 0, s, b);

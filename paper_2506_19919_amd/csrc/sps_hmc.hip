@@ -972,7 +972,7 @@ int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, i
     const HmcArgs &ha = a;
     if (dpl) hipLaunchKernelGGL(k_hmc_init<SPS_SFH_DPL>, grid, block, lds_bytes, s, c->k, ha);
     else hipLaunchKernelGGL(k_hmc_init<SPS_SFH_LOGNORMAL>, grid, block, lds_bytes, s, c->k, ha);
-    const int nit = cfg->n_warmup + cfg->n_sample, blk_it = 10;
+    const int nit = cfg->n_warmup + cfg->n_sample, blk_it = c->launch.nuts_block_iters;
     for (int b0 = 0; b0 < nit; b0 += blk_it) {
         a.it0 = b0;
         a.it1 = b0 + blk_it < nit ? b0 + blk_it : nit;
@@ -1019,6 +1019,9 @@ struct HmcxArgs {
     // per-slot copies of the galaxy's inputs, the layout the exact path reads
     float *zs, *obs_s, *sig_s;
     uint8_t *mask_s;
+    // iteration index in device memory (a captured iteration reads it there), or null: the
+    // kernels' own argument
+    int *itp;
 };
 
 #define XS(arr, p) (arr)[(size_t)(p) * a.nslot + s]
@@ -1089,10 +1092,18 @@ __global__ void __launch_bounds__(256) k_hmcx_init(HmcxArgs a) {
     a.da0[s] = 0;
 }
 
+__global__ void k_hmcx_set_it(int *itp, int v) {
+    if (threadIdx.x == 0) *itp = v;
+}
+__global__ void k_hmcx_next_it(int *itp) {
+    if (threadIdx.x == 0) *itp += 1;
+}
+
 // iteration it begins: momentum draw, H0, the first half kick and drift
-__global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it) {
+__global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it_arg) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
+    const int it = a.itp ? *a.itp : it_arg;
     const int g = a.perm[s / a.C], ch = s % a.C;
     const uint32_t chain_id = (uint32_t)(ch * a.n_gal + g);
     uint32_t w[NP];
@@ -1133,9 +1144,10 @@ __global__ void __launch_bounds__(256) k_hmcx_start(HmcxArgs a, int it) {
 // after the model call of a leapfrog step: the closing half kick; then either the next
 // step's half kick and drift, or (last step) the Metropolis test, the step-size and metric
 // adaptation and the sample statistics
-__global__ void __launch_bounds__(256) k_hmcx_step(HmcxArgs a, int it, int last) {
+__global__ void __launch_bounds__(256) k_hmcx_step(HmcxArgs a, int it_arg, int last) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= a.nslot) return;
+    const int it = a.itp ? *a.itp : it_arg;
     const int g = a.perm[s / a.C], ch = s % a.C;
     float x[NP], gn[NP], p[NP];
     const double lpn = hmcx_logpost(a, s, x, gn);
@@ -1267,7 +1279,7 @@ size_t hmc_state_bytes(int nslot) {
 // the exact-path HMC's per-slot arrays besides the chain state: floats pm, xt, th, grad [NP] +
 // logl, zs + obs_s, sig_s [nb]; double h0; bytes mask_s
 struct HmcxLayout {
-    size_t o_f, o_d, o_m, bytes;
+    size_t o_f, o_d, o_m, o_it, bytes;
 };
 static HmcxLayout hmcx_layout(int nslot, int nb) {
     HmcxLayout L{};
@@ -1278,8 +1290,20 @@ static HmcxLayout hmcx_layout(int nslot, int nb) {
     off += align256((size_t)nslot * sizeof(double));
     L.o_m = off;
     off += align256((size_t)nslot);
+    L.o_it = off;
+    off += 256;
     L.bytes = off;
     return L;
+}
+
+int release_graph(sps_ctx *c) {
+    if (!c->graph_exec) return SPS_OK;
+    SPS_HIP(hipEventSynchronize(c->graph_done));
+    (void)hipGraphExecDestroy(c->graph_exec);
+    (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    return SPS_OK;
 }
 size_t hmcx_state_bytes(const sps_ctx *c, int nslot) { return hmcx_layout(nslot, c->n_band).bytes; }
 
@@ -1352,7 +1376,7 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
         a.perm = c->d_perm;
     }
     const dim3 grid((nslot + 255) / 256), block(256);
-    // one exact value+gradient over every chain at the positions in a.th
+    // one exact value+gradient over every chain at the positions in a.th (the start)
     auto model = [&]() {
         return launch_exact(c, s, nslot, sfh, cfg->prec, a.th, a.zs, nullptr, a.obs_s, a.sig_s, a.mask_s, a.logl,
                             a.grad, true);
@@ -1365,12 +1389,47 @@ static int launch_hmc_exact(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, i
     } else if ((rc = move_state(c, s, cs, state, cfg, n_gal, a.perm, 0, it0))) {
         return rc;
     }
-    for (int it = it0; it < it1; ++it) {
-        hipLaunchKernelGGL(k_hmcx_start, grid, block, 0, s, a, it);
+    // one iteration: the momentum draw and first half step, then per leapfrog step the exact
+    // value+gradient over every chain and the per-chain closing kick / drift / end of iteration
+    auto iteration = [&](hipStream_t st, int it) -> int {
+        hipLaunchKernelGGL(k_hmcx_start, grid, block, 0, st, a, it);
         for (int l = 0; l < cfg->n_leapfrog; ++l) {
-            if ((rc = model())) return rc;
-            hipLaunchKernelGGL(k_hmcx_step, grid, block, 0, s, a, it, (int)(l == cfg->n_leapfrog - 1));
+            const int r = launch_exact(c, st, nslot, sfh, cfg->prec, a.th, a.zs, nullptr, a.obs_s, a.sig_s,
+                                       a.mask_s, a.logl, a.grad, true);
+            if (r) return r;
+            hipLaunchKernelGGL(k_hmcx_step, grid, block, 0, st, a, it, (int)(l == cfg->n_leapfrog - 1));
         }
+        if (a.itp) hipLaunchKernelGGL(k_hmcx_next_it, dim3(1), dim3(64), 0, st, a.itp);
+        return SPS_OK;
+    };
+    if (c->launch.hmcx_graph && it1 - it0 >= 2) {
+        // capture one iteration on the context's capture stream (the iteration index lives in
+        // device memory and the captured iteration advances it), then replay it on s
+        if ((rc = release_graph(c))) return rc;
+        a.itp = (int *)(W + L.o_it);
+        hipLaunchKernelGGL(k_hmcx_set_it, dim3(1), dim3(64), 0, s, a.itp, it0);
+        SPS_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = iteration(c->cap_stream, it0);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+        if (rc || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : hip_check(ec, "hipStreamEndCapture");
+        }
+        hipGraphExec_t ge = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_check(ei, "hipGraphInstantiate");
+        }
+        c->graph = g;
+        c->graph_exec = ge;
+        for (int it = it0; it < it1; ++it) SPS_HIP(hipGraphLaunch(ge, s));
+        SPS_HIP(hipEventRecord(c->graph_done, s));
+        a.itp = nullptr;
+    } else {
+        for (int it = it0; it < it1; ++it)
+            if ((rc = iteration(s, it))) return rc;
     }
     if (state && (rc = move_state(c, s, cs, state, cfg, n_gal, a.perm, 1, it1))) return rc;
     if (it1 == nit)
@@ -1439,7 +1498,7 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
     a.pm = (float *)((char *)c->d_hstate + chain_state_bytes(nslot));
     a.xt = a.pm + (size_t)NP * ntmp;
     a.ntmp = ntmp;
-    const int blk_it = 25;
+    const int blk_it = c->launch.hmc_block_iters;
     dim3 grid((nslot * HG + 63) / 64), block(64);
     const bool dpl = (sfh == SPS_SFH_DPL);
     const size_t lds_bytes = approx_lds_bytes(c->n_band, false, HG);

@@ -109,6 +109,14 @@ struct sps_ctx {
     // NUTS, sized by sps_reserve_nuts: chain state, trajectory scratch and tree state
     void *d_nwork = nullptr;
     size_t nwork_bytes = 0;
+    // launch choices (sps_set_launch, the autotuner); none changes a result
+    sps_launch_cfg launch{0, 1, 25, 10, 1};
+    // the exact-path HMC's captured iteration: kept until the next capture or destroy, after
+    // graph_done (recorded behind its last replay) has completed
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipEvent_t graph_done = nullptr;
     // kernel timing (sps_set_kernel_timing): 2 events per pair, pairs used cyclically
     std::vector<hipEvent_t> tev;
     long long tev_calls = 0;
@@ -194,6 +202,8 @@ int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int
                float *post_sd, float *rhat, float *accept, float *step, float *inv_metric, void *state);
 
 size_t nuts_state_bytes(int nslot, int max_depth);
+// waits for the replays of the exact-path HMC's captured iteration, then frees it
+int release_graph(sps_ctx *c);
 int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, int sfh, const float *z,
                 const float *obs, const float *sigma, const uint8_t *mask, const float *bounds, const float *prior,
                 const float *theta0, float *samples, float *post_mean, float *post_sd, float *rhat, float *accept,
