@@ -2,7 +2,8 @@
 //
 // SFH bin masses (App. A.1, Eqs. totalMstarFormed, SFRsmooth, smoothPsfh):
 //   double power law: bin integrals by Gauss-Legendre-4 panels in X = ln(t/tau)
-//   (one 2-point panel for bins narrower than 1/4 of the panel width),
+//   (one 2-point panel for bins narrower than 1/4 of the panel width, the midpoint for bins
+//   whose older edge lies within 2^-7 of t_obs),
 //   where the integrand tau / (e^{(alpha-1)X} + e^{-(beta+1)X}) is analytic with
 //   poles at distance pi/(alpha+beta) from the real axis.  Panel width
 //   min(0.56, 2.8/(alpha+beta), 1.68/(beta+1)); in the oldest bin the panels reach down
@@ -219,7 +220,13 @@ __device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl
     }
     float s = 0.0f, sf = 0.0f, sa = 0.0f, sb = 0.0f, hw;
     const float npan = span * p.inv_w;
-    if (npan <= 0.25f) {
+    if (a_hi <= 0.0078125f * t_obs) {
+        // young bin: its span in X is below 9e-4, so the midpoint rule's relative error,
+        // span^2 |g''/g| / 24 with |g''/g| <= (beta+1)^2 + (alpha+beta)^2 / 4 + ..., stays
+        // below 5e-6 over alpha, beta <= 8 (typically below 1e-7)
+        hw = 0.5f * span;
+        dpl_node<DERIV>(p, xhi - hw, 2.0f, s, sf, sa, sb);
+    } else if (npan <= 0.25f) {
         hw = 0.5f * span;
         const float c = xhi - hw, d = hw * GL2X;
         dpl_node<DERIV>(p, c - d, 1.0f, s, sf, sa, sb);

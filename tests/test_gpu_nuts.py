@@ -93,7 +93,9 @@ def test_warmup_adaptation_matches_oracle(ctx, orc):
     assert ok.all() and excused.mean() <= 0.5, (ok, excused)
     same = ~excused
     assert same.sum() >= 5
-    np.testing.assert_allclose(out["step"].cpu().numpy()[same], ref["step"][same], rtol=1e-3)
+    # dual averaging moves log eps by ~20 sqrt(m) eta times the acceptance statistic's
+    # difference, which FP32 energies over trees of up to 15 leaves make ~1e-4: a few 1e-3
+    np.testing.assert_allclose(out["step"].cpu().numpy()[same], ref["step"][same], rtol=3e-3)
     assert np.all(np.abs(np.log(ref["step"] / 0.02)) > 0.05)   # the step sizes did adapt
 
 
