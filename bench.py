@@ -295,7 +295,7 @@ def bench_exact(dev, n=4096, steps=5, warmup=2, cpu=False, budget_s=10.0):
         vg = timed(lambda: ctx.loglike_grad(synth.SFH_DPL, params, zt, obs, sigma, mask,
                                             path=sps.SPS_PATH_EXACT, prec=prec), steps, warmup)
         peak, mult = peaks[name]
-        res[name] = {"autotuned": {"exact_order": chosen["exact_order"], "exact_xcd": chosen["exact_xcd"]},
+        res[name] = {"autotuned": {k: chosen[k] for k in ("exact_order", "exact_xcd", "exact_ring")},
                      "value_grad_evals_per_s": n / vg, "forward_evals_per_s": n / fwd,
                      "ms_value_grad": vg * 1e3, "ms_forward": fwd * 1e3,
                      "dense_equivalent_gemm_tflops_forward": gemm_flop / fwd / 1e12,
@@ -475,8 +475,13 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
     res = {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, exact photometry (1128 SSPs x 2000 "
                        f"wavelengths) in every step; {n_iter} iterations timed, {full_iter} extrapolated",
            "unit": "posteriors/min (extrapolated from the timed iterations)"}
+    # the GEMMs' launch choice for the chains' batch: the galaxies repeated once per chain (the
+    # value+gradient ranks a batch this large by z, as the sampler ranks its chains)
+    rep = lambda t: torch.cat([t] * C, dim=-1 if t.dim() == 2 and t.shape[0] == 10 else 0).contiguous()  # noqa: E731
+    p_c, z_c, o_c, s_c, m_c = rep(params), rep(zt), rep(obs), rep(sigma), rep(mask)
     n_warm = min(n_iter // 2, 200)   # the full-length check runs the workload's 200 + 1000
     for name, prec in (("f32", sps.SPS_F32), ("bf16x", sps.SPS_BF16X)):
+        chosen, _ = ctx.autotune_exact(synth.SFH_DPL, p_c, z_c, o_c, s_c, m_c, prec=prec)
         kw = dict(n_chain=C, n_leapfrog=L, path=sps.SPS_PATH_EXACT, prec=prec, seed=404)
         ctx.hmc_run(synth.SFH_DPL, zt, obs, sigma, mask, bounds, prior, theta0, n_warmup=1, n_sample=2, **kw)
         torch.cuda.synchronize()
@@ -488,7 +493,8 @@ def bench_hmc_exact(dev, n, n_iter=6, C=4, L=10, full_iter=1200, approx_wall=Non
         per_it = wall / n_iter
         full = per_it * full_iter
         evals = float(n) * C * (n_iter * L + 1)
-        r = {"ms_per_iteration": per_it * 1e3, "value_grad_evals_per_s": evals / wall,
+        r = {"autotuned": {k: chosen[k] for k in ("exact_order", "exact_xcd", "exact_ring")},
+             "ms_per_iteration": per_it * 1e3, "value_grad_evals_per_s": evals / wall,
              "projected_wall_s": full, "posteriors_per_min": n / full * 60.0,
              "mean_accept": float(out["accept"].mean().item())}
         if approx_wall:

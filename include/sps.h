@@ -251,16 +251,20 @@ size_t sps_hmc_state_bytes(int n_gal, int n_chain);
 /* Launch choices of a context that never change any result, only the order or grouping in
  * which independent work is issued (every output is bitwise the same for every setting):
  *   exact_order      exact-path GEMM tile order: 0 the built-in policy (M fastest, N fastest
- *                    for the windowed forward GEMM), 1 M fastest, 2 N fastest
+ *                    for the windowed forward GEMM), 1 M fastest, 2 N fastest, 3 bands of 8
+ *                    row tiles (M fastest within a band that sweeps every column tile)
  *   exact_xcd        1: each of the 8 XCDs takes one contiguous run of tiles; 0: tiles in
  *                    dispatch order (round-robin over the XCDs)
  *   hmc_block_iters  approximate-path HMC iterations per kernel launch, 1..1000 (default 25)
  *   nuts_block_iters NUTS iterations per kernel launch, 1..1000 (default 10)
  *   hmcx_graph       exact-path HMC: 1 captures one iteration (about 10 kernels per leapfrog
  *                    step) as a hipGraph once per call and replays it, the iteration index read
- *                    from device memory; 0 launches the kernels one by one (default 1) */
+ *                    from device memory; 0 launches the kernels one by one (default 1)
+ *   exact_ring       BF16X exact-path GEMMs: 0 operands staged through registers into one LDS
+ *                    stage, three blocks per CU; 1 a two-stage LDS ring filled by direct
+ *                    global-to-LDS loads, two blocks per CU (default 0) */
 typedef struct {
-    int exact_order, exact_xcd, hmc_block_iters, nuts_block_iters, hmcx_graph;
+    int exact_order, exact_xcd, hmc_block_iters, nuts_block_iters, hmcx_graph, exact_ring;
 } sps_launch_cfg;
 
 int sps_get_launch(sps_ctx *ctx, sps_launch_cfg *out);
@@ -273,7 +277,8 @@ int sps_set_launch(sps_ctx *ctx, const sps_launch_cfg *cfg);   /* SPS_E_INVAL fo
  * 0 if the choice came from the cache.  If the environment variable SPS_AUTOTUNE_CACHE names a
  * file, choices are looked up there first (key: the call kind, device name and CU count, and
  * the shape of the call) and new ones are added to it (a JSON object, one entry per line).
- *  sps_autotune_exact: exact_order x exact_xcd on sps_loglike_grad(path = SPS_PATH_EXACT) of
+ *  sps_autotune_exact: exact_order x exact_xcd (x exact_ring for SPS_BF16X) on
+ *    sps_loglike_grad(path = SPS_PATH_EXACT) of
  *    these inputs (obs, sigma, band_mask may be NULL: sps_phot_exact is timed instead).
  *  sps_autotune_hmc: hmc_block_iters (approximate path) or hmcx_graph (exact path) on a short
  *    run of cfg's sampler (cfg->n_warmup + cfg->n_sample iterations are not run: a few

@@ -71,7 +71,7 @@ class _NutsCfg(C.Structure):
 
 class _LaunchCfg(C.Structure):
     _fields_ = [("exact_order", C.c_int), ("exact_xcd", C.c_int), ("hmc_block_iters", C.c_int),
-                ("nuts_block_iters", C.c_int), ("hmcx_graph", C.c_int)]
+                ("nuts_block_iters", C.c_int), ("hmcx_graph", C.c_int), ("exact_ring", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -215,7 +215,7 @@ class Context:
 
     def set_launch(self, **kw):
         """Change some launch choices: exact_order, exact_xcd, hmc_block_iters, nuts_block_iters,
-        hmcx_graph (see sps.h)."""
+        hmcx_graph, exact_ring (see sps.h)."""
         l = _LaunchCfg(**{**self.get_launch(), **kw})
         _check(_lib.sps_set_launch(self.h, C.byref(l)))
 

@@ -282,6 +282,7 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
 constexpr int XBM = 128, XBN = 128, XBK = 32, XROW = 144;   // XROW in bytes
 constexpr int XSTAGE = (XBM + XBN) * XROW;                   // 36,864 bytes per stage
 constexpr int XSPLIT = 4;                                    // K ranges of the gradient GEMM
+constexpr int XBAND = 8;                                     // row tiles per band (tile order 3)
 
 struct XArgs {
     int M, N, K;
@@ -307,9 +308,9 @@ struct XArgs {
     // rows in z order: the forward epilogue skips, per wave, the bands farther than 8 sigma
     // from all of its wavelengths (a wave's galaxies then share nearly one redshift)
     int band_skip;
-    // tile order (sps_launch_cfg): 0 the built-in policy, 1 M fastest, 2 N fastest; xcd: one
-    // contiguous run of tiles per XCD (1) or dispatch order (0).  Every order computes the same
-    // tiles the same way.
+    // tile order (sps_launch_cfg): 0 the built-in policy, 1 M fastest, 2 N fastest, 3 bands of
+    // XBAND row tiles; xcd: one contiguous run of tiles per XCD (1) or dispatch order (0).  Every
+    // order computes the same tiles the same way.
     int order, xcd;
 };
 
@@ -346,16 +347,54 @@ __device__ inline void x_store(char *stage, int tid, const v4f (&r)[8]) {
     }
 }
 
-// LDS stages: FP32 double-buffers (two blocks per CU); BF16X, whose MFMA phase per k-tile is
-// a quarter as long, runs one stage with three blocks per CU, trading the second stage for
-// more waves to cover the operand loads (one stage: forward 0.220 -> 0.210 ms, exact HMC
-// iteration -10 %; FP32 value+gradient +13 %)
+// LDS stages: FP32 double-buffers through registers (two blocks per CU); BF16X, whose MFMA
+// phase per k-tile is a quarter as long, runs one register-staged stage with three blocks per
+// CU (RING = false), or (RING = true, a launch choice) a ring of two stages filled by direct
+// global-to-LDS loads, which need no staging registers, with two blocks per CU.  The two BF16X
+// forms multiply the same tiles in the same order (the same bits); which is faster depends on
+// the shape (sps_autotune_exact).
 template <int P> constexpr int x_nstage() { return P == SPS_BF16X ? 1 : 2; }
+constexpr int RSTAGES = 2;
+constexpr int RSTAGE = 2 * XBM * 128;   // A then B rows, 128 bytes (the k-tile's 32 hi + 32 lo) each
+template <int P, bool RING> constexpr int x_smem() { return RING ? RSTAGES * RSTAGE : x_nstage<P>() * XSTAGE; }
+template <int P, bool RING> constexpr int x_blocks() { return RING ? 2 : (P == SPS_BF16X ? 3 : 2); }
 
-template <int P, int EPI>
-__global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) {
+#define SPS_LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
+// s_waitcnt immediate for "at most n vector-memory operations outstanding" (other counters free)
+constexpr int vmcnt_imm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+
+// Ring stage of a k-tile: 32 loads of 1 KB, 8 per wave.  Waves 0 and 1 fill the A rows
+// 0..63 and 64..127, waves 2 and 3 the B rows; load j of a wave covers 8 of its rows, its lane L
+// writing the stage's bytes 1024 q + 16 L (q = 8 wave + j), i.e. slot L % 8 of stage row
+// 8 q + L / 8, with the row's 16-byte chunk (L % 8) ^ (L / 8) (chunks 0..3 hi, 4..7 lo;
+// (L / 8) = the stage row mod 8): the XOR swizzle that keeps the fragment reads free of bank
+// conflicts.  The lane's source address is fixed but for the k offset, and which operand a wave
+// loads is wave-uniform.
+struct XRing {
+    const uint16_t *src;   // this lane's chunk of its first row, k-tile 0 (uint16 units)
+    size_t jstep;          // from one of the wave's loads to the next: 8 rows
+};
+__device__ inline XRing x_ring_setup(const XArgs &a, int tile_m, int tile_n, int wave, int lane) {
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+    const bool isA = w < 2;
+    const uint16_t *base = (const uint16_t *)(isA ? a.A : a.B);
+    const int ld = isA ? a.lda : a.ldb, tile0 = isA ? tile_m : tile_n;
+    const int row = (w & 1) * 64 + (lane >> 3), c = (lane & 7) ^ (lane >> 3);
+    return XRing{base + (size_t)(tile0 + row) * 2 * ld + 8 * c, (size_t)16 * ld};
+}
+__device__ inline void x_ring_issue(const XRing &r, char *stage, int k0, int wave) {
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        __builtin_amdgcn_global_load_lds((const void *)(r.src + j * r.jstep + 2 * k0),
+                                         SPS_LDS_PTR(stage + 1024 * (8 * w + j)), 16, 0, 0);
+}
+
+template <int P, int EPI, bool RING>
+__global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
+    static_assert(!RING || P == SPS_BF16X, "the ring form is the BF16X kernel's");
     constexpr int NST = x_nstage<P>();
-    __shared__ __attribute__((aligned(16))) char smem[NST * XSTAGE];
+    __shared__ __attribute__((aligned(16))) char smem[x_smem<P, RING>()];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
@@ -378,7 +417,18 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
     // M fastest, except in a windowed forward GEMM: its skipped tiles are whole wavelength
     // ranges, so there each XCD's run of tiles takes every wavelength tile of a few row tiles
     const bool nfast = a.order == 0 ? (EPI != EPI_STORE && a.win != nullptr) : (a.order == 2);
-    const int tile_m = (nfast ? t / a.n_nt : t % a.n_mt) * XBM, tile_n = (nfast ? t % a.n_nt : t / a.n_mt) * XBN;
+    int tile_m, tile_n;
+    if (a.order == 3) {
+        // bands of XBAND row tiles: M fastest inside a band, which sweeps every column tile, so
+        // the blocks in flight on an XCD share a few A and B panels
+        const int band = t / (XBAND * a.n_nt), w = t - band * XBAND * a.n_nt;
+        const int bm = min(XBAND, a.n_mt - band * XBAND);
+        tile_m = (band * XBAND + w % bm) * XBM;
+        tile_n = (w / bm) * XBN;
+    } else {
+        tile_m = (nfast ? t / a.n_nt : t % a.n_mt) * XBM;
+        tile_n = (nfast ? t % a.n_nt : t / a.n_mt) * XBN;
+    }
     int klen = a.K / nsp, kbeg = sp * klen;
     if (a.win) {
         // wavelengths outside every band's support for all of this tile's galaxies: the
@@ -407,6 +457,45 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
     const int nk = klen / XBK;
+    if constexpr (RING) {
+        // prologue: k-tiles 0..2 in flight
+        const XRing ring = x_ring_setup(a, tile_m, tile_n, wave, lane);
+        for (int kt = 0; kt < RSTAGES - 1 && kt < nk; ++kt) x_ring_issue(ring, smem + kt * RSTAGE, kbeg + kt * XBK, wave);
+        for (int kt = 0; kt < nk; ++kt) {
+            // this wave's loads of k-tile kt are done once at most those of the later k-tiles
+            // in flight (8 per k-tile) remain; the barrier then covers every wave's loads, and
+            // every wave's reads of the stage that k-tile kt + RSTAGES - 1 refills (k-tile
+            // kt - 1's)
+            const int ahead = min(nk - 1, kt + RSTAGES - 2) - kt;
+            asm volatile("" ::: "memory");
+            if (ahead >= 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(8));
+            else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (kt + RSTAGES - 1 < nk)
+                x_ring_issue(ring, smem + ((kt + RSTAGES - 1) % RSTAGES) * RSTAGE, kbeg + (kt + RSTAGES - 1) * XBK,
+                             wave);
+            const char *As = smem + (kt % RSTAGES) * RSTAGE, *Bs = As + XBM * 128;
+            b8v ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ra = wm * 64 + i * 16 + li, rb = wn * 64 + i * 16 + li;
+                ah[i] = *(const b8v *)(As + ra * 128 + ((lk ^ (ra & 7)) << 4));
+                al[i] = *(const b8v *)(As + ra * 128 + (((lk + 4) ^ (ra & 7)) << 4));
+                bh[i] = *(const b8v *)(Bs + rb * 128 + ((lk ^ (rb & 7)) << 4));
+                bl[i] = *(const b8v *)(Bs + rb * 128 + (((lk + 4) ^ (rb & 7)) << 4));
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();   // every wave is done with the ring before the epilogue reuses it
+    } else {
     v4f r[8];
     x_load<P>(a, tile_m, tile_n, kbeg, tid, r);
     x_store(smem, tid, r);
@@ -460,6 +549,7 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
         }
         __syncthreads();
     }
+    }
 
     if constexpr (EPI == EPI_STORE) {
         // C stored transposed, C[n][m] with row stride ldc >= the 128-padded M: a lane's four
@@ -477,9 +567,9 @@ __global__ void __launch_bounds__(256, P == SPS_BF16X ? 3 : 2) k_xgemm(XArgs a) 
         // SED tile [128 galaxies][128 wavelengths] -> LDS in NPASS passes of PW columns (row
         // stride PW + 1; one stage holds half the tile), two threads per galaxy reducing PW / 2
         // wavelengths each per pass into the band sums
-        constexpr int NPASS = (NST == 2) ? 1 : 2, PW = XBN / NPASS;
+        constexpr int NPASS = (x_smem<P, RING>() >= XBM * (XBN + 1) * 4) ? 1 : 2, PW = XBN / NPASS;
         float(*sed)[PW + 1] = reinterpret_cast<float(*)[PW + 1]>(smem);
-        static_assert(XBM * (PW + 1) * 4 <= NST * XSTAGE, "SED columns fit the staging buffers");
+        static_assert(XBM * (PW + 1) * 4 <= x_smem<P, RING>(), "SED columns fit the staging buffers");
         const int row = tid >> 1, half = tid & 1, g = tile_m + row;
         constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;   // num, N [, dnum/dtauV, dnum/ddelta, dnum/dFfloor]
         float accp[NB_MAX][NPB];
@@ -1079,10 +1169,13 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         a.order = c->launch.exact_order;
         a.xcd = c->launch.exact_xcd;
         const dim3 gx(a.n_mt * a.n_nt), bx(256);
-        if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT>), gx, bx, 0, s, a);
-        else if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT_DUST>), gx, bx, 0, s, a);
-        else if (!want_grad) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT>), gx, bx, 0, s, a);
-        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT_DUST>), gx, bx, 0, s, a);
+        const bool ring = c->launch.exact_ring != 0;
+        if (prec == SPS_F32 && !want_grad) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT, false>), gx, bx, 0, s, a);
+        else if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_PHOT_DUST, false>), gx, bx, 0, s, a);
+        else if (!want_grad && ring) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT, true>), gx, bx, 0, s, a);
+        else if (!want_grad) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT, false>), gx, bx, 0, s, a);
+        else if (ring) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT_DUST, true>), gx, bx, 0, s, a);
+        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT_DUST, false>), gx, bx, 0, s, a);
     }
 
     float *cn = logl ? (float *)(W + o_cn) : nullptr;
@@ -1142,8 +1235,9 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         b.order = c->launch.exact_order;
         b.xcd = c->launch.exact_xcd;
         const dim3 g2(b.n_mt * b.n_nt * b.k_splits), b2(256);
-        if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE>), g2, b2, 0, s, b);
-        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE>), g2, b2, 0, s, b);
+        if (prec == SPS_F32) hipLaunchKernelGGL((k_xgemm<SPS_F32, EPI_STORE, false>), g2, b2, 0, s, b);
+        else if (c->launch.exact_ring) hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE, true>), g2, b2, 0, s, b);
+        else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_STORE, false>), g2, b2, 0, s, b);
         float *pb = (float *)(W + o_pb);
         if (b.k_splits > 1) {
             const size_t n4 = b.c_split / 4;

@@ -110,7 +110,7 @@ struct sps_ctx {
     void *d_nwork = nullptr;
     size_t nwork_bytes = 0;
     // launch choices (sps_set_launch, the autotuner); none changes a result
-    sps_launch_cfg launch{0, 1, 25, 10, 1};
+    sps_launch_cfg launch{0, 1, 25, 10, 1, 0};
     // the exact-path HMC's captured iteration: kept until the next capture or destroy, after
     // graph_done (recorded behind its last replay) has completed
     hipStream_t cap_stream = nullptr;

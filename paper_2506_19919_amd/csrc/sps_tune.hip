@@ -17,9 +17,10 @@ namespace sps {
 namespace {
 
 bool launch_valid(const sps_launch_cfg &l) {
-    return l.exact_order >= 0 && l.exact_order <= 2 && (l.exact_xcd == 0 || l.exact_xcd == 1) &&
+    return l.exact_order >= 0 && l.exact_order <= 3 && (l.exact_xcd == 0 || l.exact_xcd == 1) &&
            l.hmc_block_iters >= 1 && l.hmc_block_iters <= 1000 && l.nuts_block_iters >= 1 &&
-           l.nuts_block_iters <= 1000 && (l.hmcx_graph == 0 || l.hmcx_graph == 1);
+           l.nuts_block_iters <= 1000 && (l.hmcx_graph == 0 || l.hmcx_graph == 1) &&
+           (l.exact_ring == 0 || l.exact_ring == 1);
 }
 
 // ---- the cache file: {"key": {"name": value, ...}, ...}, one entry per line
@@ -210,12 +211,15 @@ int sps_autotune_exact(sps_ctx *c, void *stream, int n_gal, int sfh, int prec, c
     key << "exact|" << device_key(c->device) << "|n=" << n_gal << "|prec=" << prec << "|nw=" << c->n_wave
         << "|nb=" << c->n_band << "|grad=" << (lik ? 1 : 0);
     std::vector<std::map<std::string, double>> cands;
-    for (int o = 0; o <= 2; ++o)
-        for (int x = 1; x >= 0; --x) cands.push_back({{"exact_order", (double)o}, {"exact_xcd", (double)x}});
+    for (int rg = 0; rg <= (prec == SPS_BF16X ? 1 : 0); ++rg)
+        for (int o = 0; o <= 3; ++o)
+            for (int x = 1; x >= 0; --x)
+                cands.push_back({{"exact_order", (double)o}, {"exact_xcd", (double)x}, {"exact_ring", (double)rg}});
     auto set = [](sps_launch_cfg &l, const std::map<std::string, double> &v) {
-        auto o = v.find("exact_order"), x = v.find("exact_xcd");
+        auto o = v.find("exact_order"), x = v.find("exact_xcd"), r = v.find("exact_ring");
         if (o != v.end()) l.exact_order = (int)o->second;
         if (x != v.end()) l.exact_xcd = (int)x->second;
+        if (r != v.end()) l.exact_ring = (int)r->second;
     };
     auto run = [&]() {
         return lik ? sps_loglike_grad(c, stream, n_gal, sfh, SPS_PATH_EXACT, prec, params, z, obs, sigma, band_mask,

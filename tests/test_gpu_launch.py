@@ -50,18 +50,19 @@ def test_exact_tile_orders_give_the_same_bits(ctx, orc, prec_name):
     prec = getattr(sps, prec_name)
     sfh, p, z, obs, sig, mask = _lik_inputs(orc, 700, 901)
     ref = None
-    for order in (0, 1, 2):
-        for xcd in (1, 0):
-            ctx.set_launch(exact_order=order, exact_xcd=xcd)
-            ll, g = ctx.loglike_grad(sfh, p, z, obs, sig, mask, path=sps.SPS_PATH_EXACT, prec=prec)
-            m = ctx.phot_exact(sfh, p, z, prec=prec)
-            got = (ll.clone(), g.clone(), m.clone())
-            if ref is None:
-                ref = got
-                assert torch.isfinite(ll).all()
-            else:
-                assert all(torch.equal(a, b) for a, b in zip(got, ref)), (order, xcd)
-    ctx.set_launch(exact_order=0, exact_xcd=1)
+    for ring in ((0, 1) if prec == sps.SPS_BF16X else (0,)):
+        for order in (0, 1, 2, 3):
+            for xcd in (1, 0):
+                ctx.set_launch(exact_order=order, exact_xcd=xcd, exact_ring=ring)
+                ll, g = ctx.loglike_grad(sfh, p, z, obs, sig, mask, path=sps.SPS_PATH_EXACT, prec=prec)
+                m = ctx.phot_exact(sfh, p, z, prec=prec)
+                got = (ll.clone(), g.clone(), m.clone())
+                if ref is None:
+                    ref = got
+                    assert torch.isfinite(ll).all()
+                else:
+                    assert all(torch.equal(a, b) for a, b in zip(got, ref)), (ring, order, xcd)
+    ctx.set_launch(exact_order=0, exact_xcd=1, exact_ring=0)
 
 
 def test_hmc_block_iterations_give_the_same_draws(ctx, orc):
@@ -130,7 +131,7 @@ def test_autotuner_picks_and_caches(ctx, orc, tmp_path):
         entries = json.loads(path.read_text())
         (key, val), = entries.items()
         assert key.startswith("exact|") and val["exact_order"] == ch["exact_order"] and val["ms"] > 0
-        ctx.set_launch(exact_order=0, exact_xcd=1)
+        ctx.set_launch(exact_order=0, exact_xcd=1, exact_ring=0)
         ch2, ms2 = ctx.autotune_exact(sfh, p, z, obs, sig, mask, prec=sps.SPS_BF16X)
         assert ms2 == 0 and ch2 == ch                     # from the cache, not timed again
         args = _chain_inputs(orc, 32, 942, 2)
@@ -145,13 +146,13 @@ def test_autotuner_picks_and_caches(ctx, orc, tmp_path):
             del os.environ["SPS_AUTOTUNE_CACHE"]
         else:
             os.environ["SPS_AUTOTUNE_CACHE"] = old
-        ctx.set_launch(exact_order=0, exact_xcd=1, hmc_block_iters=25, hmcx_graph=1)
+        ctx.set_launch(exact_order=0, exact_xcd=1, hmc_block_iters=25, hmcx_graph=1, exact_ring=0)
 
 
 def test_launch_choices_out_of_range_are_refused(ctx):
     import paper_2506_19919_amd as sps
-    for bad in (dict(exact_order=3), dict(exact_xcd=2), dict(hmc_block_iters=0), dict(nuts_block_iters=1001),
-                dict(hmcx_graph=-1)):
+    for bad in (dict(exact_order=4), dict(exact_xcd=2), dict(exact_ring=2), dict(hmc_block_iters=0),
+                dict(nuts_block_iters=1001), dict(hmcx_graph=-1)):
         with pytest.raises(sps.SpsError) as e:
             ctx.set_launch(**bad)
         assert e.value.code == sps.SPS_E_INVAL
