@@ -173,11 +173,12 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
             S += (double)m;
         }
     } else {
+        const Logn p = make_logn(th[1], th[2]);
         for (int i = q; i < NA; i += G) {
-            double m, a, b;
-            logn_bin<false>(k, i, t_obs, (double)th[1], (double)th[2], m, a, b);
-            col[i] = (float)m;
-            S += m;
+            float m, a, b;
+            logn_bin<false>(k, i, t_obs_f, p, m, a, b);
+            col[i] = m;
+            S += (double)m;
         }
     }
     S = group_sum<G>(S);
@@ -231,9 +232,12 @@ __device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, i
     float A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
     double dA0 = 0.0, dA1 = 0.0, dB0 = 0.0, dB1 = 0.0;
     Dpl p;
+    Logn lp;
     if (sfh == SPS_SFH_DPL) {
         p = make_dpl(th[1], th[2], th[3]);
         dpl_at_obs(p, t_obs_f);
+    } else {
+        lp = make_logn(th[1], th[2]);
     }
     // smooth part: dP_age/dF_burst = P_burst - P_smooth; the P_burst term is added below
     for (int i = q; i < NA; i += G) {
@@ -245,7 +249,11 @@ __device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, i
             dpl_bin<true>(k, i, t_obs_f, p, m, mt, ma, mb);
             ps = m * invS;
         } else {
-            logn_bin<true>(k, i, t_obs, (double)th[1], (double)th[2], dm, dmt, dmw);
+            float fm, ft, fw;
+            logn_bin<true>(k, i, t_obs_f, lp, fm, ft, fw);
+            dm = fm;
+            dmt = ft;
+            dmw = fw;
             ps = (float)(dm / ws.S);
         }
         fbar = fmaf(-gbar, ps, fbar);
