@@ -390,54 +390,62 @@ __device__ inline v4f mfma3(const b8v &ah, const b8v &al, const b8v &bh, const b
 template <int MODE_ADJ, bool PK, int G>
 __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, const ApproxLds &L, int lane, int kk,
                                          float f, float scale, int kmin, int kmax, int nbk, int n_out) {
+    // both halves of the wave in one sweep: each B fragment is loaded once and multiplied into
+    // the two halves' accumulators
+    constexpr int NH = 2 / G;
     const int li = lane & 15, lk = lane >> 4;
     const size_t lo_off = (size_t)k.n_z * QB_NODE;
+    v4f acc[NH][6][2];
 #pragma unroll
-    for (int h = 0; h < 2 / G; ++h) {
-        v4f acc[6][2];
+    for (int h = 0; h < NH; ++h)
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
 #pragma unroll
-            for (int m = 0; m < 2; ++m) acc[nb][m] = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int kb = kmin; kb <= kmax; ++kb) {
-            const bool act = (kk == kb);
-            if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
-            float w0[2], w1[2];
-            pass_weights(L, lane, lane / G, h, act, f, scale, w0, w1);
-            const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
-#pragma unroll 1
-            for (int ks = 0; ks < KSTEPS; ++ks) {
-                b8v a0h[2], a0l[2], a1h[2], a1l[2];
-                a_frags<PK>(L, lane, h, ks, w0, w1, a0h, a0l, a1h, a1l);
+            for (int m = 0; m < 2; ++m) acc[h][nb][m] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kb = kmin; kb <= kmax; ++kb) {
+        const bool act = (kk == kb);
+        if (__builtin_amdgcn_readfirstlane(__ballot(act) != 0ull) == 0) continue;
+        float w0[NH][2], w1[NH][2];
 #pragma unroll
-                for (int nb = 0; nb < 6; ++nb) {
-                    if (nb >= nbk) break;
-                    const size_t o = (size_t)(nb * KSTEPS + ks) * 512;
-                    const b8v q0h = *(const b8v *)(b0 + o), q0l = *(const b8v *)(b0 + lo_off + o);
-                    const b8v q1h = *(const b8v *)(b1 + o), q1l = *(const b8v *)(b1 + lo_off + o);
+        for (int h = 0; h < NH; ++h) pass_weights(L, lane, lane / G, h, act, f, scale, w0[h], w1[h]);
+        const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
+#pragma unroll 1
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            b8v a0h[NH][2], a0l[NH][2], a1h[NH][2], a1l[NH][2];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) a_frags<PK>(L, lane, h, ks, w0[h], w1[h], a0h[h], a0l[h], a1h[h], a1l[h]);
+#pragma unroll
+            for (int nb = 0; nb < 6; ++nb) {
+                if (nb >= nbk) break;
+                const size_t o = (size_t)(nb * KSTEPS + ks) * 512;
+                const b8v q0h = *(const b8v *)(b0 + o), q0l = *(const b8v *)(b0 + lo_off + o);
+                const b8v q1h = *(const b8v *)(b1 + o), q1l = *(const b8v *)(b1 + lo_off + o);
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
 #pragma unroll
                     for (int m = 0; m < 2; ++m) {
-                        acc[nb][m] = mfma3(a0h[m], a0l[m], q0h, q0l, acc[nb][m]);
-                        acc[nb][m] = mfma3(a1h[m], a1l[m], q1h, q1l, acc[nb][m]);
+                        acc[h][nb][m] = mfma3(a0h[h][m], a0l[h][m], q0h, q0l, acc[h][nb][m]);
+                        acc[h][nb][m] = mfma3(a1h[h][m], a1l[h][m], q1h, q1l, acc[h][nb][m]);
                     }
-                }
             }
-            __syncthreads();   // the next pass rewrites the weight slots
         }
-        // all of this half's A reads are done: its results overwrite its own region (T in
-        // FP32, dP_age in 24 bits)
+        __syncthreads();   // the next pass rewrites the weight slots
+    }
+    // all A reads are done: each half's results overwrite its own region (T in FP32, dP_age in
+    // 24 bits)
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb)
             if (nb < nbk && 16 * nb + li < n_out) {
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     const int r = 16 * nb + li, c = 16 * m + 4 * lk;
-                    if (MODE_ADJ && PK) store4_24(L.hi(h), L.lo(h), prow(r) * HALF + c, acc[nb][m]);
-                    else *(v4f *)(L.t(h) + r * HALF + c) = acc[nb][m];
+                    if (MODE_ADJ && PK) store4_24(L.hi(h), L.lo(h), prow(r) * HALF + c, acc[h][nb][m]);
+                    else *(v4f *)(L.t(h) + r * HALF + c) = acc[h][nb][m];
                 }
             }
-        __syncthreads();
-    }
+    __syncthreads();
 }
 
 // T[g][r] = sum_i P_age[g][i] ((1 - f) Qk[r][i] + f Qk+1[r][i]), P_age = scale x the column
