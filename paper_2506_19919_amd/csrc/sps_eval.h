@@ -596,4 +596,38 @@ __device__ inline double log_prior_skewnorm(const float *pri, float x, float &dl
     return log(2.0 / om) - 0.9189385332046727 - 0.5 * y * y + lphi;
 }
 
+// the skew-normal prior's constants of one parameter, formed once per launch: xi, 1 / omega,
+// s and log(2 / omega) - log sqrt(2 pi), in FP64 (the log prior enters the FP64 Hamiltonian)
+struct PriorC {
+    double xi, inv_om, sk, c0;
+};
+__device__ inline PriorC prior_const(const float *pri) {
+    const double om = pri[1];
+    return PriorC{(double)pri[0], 1.0 / om, (double)pri[2], log(2.0 / om) - 0.9189385332046727};
+}
+// the NP parameters' constants into LDS (every lane of the workgroup must call it)
+__device__ inline void stage_prior(const float *prior, PriorC *pc) {
+    if (threadIdx.x < NP) pc[threadIdx.x] = prior_const(prior + 3 * threadIdx.x);
+    __syncthreads();
+}
+// log_prior_skewnorm from the precomputed constants
+__device__ inline double log_prior_pc(const PriorC &c, float x, float &dlp) {
+    const double y = ((double)x - c.xi) * c.inv_om, v = c.sk * y;
+    double lphi, ratio;
+    if (c.sk == 0.0) {
+        lphi = -0.69314718055994531;
+        ratio = 0.79788456080286536;
+    } else if (v < -5.0) {
+        const double e = erfcx(-v * 0.7071067811865475);
+        lphi = log(0.5 * e) - 0.5 * v * v;
+        ratio = 0.7978845608028654 / e;
+    } else {
+        const double P = Phi_d(v);
+        lphi = log(P);
+        ratio = phi_d(v) / P;
+    }
+    dlp = (float)((c.sk * ratio - y) * c.inv_om);
+    return c.c0 - 0.5 * y * y + lphi;
+}
+
 }  // namespace sps

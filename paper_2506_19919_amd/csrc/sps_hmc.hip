@@ -215,6 +215,13 @@ __device__ __noinline__ double log_prior_all(const float *prior, const float (&x
     for (int p = 0; p < NP; ++p) lp += log_prior_skewnorm(prior + 3 * p, x[p], dlp[p]);
     return lp;
 }
+// the same from the constants staged in LDS (stage_prior)
+__device__ __noinline__ double log_prior_all_pc(const PriorC *pc, const float (&x)[NP], float (&dlp)[NP]) {
+    double lp = 0.0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) lp += log_prior_pc(pc[p], x[p], dlp[p]);
+    return lp;
+}
 
 // Metropolis test of a proposal with energy change dH (FP64) against the uniform word w;
 // alpha = min(1, exp(-dH)), 0 for a divergent proposal (non-finite H1 or dH > 1000).
@@ -231,9 +238,8 @@ __device__ __noinline__ bool metropolis(double H1, double dH, uint32_t w, float 
 
 // log posterior and its gradient at the position held in the lane's trajectory scratch
 template <int SFH>
-__device__ __forceinline__ double logpost(const DevConsts &k, const float *ledge, const HmcArgs &a, const LaneCtx &lc0,
-                                          const ApproxLds &L,
-                                float (&g)[NP]) {
+__device__ __forceinline__ double logpost(const DevConsts &k, const float *ledge, const PriorC *pc, const HmcArgs &a,
+                                          const LaneCtx &lc0, const ApproxLds &L, float (&g)[NP]) {
     float x[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) x[p] = TMP(a.xt, p);
@@ -257,7 +263,7 @@ __device__ __forceinline__ double logpost(const DevConsts &k, const float *ledge
 #pragma unroll
     for (int p = 0; p < NP; ++p) x[p] = TMP(a.xt, p);
     float dlp[NP];
-    const double lp = logl + log_prior_all(a.prior, x, dlp);
+    const double lp = logl + log_prior_all_pc(pc, x, dlp);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         float t, dth;
@@ -315,6 +321,8 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
     const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
+    __shared__ PriorC pcs[NP];
+    stage_prior(a.prior, pcs);
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     float x[NP], gr[NP];
@@ -326,7 +334,7 @@ __global__ void __launch_bounds__(64) k_hmc_init(DevConsts k, HmcArgs a) {
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) TMP(a.xt, p) = x[p];
-    const double lp = logpost<SFH>(k, ledge, a, lc, lds, gr);
+    const double lp = logpost<SFH>(k, ledge, pcs, a, lc, lds, gr);
     if (!si.valid) return;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -355,6 +363,8 @@ __global__ void __launch_bounds__(64, 2) k_hmc(DevConsts k, HmcArgs a) {
     const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
+    __shared__ PriorC pcs[NP];
+    stage_prior(a.prior, pcs);
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     const bool valid = si.valid;
@@ -404,7 +414,7 @@ __global__ void __launch_bounds__(64, 2) k_hmc(DevConsts k, HmcArgs a) {
                 TMP(a.xt, t) = fmaf(eps * ST(a.minv, t), p[t], TMP(a.xt, t));
             }
             asm volatile("" ::: "memory");
-            lpn = logpost<SFH>(k, ledge, a, lc, lds, gn);
+            lpn = logpost<SFH>(k, ledge, pcs, a, lc, lds, gn);
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int t = 0; t < NP; ++t) p[t] = fmaf(0.5f * eps, gn[t], TMP(a.pm, t));
@@ -603,6 +613,8 @@ __global__ void __launch_bounds__(64, 2) k_nuts(DevConsts k, NutsArgs a) {
     const ApproxLds lds = approx_lds(lds_dyn, k.n_band, false, HG);
     __shared__ float ledge[NA + 1];
     stage_log_age_edges(k, ledge);
+    __shared__ PriorC pcs[NP];
+    stage_prior(a.prior, pcs);
     const SlotInfo si = slot_info(a);
     const LaneCtx lc = lane_ctx(k, a, si);
     const uint32_t chain_id = si.chain_id;
@@ -693,7 +705,7 @@ __global__ void __launch_bounds__(64, 2) k_nuts(DevConsts k, NutsArgs a) {
         }
         asm volatile("" ::: "memory");
         float ge[NP];
-        const double lpe = logpost<SFH>(k, ledge, a, lc, lds, ge);
+        const double lpe = logpost<SFH>(k, ledge, pcs, a, lc, lds, ge);
         asm volatile("" ::: "memory");
         ++wave_steps;
         if (!act) continue;
