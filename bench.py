@@ -358,6 +358,18 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False, cpu=False, 
     rhat = out["rhat"].cpu().numpy()
     conv = float(np.mean(np.all(rhat < 1.2, axis=0)))
     evals = float(n) * C * (n_warm + n_samp) * L
+    one_shot = None
+    if not adapt_metric:
+        # the one-shot value+gradient kernel on a batch of the sampler's size (n x C rows: each
+        # galaxy repeated per chain, same uneven bands), the rate the fused kernel compares with
+        rep = lambda t: torch.cat([t] * C, dim=-1).contiguous()   # noqa: E731
+        pb, zb = rep(params), rep(zt)
+        ob = torch.cat([obs] * C, dim=0).contiguous()
+        sb = torch.cat([sigma] * C, dim=0).contiguous()
+        mb = torch.cat([mask] * C, dim=0).contiguous()
+        t_one = timed(lambda: ctx.loglike_grad(synth.SFH_DPL, pb, zb, ob, sb, mb), 20, 3)
+        one_shot = n * C / t_one
+        log(f"[bench]   one-shot value+grad on the same {n * C} rows: {t_one * 1e3:.3f} ms ({one_shot:.3e} evals/s)")
     ctx.close()
     log(f"[bench]   HMC wall {wall:.2f} s, converged fraction {conv:.3f} (adapt_metric={adapt_metric}, L={L})")
     res = {"workload": f"{n} galaxies x {C} chains, {L} leapfrog steps, {n_warm} warm-up + {n_samp} samples, "
@@ -370,6 +382,9 @@ def bench_hmc(dev, n, n_warm, n_samp, C=4, L=10, adapt_metric=False, cpu=False, 
            "value_grad_evals_per_s": evals / wall,
            "wall_s": wall,
            "mean_accept": float(out["accept"].mean().item())}
+    if one_shot:
+        res["one_shot_same_batch_evals_per_s"] = one_shot
+        res["fused_over_one_shot_same_batch"] = evals / wall / one_shot
     if cpu:
         import oracle
         m = max(1, oracle_threads() // C)
@@ -674,9 +689,17 @@ def main():
     ap.add_argument("--hmc-gal", type=int, default=16_384)
     ap.add_argument("--hmc-warmup", type=int, default=200)
     ap.add_argument("--hmc-sample", type=int, default=1000)
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs to run after the headline (all, or any of exact_f64, approx_fwd, "
+                         "exact, accuracy, hmc, nuts, posterior_agreement, hmc_exact)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="also run 3 plain 1 GiB device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
+
+    def leg(name, off):
+        return not off and ("all" in legs or name in legs)
+
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by "
                                    "independent galaxies and is measured per GPU (--gpus 1)"}))
@@ -785,27 +808,27 @@ def main():
     del params, zt, obs, sigma, mask, logl, grad, mags
     ctx.close()
     cpu = not args.no_cpu_baseline
-    if not args.no_exact:
+    if leg("exact_f64", args.no_exact):
         out["exact_f64"] = bench_exact_f64(dev, cpu=cpu)
-    if not args.no_approx_fwd:
+    if leg("approx_fwd", args.no_approx_fwd):
         out["approx_fwd"] = bench_approx_fwd(dev, cpu=cpu)
-    if not args.no_exact:
+    if leg("exact", args.no_exact):
         out["exact"] = bench_exact(dev, cpu=cpu)
-    if not args.no_accuracy:
+    if leg("accuracy", args.no_accuracy):
         out["approx_accuracy"] = bench_approx_accuracy(dev)
-    if not args.no_hmc:
+    if leg("hmc", args.no_hmc):
         out["hmc"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample, cpu=cpu)
         out["hmc_adapted_metric"] = bench_hmc(dev, args.hmc_gal, args.hmc_warmup, args.hmc_sample,
                                               adapt_metric=True)
-    if not args.no_nuts:
+    if leg("nuts", args.no_nuts):
         out["nuts"] = bench_nuts(dev)
-    if not args.no_posterior_agreement:
+    if leg("posterior_agreement", args.no_posterior_agreement):
         out["posterior_agreement"] = bench_posterior_agreement(dev)
-    if not args.no_hmc_exact:
+    if leg("hmc_exact", args.no_hmc_exact):
         aw = out["hmc"]["wall_s"] if "hmc" in out else None
         out["hmc_exact"] = bench_hmc_exact(dev, args.hmc_gal, n_iter=args.hmc_exact_iters,
                                            full_iter=args.hmc_warmup + args.hmc_sample, approx_wall=aw)
-    if not args.no_hmc_exact:
+    if leg("hmc_exact", args.no_hmc_exact):
         out["hmc_exact_graph"] = bench_hmc_exact_graph(dev)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

@@ -90,8 +90,9 @@ struct GemmArgs {
     const double *wave, *trap;
     int n_band;
     double fc[NB_MAX], fs[NB_MAX];
-    float *part;               // [n_tiles_n][M][npart]
+    float *part;               // [k_split][n_tiles_n][M][npart]
     int npart;
+    int k_chunk;               // K columns per blockIdx.z (a multiple of BK)
 };
 
 // ------------------------------------------------------------------ GEMM + epilogue
@@ -127,7 +128,8 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
 
     const T *Ah = (const T *)a.A_hi, *Al = (const T *)a.A_lo;
     const T *Bh = (const T *)a.B_hi, *Bl = (const T *)a.B_lo;
-    for (int k0 = 0; k0 < a.K_pad; k0 += BK) {
+    const int k_beg = blockIdx.z * a.k_chunk, k_end = min(a.K_pad, k_beg + a.k_chunk);
+    for (int k0 = k_beg; k0 < k_end; k0 += BK) {
         // ---- stage A: rows = galaxies (beyond M: zero); columns padded with zeros in memory
         for (int e = tid; e < BM * BK; e += 256) {
             const int r = e / BK, c = e % BK, m = tile_m + r;
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
                 const E tb = e_exp((E)(-0.5 * x * x));
                 const E stw = s * tb * wq;
                 acc_p[b][0] += stw * F;
-                acc_p[b][1] += tb * qi;
+                if (blockIdx.z == 0) acc_p[b][1] += tb * qi;   // the band normaliser, once over the K split
                 if constexpr (EPI == EPI_PHOT_DUST) {
                     const E dtv = -(1 - ffl) * xd * ee;
                     acc_p[b][2] += stw * dtv;
@@ -253,7 +255,7 @@ __global__ void __launch_bounds__(256) k_exact_gemm(GemmArgs a) {
                 acc_p[b][q] = v;
             }
         if (sub == 0 && g < a.M) {
-            E *out = (E *)a.part + ((size_t)blockIdx.x * a.M + g) * a.npart;
+            E *out = (E *)a.part + (((size_t)blockIdx.z * gridDim.x + blockIdx.x) * a.M + g) * a.npart;
 #pragma unroll
             for (int b = 0; b < NB_MAX; ++b) {
                 if (b >= a.n_band) break;
@@ -653,59 +655,62 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
 
 // ------------------------------------------------------------------ FP64 weights rows P_SSP[g][s]
 // FP64 weights from FP64 bin edges: closed-form log-normal or 8-point Gauss-Legendre DPL
-// panels, closed-form triweight and normal CDFs (the FP64 parity path)
+// panels, closed-form triweight and normal CDFs (the FP64 parity path).  One wave per galaxy:
+// lane i takes age bins i and i + 64, the smooth and burst normalisers are wave sums, and the
+// row is written with consecutive lanes on consecutive age bins.
 __global__ void __launch_bounds__(64) k_exact_weights64(DevConsts k, int n, int sfh, const double *params_v,
                                                         const double *z_v, const double *edges, double *w_out) {
-    const int lane = threadIdx.x, g = blockIdx.x * 64 + lane;
-    const int gg = g < n ? g : n - 1;
-    {
-        const double *prm = params_v;
-        const double *age_lo = edges, *age_hi = edges + NA, *lage_lo = edges + 2 * NA, *lage_hi = edges + 3 * NA;
-        const double *met_lo = edges + 4 * NA, *met_hi = edges + 4 * NA + NZ;
-        double th[NP];
+    static_assert(NA <= 128 && NZ <= 64, "two age bins per lane, one metallicity bin per lane");
+    __shared__ double spz[NZ];
+    const int lane = threadIdx.x, g = blockIdx.x;
+    const double *prm = params_v;
+    const double *age_lo = edges, *age_hi = edges + NA, *lage_lo = edges + 2 * NA, *lage_hi = edges + 3 * NA;
+    const double *met_lo = edges + 4 * NA, *met_hi = edges + 4 * NA + NZ;
+    double th[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + gg];
-        const double t_obs = age_universe_gyr(k, z_v[gg]);
-        const double sig_z = k.sigma_logz_d;
-        double pz[NZ];
-        for (int j = 0; j < NZ; ++j) {
-            const double xl = (met_lo[j] - th[6]) / sig_z, xh = (met_hi[j] - th[6]) / sig_z;
-            pz[j] = (xl > 0.0) ? Phic_d(xl) - Phic_d(xh) : Phi_d(xh) - Phi_d(xl);
-        }
-        double S = 0.0, Zb = 0.0;
-        const double l_obs = log10(t_obs * 1e9), s3 = 3.0 * k.burst_sig_d;
-        auto mass = [&](int i) {
-            double m, a0, a1;
-            if (sfh == SPS_SFH_LOGNORMAL) {
-                logn_bin_e<false>(age_lo[i], age_hi[i], t_obs, th[1], th[2], m, a0, a1);
-            } else {
-                m = dpl_bin_f64(k, age_lo[i], age_hi[i], t_obs, th[1], th[2], th[3]);
-            }
-            return m;
-        };
-        auto burst = [&](int i) {
-            const double lo = lage_lo[i];
-            if (!(lo < l_obs)) return 0.0;
-            const double hi = fmin(lage_hi[i], l_obs);
-            auto cdf = [](double u) {
-                u = fmin(fmax(u, -1.0), 1.0);
-                const double u2 = u * u;
-                return 0.5 + 1.09375 * u * (1.0 - u2 + u2 * u2 * (0.6 - u2 / 7.0));
-            };
-            return cdf((hi - th[5]) / s3) - cdf((lo - th[5]) / s3);
-        };
-        for (int i = 0; i < NA; ++i) {
-            S += mass(i);
-            Zb += burst(i);
-        }
-        if (g >= n) return;
-        double *w = w_out + (size_t)g * S_PAD;
-        for (int i = 0; i < NA; ++i) {
-            const double pa = (1.0 - th[4]) * mass(i) / S + (Zb > 0.0 ? th[4] * burst(i) / Zb : 0.0);
-            for (int j = 0; j < NZ; ++j) w[j * NA + i] = pz[j] * pa;
-        }
-        for (int s = NSSP; s < S_PAD; ++s) w[s] = 0.0;
+    for (int p = 0; p < NP; ++p) th[p] = prm[(size_t)p * n + g];
+    const double t_obs = age_universe_gyr(k, z_v[g]);
+    if (lane < NZ) {
+        const double xl = (met_lo[lane] - th[6]) / k.sigma_logz_d, xh = (met_hi[lane] - th[6]) / k.sigma_logz_d;
+        spz[lane] = (xl > 0.0) ? Phic_d(xl) - Phic_d(xh) : Phi_d(xh) - Phi_d(xl);
     }
+    const double l_obs = log10(t_obs * 1e9), s3 = 3.0 * k.burst_sig_d;
+    auto mass = [&](int i) {
+        if (i >= NA) return 0.0;
+        double m, a0, a1;
+        if (sfh == SPS_SFH_LOGNORMAL) logn_bin_e<false>(age_lo[i], age_hi[i], t_obs, th[1], th[2], m, a0, a1);
+        else m = dpl_bin_f64(k, age_lo[i], age_hi[i], t_obs, th[1], th[2], th[3]);
+        return m;
+    };
+    auto burst = [&](int i) {
+        if (i >= NA) return 0.0;
+        const double lo = lage_lo[i];
+        if (!(lo < l_obs)) return 0.0;
+        const double hi = fmin(lage_hi[i], l_obs);
+        auto cdf = [](double u) {
+            u = fmin(fmax(u, -1.0), 1.0);
+            const double u2 = u * u;
+            return 0.5 + 1.09375 * u * (1.0 - u2 + u2 * u2 * (0.6 - u2 / 7.0));
+        };
+        return cdf((hi - th[5]) / s3) - cdf((lo - th[5]) / s3);
+    };
+    const double m0 = mass(lane), m1 = mass(lane + 64), b0 = burst(lane), b1 = burst(lane + 64);
+    double S = m0 + m1, Zb = b0 + b1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        S += __shfl_xor(S, o, 64);
+        Zb += __shfl_xor(Zb, o, 64);
+    }
+    __syncthreads();
+    double *w = w_out + (size_t)g * S_PAD;
+    const double pa0 = (1.0 - th[4]) * m0 / S + (Zb > 0.0 ? th[4] * b0 / Zb : 0.0);
+    const double pa1 = (1.0 - th[4]) * m1 / S + (Zb > 0.0 ? th[4] * b1 / Zb : 0.0);
+    for (int j = 0; j < NZ; ++j) {
+        const double pz = spz[j];
+        w[j * NA + lane] = pz * pa0;
+        if (lane + 64 < NA) w[j * NA + lane + 64] = pz * pa1;
+    }
+    for (int s = NSSP + lane; s < S_PAD; s += 64) w[s] = 0.0;
 }
 
 // ------------------------------------------------------------------ FP32 / BF16X weights, GPL lanes per galaxy
@@ -957,6 +962,25 @@ __global__ void __launch_bounds__(256) k_sum_tiles(int n, int npart, int n_tiles
     out[(size_t)q * n + g] = v;
 }
 
+// FP64 partials [t][g][q] summed over the wavelength tiles and the K split: out[g][q].  One
+// block per galaxy; thread (r, q) sums every R-th partial of quantity q, then the R row sums
+// of each quantity are added in LDS.
+__global__ void __launch_bounds__(256) k_sum_parts64(int n, int npart, int n_parts, const double *part,
+                                                     double *out) {
+    __shared__ double red[256];
+    const int g = blockIdx.x, tid = threadIdx.x, R = 256 / npart, r = tid / npart, q = tid % npart;
+    double v = 0.0;
+    if (r < R)
+        for (int t = r; t < n_parts; t += R) v += part[((size_t)t * n + g) * npart + q];
+    red[tid] = v;
+    __syncthreads();
+    if (tid < npart) {
+        double acc = 0.0;
+        for (int i = 0; i < R; ++i) acc += red[i * npart + tid];
+        out[(size_t)g * npart + tid] = acc;
+    }
+}
+
 // the weights adjoint -> grad slots 1..6, GPL lanes per galaxy
 template <int GPL>
 __global__ void __launch_bounds__(64) k_exact_adjoint(DevConsts k, int n, int sfh, const float *params,
@@ -1045,10 +1069,25 @@ struct ExactLayout {
     size_t o_w = 0, o_pw = 0, o_part = 0, o_psum = 0, o_win = 0, o_cn = 0, o_rb = 0, o_wb = 0, o_pb = 0;
     size_t bytes = 0;
 };
+// FP64 GEMM K split: a few row tiles (the 64-galaxy parity batch is one) leave most of the
+// chip idle, so the SSP axis is cut into chunks of at least four k-tiles until the grid holds
+// about 512 blocks; each chunk writes its own band partials, which the finish kernel sums.
+struct F64Split {
+    int ks, chunk;
+};
+static F64Split f64_split(int n, int n_tiles) {
+    const int steps = S_PAD / Prec<SPS_F64>::BK, blocks = n_tiles * ((n + BM - 1) / BM);
+    int ks = 1;
+    while (blocks * ks < 512 && steps / (2 * ks) >= 4) ks *= 2;
+    const int per = (steps + ks - 1) / ks;
+    return F64Split{(steps + per - 1) / per, per * Prec<SPS_F64>::BK};
+}
+
 static ExactLayout exact_layout(const sps_ctx *c, int n, int prec, bool logl, bool grad) {
     const int nw = c->n_wave, nb = c->n_band;
     const bool f64 = (prec == SPS_F64);
     const int n_tiles = f64 ? (nw + BN - 1) / BN : c->lw / XBN;
+    const int n_parts = f64 ? n_tiles * f64_split(n, n_tiles).ks : n_tiles;
     const int mp = round_up(n, XBM);              // A operands are read in whole 128-row tiles
     const bool want_grad = logl && grad;
     const int npart = (want_grad ? 5 : 2) * nb;
@@ -1060,8 +1099,8 @@ static ExactLayout exact_layout(const sps_ctx *c, int n, int prec, bool logl, bo
     auto carve = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~(size_t)255; return o; };
     L.o_w = carve((size_t)nsplit * mp * S_PAD * tsz);
     L.o_pw = f64 ? 0 : carve((size_t)PW_SLOTS * n * 4);
-    L.o_part = carve((size_t)n_tiles * n * npart * esz);
-    L.o_psum = f64 ? 0 : carve((size_t)n * npart * 4);
+    L.o_part = carve((size_t)n_parts * n * npart * esz);
+    L.o_psum = carve((size_t)n * npart * esz);
     L.o_win = f64 ? 0 : carve((size_t)(mp / XBM) * sizeof(int4));
     if (logl) {
         L.o_cn = carve((size_t)n * NB_MAX * 4);
@@ -1076,7 +1115,13 @@ static ExactLayout exact_layout(const sps_ctx *c, int n, int prec, bool logl, bo
 }
 
 size_t exact_ws_bytes(const sps_ctx *c, int n, int prec, bool logl, bool grad) {
-    return exact_layout(c, n, prec, logl, grad).bytes;
+    if (prec != SPS_F64) return exact_layout(c, n, prec, logl, grad).bytes;
+    // the FP64 K split grows as the batch shrinks: size for the largest need of any batch up
+    // to n, which within one split factor falls on a whole number of row tiles or on n
+    size_t most = 0;
+    for (int t = 1; t <= (n + BM - 1) / BM; ++t)
+        most = std::max(most, exact_layout(c, std::min(t * BM, n), prec, logl, grad).bytes);
+    return most;
 }
 
 static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
@@ -1102,7 +1147,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
 
     float *pw = f64 ? nullptr : (float *)(W + o_pw);
     if (f64) {
-        hipLaunchKernelGGL(k_exact_weights64, dim3((n + 63) / 64), dim3(64), 0, s, c->k, n, sfh,
+        hipLaunchKernelGGL(k_exact_weights64, dim3(n), dim3(64), 0, s, c->k, n, sfh,
                            (const double *)params, (const double *)z, c->d_edges, (double *)w_hi);
     } else {
         if (n >= GPL_BIG_N)
@@ -1138,7 +1183,9 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         for (int b = 0; b < NB_MAX; ++b) { a.fc[b] = c->h_fc[b]; a.fs[b] = c->h_fs[b]; }
         a.part = part;
         a.npart = npart;
-        dim3 gg(n_tiles, (n + BM - 1) / BM), bg(256);
+        const F64Split sp = f64_split(n, n_tiles);
+        a.k_chunk = sp.chunk;
+        dim3 gg(n_tiles, (n + BM - 1) / BM, sp.ks), bg(256);
         hipLaunchKernelGGL((k_exact_gemm<SPS_F64, EPI_PHOT>), gg, bg, 0, s, a);
     } else {
         const FiltConst fl = filt_const(c->h_fc, c->h_fs);
@@ -1180,14 +1227,18 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
 
     float *cn = logl ? (float *)(W + o_cn) : nullptr;
     dim3 gf((n + 127) / 128), bf(128);
-    int n_fin = n_tiles;   // tiles the finish kernel sums (1 once they are pre-summed)
+    int n_fin = f64 ? n_tiles * f64_split(n, n_tiles).ks : n_tiles;   // partials the finish kernel sums
     if (!f64) {
         float *psum = (float *)(W + o_psum);
         hipLaunchKernelGGL(k_sum_tiles, dim3((n + 255) / 256, npart), dim3(256), 0, s, n, npart, n_tiles,
                            (const float *)part, psum);
         part = psum;
-        n_fin = 1;
+    } else {
+        double *psum = (double *)(W + o_psum);
+        hipLaunchKernelGGL(k_sum_parts64, dim3(n), dim3(256), 0, s, n, npart, n_fin, (const double *)part, psum);
+        part = (float *)psum;
     }
+    n_fin = 1;
     switch (prec) {
         case SPS_F64:
             hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
