@@ -209,7 +209,8 @@ def bench_exact_f64(dev, n=64, steps=20, warmup=3, cpu=True):
     return res
 
 
-def bench_approx_fwd(dev, n=100_000, steps=20, warmup=3, cpu=True, budget_s=8.0):
+def bench_approx_fwd(dev, n=100_000, steps=20, warmup=3, cpu=True, budget_s=8.0,
+                     sweep=(100_000, 1_000_000, 10_000_000)):
     """Approximate magnitudes (the z-table path), forward only: n log-normal-SFH galaxies with a
     burst, 6 bands; evals/s, algorithmic HBM rate and the model kernel's own duration."""
     import torch
@@ -247,6 +248,32 @@ def bench_approx_fwd(dev, n=100_000, steps=20, warmup=3, cpu=True, budget_s=8.0)
         res.update(busy)
     log(f"[bench]   {t * 1e3:.3f} ms per call (kernel {kernel_ms:.3f} ms), "
         f"{res['hbm_gbps_algorithmic_call']:.1f} GB/s algorithmic")
+    if sweep:
+        # batch-size sweep (10^5 .. 10^7): at 10^5 galaxies a launch holds ~1,600 waves, below
+        # one round of the chip's 2,048 wave slots, so the per-galaxy rate there is latency-bound
+        big = max(sweep)
+        ths, zs = synth.galaxies_lognormal(big, 112, burst=True)
+        cs = sps.Context(ssp, filt, precisions=(sps.SPS_F64,), max_gal=big)
+        cs.build_ztable(64, 0.1, 3.0)
+        rows = []
+        for m in sweep:
+            pm = torch.as_tensor(synth.soa32(ths[:m])).to(dev)
+            zm = torch.as_tensor(zs[:m].astype(np.float32)).to(dev)
+            om = torch.empty((m, 6), dtype=torch.float32, device=dev)
+            f = lambda: cs.phot_approx(synth.SFH_LOGNORMAL, pm, zm, out=om)   # noqa: E731,B023
+            f()
+            torch.cuda.synchronize()
+            reps = max(3, min(steps, int(2e6 // m)))
+            cs.set_kernel_timing(reps)
+            tm = timed(f, reps, 0)
+            km = float(np.mean(cs.kernel_times()))
+            cs.set_kernel_timing(0)
+            rows.append({"n_gal": m, "ms_per_call": tm * 1e3, "kernel_ms": km, "evals_per_s": m / tm,
+                         "frac_of_fp32_vector_peak": WORK_PER_FWD * m / (km * 1e-3) / 1e12 / PEAK_FP32_VECTOR})
+            log(f"[bench]   sweep {m}: {tm * 1e3:.3f} ms per call, kernel {km:.3f} ms")
+            del pm, zm, om
+        cs.close()
+        res["batch_sweep"] = rows
     if cpu:
         import oracle
         orc = oracle.Oracle(ssp, filt)

@@ -177,6 +177,19 @@ int sps_loglike_grad(sps_ctx *ctx, void *stream, int n_gal, int sfh, int path, i
                      const float *params, const float *z, const float *obs, const float *sigma,
                      const uint8_t *band_mask, float *logl_out, float *grad_out);
 
+/* Vector-Jacobian product of the magnitudes: grad_out[p][g] = sum_b gbar[g][b] dm_b/dtheta_p
+ * for the 10 physical parameters (Sec. 4: the gradients a gradient-based sampler or a
+ * user's own loss needs; the backward of the magnitude outputs of Eq. photo_integral_approx
+ * and Eq. photo_integral_exact).  It is the same hand-written adjoint as sps_loglike_grad's,
+ * seeded with the caller's band adjoints gbar [n_gal][n_band] (FP32, every band used) in
+ * place of the likelihood's residual terms.  path SPS_PATH_APPROX (prec ignored, needs a z
+ * table) or SPS_PATH_EXACT (prec SPS_F32 or SPS_BF16X; n_gal <= the reserved exact rows).
+ * All arrays are caller-owned device memory; grad_out [10][n_gal] FP32 is overwritten.
+ * Errors: SPS_E_INVAL (null array, bad path or precision), SPS_E_STATE (no z table, table
+ * not uploaded, too few reserved rows). */
+int sps_phot_vjp(sps_ctx *ctx, void *stream, int n_gal, int sfh, int path, int prec,
+                 const float *params, const float *z, const float *gbar, float *grad_out);
+
 /* Log posterior on the unbounded parameters x (App. C): theta_p = F_B(x_p) with
  * bounds[p] = (y_lo, y_hi, k, x0), plus the skew-normal log prior with
  * prior[p] = (xi, omega, s) on x_p; value logp_out [n_gal] and gradient

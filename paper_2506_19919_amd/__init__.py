@@ -31,7 +31,7 @@ ABI_FUNCTIONS = ("sps_create", "sps_reserve", "sps_reserve_exact", "sps_status",
                  "sps_phot_exact", "sps_loglike_grad", "sps_logpost_grad", "sps_hmc_run", "sps_hmc_state_bytes",
                  "sps_set_kernel_timing", "sps_kernel_times", "sps_nuts_run", "sps_reserve_nuts",
                  "sps_loglike_grad_static", "sps_get_launch", "sps_set_launch", "sps_autotune_exact",
-                 "sps_autotune_hmc")
+                 "sps_autotune_hmc", "sps_phot_vjp")
 
 
 class SpsError(RuntimeError):
@@ -324,6 +324,17 @@ class Context:
                                      _ptr(grad_out) if grad else None))
         return (logl_out, grad_out) if grad else logl_out
 
+    def phot_vjp(self, sfh, params, z, gbar, path=SPS_PATH_APPROX, prec=SPS_F32, grad_out=None, stream=None):
+        """sum_b gbar[g][b] dm_b/dtheta_p for the 10 physical parameters, [10][n_gal]: the
+        backward of the magnitudes (approximate path, or exact in SPS_F32 / SPS_BF16X)."""
+        n = self._gal(params, z)
+        _dev(gbar, torch.float32, (n, self.n_band), "gbar", self.device)
+        if grad_out is None:
+            grad_out = torch.empty((NPARAM, n), dtype=torch.float32, device=self.device)
+        _check(_lib.sps_phot_vjp(self.h, _stream(stream), n, sfh, path, prec, _ptr(params), _ptr(z), _ptr(gbar),
+                                 _ptr(grad_out)))
+        return grad_out
+
     def loglike_grad_static(self, sfh, params, z, obs, sigma, mask, grad=True, logl_out=None, grad_out=None,
                             stream=None):
         """loglike_grad on the approximate path through the entry point that allocates nothing
@@ -452,3 +463,47 @@ class LogLike(torch.autograd.Function):
 
 def loglike(sps_ctx, params, z, obs, sigma, mask, sfh=SPS_SFH_DPL, path=SPS_PATH_APPROX, prec=SPS_F32):
     return LogLike.apply(params, z, obs, sigma, mask, sps_ctx, sfh, path, prec)
+
+
+class PhotApprox(torch.autograd.Function):
+    """Approximate magnitudes [n_gal][n_band] of params [10][n_gal]; backward: the library's
+    vector-Jacobian product of the band adjoints."""
+
+    @staticmethod
+    def forward(ctx, params, z, sps_ctx, sfh):
+        p = params.detach().contiguous()
+        ctx.save_for_backward(p, z)
+        ctx.sps, ctx.sfh = sps_ctx, sfh
+        return sps_ctx.phot_approx(sfh, p, z)
+
+    @staticmethod
+    def backward(ctx, gbar):
+        p, z = ctx.saved_tensors
+        g = ctx.sps.phot_vjp(ctx.sfh, p, z, gbar.contiguous().float(), path=SPS_PATH_APPROX)
+        return g, None, None, None
+
+
+class PhotExact(torch.autograd.Function):
+    """Exact magnitudes [n_gal][n_band] in SPS_F32 or SPS_BF16X; backward: the exact path's
+    vector-Jacobian product (the adjoint GEMM) of the band adjoints."""
+
+    @staticmethod
+    def forward(ctx, params, z, sps_ctx, sfh, prec):
+        p = params.detach().contiguous()
+        ctx.save_for_backward(p, z)
+        ctx.sps, ctx.sfh, ctx.prec = sps_ctx, sfh, prec
+        return sps_ctx.phot_exact(sfh, p, z, prec=prec)
+
+    @staticmethod
+    def backward(ctx, gbar):
+        p, z = ctx.saved_tensors
+        g = ctx.sps.phot_vjp(ctx.sfh, p, z, gbar.contiguous().float(), path=SPS_PATH_EXACT, prec=ctx.prec)
+        return g, None, None, None, None
+
+
+def phot_approx(sps_ctx, params, z, sfh=SPS_SFH_DPL):
+    return PhotApprox.apply(params, z, sps_ctx, sfh)
+
+
+def phot_exact(sps_ctx, params, z, sfh=SPS_SFH_DPL, prec=SPS_F32):
+    return PhotExact.apply(params, z, sps_ctx, sfh, prec)

@@ -247,8 +247,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     const uint32_t mask = (MODE == MODE_MAGS) ? 0xffu : (uint32_t)__float_as_int(rec[REC_MASK]);
     float mags[NB_MAX] = {}, gr[NP];
     double logl;
-    constexpr int EM = (MODE == MODE_LOGPOST_GRAD) ? MODE_LOGL_GRAD : MODE;
-    approx_eval<EM, true>(k, ledge, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
+    constexpr int EM = (MODE == MODE_LOGPOST_GRAD || MODE == MODE_VJP) ? MODE_LOGL_GRAD : MODE;
+    approx_eval<EM, true, 1, MODE == MODE_VJP>(k, ledge, a.sfh, a.qf, a.qa, lds, th, zf, kk, f, t_obs, m0, kmin, kmax, rec + REC_OBS, rec + REC_SIG,
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(256) k_unpermute(int n, int nb, const int *__r
         for (int b = 0; b < nb; ++b) mag[(size_t)i * nb + b] = o[b];
         return;
     }
-    val[i] = o[0];
+    if (val) val[i] = o[0];
     if (MODE != MODE_LOGL && grad) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) grad[(size_t)p * n + i] = o[1 + p];
@@ -399,6 +399,13 @@ int launch_approx_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, int s
             if (tev) (void)hipEventRecord(tev[1], s);
             hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
                                out_val, out_grad);
+            break;
+        case MODE_VJP:
+            if (tev) (void)hipEventRecord(tev[0], s);
+            hipLaunchKernelGGL(k_approx<MODE_VJP>, grid, block, lds_bytes, s, c->k, a);
+            if (tev) (void)hipEventRecord(tev[1], s);
+            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
+                               nullptr, out_grad);
             break;
         case MODE_LOGPOST_GRAD:
             if (tev) (void)hipEventRecord(tev[0], s);

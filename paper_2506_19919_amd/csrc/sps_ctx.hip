@@ -695,6 +695,26 @@ int sps_loglike_grad(sps_ctx *c, void *stream, int n_gal, int sfh, int path, int
                         logl_out, grad_out);
 }
 
+int sps_phot_vjp(sps_ctx *c, void *stream, int n_gal, int sfh, int path, int prec, const float *params,
+                 const float *z, const float *gbar, float *grad_out) {
+    int rc = enter(c);
+    if (rc) return rc;
+    if ((rc = check_gal(c, n_gal, sfh))) return rc;
+    if (path != SPS_PATH_APPROX && path != SPS_PATH_EXACT) return set_error(SPS_E_INVAL, "bad path");
+    if (n_gal == 0) return SPS_OK;
+    if (!params || !z || !gbar || !grad_out) return set_error(SPS_E_INVAL, "null array");
+    if (path == SPS_PATH_APPROX) {
+        if (c->k.n_z == 0) return set_error(SPS_E_STATE, "build the z table first (sps_build_ztable)");
+        return launch_approx(c, (hipStream_t)stream, n_gal, sfh, MODE_VJP, params, z, gbar, nullptr, nullptr,
+                             nullptr, nullptr, nullptr, nullptr, grad_out);
+    }
+    if (prec != SPS_F32 && prec != SPS_BF16X)
+        return set_error(SPS_E_INVAL, "exact-path vector-Jacobian products run in SPS_F32 or SPS_BF16X");
+    if (!(c->prec_mask & (1u << prec))) return set_error(SPS_E_STATE, "this precision's SSP table was not uploaded");
+    return launch_exact(c, (hipStream_t)stream, n_gal, sfh, prec, params, z, nullptr, gbar, nullptr, nullptr,
+                        nullptr, grad_out, false, true);
+}
+
 int sps_logpost_grad(sps_ctx *c, void *stream, int n_gal, int sfh, const float *x, const float *z,
                      const float *obs, const float *sigma, const uint8_t *band_mask, const float *bounds,
                      const float *prior, float *logp_out, float *grad_out) {

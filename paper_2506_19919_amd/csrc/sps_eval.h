@@ -471,13 +471,16 @@ __device__ __forceinline__ void contract_adjoint(const DevConsts &k, const uint1
 // Lanes with kk < 0 take part without contributing.  kmin/kmax: wave-uniform range of
 // the lanes' buckets.  L: the wave's LDS block.  G adjacent lanes may share a galaxy (value
 // and gradient only): they split its age bins and bands, and all end with the same results.
-template <int MODE, bool PK, int G = 1>
+// VJP (with MODE_LOGL_GRAD): obs_g holds the caller's adjoints dL/dm_b of the magnitudes in
+// place of observations, and the gradient is their vector-Jacobian product (no likelihood).
+template <int MODE, bool PK, int G = 1, bool VJP = false>
 __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *ledge, int sfh, const uint16_t *qf,
                                             const uint16_t *qa, const ApproxLds &L0,
                                    const float (&th)[NP], float zf, int kk, float f, double t_obs, double m0,
                                    int kmin, int kmax, const float *obs_g, const float *sig_g, uint32_t mask,
                                    float *mag_out, double &logl, float (&gr)[NP]) {
     static_assert(G == 1 || MODE == MODE_LOGL_GRAD, "shared galaxies: value and gradient only");
+    static_assert(!VJP || MODE == MODE_LOGL_GRAD, "the vector-Jacobian product is the gradient pass");
     const int nb = k.n_band;
     const int lane = opaque((int)threadIdx.x & (WAVE - 1));
     const ApproxLds L{L0.base, opaque(L0.rstride), opaque(L0.w_off)};
@@ -520,11 +523,16 @@ __device__ __forceinline__ void approx_eval(const DevConsts &k, const float *led
             continue;
         }
         if ((mask >> b) & 1u) {
-            const double s = sig_g[b];
-            const double r = (mag - (double)obs_g[b]) / s;
-            logl_d += -0.5 * r * r - (double)logf(sig_g[b] * 2.5066282746310002f);
+            float gm;                                        // d logL / d m_b
+            if (VJP) {
+                gm = obs_g[b];
+            } else {
+                const double s = sig_g[b];
+                const double r = (mag - (double)obs_g[b]) / s;
+                logl_d += -0.5 * r * r - (double)logf(sig_g[b] * 2.5066282746310002f);
+                gm = (float)(-r / s);
+            }
             if (MODE != MODE_LOGL) {
-                const float gm = (float)(-r / s);            // d logL / d m_b
                 const float c = gm * (-2.5f / LN10F);        // d logL / d ln(F S)
                 sbar[b] = (float)(c / sb);
                 const float fbar = c / d.F;

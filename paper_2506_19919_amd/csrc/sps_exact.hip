@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w)
 template <int P>
 __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *params_v, const void *z_v,
                                const void *part_v, int npart, void *mag_v, const float *obs, const float *sigma,
-                               const uint8_t *mask, float *logl, float *grad, float *cnum) {
+                               const uint8_t *mask, float *logl, float *grad, float *cnum, int vjp) {
     typedef typename Prec<P>::E E;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -823,14 +823,20 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
         return;
     }
     double ll = 0.0, g0 = 0.0, g7 = 0.0, g8 = 0.0, g9 = 0.0;
-    const uint32_t mk = mask[g];
+    // vjp: obs holds the caller's adjoints dL/dm_b (every band), in place of observations
+    const uint32_t mk = (vjp || !mask) ? 0xffffffffu : mask[g];
     for (int b = 0; b < nb; ++b) {
         double cb = 0.0;
         if ((mk >> b) & 1u) {
-            const double m = m0 - 2.5 * log10(num[b] / nrm[b]);
-            const double s = sigma[(size_t)g * nb + b], r = (m - (double)obs[(size_t)g * nb + b]) / s;
-            ll += -0.5 * r * r - log(s * 2.5066282746310002);
-            const double gm = -r / s;
+            double gm;   // d logL / d m_b
+            if (vjp) {
+                gm = (double)obs[(size_t)g * nb + b];
+            } else {
+                const double m = m0 - 2.5 * log10(num[b] / nrm[b]);
+                const double s = sigma[(size_t)g * nb + b], r = (m - (double)obs[(size_t)g * nb + b]) / s;
+                ll += -0.5 * r * r - log(s * 2.5066282746310002);
+                gm = -r / s;
+            }
             g0 += -2.5 * gm;
             cb = gm * (-2.5 / 2.302585092994046) / num[b];   // d logL / d num_b
             g7 += cb * dd[0][b];
@@ -839,7 +845,7 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
         }
         if (cnum) cnum[(size_t)g * NB_MAX + b] = (float)cb;
     }
-    logl[g] = (float)ll;
+    if (logl) logl[g] = (float)ll;
     if (grad) {
         grad[(size_t)0 * n + g] = (float)g0;
         grad[(size_t)7 * n + g] = (float)g7;
@@ -1126,7 +1132,7 @@ size_t exact_ws_bytes(const sps_ctx *c, int n, int prec, bool logl, bool grad) {
 
 static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                       void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
-                      float *grad, bool zordered) {
+                      float *grad, bool zordered, bool vjp) {
     const int nw = c->n_wave, nb = c->n_band;
     const bool f64 = (prec == SPS_F64);
     const int n_tiles = f64 ? (nw + BN - 1) / BN : c->lw / XBN;
@@ -1134,7 +1140,8 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
     const bool want_grad = grad != nullptr;
     const int npart = (want_grad ? 5 : 2) * nb;
     const int lw = c->lw;                         // padded wavelength stride of Rbar
-    const ExactLayout Lo = exact_layout(c, n, prec, logl != nullptr, want_grad);
+    const bool lik = logl != nullptr || vjp;     // the likelihood's (or the adjoints') finish
+    const ExactLayout Lo = exact_layout(c, n, prec, lik, want_grad);
     const size_t o_w = Lo.o_w, o_pw = Lo.o_pw, o_part = Lo.o_part, o_psum = Lo.o_psum, o_win = Lo.o_win;
     const size_t o_cn = Lo.o_cn, o_rb = Lo.o_rb, o_wb = Lo.o_wb, o_pb = Lo.o_pb;
     if (c->work_bytes < Lo.bytes || n > c->max_exact)
@@ -1225,7 +1232,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         else hipLaunchKernelGGL((k_xgemm<SPS_BF16X, EPI_PHOT_DUST, false>), gx, bx, 0, s, a);
     }
 
-    float *cn = logl ? (float *)(W + o_cn) : nullptr;
+    float *cn = lik ? (float *)(W + o_cn) : nullptr;
     dim3 gf((n + 127) / 128), bf(128);
     int n_fin = f64 ? n_tiles * f64_split(n, n_tiles).ks : n_tiles;   // partials the finish kernel sums
     if (!f64) {
@@ -1242,15 +1249,15 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
     switch (prec) {
         case SPS_F64:
             hipLaunchKernelGGL(k_exact_finish<SPS_F64>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
-                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn, vjp ? 1 : 0);
             break;
         case SPS_F32:
             hipLaunchKernelGGL(k_exact_finish<SPS_F32>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
-                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn, vjp ? 1 : 0);
             break;
         default:
             hipLaunchKernelGGL(k_exact_finish<SPS_BF16X>, gf, bf, 0, s, c->k, n, n_fin, params, z, (const void *)part,
-                               npart, mag_out, obs, sigma, mask, logl, grad, cn);
+                               npart, mag_out, obs, sigma, mask, logl, grad, cn, vjp ? 1 : 0);
             break;
     }
     if (want_grad) {
@@ -1322,10 +1329,9 @@ __global__ void __launch_bounds__(256) k_exact_order_in(int n, int nb, const int
     for (int p = 0; p < NP; ++p) params_s[(size_t)p * n + r] = params[(size_t)p * n + g];
     z_s[r] = z[g];
     if (obs)
-        for (int b = 0; b < nb; ++b) {
-            obs_s[(size_t)r * nb + b] = obs[(size_t)g * nb + b];
-            sig_s[(size_t)r * nb + b] = sigma[(size_t)g * nb + b];
-        }
+        for (int b = 0; b < nb; ++b) obs_s[(size_t)r * nb + b] = obs[(size_t)g * nb + b];
+    if (sigma)
+        for (int b = 0; b < nb; ++b) sig_s[(size_t)r * nb + b] = sigma[(size_t)g * nb + b];
     if (mask) mask_s[r] = mask[g];
 }
 
@@ -1374,10 +1380,10 @@ size_t exact_xsort_bytes(const sps_ctx *c, int n) { return n >= XSORT_MIN ? xsor
 
 int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void *params, const void *z,
                  void *mag_out, const float *obs, const float *sigma, const uint8_t *mask, float *logl,
-                 float *grad, bool ordered) {
+                 float *grad, bool ordered, bool vjp) {
     if (prec == SPS_F64 || ordered || n < XSORT_MIN)
         return exact_core(c, s, n, sfh, prec, params, z, mag_out, obs, sigma, mask, logl, grad,
-                          ordered && prec != SPS_F64);
+                          ordered && prec != SPS_F64, vjp);
     const DevConsts grid = z_sort_grid(c);
     const int nb = c->n_band;
     const XsortLayout xl = xsort_layout(c, n);
@@ -1397,8 +1403,8 @@ int launch_exact(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const void
     hipLaunchKernelGGL(k_exact_order_in, g1, b1, 0, s, n, nb, (const int *)c->d_perm, (const float *)params,
                        (const float *)z, obs, sigma, mask, par_s, z_s, obs_s, sig_s, msk_s);
     rc = exact_core(c, s, n, sfh, prec, par_s, z_s, mag_out ? mag_s : nullptr, obs ? obs_s : nullptr,
-                    obs ? sig_s : nullptr, mask ? msk_s : nullptr, logl ? ll_s : nullptr, grad ? gr_s : nullptr,
-                    true);
+                    sigma ? sig_s : nullptr, mask ? msk_s : nullptr, logl ? ll_s : nullptr, grad ? gr_s : nullptr,
+                    true, vjp);
     if (rc) return rc;
     hipLaunchKernelGGL(k_exact_order_out, g1, b1, 0, s, n, nb, (const int *)c->d_perm, mag_s, ll_s, gr_s,
                        (float *)mag_out, logl, grad);

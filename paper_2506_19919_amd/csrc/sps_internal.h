@@ -192,10 +192,12 @@ int launch_approx(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int mode, const
                   const float *z, const float *obs, const float *sigma, const uint8_t *mask,
                   const float *bounds, const float *prior, float *out_mag, float *out_val, float *out_grad);
 // ordered: the galaxies already come in z order (the exact-path HMC ranks its chains); else the
-// FP32 / BF16X paths rank them by z internally and return the outputs in the caller's order
+// FP32 / BF16X paths rank them by z internally and return the outputs in the caller's order.
+// vjp: obs holds the magnitudes' adjoints (sigma, mask and logl null) and grad receives their
+// vector-Jacobian product
 int launch_exact(sps_ctx *c, hipStream_t s, int n_gal, int sfh, int prec, const void *params,
                  const void *z, void *mag_out, const float *obs, const float *sigma,
-                 const uint8_t *mask, float *logl, float *grad, bool ordered = false);
+                 const uint8_t *mask, float *logl, float *grad, bool ordered = false, bool vjp = false);
 int launch_hmc(sps_ctx *c, hipStream_t s, const sps_hmc_cfg *cfg, int n_gal, int sfh, const float *z,
                const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                const float *prior, const float *theta0, float *samples, float *post_mean,
@@ -210,6 +212,7 @@ int launch_nuts(sps_ctx *c, hipStream_t s, const sps_nuts_cfg *cfg, int n_gal, i
                 float *step, float *inv_metric, int *depth, int *n_leaf, unsigned long long *lockstep);
 
 // modes of the approximate-path kernel
-enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3 };
+// MODE_VJP: the gradient pass with the magnitudes' adjoints supplied in place of observations
+enum { MODE_MAGS = 0, MODE_LOGL = 1, MODE_LOGL_GRAD = 2, MODE_LOGPOST_GRAD = 3, MODE_VJP = 4 };
 
 }  // namespace sps
