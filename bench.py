@@ -43,6 +43,7 @@ APPROX_FWD_BYTES = 4 * (10 + 1 + 6)
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_approx_logl_grad_1M_traffic.md")
 FWD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_approx_mags_100k_counters.md")
+EXACT_COUNTERS_FILE = os.path.join(ROOT, "profiles", "exact_4096x5000_kernel_trace.md")
 
 
 def log(msg):
@@ -333,6 +334,14 @@ def bench_exact(dev, n=4096, steps=5, warmup=2, cpu=False, budget_s=10.0):
         log(f"[bench]   {name}: fwd {fwd * 1e3:.3f} ms, value+grad {vg * 1e3:.3f} ms")
     obs_h = obs.cpu().numpy().astype(np.float64)
     ctx.close()
+    # executed matrix-core utilisation of the GEMMs (rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES, from the
+    # committed counter summary while the kernel sources match it)
+    vals = profile_values(EXACT_COUNTERS_FILE, "busy_")
+    if vals:
+        for name in ("f32", "bf16x"):
+            res[name]["mfma_busy_rocprof"] = {
+                part: float(vals[f"busy_mfma_{name}_{part}"]) for part in ("forward", "forward_dust", "gradient")
+                if f"busy_mfma_{name}_{part}" in vals}
     if cpu:
         import oracle
         orc = oracle.Oracle(ssp, filt)
@@ -722,6 +731,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="also run 3 plain 1 GiB device copies (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.hmc_exact_iters < 4:
+        ap.error("--hmc-exact-iters must be at least 4 (half warm-up, and at least two samples)")
     legs = set(args.legs.split(","))
 
     def leg(name, off):
