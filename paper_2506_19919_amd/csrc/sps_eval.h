@@ -411,15 +411,25 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
         const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
 #pragma unroll 1
         for (int ks = 0; ks < KSTEPS; ++ks) {
+            // the first fragment set is loaded before the A fragments are built, and each later
+            // one while the previous one's products issue
+            size_t o = (size_t)ks * 512;
+            b8v n0h = *(const b8v *)(b0 + o), n0l = *(const b8v *)(b0 + lo_off + o);
+            b8v n1h = *(const b8v *)(b1 + o), n1l = *(const b8v *)(b1 + lo_off + o);
             b8v a0h[NH][2], a0l[NH][2], a1h[NH][2], a1l[NH][2];
 #pragma unroll
             for (int h = 0; h < NH; ++h) a_frags<PK>(L, lane, h, ks, w0[h], w1[h], a0h[h], a0l[h], a1h[h], a1l[h]);
 #pragma unroll
             for (int nb = 0; nb < 6; ++nb) {
                 if (nb >= nbk) break;
-                const size_t o = (size_t)(nb * KSTEPS + ks) * 512;
-                const b8v q0h = *(const b8v *)(b0 + o), q0l = *(const b8v *)(b0 + lo_off + o);
-                const b8v q1h = *(const b8v *)(b1 + o), q1l = *(const b8v *)(b1 + lo_off + o);
+                const b8v q0h = n0h, q0l = n0l, q1h = n1h, q1l = n1l;
+                if (nb + 1 < nbk) {
+                    o = (size_t)((nb + 1) * KSTEPS + ks) * 512;
+                    n0h = *(const b8v *)(b0 + o);
+                    n0l = *(const b8v *)(b0 + lo_off + o);
+                    n1h = *(const b8v *)(b1 + o);
+                    n1l = *(const b8v *)(b1 + lo_off + o);
+                }
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
 #pragma unroll
