@@ -550,6 +550,7 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
             wc[4 * l] = (float)std::log(lam / 5500.0);
             wc[4 * l + 1] = (float)(lam * q);
             wc[4 * l + 2] = (float)(q / lam);
+            wc[4 * l + 3] = (float)lam;
         }
         if ((rc = upload((void **)&c->d_wc, wc.data(), wc.size() * sizeof(float)))) return fail(rc);
     }

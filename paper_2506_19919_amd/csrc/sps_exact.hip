@@ -57,6 +57,9 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h <<
 __device__ inline float e_exp(float x) { return expf(x); }
 __device__ inline double e_exp(double x) { return exp(x); }
 
+constexpr double GAUSS_K2 = 0.84932180028801904272;   // sqrt(log2(e) / 2): exp(-x^2 / 2) = exp2(-(K x)^2)
+constexpr float LOG2E_F = 1.4426950408889634f;
+
 struct FiltConst {
     double fc[NB_MAX], inv_fs[NB_MAX];   // band centres and 1 / widths (FP64, as in the forward epilogue)
     double lo8[NB_MAX], hi8[NB_MAX];     // c - 8 sigma, c + 8 sigma: the support the kernels keep
@@ -299,7 +302,7 @@ struct XArgs {
     int ldc, n_store;
     const float *params, *z;   // photometry epilogue
     const double *wave;
-    const float *wc;           // [N][4]: ln(l / 5500), l q, q / l
+    const float *wc;           // [N][4]: ln(l / 5500), l q, q / l, l
     int n_wave, n_band;
     double fc[NB_MAX], inv_fs[NB_MAX];
     float *part;               // [n_nt][npart][M] (quantity-major: the finish reads it coalesced)
@@ -583,6 +586,17 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
         const float tauv = a.params[(size_t)7 * a.M + gg], delta = a.params[(size_t)8 * a.M + gg];
         const float ffl = a.params[(size_t)9 * a.M + gg];
         const double opz = 1.0 + (double)a.z[gg];
+        // the galaxy's filter offsets as one FP32 FMA per band and wavelength: t = l ta_b + tc_b
+        // = x_b sqrt(log2(e) / 2) with x_b = ((1+z) l - c_b) / s_b, so T_b = exp2(-t^2); the
+        // constants are formed in FP64 (|t| errs by ~1e-6 near a band, 3e-6 of T_b); the dust
+        // exponents carry log2(e) too
+        float ta[NB_MAX], tc[NB_MAX];
+#pragma unroll
+        for (int bb = 0; bb < NB_MAX; ++bb) {
+            ta[bb] = (float)(opz * a.inv_fs[bb] * GAUSS_K2);
+            tc[bb] = (float)(-a.fc[bb] * a.inv_fs[bb] * GAUSS_K2);
+        }
+        const float delta2 = delta * LOG2E_F, tauv2 = -tauv * LOG2E_F;
 #pragma unroll
         for (int pp = 0; pp < NPASS; ++pp) {
         if (pp > 0) __syncthreads();   // the previous pass's reads are done
@@ -614,17 +628,16 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
         for (int cc = 0; cc < PW / 2; ++cc) {
             const int c = pp * PW + half * (PW / 2) + cc, l = tile_n + c;
             if (l >= a.n_wave) break;
-            const v4f w = *(const v4f *)(a.wc + 4 * (size_t)l);   // ln x, l q, q / l
-            const float xd = __expf(delta * w[0]), ee = __expf(-tauv * xd);
+            const v4f w = *(const v4f *)(a.wc + 4 * (size_t)l);   // ln x, l q, q / l, l
+            const float xd = __builtin_amdgcn_exp2f(delta2 * w[0]), ee = __builtin_amdgcn_exp2f(tauv2 * xd);
             const float F = ffl + (1.0f - ffl) * ee;
             const float sw = sed[row][half * (PW / 2) + cc] * w[1];
-            const double lo = opz * a.wave[l];
 #pragma unroll
             for (int bb = 0; bb < NB_MAX; ++bb) {
                 if (bb >= a.n_band) break;
                 if (!((act >> bb) & 1u)) continue;
-                const float x = (float)((lo - a.fc[bb]) * a.inv_fs[bb]);
-                const float tb = __expf(-0.5f * x * x);
+                const float t = fmaf(w[3], ta[bb], tc[bb]);
+                const float tb = __builtin_amdgcn_exp2f(-t * t);
                 const float stw = sw * tb;
                 accp[bb][0] = fmaf(stw, F, accp[bb][0]);
                 accp[bb][1] = fmaf(tb, w[2], accp[bb][1]);
@@ -873,16 +886,21 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
     }
     const double opz = 1.0 + (double)z[g];
     const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
-    float cb[NB_MAX];
+    float cb[NB_MAX], ta[NB_MAX], tc[NB_MAX];   // filter offsets as in the forward epilogue
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) cb[b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
+    for (int b = 0; b < NB_MAX; ++b) {
+        cb[b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
+        ta[b] = (float)(opz * fl.inv_fs[b] * GAUSS_K2);
+        tc[b] = (float)(-fl.fc[b] * fl.inv_fs[b] * GAUSS_K2);
+    }
+    const float delta2 = delta * LOG2E_F, tauv2 = -tauv * LOG2E_F;
     for (int ch = c_lo; ch < c_hi; ++ch) {
         const int lb0 = ch * 256, l = lb0 + tid, lc = min(l, n_wave - 1);
         // every load of the chunk first (the element's own wavelength data does not wait for
         // the band mask), then the bands within 8 sigma of some redshifted wavelength of the
         // chunk (uniform)
-        const double wl = wave[lc], w0 = wave[min(lb0, n_wave - 1)], w1 = wave[min(lb0 + 255, n_wave - 1)];
-        const v4f w = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l
+        const double w0 = wave[min(lb0, n_wave - 1)], w1 = wave[min(lb0 + 255, n_wave - 1)];
+        const v4f w = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l, l
         unsigned act = 0;
         if (lb0 < n_wave) {
             const double u0 = opz * w0, u1 = opz * w1;
@@ -892,16 +910,15 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
         if (l >= ld) continue;
         float v = 0.0f;
         if (l < n_wave && act) {
-            const double lo = opz * wl;
             float sum = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB_MAX; ++b) {
                 if (b >= nb || !((act >> b) & 1u)) continue;
-                const float x = (float)((lo - fl.fc[b]) * fl.inv_fs[b]);
-                if (fabsf(x) < 8.0f) sum = fmaf(cb[b], __expf(-0.5f * x * x), sum);
+                const float t = fmaf(w[3], ta[b], tc[b]);
+                if (fabsf(t) < 8.0f * GAUSS_K2) sum = fmaf(cb[b], __builtin_amdgcn_exp2f(-t * t), sum);
             }
             if (sum != 0.0f) {
-                const float F = ffl + (1.0f - ffl) * __expf(-tauv * __expf(delta * w[0]));
+                const float F = ffl + (1.0f - ffl) * __builtin_amdgcn_exp2f(tauv2 * __builtin_amdgcn_exp2f(delta2 * w[0]));
                 v = sum * F * w[1];
             }
         }
