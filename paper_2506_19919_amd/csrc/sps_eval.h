@@ -411,32 +411,34 @@ __device__ __forceinline__ void contract(const DevConsts &k, const uint16_t *q, 
         const uint16_t *b0 = q + (size_t)kb * QB_NODE + lane * 8, *b1 = b0 + QB_NODE;
 #pragma unroll 1
         for (int ks = 0; ks < KSTEPS; ++ks) {
-            // the first fragment set is loaded before the A fragments are built, and each later
-            // one while the previous one's products issue
+            // node k's first fragment pair is loaded before the A fragments are built and each
+            // later one while the previous products issue; node k+1's pair of a block is loaded
+            // ahead of the block's node-k products (each accumulator still takes its node-k
+            // products first)
             size_t o = (size_t)ks * 512;
             b8v n0h = *(const b8v *)(b0 + o), n0l = *(const b8v *)(b0 + lo_off + o);
-            b8v n1h = *(const b8v *)(b1 + o), n1l = *(const b8v *)(b1 + lo_off + o);
             b8v a0h[NH][2], a0l[NH][2], a1h[NH][2], a1l[NH][2];
 #pragma unroll
             for (int h = 0; h < NH; ++h) a_frags<PK>(L, lane, h, ks, w0[h], w1[h], a0h[h], a0l[h], a1h[h], a1l[h]);
 #pragma unroll
             for (int nb = 0; nb < 6; ++nb) {
                 if (nb >= nbk) break;
-                const b8v q0h = n0h, q0l = n0l, q1h = n1h, q1l = n1l;
+                const size_t oc = (size_t)(nb * KSTEPS + ks) * 512;
+                const b8v q1h = *(const b8v *)(b1 + oc), q1l = *(const b8v *)(b1 + lo_off + oc);
+                const b8v q0h = n0h, q0l = n0l;
                 if (nb + 1 < nbk) {
                     o = (size_t)((nb + 1) * KSTEPS + ks) * 512;
                     n0h = *(const b8v *)(b0 + o);
                     n0l = *(const b8v *)(b0 + lo_off + o);
-                    n1h = *(const b8v *)(b1 + o);
-                    n1l = *(const b8v *)(b1 + lo_off + o);
                 }
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
 #pragma unroll
-                    for (int m = 0; m < 2; ++m) {
-                        acc[h][nb][m] = mfma3(a0h[h][m], a0l[h][m], q0h, q0l, acc[h][nb][m]);
-                        acc[h][nb][m] = mfma3(a1h[h][m], a1l[h][m], q1h, q1l, acc[h][nb][m]);
-                    }
+                    for (int m = 0; m < 2; ++m) acc[h][nb][m] = mfma3(a0h[h][m], a0l[h][m], q0h, q0l, acc[h][nb][m]);
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) acc[h][nb][m] = mfma3(a1h[h][m], a1l[h][m], q1h, q1l, acc[h][nb][m]);
             }
         }
         __syncthreads();   // the next pass rewrites the weight slots
