@@ -894,41 +894,45 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
         tc[b] = (float)(-fl.fc[b] * fl.inv_fs[b] * GAUSS_K2);
     }
     const float delta2 = delta * LOG2E_F, tauv2 = -tauv * LOG2E_F;
-    for (int ch = c_lo; ch < c_hi; ++ch) {
-        const int lb0 = ch * 256, l = lb0 + tid, lc = min(l, n_wave - 1);
-        // every load of the chunk first (the element's own wavelength data does not wait for
-        // the band mask), then the bands within 8 sigma of some redshifted wavelength of the
-        // chunk (uniform)
-        const double w0 = wave[min(lb0, n_wave - 1)], w1 = wave[min(lb0 + 255, n_wave - 1)];
-        const v4f w = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l, l
-        unsigned act = 0;
-        if (lb0 < n_wave) {
-            const double u0 = opz * w0, u1 = opz * w1;
-            for (int b = 0; b < nb; ++b)
-                if (u0 < fl.hi8[b] && u1 > fl.lo8[b]) act |= 1u << b;
-        }
-        if (l >= ld) continue;
-        float v = 0.0f;
-        if (l < n_wave && act) {
-            float sum = 0.0f;
+    // RU chunks per step, their wavelength constants loaded together: each chunk's work is a
+    // few dozen instructions, so a step that waited out its own load before computing left the
+    // block latency-bound.  Bands are tested per element (a wave's 64 wavelengths lie within a
+    // fraction of a filter width of each other, so the test rarely diverges).
+    constexpr int RU = 4;
+    for (int ch0 = c_lo; ch0 < c_hi; ch0 += RU) {
+        v4f w[RU];
 #pragma unroll
-            for (int b = 0; b < NB_MAX; ++b) {
-                if (b >= nb || !((act >> b) & 1u)) continue;
-                const float t = fmaf(w[3], ta[b], tc[b]);
-                if (fabsf(t) < 8.0f * GAUSS_K2) sum = fmaf(cb[b], __builtin_amdgcn_exp2f(-t * t), sum);
-            }
-            if (sum != 0.0f) {
-                const float F = ffl + (1.0f - ffl) * __builtin_amdgcn_exp2f(tauv2 * __builtin_amdgcn_exp2f(delta2 * w[0]));
-                v = sum * F * w[1];
-            }
+        for (int u = 0; u < RU; ++u) {
+            const int l = (ch0 + u) * 256 + tid, lc = min(l, n_wave - 1);
+            w[u] = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l, l
         }
-        if (P == SPS_F32) {
-            ((float *)rb)[(size_t)g * ld + l] = v;
-        } else {
-            const uint16_t h = f2bf(v);
-            const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
-            ((uint16_t *)rb)[o] = h;
-            ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int l = (ch0 + u) * 256 + tid;
+            if (ch0 + u >= c_hi || l >= ld) break;
+            float v = 0.0f;
+            if (l < n_wave) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int b = 0; b < NB_MAX; ++b) {
+                    if (b >= nb) break;
+                    const float t = fmaf(w[u][3], ta[b], tc[b]);
+                    if (fabsf(t) < 8.0f * GAUSS_K2) sum = fmaf(cb[b], __builtin_amdgcn_exp2f(-t * t), sum);
+                }
+                if (sum != 0.0f) {
+                    const float F =
+                        ffl + (1.0f - ffl) * __builtin_amdgcn_exp2f(tauv2 * __builtin_amdgcn_exp2f(delta2 * w[u][0]));
+                    v = sum * F * w[u][1];
+                }
+            }
+            if (P == SPS_F32) {
+                ((float *)rb)[(size_t)g * ld + l] = v;
+            } else {
+                const uint16_t h = f2bf(v);
+                const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
+                ((uint16_t *)rb)[o] = h;
+                ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
+            }
         }
     }
 }
