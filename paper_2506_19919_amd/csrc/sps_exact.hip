@@ -437,21 +437,16 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
     int klen = a.K / nsp, kbeg = sp * klen;
     if (a.win) {
         // wavelengths outside every band's support for all of this tile's galaxies: the
-        // forward tile's band sums are below exp(-32) of the band's and are written as zeros;
-        // the gradient GEMM's Rbar is exactly zero there, so its K range is clipped
+        // forward tile's band sums are below exp(-32) of the band's: the tile is not computed
+        // and the tile sum (k_sum_tiles) skips it; the gradient GEMM's Rbar is exactly zero
+        // there, so its K range is clipped
         const int4 w = a.win[tile_m / XBM];
         if constexpr (EPI == EPI_STORE) {
             const int k0 = max(kbeg, w.z * XBK), k1 = min(kbeg + klen, w.w * XBK);
             kbeg = k0;
             klen = max(k1 - k0, 0);
         } else if (tile_n / XBN < w.x || tile_n / XBN >= w.y) {
-            constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;
-            const int g = tile_m + (tid >> 1);
-            if ((tid & 1) == 0 && g < a.M) {
-                float *out = a.part + (size_t)(tile_n / XBN) * a.npart * a.M + g;
-                for (int q = 0; q < NPB * a.n_band; ++q) out[(size_t)q * a.M] = 0.0f;
-            }
-            return;
+            return;   // k_sum_tiles reads only the tiles inside the window
         }
     }
 
@@ -980,12 +975,15 @@ __global__ void __launch_bounds__(256) k_sum_splits(size_t n4, int n_split, size
     c[i] = v;
 }
 
-// per-tile photometry partials summed over the wavelength tiles: out[q][g] = sum_t part[t][q][g]
-__global__ void __launch_bounds__(256) k_sum_tiles(int n, int npart, int n_tiles, const float *part, float *out) {
+// per-tile photometry partials summed over the wavelength tiles: out[q][g] = sum_t part[t][q][g],
+// over the tiles of the galaxy's row-tile window (the forward GEMM writes no partials outside it)
+__global__ void __launch_bounds__(256) k_sum_tiles(int n, int npart, int n_tiles, const int4 *win, const float *part,
+                                                   float *out) {
     const int g = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
     if (g >= n) return;
+    const int4 w = win[g / XBM];
     float v = 0.0f;
-    for (int t = 0; t < n_tiles; ++t) v += part[((size_t)t * npart + q) * n + g];
+    for (int t = w.x; t < min(w.y, n_tiles); ++t) v += part[((size_t)t * npart + q) * n + g];
     out[(size_t)q * n + g] = v;
 }
 
@@ -1259,7 +1257,7 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
     if (!f64) {
         float *psum = (float *)(W + o_psum);
         hipLaunchKernelGGL(k_sum_tiles, dim3((n + 255) / 256, npart), dim3(256), 0, s, n, npart, n_tiles,
-                           (const float *)part, psum);
+                           (const int4 *)win, (const float *)part, psum);
         part = psum;
     } else {
         double *psum = (double *)(W + o_psum);
