@@ -868,8 +868,8 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
 // are loaded once (a block per chunk spent most of its short life waiting on those loads).
 template <int P>
 __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
-                                                    const float *params, const float *z, const double *wave,
-                                                    const float *wc, const float *cnum, const int4 *win, void *rb) {
+                                                    const float *params, const float *z, const float *wc,
+                                                    const float *cnum, const int4 *win, void *rb) {
     const int g = blockIdx.x, tid = threadIdx.x;
     // the gradient GEMM reads only the k-tiles inside its row tile's filter-support window:
     // chunks wholly outside it are never read and are not written
@@ -1285,10 +1285,10 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
         const FiltConst fl = filt_const(c->h_fc, c->h_fs);
         if (prec == SPS_F32)
             hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, win, r_hi);
+                               (const float *)params, (const float *)z, c->d_wc, cn, win, r_hi);
         else
             hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wave, c->d_wc, cn, win, r_hi);
+                               (const float *)params, (const float *)z, c->d_wc, cn, win, r_hi);
         XArgs b{};
         b.win = win;
         b.M = n;
