@@ -311,7 +311,7 @@ int sps_autotune_hmc(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_g
  * under HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same
  * arguments, kernels and results as sps_loglike_grad with path = SPS_PATH_APPROX, but its
  * per-call buffers (sort order, histogram, input and output records) are a static device
- * array of the library, about 6.6 MB per device for SPS_STATIC_MAX_GAL galaxies, held until
+ * array of the library, about 6.8 MB per device for SPS_STATIC_MAX_GAL galaxies, held until
  * the process ends; it allocates nothing and calls no allocating routine.  n_gal above
  * SPS_STATIC_MAX_GAL is SPS_E_INVAL.  Every call on one device shares that device's array,
  * which keeps the last call's contents (each call clears what it needs): calls that overlap in

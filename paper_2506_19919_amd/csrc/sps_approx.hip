@@ -15,21 +15,21 @@
 namespace sps {
 
 // ------------------------------------------------------------------ bucket sort
-__global__ void k_zero_int(int *p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
+// Counting sort by z bucket without global atomics: every block of SORT_T galaxies counts its
+// buckets in LDS and writes its count row; one block per bucket turns its column of counts
+// into exclusive offsets (and the bucket's total); a block's galaxies of bucket b then go to
+// the bucket's start (the totals' exclusive scan) + the block's offset + their rank within the
+// block.  (Global bucket cursors had every block add to the same few counters.)
+constexpr int SORT_BLOCK = 256, SORT_PER_THREAD = SORT_T / SORT_BLOCK;
 
-constexpr int SORT_BLOCK = 256, SORT_PER_THREAD = 16, SORT_TILE = SORT_BLOCK * SORT_PER_THREAD;
-
-// per-block histogram in LDS, one global atomic per bucket per block
-__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_hist(DevConsts k, int n, const float *__restrict__ z,
-                                                           int *__restrict__ hist) {
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_count(DevConsts k, int n, const float *__restrict__ z,
+                                                            int *__restrict__ counts) {
     extern __shared__ int sh[];
     const int nbk = k.n_z;
     for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) sh[b] = 0;
     __syncthreads();
-    const int base = blockIdx.x * SORT_TILE;
+    const int base = blockIdx.x * SORT_T;
+#pragma unroll
     for (int t = 0; t < SORT_PER_THREAD; ++t) {
         const int i = base + t * SORT_BLOCK + threadIdx.x;
         if (i < n) {
@@ -39,56 +39,37 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_hist(DevConsts k, int n, 
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK)
-        if (sh[b]) atomicAdd(&hist[b], sh[b]);
+    // bucket-major [nbk][nblk]: each bucket's column is contiguous for k_bucket_offsets
+    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) counts[(size_t)b * gridDim.x + blockIdx.x] = sh[b];
 }
 
-// exclusive scan of hist[0..nb) into cursor[0..nb); one block of 1024 threads
-__global__ void __launch_bounds__(1024) k_bucket_scan(int nb, const int *__restrict__ hist, int *__restrict__ cursor) {
-    __shared__ int s[1024];
-    int t = threadIdx.x;
-    s[t] = (t < nb) ? hist[t] : 0;
+// bucket blockIdx.x: its column of block counts (counts[b][blk]) -> exclusive offsets in place,
+// total -> tot[b]
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_offsets(int nbk, int nblk, int *__restrict__ counts,
+                                                              int *__restrict__ tot) {
+    __shared__ int part[SORT_BLOCK];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int per = (nblk + SORT_BLOCK - 1) / SORT_BLOCK, r0 = tid * per;
+    int s = 0;
+    int *col = counts + (size_t)b * nblk;
+    for (int j = 0; j < per; ++j)
+        if (r0 + j < nblk) s += col[r0 + j];
+    part[tid] = s;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int v = (t >= o) ? s[t - o] : 0;
+    for (int o = 1; o < SORT_BLOCK; o <<= 1) {
+        const int x = (tid >= o) ? part[tid - o] : 0;
         __syncthreads();
-        s[t] += v;
+        part[tid] += x;
         __syncthreads();
     }
-    if (t < nb) cursor[t] = s[t] - ((t < nb) ? hist[t] : 0);
-}
-
-// each block reserves a range per bucket in the global cursor, then places its galaxies
-// (the order only: k_bucket_gather places them with their input records)
-__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
-                                                              int *__restrict__ cursor, int *__restrict__ perm,
-                                                              int *__restrict__ status) {
-    extern __shared__ int sh[];
-    const int nbk = k.n_z;
-    int *cnt = sh, *pos = sh + nbk;
-    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
-    __syncthreads();
-    const int base = blockIdx.x * SORT_TILE;
-    int kk_t[SORT_PER_THREAD];
-    for (int t = 0; t < SORT_PER_THREAD; ++t) {
-        const int i = base + t * SORT_BLOCK + threadIdx.x;
-        kk_t[t] = -2;
-        if (i < n) {
-            float f;
-            const int kk = z_bucket(k, z[i], &f);
-            kk_t[t] = kk < 0 ? nbk - 1 : kk;
-            atomicAdd(&cnt[kk_t[t]], 1);
-            if (kk < 0 && status) atomicOr(status, STATUS_Z_RANGE);
+    int run = part[tid] - s;
+    for (int j = 0; j < per; ++j)
+        if (r0 + j < nblk) {
+            const int v = col[r0 + j];
+            col[r0 + j] = run;
+            run += v;
         }
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nbk; b += SORT_BLOCK) pos[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
-    __syncthreads();
-    for (int t = 0; t < SORT_PER_THREAD; ++t) {
-        const int i = base + t * SORT_BLOCK + threadIdx.x;
-        if (kk_t[t] < 0) continue;
-        perm[atomicAdd(&pos[kk_t[t]], 1)] = i;
-    }
+    if (tid == SORT_BLOCK - 1) tot[b] = part[tid];
 }
 
 // exclusive prefix sum of v[0..n) into out[0..n), n <= 4 SORT_BLOCK; every thread of the block
@@ -115,81 +96,136 @@ __device__ inline void block_exclusive_scan(const int *v, int *out, int n, int *
     __syncthreads();
 }
 
+// the sort's placement of the order alone (k_bucket_gather places the galaxies with their input
+// records): a block's galaxies of bucket b go to the bucket's start + the block's offset + their
+// rank within the block
+__global__ void __launch_bounds__(SORT_BLOCK) k_bucket_scatter(DevConsts k, int n, const float *__restrict__ z,
+                                                              const int *__restrict__ tot,
+                                                              const int *__restrict__ offsets, int *__restrict__ perm,
+                                                              int *__restrict__ status) {
+    extern __shared__ int sh[];
+    __shared__ int part[SORT_BLOCK];
+    const int nbk = k.n_z, tid = threadIdx.x;
+    int *cnt = sh, *pos = sh + nbk;
+    for (int b = tid; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * SORT_T;
+    int kk_t[SORT_PER_THREAD], lr[SORT_PER_THREAD];
+#pragma unroll
+    for (int t = 0; t < SORT_PER_THREAD; ++t) {
+        const int i = base + t * SORT_BLOCK + tid;
+        kk_t[t] = -1;
+        lr[t] = 0;
+        if (i < n) {
+            float f;
+            const int kk = z_bucket(k, z[i], &f);
+            kk_t[t] = kk < 0 ? nbk - 1 : kk;
+            lr[t] = atomicAdd(&cnt[kk_t[t]], 1);
+            if (kk < 0 && status) atomicOr(status, STATUS_Z_RANGE);
+        }
+    }
+    block_exclusive_scan(tot, pos, nbk, part);
+    for (int b = tid; b < nbk; b += SORT_BLOCK) pos[b] += offsets[(size_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < SORT_PER_THREAD; ++t)
+        if (kk_t[t] >= 0) perm[pos[kk_t[t]] + lr[t]] = base + t * SORT_BLOCK + tid;
+}
+
 // The sort's placement with the record gather, staged through LDS so that the record writes
-// are whole, contiguous lines: a block's galaxies are laid out in LDS in sorted order (one run
-// per bucket, each run contiguous at its destination too) and the block then copies the runs
-// out as consecutive 16-byte chunks.  LDS: GATHER_TILE records of RSTRIDE floats, their
-// destinations and sources, and the per-bucket counts, global offsets and local starts.
-constexpr int GATHER_PER_THREAD = 2, GATHER_TILE = SORT_BLOCK * GATHER_PER_THREAD;
+// are whole, contiguous lines.  Every load is issued up front: each thread reads its galaxies'
+// inputs (coalesced, in the caller's order), builds their records and writes them to LDS in that
+// order, while the bucket totals and the block's offsets are read too; after the local ranks and
+// the scans, a sorted index over the LDS rows lets the block copy each bucket run out as
+// consecutive 16-byte chunks.  LDS: GATHER_TILE records of RSTRIDE floats, the sorted slots'
+// rows and destinations, and per bucket the local counts, the block's destinations, the local
+// starts and the totals.
+constexpr int GATHER_PER_THREAD = SORT_PER_THREAD, GATHER_TILE = SORT_T;
 constexpr int RSTRIDE = REC + 4;   // 144-byte LDS rows: 16-byte writes of different rows spread over the banks
+constexpr int GATHER_BK = SORT_MAX_BUCKETS / SORT_BLOCK;   // buckets per thread, at most
 __host__ __device__ inline size_t gather_lds_bytes(int nbk) {
-    return ((size_t)GATHER_TILE * RSTRIDE + 2 * GATHER_TILE + 3 * (size_t)nbk) * sizeof(int);
+    return ((size_t)GATHER_TILE * RSTRIDE + 2 * GATHER_TILE + 4 * (size_t)nbk) * sizeof(int);
 }
 
 __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_gather(DevConsts k, int n, const float *__restrict__ z,
-                                                             int *__restrict__ cursor, int *__restrict__ perm,
+                                                             const int *__restrict__ tot,
+                                                             const int *__restrict__ offsets, int *__restrict__ perm,
                                                              GatherArgs ga) {
     extern __shared__ __attribute__((aligned(16))) int gsh[];
     __shared__ int part[SORT_BLOCK];
     const int nbk = k.n_z, nb = k.n_band, tid = threadIdx.x;
     float *recs = (float *)gsh;
-    int *dest = gsh + GATHER_TILE * RSTRIDE, *src = dest + GATHER_TILE;
-    int *cnt = src + GATHER_TILE, *pos = cnt + nbk, *start = pos + nbk;
-    for (int b = tid; b < nbk; b += SORT_BLOCK) cnt[b] = 0;
+    int *row_of = gsh + GATHER_TILE * RSTRIDE, *dest = row_of + GATHER_TILE;
+    int *cnt = dest + GATHER_TILE, *pos = cnt + nbk, *start = pos + nbk, *tots = start + nbk;
+    int tv[GATHER_BK], ov[GATHER_BK];
+#pragma unroll
+    for (int j = 0; j < GATHER_BK; ++j) {
+        const int b = tid + j * SORT_BLOCK;
+        tv[j] = b < nbk ? tot[b] : 0;
+        ov[j] = b < nbk ? offsets[(size_t)b * gridDim.x + blockIdx.x] : 0;
+        if (b < nbk) cnt[b] = 0;
+    }
     __syncthreads();
     const int base = blockIdx.x * GATHER_TILE;
     int bk[GATHER_PER_THREAD], lr[GATHER_PER_THREAD];
 #pragma unroll
     for (int u = 0; u < GATHER_PER_THREAD; ++u) {
-        const int i = base + u * SORT_BLOCK + tid;
+        const int nat = u * SORT_BLOCK + tid, i = base + nat;
         bk[u] = -1;
         lr[u] = 0;
-        if (i < n) {
-            float f;
-            const int kk = z_bucket(k, z[i], &f);
-            bk[u] = kk < 0 ? nbk - 1 : kk;
-            lr[u] = atomicAdd(&cnt[bk[u]], 1);
-            if (kk < 0 && ga.status) atomicOr(ga.status, STATUS_Z_RANGE);
-        }
-    }
-    __syncthreads();
-    for (int b = tid; b < nbk; b += SORT_BLOCK) pos[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
-    block_exclusive_scan(cnt, start, nbk, part);
-#pragma unroll
-    for (int u = 0; u < GATHER_PER_THREAD; ++u) {
-        if (bk[u] < 0) continue;
-        const int i = base + u * SORT_BLOCK + tid;
-        const int sl = start[bk[u]] + lr[u], at = pos[bk[u]] + lr[u];
-        dest[sl] = at;
-        src[sl] = i;
+        if (i >= n) continue;
+        const float zi = z[i];
         float r[REC];
 #pragma unroll
         for (int p = 0; p < NP; ++p) r[p] = ga.params[(size_t)p * n + i];
-        r[REC_Z] = z[i];
+        r[REC_Z] = zi;
 #pragma unroll
         for (int b = 0; b < NB_MAX; ++b) {
             r[REC_OBS + b] = (ga.obs && b < nb) ? ga.obs[(size_t)i * nb + b] : 0.0f;
             r[REC_SIG + b] = (ga.sigma && b < nb) ? ga.sigma[(size_t)i * nb + b] : 1.0f;
         }
         r[REC_MASK] = __int_as_float(ga.mask ? (int)ga.mask[i] : 0xff);
+        float f;
+        const int kk = z_bucket(k, zi, &f);
+        bk[u] = kk < 0 ? nbk - 1 : kk;
+        lr[u] = atomicAdd(&cnt[bk[u]], 1);
+        if (kk < 0 && ga.status) atomicOr(ga.status, STATUS_Z_RANGE);
         // per-galaxy cosmology, once per call here rather than in the model kernel
         double t_obs, m0;
-        cosmo_at(k, (double)z[i], t_obs, m0);
+        cosmo_at(k, (double)zi, t_obs, m0);
         r[REC_TOBS] = __int_as_float(__double2loint(t_obs));
         r[REC_TOBS + 1] = __int_as_float(__double2hiint(t_obs));
         r[REC_M0] = __int_as_float(__double2loint(m0));
         r[REC_M0 + 1] = __int_as_float(__double2hiint(m0));
-        v4f *row = (v4f *)(recs + (size_t)sl * RSTRIDE);
+        v4f *row = (v4f *)(recs + (size_t)nat * RSTRIDE);
 #pragma unroll
         for (int q = 0; q < REC / 4; ++q) row[q] = v4f{r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
-        ga.inv[i] = at;
+    }
+#pragma unroll
+    for (int j = 0; j < GATHER_BK; ++j)
+        if (tid + j * SORT_BLOCK < nbk) tots[tid + j * SORT_BLOCK] = tv[j];
+    __syncthreads();
+    // the block's first destination per bucket: the bucket's start plus the block's offset
+    block_exclusive_scan(tots, pos, nbk, part);
+#pragma unroll
+    for (int j = 0; j < GATHER_BK; ++j)
+        if (tid + j * SORT_BLOCK < nbk) pos[tid + j * SORT_BLOCK] += ov[j];
+    block_exclusive_scan(cnt, start, nbk, part);
+#pragma unroll
+    for (int u = 0; u < GATHER_PER_THREAD; ++u) {
+        if (bk[u] < 0) continue;
+        const int nat = u * SORT_BLOCK + tid;
+        const int sl = start[bk[u]] + lr[u], at = pos[bk[u]] + lr[u];
+        row_of[sl] = nat;
+        dest[sl] = at;
+        ga.inv[base + nat] = at;
     }
     __syncthreads();
     const int nv = min(GATHER_TILE, n - base);
     for (int c = tid; c < nv * (REC / 4); c += SORT_BLOCK) {
-        const int r = c / (REC / 4), q = c % (REC / 4);
-        ((v4f *)(ga.rec + (size_t)dest[r] * REC))[q] = ((const v4f *)(recs + (size_t)r * RSTRIDE))[q];
-        if (q == 0) perm[dest[r]] = src[r];
+        const int r = c / (REC / 4), q = c % (REC / 4), nat = row_of[r];
+        ((v4f *)(ga.rec + (size_t)dest[r] * REC))[q] = ((const v4f *)(recs + (size_t)nat * RSTRIDE))[q];
+        if (q == 0) perm[dest[r]] = base + nat;
     }
 }
 
@@ -341,19 +377,20 @@ __global__ void __launch_bounds__(WAVE) k_weights(DevConsts k, int n, int sfh, c
 // ------------------------------------------------------------------ launchers
 int launch_bucket_sort_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, const float *z, const GatherArgs *ga,
                           const DevConsts *grid) {
+    if (n <= 0) return SPS_OK;
     const DevConsts &kb = grid ? *grid : c->k;   // bucket grid
     const int nbk = kb.n_z;  // n_z - 1 intervals + 1 out-of-range bucket
-    int *hist = ws.hist, *cursor = ws.hist + 1025;
-    hipLaunchKernelGGL(k_zero_int, dim3((nbk + 255) / 256), dim3(256), 0, s, hist, nbk);
-    const dim3 gs((n + SORT_TILE - 1) / SORT_TILE);
-    hipLaunchKernelGGL(k_bucket_hist, gs, dim3(SORT_BLOCK), nbk * sizeof(int), s, kb, n, z, hist);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, nbk, hist, cursor);
+    if (nbk < 1 || nbk > SORT_MAX_BUCKETS) return set_error(SPS_E_INVAL, "bucket sort: bad bucket count");
+    int *tot = ws.hist, *counts = ws.hist + SORT_MAX_BUCKETS;
+    const int nblk = (n + SORT_T - 1) / SORT_T;
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(SORT_BLOCK), nbk * sizeof(int), s, kb, n, z, counts);
+    hipLaunchKernelGGL(k_bucket_offsets, dim3(nbk), dim3(SORT_BLOCK), 0, s, nbk, nblk, counts, tot);
     if (ga && ga->rec) {
-        hipLaunchKernelGGL(k_bucket_gather, dim3((n + GATHER_TILE - 1) / GATHER_TILE), dim3(SORT_BLOCK),
-                           gather_lds_bytes(nbk), s, c->k, n, z, cursor, ws.perm, *ga);
+        hipLaunchKernelGGL(k_bucket_gather, dim3(nblk), dim3(SORT_BLOCK), gather_lds_bytes(nbk), s, c->k, n, z,
+                           (const int *)tot, (const int *)counts, ws.perm, *ga);
     } else {
-        hipLaunchKernelGGL(k_bucket_scatter, gs, dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, kb, n, z, cursor,
-                           ws.perm, grid ? nullptr : c->d_status);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(SORT_BLOCK), 2 * nbk * sizeof(int), s, kb, n, z,
+                           (const int *)tot, (const int *)counts, ws.perm, grid ? nullptr : c->d_status);
     }
     SPS_HIP(hipGetLastError());
     return SPS_OK;

@@ -19,7 +19,7 @@ constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr size_t ST_PERM = 0;
 constexpr size_t ST_INV = ST_PERM + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
 constexpr size_t ST_HIST = ST_INV + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
-constexpr size_t ST_REC = ST_HIST + al256((size_t)2 * 1025 * sizeof(int));
+constexpr size_t ST_REC = ST_HIST + al256(sort_ws_ints(SPS_STATIC_MAX_GAL) * sizeof(int));
 constexpr size_t ST_OREC = ST_REC + al256((size_t)SPS_STATIC_MAX_GAL * REC * sizeof(float));
 constexpr size_t ST_BYTES = ST_OREC + al256((size_t)SPS_STATIC_MAX_GAL * OREC * sizeof(float));
 static __device__ __align__(256) unsigned char scratch[ST_BYTES];
@@ -299,11 +299,14 @@ int sps_reserve(sps_ctx *c, int max_gal) {
     (void)hipFree(c->d_rec);
     (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hstate);
+    (void)hipFree(c->d_hist);
+    c->d_hist = nullptr;
     c->d_perm = c->d_inv = nullptr;
     c->d_rec = c->d_orec = nullptr;
     c->d_hstate = nullptr;
     c->hstate_bytes = 0;
     c->max_gal = 0;
+    SPS_HIP(hipMalloc(&c->d_hist, sort_ws_ints(max_gal) * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_perm, (size_t)max_gal * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_inv, (size_t)max_gal * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_rec, (size_t)max_gal * REC * sizeof(float)));
@@ -557,8 +560,7 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming) != hipSuccess)
         return fail(set_error(SPS_E_HIP, "stream / event creation failed"));
-    if (hipMalloc(&c->d_hist, 2 * 1025 * sizeof(int)) != hipSuccess ||
-        hipMalloc(&c->d_status, sizeof(int)) != hipSuccess || hipMemset(c->d_status, 0, sizeof(int)) != hipSuccess)
+    if (hipMalloc(&c->d_status, sizeof(int)) != hipSuccess || hipMemset(c->d_status, 0, sizeof(int)) != hipSuccess)
         return fail(set_error(SPS_E_NOMEM, "workspace allocation failed"));
     if ((rc = sps_reserve(c, max_gal))) return fail(rc);
     *out = c;

@@ -94,7 +94,7 @@ struct sps_ctx {
     int *d_inv = nullptr;          // position of each galaxy in that order
     float *d_rec = nullptr;        // inputs in z-bucket order, one 128-byte record per galaxy
     float *d_orec = nullptr;       // outputs in z-bucket order, 64 bytes per galaxy
-    int *d_hist = nullptr;         // bucket histogram / cursors [2 * 1025]
+    int *d_hist = nullptr;         // z-bucket sort: bucket totals and per-block counts (sort_ws_ints)
     int *d_status = nullptr;       // device-side error bits (STATUS_*), read and cleared by sps_status
     void *d_hstate = nullptr;      // chain state of the approximate-path HMC, max_gal chain slots
     size_t hstate_bytes = 0;
@@ -146,6 +146,14 @@ constexpr int REC = 32;
 // offset, each as an FP64 value in two words (low, high)
 enum { REC_Z = 10, REC_OBS = 11, REC_SIG = 19, REC_MASK = 27, REC_TOBS = 28, REC_M0 = 30 };
 constexpr int OREC = 16;          // output record: mags[8] or (value, grad[10])
+
+// z-bucket sort workspace (ints): the buckets' totals, then one count row per block of
+// SORT_T galaxies (at most SORT_MAX_BUCKETS buckets: z-table nodes <= 1024)
+constexpr int SORT_T = 512;
+constexpr int SORT_MAX_BUCKETS = 1024;
+__host__ __device__ constexpr size_t sort_ws_ints(int max_gal) {
+    return (size_t)SORT_MAX_BUCKETS * (1 + (size_t)((max_gal + SORT_T - 1) / SORT_T));
+}
 struct GatherArgs {
     const float *params, *obs, *sigma;  // obs, sigma may be null (magnitudes only)
     const uint8_t *mask;                // may be null (all bands)
