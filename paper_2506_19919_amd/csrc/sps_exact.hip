@@ -567,9 +567,13 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
         // SED tile [128 galaxies][128 wavelengths] -> LDS in NPASS passes of PW columns (row
         // stride PW + 1; one stage holds half the tile), two threads per galaxy reducing PW / 2
         // wavelengths each per pass into the band sums
-        constexpr int NPASS = (x_smem<P, RING>() >= XBM * (XBN + 1) * 4) ? 1 : 2, PW = XBN / NPASS;
+        constexpr int NPASS = (x_smem<P, RING>() >= XBM * (XBN + 1) * 4 + XBN * 16) ? 1 : 2, PW = XBN / NPASS;
         float(*sed)[PW + 1] = reinterpret_cast<float(*)[PW + 1]>(smem);
-        static_assert(XBM * (PW + 1) * 4 <= x_smem<P, RING>(), "SED columns fit the staging buffers");
+        // the tile's wavelength constants (ln x, l q, q / l, l) in LDS after the SED columns:
+        // read once per tile instead of one dependent global load per column and thread
+        v4f *swc = reinterpret_cast<v4f *>(smem + XBM * (PW + 1) * 4);
+        static_assert(XBM * (PW + 1) * 4 + XBN * 16 <= x_smem<P, RING>(), "SED columns fit the staging buffers");
+        static_assert((XBM * (PW + 1) * 4) % 16 == 0, "aligned wavelength constants");
         const int row = tid >> 1, half = tid & 1, g = tile_m + row;
         constexpr int NPB = (EPI == EPI_PHOT_DUST) ? 5 : 2;   // num, N [, dnum/dtauV, dnum/ddelta, dnum/dFfloor]
         float accp[NB_MAX][NPB];
@@ -592,6 +596,9 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
             tc[bb] = (float)(-a.fc[bb] * a.inv_fs[bb] * GAUSS_K2);
         }
         const float delta2 = delta * LOG2E_F, tauv2 = -tauv * LOG2E_F;
+        // (beyond the grid the constants are zero, and so are the SED columns: those columns
+        // add exact zeros)
+        if (tid < XBN) swc[tid] = *(const v4f *)(a.wc + 4 * (size_t)(tile_n + tid));
 #pragma unroll
         for (int pp = 0; pp < NPASS; ++pp) {
         if (pp > 0) __syncthreads();   // the previous pass's reads are done
@@ -620,27 +627,40 @@ __global__ void __launch_bounds__(256, (x_blocks<P, RING>())) k_xgemm(XArgs a) {
                 if (__ballot(l0 < a.n_wave && x0 < 8.0 && x1 > -8.0) != 0) act |= 1u << bb;
             }
         }
-        for (int cc = 0; cc < PW / 2; ++cc) {
-            const int c = pp * PW + half * (PW / 2) + cc, l = tile_n + c;
-            if (l >= a.n_wave) break;
-            const v4f w = *(const v4f *)(a.wc + 4 * (size_t)l);   // ln x, l q, q / l, l
-            const float xd = __builtin_amdgcn_exp2f(delta2 * w[0]), ee = __builtin_amdgcn_exp2f(tauv2 * xd);
-            const float F = ffl + (1.0f - ffl) * ee;
-            const float sw = sed[row][half * (PW / 2) + cc] * w[1];
+        // four columns at a time: their LDS reads issue together, and each band's sums take the
+        // columns in order (the same sums as one column after another)
+        for (int c4 = 0; c4 < PW / 2; c4 += 4) {
+            v4f w[4];   // ln x, l q, q / l, l
+            float xd[4], ee[4], F[4], sw[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                w[u] = swc[pp * PW + half * (PW / 2) + c4 + u];
+                sw[u] = sed[row][half * (PW / 2) + c4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xd[u] = __builtin_amdgcn_exp2f(delta2 * w[u][0]);
+                ee[u] = __builtin_amdgcn_exp2f(tauv2 * xd[u]);
+                F[u] = ffl + (1.0f - ffl) * ee[u];
+                sw[u] = sw[u] * w[u][1];
+            }
 #pragma unroll
             for (int bb = 0; bb < NB_MAX; ++bb) {
                 if (bb >= a.n_band) break;
                 if (!((act >> bb) & 1u)) continue;
-                const float t = fmaf(w[3], ta[bb], tc[bb]);
-                const float tb = __builtin_amdgcn_exp2f(-t * t);
-                const float stw = sw * tb;
-                accp[bb][0] = fmaf(stw, F, accp[bb][0]);
-                accp[bb][1] = fmaf(tb, w[2], accp[bb][1]);
-                if constexpr (EPI == EPI_PHOT_DUST) {
-                    const float dtv = -(1.0f - ffl) * xd * ee;
-                    accp[bb][2] = fmaf(stw, dtv, accp[bb][2]);
-                    accp[bb][3] = fmaf(stw * dtv, tauv * w[0], accp[bb][3]);
-                    accp[bb][4] = fmaf(stw, 1.0f - ee, accp[bb][4]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float t = fmaf(w[u][3], ta[bb], tc[bb]);
+                    const float tb = __builtin_amdgcn_exp2f(-t * t);
+                    const float stw = sw[u] * tb;
+                    accp[bb][0] = fmaf(stw, F[u], accp[bb][0]);
+                    accp[bb][1] = fmaf(tb, w[u][2], accp[bb][1]);
+                    if constexpr (EPI == EPI_PHOT_DUST) {
+                        const float dtv = -(1.0f - ffl) * xd[u] * ee[u];
+                        accp[bb][2] = fmaf(stw, dtv, accp[bb][2]);
+                        accp[bb][3] = fmaf(stw * dtv, tauv * w[u][0], accp[bb][3]);
+                        accp[bb][4] = fmaf(stw, 1.0f - ee[u], accp[bb][4]);
+                    }
                 }
             }
         }
