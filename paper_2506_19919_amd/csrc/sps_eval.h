@@ -166,17 +166,21 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
     if (sfh == SPS_SFH_DPL) {
         Dpl p = make_dpl(th[1], th[2], th[3]);
         dpl_at_obs(p, t_obs_f);
+        AgeEdges<G> ed(k, q);
         for (int i = q; i < NA; i += G) {
-            float m, a, b, c;
-            dpl_bin<false>(k, i, t_obs_f, p, m, a, b, c);
+            float m, a, b, c, a_lo, a_hi;
+            ed.step(i, a_lo, a_hi);
+            dpl_bin<false>(a_lo, a_hi, t_obs_f, p, m, a, b, c);
             col[i] = m;
             S += (double)m;
         }
     } else {
         const Logn p = make_logn(th[1], th[2]);
+        AgeEdges<G> ed(k, q);
         for (int i = q; i < NA; i += G) {
-            float m, a, b;
-            logn_bin<false>(k, i, t_obs_f, p, m, a, b);
+            float m, a, b, a_lo, a_hi;
+            ed.step(i, a_lo, a_hi);
+            logn_bin<false>(a_lo, a_hi, t_obs_f, p, m, a, b);
             col[i] = m;
             S += (double)m;
         }
@@ -240,17 +244,19 @@ __device__ inline void adjoint_weights(const DevConsts &k, const float *ledge, i
         lp = make_logn(th[1], th[2]);
     }
     // smooth part: dP_age/dF_burst = P_burst - P_smooth; the P_burst term is added below
+    AgeEdges<G> ed(k, q);
     for (int i = q; i < NA; i += G) {
         const float gbar = col[i];
         float ps;
-        float m, mt, ma, mb;
+        float m, mt, ma, mb, a_lo, a_hi;
         double dm, dmt, dmw;
+        ed.step(i, a_lo, a_hi);
         if (sfh == SPS_SFH_DPL) {
-            dpl_bin<true>(k, i, t_obs_f, p, m, mt, ma, mb);
+            dpl_bin<true>(a_lo, a_hi, t_obs_f, p, m, mt, ma, mb);
             ps = m * invS;
         } else {
             float fm, ft, fw;
-            logn_bin<true>(k, i, t_obs_f, lp, fm, ft, fw);
+            logn_bin<true>(a_lo, a_hi, t_obs_f, lp, fm, ft, fw);
             dm = fm;
             dmt = ft;
             dmw = fw;

@@ -166,13 +166,30 @@ __device__ inline void dpl_node(const Dpl &p, float X, float wg, float &s, float
     }
 }
 
-// Mass formed in age bin i (rate amplitude 1) and, if DERIV, its derivatives
+// Mass formed in the age bin [a_lo, a_hi) (rate amplitude 1) and, if DERIV, its derivatives
 // w.r.t. (tau, alpha, beta).
+// The age edges of the bins i = q, q + G, ... in turn, each bin's edges read one bin ahead of their
+// use (the bins are contiguous: the upper edge of bin i is the lower edge of bin i + 1, so with
+// G = 1 each step reads one edge)
+template <int G>
+struct AgeEdges {
+    const DevConsts &k;
+    float lo, hi;
+    __device__ AgeEdges(const DevConsts &k_, int q) : k(k_), lo(k_.age_lo[q]), hi(k_.age_hi[q]) {}
+    // the edges of bin i, then those of bin i + G prefetched
+    __device__ void step(int i, float &a_lo, float &a_hi) {
+        a_lo = lo;
+        a_hi = hi;
+        const int in = min(i + G, NA - 1);
+        lo = (G == 1) ? hi : k.age_lo[in];
+        hi = k.age_hi[in];
+    }
+};
+
 template <bool DERIV>
-__device__ inline void dpl_bin(const DevConsts &k, int i, float t_obs, const Dpl &p, float &m,
-                               float &d_tau, float &d_al, float &d_be) {
+__device__ inline void dpl_bin(float a_lo, float a_hi, float t_obs, const Dpl &p, float &m, float &d_tau,
+                               float &d_al, float &d_be) {
     m = d_tau = d_al = d_be = 0.0f;
-    const float a_lo = k.age_lo[i], a_hi = k.age_hi[i];
     if (!(a_lo < t_obs)) return;
     // span W of the bin in X is formed directly as log1p of the age-edge ratio (young bins
     // are ~1e-5 wide at |X| ~ 1, where xhi - xlo would cancel in FP32)
@@ -337,10 +354,9 @@ __device__ inline Logn make_logn(float tp, float w) {
 }
 
 template <bool DERIV>
-__device__ inline void logn_bin(const DevConsts &k, int i, float t_obs, const Logn &p, float &m, float &d_tp,
+__device__ inline void logn_bin(float a_lo, float a_hi, float t_obs, const Logn &p, float &m, float &d_tp,
                                 float &d_w) {
     m = d_tp = d_w = 0.0f;
-    const float a_lo = k.age_lo[i], a_hi = k.age_hi[i];
     if (!(a_lo < t_obs)) return;
     const float x_hi = (__builtin_amdgcn_logf(t_obs - a_lo) * 0.69314718055994531f - p.ltp) * p.inv_w - p.w;
     if (!(a_hi < t_obs)) {
