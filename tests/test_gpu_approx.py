@@ -304,3 +304,33 @@ def test_other_band_counts_match_oracle(oracle_mod, ssp2000, n_band):
         assert ok.all(), (np.argwhere(~ok)[:10], g[~ok][:10], rg[~ok][:10])
     finally:
         c.close()
+
+
+def test_many_table_nodes(ssp2000, filt6, orc):
+    # a 1000-node z table: 1000 sort buckets (four per thread of the sort's scans) over a ragged
+    # batch of several sort blocks; magnitudes and the likelihood gradient against the oracle
+    # built on the same nodes
+    import oracle
+    import paper_2506_19919_amd as sps
+    n, n_z = 3001, 1000
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32,), max_gal=4096)
+    try:
+        c.build_ztable(n_z, 0.1, 3.0)
+        o = oracle.Oracle(ssp2000, filt6)
+        o.build_ztable(n_z, 0.1, 3.0)
+        sfh, th, z = gal_inputs("dpl", n, 4242)
+        m = c.phot_approx(sfh, soa(th), dev(z)).cpu().numpy().astype(np.float64)
+        ref = o.phot_approx(sfh, th, z)
+        assert np.abs(m - ref).max() <= MAG_TOL, np.abs(m - ref).max()
+        obs, sig, masks = _obs(o, sfh, th, z, 17, synth.band_masks(n, 6, 18))
+        ll, g = c.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8))
+        g = g.cpu().numpy().T.astype(np.float64)
+        rl, rg = o.loglike_grad(sfh, th, z, obs, sig, masks)
+        prop, m_ref = grad_tol(o, sfh, th, z, sig, masks, m)
+        assert grad_ok(g, rg, prop).all()
+        r = np.abs(m_ref - obs) / sig
+        bar = np.sum(r * (np.abs(m - m_ref) + 2e-6) / sig, axis=1) + 1e-5 * np.abs(rl) + 1e-5
+        assert np.all(np.abs(ll.cpu().numpy() - rl) <= bar)
+        c.status()
+    finally:
+        c.close()
