@@ -99,7 +99,7 @@ int sps_create(sps_ctx **out, int device, const sps_ssp_desc *ssp, const sps_fil
                const sps_model_desc *model, unsigned prec_mask, int max_gal);
 
 /* Grow the per-galaxy workspace to max_gal galaxies: the approximate path's records
- * (196 B per galaxy) and the approximate-path HMC's chain state for max_gal chain slots
+ * (140 B per galaxy) and the approximate-path HMC's chain state for max_gal chain slots
  * (n_gal * n_chain; about 470 B per slot with its trajectory scratch).  Synchronises the
  * device; never shrinks. */
 int sps_reserve(sps_ctx *ctx, int max_gal);
@@ -310,8 +310,8 @@ int sps_autotune_hmc(sps_ctx *ctx, void *stream, const sps_hmc_cfg *cfg, int n_g
 /* sps_loglike_grad (approximate path) for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same
  * arguments, kernels and results as sps_loglike_grad with path = SPS_PATH_APPROX, but its
- * per-call buffers (sort order, histogram, input and output records) are a static device
- * array of the library, about 6.8 MB per device for SPS_STATIC_MAX_GAL galaxies, held until
+ * per-call buffers (sort order, bucket counts, input records) are a static device
+ * array of the library, about 4.6 MB per device for SPS_STATIC_MAX_GAL galaxies, held until
  * the process ends; it allocates nothing and calls no allocating routine.  n_gal above
  * SPS_STATIC_MAX_GAL is SPS_E_INVAL.  Every call on one device shares that device's array,
  * which keeps the last call's contents (each call clears what it needs): calls that overlap in

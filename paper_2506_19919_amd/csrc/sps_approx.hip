@@ -218,7 +218,6 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_bucket_gather(DevConsts k, int n
         const int sl = start[bk[u]] + lr[u], at = pos[bk[u]] + lr[u];
         row_of[sl] = nat;
         dest[sl] = at;
-        ga.inv[base + nat] = at;
     }
     __syncthreads();
     const int nv = min(GATHER_TILE, n - base);
@@ -237,7 +236,8 @@ struct ApproxArgs {
     const float *bounds;      // [10][4]
     const float *prior;       // [10][3]
     const uint16_t *qf, *qa;  // z table fragments (forward, adjoint contraction)
-    float *orec;              // output records in z-bucket order
+    const int *perm;          // the caller's index of each galaxy in bucket order
+    float *mag, *val, *grad;  // outputs in the caller's order: [n][n_band], [n], [10][n] (may be null)
 };
 
 template <int MODE>
@@ -249,6 +249,9 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
     const int lane = threadIdx.x;
     const int idx = blockIdx.x * WAVE + lane;
     const bool valid = idx < a.n;
+    // the galaxy's place in the caller's arrays (its results are written there directly: each
+    // lane's few scattered stores cost the VALU-bound kernel less than a separate reordering pass)
+    const int dst_g = a.perm[valid ? idx : a.n - 1];
     // parameters, z, mask and the cosmology from the record now; observations and sigma are
     // read from it where the likelihood needs them (not held in registers through the model)
     const float *rec = a.rec + (size_t)(valid ? idx : a.n - 1) * REC;
@@ -288,14 +291,11 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
                     mask, mags, logl, gr);
     if (!valid) return;
     const float bad = (kk >= 0) ? 0.0f : __int_as_float(0x7fc00000);
-    // whole 64-byte records (full-line writes)
-    v4f *dst = (v4f *)(a.orec + (size_t)idx * OREC);
-    const v4f zero4 = v4f{0.f, 0.f, 0.f, 0.f};
     if (MODE == MODE_MAGS) {
-        dst[0] = v4f{mags[0] + bad, mags[1] + bad, mags[2] + bad, mags[3] + bad};
-        dst[1] = v4f{mags[4] + bad, mags[5] + bad, mags[6] + bad, mags[7] + bad};
-        dst[2] = zero4;
-        dst[3] = zero4;
+        const int nb = k.n_band;
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b)
+            if (b < nb) a.mag[(size_t)dst_g * nb + b] = mags[b] + bad;
         return;
     }
     float val = (float)logl;
@@ -309,37 +309,10 @@ __global__ void __launch_bounds__(WAVE, 2) k_approx(DevConsts k, ApproxArgs a) {
         }
         val = (float)lp;
     }
-    if (MODE == MODE_LOGL) {
-        dst[0] = v4f{val + bad, 0.f, 0.f, 0.f};
-        dst[1] = zero4;
-        dst[2] = zero4;
-        dst[3] = zero4;
-        return;
-    }
-    dst[0] = v4f{val + bad, gr[0] + bad, gr[1] + bad, gr[2] + bad};
-    dst[1] = v4f{gr[3] + bad, gr[4] + bad, gr[5] + bad, gr[6] + bad};
-    dst[2] = v4f{gr[7] + bad, gr[8] + bad, gr[9] + bad, 0.f};
-    dst[3] = zero4;
-}
-
-// results back into the caller's order: thread i reads its galaxy's record (one line)
-// and writes coalesced outputs
-template <int MODE>
-__global__ void __launch_bounds__(256) k_unpermute(int n, int nb, const int *__restrict__ inv,
-                                                   const float *__restrict__ orec, float *__restrict__ mag,
-                                                   float *__restrict__ val, float *__restrict__ grad) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float *o = orec + (size_t)inv[i] * OREC;
-    if (MODE == MODE_MAGS) {
-        for (int b = 0; b < nb; ++b) mag[(size_t)i * nb + b] = o[b];
-        return;
-    }
-    if (val) val[i] = o[0];
-    if (MODE != MODE_LOGL && grad) {
+    if (a.val) a.val[dst_g] = val + bad;
+    if (MODE == MODE_LOGL || !a.grad) return;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) grad[(size_t)p * n + i] = o[1 + p];
-    }
+    for (int p = 0; p < NP; ++p) a.grad[(size_t)p * a.n + dst_g] = gr[p] + bad;
 }
 
 // ------------------------------------------------------------------ SSP weights output
@@ -396,7 +369,7 @@ int launch_bucket_sort_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, 
     return SPS_OK;
 }
 
-ApproxWs ctx_ws(sps_ctx *c) { return ApproxWs{c->d_perm, c->d_inv, c->d_hist, c->d_rec, c->d_orec}; }
+ApproxWs ctx_ws(sps_ctx *c) { return ApproxWs{c->d_perm, c->d_hist, c->d_rec}; }
 
 int launch_bucket_sort(sps_ctx *c, hipStream_t s, int n, const float *z, const GatherArgs *ga,
                        const DevConsts *grid) {
@@ -407,52 +380,24 @@ int launch_approx_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, int s
                      const float *z, const float *obs, const float *sigma, const uint8_t *mask, const float *bounds,
                      const float *prior, float *out_mag, float *out_val, float *out_grad) {
     const GatherArgs ga{params, mode == MODE_MAGS ? nullptr : obs, mode == MODE_MAGS ? nullptr : sigma,
-                        mode == MODE_MAGS ? nullptr : mask, ws.rec, ws.inv, c->d_status};
+                        mode == MODE_MAGS ? nullptr : mask, ws.rec, c->d_status};
     int rc = launch_bucket_sort_ws(c, s, ws, n, z, &ga, nullptr);
     if (rc) return rc;
-    ApproxArgs a{n, sfh, mode, ws.rec, bounds, prior, c->d_qf, c->d_qa, ws.orec};
-    const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE), ug((n + 255) / 256), ub(256);
-    const int nb = c->n_band;
-    const size_t lds_bytes = approx_lds_bytes(nb, true);
+    ApproxArgs a{n, sfh, mode, ws.rec, bounds, prior, c->d_qf, c->d_qa, ws.perm, out_mag,
+                 mode == MODE_VJP ? nullptr : out_val, out_grad};
+    const dim3 grid((n + WAVE - 1) / WAVE), block(WAVE);
+    const size_t lds_bytes = approx_lds_bytes(c->n_band, true);
     hipEvent_t *tev = timing_pair(c);
+    if (tev) (void)hipEventRecord(tev[0], s);
     switch (mode) {
-        case MODE_MAGS:
-            if (tev) (void)hipEventRecord(tev[0], s);
-            hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, lds_bytes, s, c->k, a);
-            if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_MAGS>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag, out_val,
-                               out_grad);
-            break;
-        case MODE_LOGL:
-            if (tev) (void)hipEventRecord(tev[0], s);
-            hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, lds_bytes, s, c->k, a);
-            if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGL>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag, out_val,
-                               out_grad);
-            break;
-        case MODE_LOGL_GRAD:
-            if (tev) (void)hipEventRecord(tev[0], s);
-            hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, lds_bytes, s, c->k, a);
-            if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
-                               out_val, out_grad);
-            break;
-        case MODE_VJP:
-            if (tev) (void)hipEventRecord(tev[0], s);
-            hipLaunchKernelGGL(k_approx<MODE_VJP>, grid, block, lds_bytes, s, c->k, a);
-            if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGL_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
-                               nullptr, out_grad);
-            break;
-        case MODE_LOGPOST_GRAD:
-            if (tev) (void)hipEventRecord(tev[0], s);
-            hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, lds_bytes, s, c->k, a);
-            if (tev) (void)hipEventRecord(tev[1], s);
-            hipLaunchKernelGGL(k_unpermute<MODE_LOGPOST_GRAD>, ug, ub, 0, s, n, nb, ws.inv, ws.orec, out_mag,
-                               out_val, out_grad);
-            break;
+        case MODE_MAGS: hipLaunchKernelGGL(k_approx<MODE_MAGS>, grid, block, lds_bytes, s, c->k, a); break;
+        case MODE_LOGL: hipLaunchKernelGGL(k_approx<MODE_LOGL>, grid, block, lds_bytes, s, c->k, a); break;
+        case MODE_LOGL_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGL_GRAD>, grid, block, lds_bytes, s, c->k, a); break;
+        case MODE_VJP: hipLaunchKernelGGL(k_approx<MODE_VJP>, grid, block, lds_bytes, s, c->k, a); break;
+        case MODE_LOGPOST_GRAD: hipLaunchKernelGGL(k_approx<MODE_LOGPOST_GRAD>, grid, block, lds_bytes, s, c->k, a); break;
         default: return set_error(SPS_E_INVAL, "bad approx mode");
     }
+    if (tev) (void)hipEventRecord(tev[1], s);
     SPS_HIP(hipGetLastError());
     return SPS_OK;
 }

@@ -11,17 +11,15 @@
 namespace sps {
 
 // Scratch of sps_loglike_grad_static: the approximate path's per-call buffers (z-bucket order,
-// its inverse, the sort's histogram and cursors, the input and output records) for up to
+// the sort's bucket totals and block counts, the input records) for up to
 // SPS_STATIC_MAX_GAL galaxies, laid out at 256-byte boundaries.  One copy per device, held
 // until the process ends.  In host code the array's name is not a device address: kernels
 // get the address hipGetSymbolAddress returned for the current device (g_scratch).
 constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr size_t ST_PERM = 0;
-constexpr size_t ST_INV = ST_PERM + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
-constexpr size_t ST_HIST = ST_INV + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
+constexpr size_t ST_HIST = ST_PERM + al256((size_t)SPS_STATIC_MAX_GAL * sizeof(int));
 constexpr size_t ST_REC = ST_HIST + al256(sort_ws_ints(SPS_STATIC_MAX_GAL) * sizeof(int));
-constexpr size_t ST_OREC = ST_REC + al256((size_t)SPS_STATIC_MAX_GAL * REC * sizeof(float));
-constexpr size_t ST_BYTES = ST_OREC + al256((size_t)SPS_STATIC_MAX_GAL * OREC * sizeof(float));
+constexpr size_t ST_BYTES = ST_REC + al256((size_t)SPS_STATIC_MAX_GAL * REC * sizeof(float));
 static __device__ __align__(256) unsigned char scratch[ST_BYTES];
 
 constexpr int MAX_DEVICES = 64;
@@ -245,9 +243,7 @@ void free_ctx(sps_ctx *c) {
     (void)hipFree(c->d_qa);
     (void)hipFree(c->d_ctab);
     (void)hipFree(c->d_perm);
-    (void)hipFree(c->d_inv);
     (void)hipFree(c->d_rec);
-    (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hist);
     (void)hipFree(c->d_status);
     (void)hipFree(c->d_hstate);
@@ -295,22 +291,18 @@ int sps_reserve(sps_ctx *c, int max_gal) {
     if (max_gal <= c->max_gal) return SPS_OK;
     SPS_HIP(hipDeviceSynchronize());
     (void)hipFree(c->d_perm);
-    (void)hipFree(c->d_inv);
     (void)hipFree(c->d_rec);
-    (void)hipFree(c->d_orec);
     (void)hipFree(c->d_hstate);
     (void)hipFree(c->d_hist);
     c->d_hist = nullptr;
-    c->d_perm = c->d_inv = nullptr;
-    c->d_rec = c->d_orec = nullptr;
+    c->d_perm = nullptr;
+    c->d_rec = nullptr;
     c->d_hstate = nullptr;
     c->hstate_bytes = 0;
     c->max_gal = 0;
     SPS_HIP(hipMalloc(&c->d_hist, sort_ws_ints(max_gal) * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_perm, (size_t)max_gal * sizeof(int)));
-    SPS_HIP(hipMalloc(&c->d_inv, (size_t)max_gal * sizeof(int)));
     SPS_HIP(hipMalloc(&c->d_rec, (size_t)max_gal * REC * sizeof(float)));
-    SPS_HIP(hipMalloc(&c->d_orec, (size_t)max_gal * OREC * sizeof(float)));
     const size_t hb = hmc_state_bytes(max_gal);
     SPS_HIP(hipMalloc(&c->d_hstate, hb));
     c->hstate_bytes = hb;
@@ -787,8 +779,7 @@ int sps_loglike_grad_static(sps_ctx *c, void *stream, int n_gal, int sfh, const 
     if (!params || !z || !obs || !sigma || !band_mask || !logl_out) return set_error(SPS_E_INVAL, "null array");
     char *base = g_scratch[c->device];   // set by sps_create for this device
     if (!base) return set_error(SPS_E_STATE, "no static scratch on this device");
-    const ApproxWs ws{(int *)(base + ST_PERM), (int *)(base + ST_INV), (int *)(base + ST_HIST),
-                      (float *)(base + ST_REC), (float *)(base + ST_OREC)};
+    const ApproxWs ws{(int *)(base + ST_PERM), (int *)(base + ST_HIST), (float *)(base + ST_REC)};
     return launch_approx_ws(c, (hipStream_t)stream, ws, n_gal, sfh, grad_out ? MODE_LOGL_GRAD : MODE_LOGL, params, z,
                             obs, sigma, band_mask, nullptr, nullptr, nullptr, logl_out, grad_out);
 }

@@ -91,9 +91,7 @@ struct sps_ctx {
     // per-galaxy workspace
     int max_gal = 0;
     int *d_perm = nullptr;         // galaxies ordered by z bucket
-    int *d_inv = nullptr;          // position of each galaxy in that order
     float *d_rec = nullptr;        // inputs in z-bucket order, one 128-byte record per galaxy
-    float *d_orec = nullptr;       // outputs in z-bucket order, 64 bytes per galaxy
     int *d_hist = nullptr;         // z-bucket sort: bucket totals and per-block counts (sort_ws_ints)
     int *d_status = nullptr;       // device-side error bits (STATUS_*), read and cleared by sps_status
     void *d_hstate = nullptr;      // chain state of the approximate-path HMC, max_gal chain slots
@@ -145,7 +143,6 @@ constexpr int REC = 32;
 // slots 28..31: age of the universe at z [Gyr] and the distance part of the magnitude
 // offset, each as an FP64 value in two words (low, high)
 enum { REC_Z = 10, REC_OBS = 11, REC_SIG = 19, REC_MASK = 27, REC_TOBS = 28, REC_M0 = 30 };
-constexpr int OREC = 16;          // output record: mags[8] or (value, grad[10])
 
 // z-bucket sort workspace (ints): the buckets' totals, then one count row per block of
 // SORT_T galaxies (at most SORT_MAX_BUCKETS buckets: z-table nodes <= 1024)
@@ -158,7 +155,6 @@ struct GatherArgs {
     const float *params, *obs, *sigma;  // obs, sigma may be null (magnitudes only)
     const uint8_t *mask;                // may be null (all bands)
     float *rec;                         // null: sort only
-    int *inv;
     int *status;                        // STATUS_Z_RANGE is set here for a z outside the table (or null)
 };
 // z buckets for ranking galaxies by redshift: the z table's nodes, or 64 buckets over
@@ -184,11 +180,11 @@ size_t chain_state_bytes_public(int nslot);   // chain state of nslot chains in 
 size_t hmcx_state_bytes(const sps_ctx *c, int nslot);
 int launch_weights(sps_ctx *c, hipStream_t s, int n_gal, int sfh, const float *params, const float *z,
                    float *w);
-// the approximate path's per-call buffers: z-bucket order, its inverse, the sort's histogram and
-// cursors (2 x 1025 ints), input and output records; the context's, or another owner's
+// the approximate path's per-call buffers: z-bucket order, the sort's bucket totals and block
+// counts (sort_ws_ints), the input records; the context's, or another owner's
 struct ApproxWs {
-    int *perm, *inv, *hist;
-    float *rec, *orec;
+    int *perm, *hist;
+    float *rec;
 };
 ApproxWs ctx_ws(sps_ctx *c);
 int launch_bucket_sort_ws(sps_ctx *c, hipStream_t s, const ApproxWs &ws, int n, const float *z, const GatherArgs *ga,
