@@ -206,9 +206,13 @@ __device__ inline void forward_weights(const DevConsts &k, const float *ledge, i
         for (int i = q; i < NA; i += G) col[i] = 0.0f;
     }
     {
+        // each edge's log age is read one bin ahead of its use (not behind the column update)
         BurstEdge lo = burst_edge<false>(ledge, i0, l_obs, mu, inv_s3);
+        float le = ledge[min(i0 + 1, NA)];
         for (int t = 0; t < k.burst_nbins && i0 + t < NA; ++t) {
-            const BurstEdge hi = burst_edge<false>(ledge, i0 + t + 1, l_obs, mu, inv_s3);
+            const float le_next = ledge[min(i0 + t + 2, NA)];
+            const BurstEdge hi = burst_edge_at<false>(le, l_obs, mu, inv_s3);
+            le = le_next;
             if (G == 1 || (i0 + t) % G == q) col[i0 + t] = fmaf(cb, burst_mass(lo, hi), col[i0 + t]);
             lo = hi;
         }

@@ -426,13 +426,18 @@ __device__ inline void stage_log_age_edges(const DevConsts &k, float *ledge) {
 struct BurstEdge {
     float u, tail, d;
 };
+// an edge at log age le
 template <bool DERIV>
-__device__ inline BurstEdge burst_edge(const float *ledge, int e, float l_obs, float mu, float inv_s3) {
+__device__ inline BurstEdge burst_edge_at(float le, float l_obs, float mu, float inv_s3) {
     BurstEdge r;
-    r.u = (fminf(ledge[min(e, NA)], l_obs) - mu) * inv_s3;
+    r.u = (fminf(le, l_obs) - mu) * inv_s3;
     r.tail = tri_cdf(-fabsf(r.u));
     r.d = DERIV ? tri_dcdf(r.u) : 0.0f;
     return r;
+}
+template <bool DERIV>
+__device__ inline BurstEdge burst_edge(const float *ledge, int e, float l_obs, float mu, float inv_s3) {
+    return burst_edge_at<DERIV>(ledge[min(e, NA)], l_obs, mu, inv_s3);
 }
 // profile mass between two edges (the derivative w.r.t. mu is (lo.d - hi.d) / (3 sigma))
 __device__ inline float burst_mass(const BurstEdge &lo, const BurstEdge &hi) {
