@@ -884,31 +884,44 @@ __global__ void k_exact_finish(DevConsts k, int n, int n_tiles, const void *para
 
 // Rbar[g][l] = sum_b (d logL / d num_b) F_att(l) T_b((1+z) l) l q_l  (zero beyond n_wave);
 // bands more than 8 sigma from the redshifted wavelength contribute below FP32 resolution.
-// One block per galaxy walks the row in chunks of 256 wavelengths, so the galaxy's constants
-// are loaded once (a block per chunk spent most of its short life waiting on those loads).
-template <int P>
+// One block takes G consecutive galaxies (rows of one 128-row tile, so one filter-support
+// window) and walks their rows in chunks of 256 wavelengths: the galaxies' constants are loaded
+// together once, and each batch of wavelength constants serves all of the block's galaxies.
+// With a block per galaxy, each block's short life went mostly to waiting on those two loads
+// (a block per chunk had been worse still); G = 4 pays once the batch leaves at least 8192
+// blocks to fill the chip, and below that G = 1 keeps more blocks in flight.
+constexpr int RBAR_G_BIG = 4, RBAR_BIG_MIN_GAL = 32768;
+static_assert(XBM % RBAR_G_BIG == 0, "a block's galaxies share one row tile");
+template <int P, int RBAR_G>
 __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, int nb, FiltConst fl,
                                                     const float *params, const float *z, const float *wc,
                                                     const float *cnum, const int4 *win, void *rb) {
-    const int g = blockIdx.x, tid = threadIdx.x;
+    const int g0 = blockIdx.x * RBAR_G, tid = threadIdx.x;
+    const int ng = min(RBAR_G, n - g0);   // galaxies of this block (>= 1)
     // the gradient GEMM reads only the k-tiles inside its row tile's filter-support window:
     // chunks wholly outside it are never read and are not written
     int c_lo = 0, c_hi = (ld + 255) / 256;
     if (win) {
-        const int4 w = win[g / XBM];
+        const int4 w = win[g0 / XBM];
         c_lo = (w.z * XBK) / 256;
         c_hi = min(c_hi, (w.w * XBK + 255) / 256);
     }
-    const double opz = 1.0 + (double)z[g];
-    const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g], ffl = params[(size_t)9 * n + g];
-    float cb[NB_MAX], ta[NB_MAX], tc[NB_MAX];   // filter offsets as in the forward epilogue
+    double opz[RBAR_G];
+    float cb[RBAR_G][NB_MAX], ffl[RBAR_G], delta2[RBAR_G], tauv2[RBAR_G];
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) {
-        cb[b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
-        ta[b] = (float)(opz * fl.inv_fs[b] * GAUSS_K2);
-        tc[b] = (float)(-fl.fc[b] * fl.inv_fs[b] * GAUSS_K2);
+    for (int j = 0; j < RBAR_G; ++j) {
+        const int g = min(g0 + j, n - 1);
+        opz[j] = 1.0 + (double)z[g];
+        const float tauv = params[(size_t)7 * n + g], delta = params[(size_t)8 * n + g];
+        ffl[j] = params[(size_t)9 * n + g];
+        delta2[j] = delta * LOG2E_F;
+        tauv2[j] = -tauv * LOG2E_F;
+#pragma unroll
+        for (int b = 0; b < NB_MAX; ++b) cb[j][b] = (b < nb) ? cnum[(size_t)g * NB_MAX + b] : 0.0f;
     }
-    const float delta2 = delta * LOG2E_F, tauv2 = -tauv * LOG2E_F;
+    float tc[NB_MAX];   // filter offsets as in the forward epilogue
+#pragma unroll
+    for (int b = 0; b < NB_MAX; ++b) tc[b] = (float)(-fl.fc[b] * fl.inv_fs[b] * GAUSS_K2);
     // RU chunks per step, their wavelength constants loaded together: each chunk's work is a
     // few dozen instructions, so a step that waited out its own load before computing left the
     // block latency-bound.  Bands are tested per element (a wave's 64 wavelengths lie within a
@@ -922,31 +935,39 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
             w[u] = *(const v4f *)(wc + 4 * (size_t)lc);   // ln x, l q, q / l, l
         }
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int l = (ch0 + u) * 256 + tid;
-            if (ch0 + u >= c_hi || l >= ld) break;
-            float v = 0.0f;
-            if (l < n_wave) {
-                float sum = 0.0f;
+        for (int j = 0; j < RBAR_G; ++j) {
+            if (j >= ng) break;
+            const int g = g0 + j;
+            float ta[NB_MAX];
 #pragma unroll
-                for (int b = 0; b < NB_MAX; ++b) {
-                    if (b >= nb) break;
-                    const float t = fmaf(w[u][3], ta[b], tc[b]);
-                    if (fabsf(t) < 8.0f * GAUSS_K2) sum = fmaf(cb[b], __builtin_amdgcn_exp2f(-t * t), sum);
+            for (int b = 0; b < NB_MAX; ++b) ta[b] = (float)(opz[j] * fl.inv_fs[b] * GAUSS_K2);
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int l = (ch0 + u) * 256 + tid;
+                if (ch0 + u >= c_hi || l >= ld) break;
+                float v = 0.0f;
+                if (l < n_wave) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int b = 0; b < NB_MAX; ++b) {
+                        if (b >= nb) break;
+                        const float t = fmaf(w[u][3], ta[b], tc[b]);
+                        if (fabsf(t) < 8.0f * GAUSS_K2) sum = fmaf(cb[j][b], __builtin_amdgcn_exp2f(-t * t), sum);
+                    }
+                    if (sum != 0.0f) {
+                        const float F = ffl[j] + (1.0f - ffl[j]) * __builtin_amdgcn_exp2f(
+                                                                    tauv2[j] * __builtin_amdgcn_exp2f(delta2[j] * w[u][0]));
+                        v = sum * F * w[u][1];
+                    }
                 }
-                if (sum != 0.0f) {
-                    const float F =
-                        ffl + (1.0f - ffl) * __builtin_amdgcn_exp2f(tauv2 * __builtin_amdgcn_exp2f(delta2 * w[u][0]));
-                    v = sum * F * w[u][1];
+                if (P == SPS_F32) {
+                    ((float *)rb)[(size_t)g * ld + l] = v;
+                } else {
+                    const uint16_t h = f2bf(v);
+                    const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
+                    ((uint16_t *)rb)[o] = h;
+                    ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
                 }
-            }
-            if (P == SPS_F32) {
-                ((float *)rb)[(size_t)g * ld + l] = v;
-            } else {
-                const uint16_t h = f2bf(v);
-                const size_t o = bfx_at(g, ld, l);   // interleaved hi / lo rows
-                ((uint16_t *)rb)[o] = h;
-                ((uint16_t *)rb)[o + 32] = f2bf(v - bf2f(h));
             }
         }
     }
@@ -1301,14 +1322,13 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
     }
     if (want_grad) {
         void *r_hi = W + o_rb;   // Rbar rows: FP32 [mp][lw], or BF16 hi + lo interleaved [mp][2 lw]
-        dim3 gr(n), br(256);
+        const bool big = n >= RBAR_BIG_MIN_GAL;
+        dim3 gr(big ? (n + RBAR_G_BIG - 1) / RBAR_G_BIG : n), br(256);
         const FiltConst fl = filt_const(c->h_fc, c->h_fs);
-        if (prec == SPS_F32)
-            hipLaunchKernelGGL(k_exact_rbar<SPS_F32>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wc, cn, win, r_hi);
-        else
-            hipLaunchKernelGGL(k_exact_rbar<SPS_BF16X>, gr, br, 0, s, n, nw, lw, nb, fl,
-                               (const float *)params, (const float *)z, c->d_wc, cn, win, r_hi);
+        auto kr = (prec == SPS_F32) ? (big ? k_exact_rbar<SPS_F32, RBAR_G_BIG> : k_exact_rbar<SPS_F32, 1>)
+                                    : (big ? k_exact_rbar<SPS_BF16X, RBAR_G_BIG> : k_exact_rbar<SPS_BF16X, 1>);
+        hipLaunchKernelGGL(kr, gr, br, 0, s, n, nw, lw, nb, fl, (const float *)params, (const float *)z,
+                           c->d_wc, cn, win, r_hi);
         XArgs b{};
         b.win = win;
         b.M = n;
