@@ -8,8 +8,8 @@
 // wave share the table slices Q[k], Q[k+1] and the two contractions over the
 // table run as small wave-wide GEMMs on the matrix cores.  The sort also
 // gathers each galaxy's inputs into a 128-byte record in that order, so the
-// kernel reads them coalesced; results are written in the same order and put
-// back into the caller's order by a coalescing pass.
+// kernel reads them coalesced; each lane writes its results at its galaxy's
+// index in the caller's arrays.
 #include "sps_eval.h"
 
 namespace sps {
