@@ -122,6 +122,47 @@ def test_exact_loglike_grad_large_batch(ctx2000, orc, prec_name, tol):
 
 
 @pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
+def test_exact_loglike_grad_grouped_rbar_every_output(ssp2000, filt6, orc, prec_name, tol):
+    # 40,003 galaxies (the size class of the exact-photometry HMC, where the gradient kernel
+    # takes four galaxies per block; 40,003 = 4 x 10,000 + 3 leaves a ragged last block):
+    # 32 distinct galaxies, each repeated, so that every output, wherever the internal z
+    # ranking puts its row, is checked against its prototype's oracle value.  Their redshifts
+    # lie in three of the ranking's 0.125-wide z buckets, so the copies of different galaxies
+    # mix inside a bucket and a block's four rows are mostly different galaxies
+    import paper_2506_19919_amd as sps
+    n, k = 40_003, 32
+    sfh, th0, _ = gal_inputs("dpl", k, 311)
+    z0 = f32(np.random.default_rng(315).uniform(1.0, 1.35, k))
+    noise, sig0 = synth.photometric_noise(k, 6, 312)
+    obs0 = f32(orc.phot_exact(sfh, th0, z0) + noise)
+    sig0 = f32(sig0)
+    masks0 = synth.band_masks(k, 6, 313)
+    rep = np.random.default_rng(314).integers(0, k, n)
+    rep[:k] = np.arange(k)
+    th, z, obs, sig, masks = th0[rep], z0[rep], obs0[rep], sig0[rep], masks0[rep]
+    prec = getattr(sps, prec_name)
+    c = sps.Context(ssp2000, filt6, precisions=(sps.SPS_F32, sps.SPS_BF16X), max_gal=n, max_exact=n)
+    try:
+        ll, g = c.loglike_grad(sfh, soa(th), dev(z), dev(obs), dev(sig), dev(masks, torch.uint8),
+                               path=sps.SPS_PATH_EXACT, prec=prec)
+        m_all = c.phot_exact(sfh, soa(th), dev(z), prec=prec).cpu().numpy()
+    finally:
+        c.close()
+    ll, g = ll.cpu().numpy(), g.cpu().numpy().T.astype(np.float64)
+    rl, rg = orc.loglike_grad(sfh, th0, z0, obs0, sig0, masks0, path=1)
+    m0 = orc.phot_exact(sfh, th0, z0)
+    assert np.abs(m_all - m0[rep]).max() <= tol
+    r = np.abs((m0 - obs0) / sig0) * ((masks0[:, None] >> np.arange(6)) & 1)
+    assert np.all(np.abs(ll - rl[rep]) <= (r.sum(1)[rep] / 0.05) * tol + 1e-3)
+    # per prototype, the propagation allowance of its largest magnitude difference over its copies
+    dm_max = np.zeros((k, 6))
+    np.maximum.at(dm_max, rep, np.abs(m_all - m0[rep]))
+    prop, _ = grad_tol(orc, sfh, th0, z0, sig0, masks0, m0 + dm_max, path=1)
+    ok = grad_ok(g, rg[rep], prop[rep])
+    assert ok.all(), (np.argwhere(~ok)[:8], g[~ok][:8], rg[rep][~ok][:8])
+
+
+@pytest.mark.parametrize("prec_name,tol", [("SPS_F32", 1e-4), ("SPS_BF16X", 2e-3)])
 def test_exact_full_size_sampled(ctx5000, orc5000, prec_name, tol):
     # the benchmarked configuration: 4096 galaxies x 1128 SSPs x 5000 wavelengths (32 row
     # tiles, K split of the gradient GEMM, filter-support windows over random z); magnitudes,
