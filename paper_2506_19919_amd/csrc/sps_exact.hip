@@ -782,33 +782,43 @@ __global__ void __launch_bounds__(64) k_exact_pw(DevConsts k, int n, int sfh, co
 }
 
 // weights rows W[g][s] = P_Z(j) P_age(i), s = j NA + i, zero for s >= NSSP.  A block takes
-// XG galaxies: their P_age and P_Z columns (galaxy-contiguous in pw) are staged in LDS, then
-// the rows are written with consecutive threads on consecutive s (whole lines).
-constexpr int XG = 16;
+// XG galaxies: their P_age and P_Z columns (galaxy-contiguous in pw) are staged in LDS, one row
+// of factors per galaxy, then the rows are written with consecutive threads on consecutive
+// pairs of s (whole lines; a pair is one 8-byte FP32 or two 4-byte BF16 stores, and never
+// straddles a metallicity, the padding or a 32-element chunk, NA, NSSP and S_PAD being even).
+// The lanes of a wave read consecutive pairs of one galaxy's row, and the staging writes of
+// consecutive galaxies fall in different banks (row length 106 words).
+constexpr int XG = 16, XROWF = NA + NZ;
+static_assert(NA % 2 == 0 && NSSP % 2 == 0 && S_PAD % 2 == 0 && XROWF % 2 == 0, "pairs of SSPs");
 template <int P>
 __global__ void __launch_bounds__(256) k_expand(int n, const float *pw, void *w) {
-    __shared__ float sp[NA + NZ][XG];
+    __shared__ __attribute__((aligned(8))) float sp[XG][XROWF];
     const int g0 = blockIdx.x * XG, tid = threadIdx.x;
     for (int e = tid; e < (NA + NZ) * XG; e += 256) {
         const int r = e / XG, t = e - r * XG, g = min(g0 + t, n - 1);
-        sp[r][t] = pw[(size_t)(r < NA ? r : PW_PZ + (r - NA)) * n + g];
+        sp[t][r] = pw[(size_t)(r < NA ? r : PW_PZ + (r - NA)) * n + g];
     }
     __syncthreads();
     const int ng = min(XG, n - g0);
-    for (int e = tid; e < ng * S_PAD; e += 256) {
-        const int t = e / S_PAD, sidx = e - t * S_PAD, g = g0 + t;
-        float v = 0.0f;
+    constexpr int HP = S_PAD / 2;
+    for (int e = tid; e < ng * HP; e += 256) {
+        const int t = e / HP, sidx = 2 * (e - t * HP), g = g0 + t;
+        float v0 = 0.0f, v1 = 0.0f;
         if (sidx < NSSP) {
             const int j = sidx / NA, i = sidx - j * NA;
-            v = sp[NA + j][t] * sp[i][t];
+            const float pzj = sp[t][NA + j];
+            const float2 pa = *(const float2 *)&sp[t][i];
+            v0 = pzj * pa.x;
+            v1 = pzj * pa.y;
         }
         if constexpr (P == SPS_F32) {
-            ((float *)w)[(size_t)g * S_PAD + sidx] = v;
+            *(float2 *)((float *)w + (size_t)g * S_PAD + sidx) = make_float2(v0, v1);
         } else {
-            const uint16_t h = f2bf(v);
-            const size_t o = bfx_at(g, S_PAD, sidx);   // interleaved hi / lo rows
-            ((uint16_t *)w)[o] = h;
-            ((uint16_t *)w)[o + 32] = f2bf(v - bf2f(h));
+            const uint16_t h0 = f2bf(v0), h1 = f2bf(v1);
+            const uint16_t l0 = f2bf(v0 - bf2f(h0)), l1 = f2bf(v1 - bf2f(h1));
+            const size_t o = bfx_at(g, S_PAD, sidx);   // interleaved hi / lo rows; o is even
+            *(uint32_t *)((uint16_t *)w + o) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            *(uint32_t *)((uint16_t *)w + o + 32) = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
     }
 }
