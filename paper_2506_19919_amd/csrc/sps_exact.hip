@@ -988,10 +988,14 @@ __global__ void __launch_bounds__(256) k_exact_rbar(int n, int n_wave, int ld, i
 // Thread per (galaxy, group of WB_AGES ages): each Wbar element is read once; the group's
 // dP_age are complete, its dP_Z are partial sums written SoA pb[NA + grp NZ + j][n] and added
 // by the weights adjoint.  Written SoA pb[r][n] (r < NA: dP_age).
+// Below GPL_BIG_N galaxies the grid is small: blocks of one wave (four times the blocks to
+// spread over the CUs) and two ages' loads in flight per thread; above it, blocks of 256 with
+// one age at a time were faster.
 constexpr int WB_GROUPS = 4, WB_AGES = (NA + WB_GROUPS - 1) / WB_GROUPS;
-__global__ void __launch_bounds__(256) k_wbar_reduce(int n, const float *pw, const float *wbar, int ld,
+template <int WB_T>
+__global__ void __launch_bounds__(WB_T) k_wbar_reduce(int n, const float *pw, const float *wbar, int ld,
                                                      float *pb) {
-    const int g = blockIdx.x * 256 + threadIdx.x, grp = blockIdx.y;
+    const int g = blockIdx.x * WB_T + threadIdx.x, grp = blockIdx.y;
     if (g >= n) return;
     float pz[NZ], dz[NZ];
 #pragma unroll
@@ -1000,6 +1004,7 @@ __global__ void __launch_bounds__(256) k_wbar_reduce(int n, const float *pw, con
         dz[j] = 0.0f;
     }
     const int i1 = min(NA, (grp + 1) * WB_AGES);
+#pragma unroll(WB_T == 64 ? 2 : 1)
     for (int i = grp * WB_AGES; i < i1; ++i) {
         float w[NZ];
 #pragma unroll
@@ -1371,8 +1376,12 @@ static int exact_core(sps_ctx *c, hipStream_t s, int n, int sfh, int prec, const
             hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, n4, b.k_splits, n4,
                                (v4f *)b.C);
         }
-        hipLaunchKernelGGL(k_wbar_reduce, dim3((n + 255) / 256, WB_GROUPS), dim3(256), 0, s, n, (const float *)pw,
-                           (const float *)b.C, mp, pb);
+        if (n >= GPL_BIG_N)
+            hipLaunchKernelGGL(k_wbar_reduce<256>, dim3((n + 255) / 256, WB_GROUPS), dim3(256), 0, s, n,
+                               (const float *)pw, (const float *)b.C, mp, pb);
+        else
+            hipLaunchKernelGGL(k_wbar_reduce<64>, dim3((n + 63) / 64, WB_GROUPS), dim3(64), 0, s, n,
+                               (const float *)pw, (const float *)b.C, mp, pb);
         if (n >= GPL_BIG_N)
             hipLaunchKernelGGL(k_exact_adjoint<2>, dim3((n + 31) / 32), dim3(64), 0, s, c->k, n, sfh,
                                (const float *)params, (const float *)z, (const float *)pw, (const float *)pb, grad);
